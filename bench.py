@@ -1,0 +1,192 @@
+#!/usr/bin/env python3
+"""Benchmark of the matrix-free hot path on one MI355X.
+
+Step = one matrix-free application y = A x of the variable-coefficient Q4 Laplacian on the
+curved 64^3-cell mesh (257^3 = 16,974,593 DoFs; deformation amplitude 0.1, coefficient
+a = 1 + 0.5 sin sin sin), FP64, with the input resident in HBM.  Prints one JSON line:
+DoFs/s of the step, the roofline of the dominant kernel (the cell loop, timed with HIP events
+on its stream), an FP32 figure of the same operator, and the CPU oracle on a bounded sample of
+the same workload.
+
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--solves]
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "DoFs/s matrix-free vmult FP64 vs FP32; solves/s + p99 latency at 1e-10"
+HBM_PEAK_GBS = 8000.0
+
+
+def algorithmic_bytes(p, n, real_bytes):
+    """src read + dst write once, 6 G values per quadrature point, one int32 index per cell DoF."""
+    N = (p * n + 1) ** 3
+    C = n ** 3
+    Q = C * (p + 1) ** 3
+    return 2 * real_bytes * N + 6 * real_bytes * Q + 4 * (p + 1) ** 3 * C
+
+
+def algorithmic_flops(p, n):
+    C = n ** 3
+    return C * (24 * (p + 1) ** 4 + 15 * (p + 1) ** 3)
+
+
+def time_vmult(op, x, steps, warmup):
+    """(wall s per step for clear+cell loop, event-timed s per cell-loop kernel)."""
+    import torch
+    y = op.new_vector()
+    for _ in range(warmup):
+        op.vmult(x, y)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        op.vmult(x, y)
+    torch.cuda.synchronize()
+    wall = (time.perf_counter() - t0) / steps
+    # dominant kernel alone: back-to-back cell-loop launches (accumulating) between two events
+    acc = torch.zeros_like(y)
+    op.vmult_add(x, acc)
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        op.vmult_add(x, acc)
+    e1.record()
+    torch.cuda.synchronize()
+    kern = e0.elapsed_time(e1) / 1e3 / steps
+    return wall, kern, y
+
+
+def cpu_baseline(p, n, amp, alpha, x_np, budget_s=12.0):
+    """Oracle element-by-element application on a bounded sample of cells, scaled to DoFs/s."""
+    import numpy as np
+    from oracle.ebe import ebe_vmult
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    cores = len(os.sched_getaffinity(0))
+    C = n ** 3
+    N = (p * n + 1) ** 3
+    chunk = 256
+    done, elapsed = 0, 0.0
+    ctx = threadpool_limits(limits=cores) if threadpool_limits else None
+    try:
+        while elapsed < budget_s and done < C:
+            cells = np.arange(done, min(C, done + chunk))
+            t0 = time.perf_counter()
+            ebe_vmult(p, n, amp, alpha, x_np, 1, cells=cells, chunk=chunk)
+            elapsed += time.perf_counter() - t0
+            done += len(cells)
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    dofs_per_s = (done / C) * N / elapsed
+    return {"value": dofs_per_s, "unit": "DoFs/s", "cores": cores, "kind": "oracle",
+            "sample": f"{done} of {C} cells (element-by-element, dense cell matrices), {elapsed:.1f} s, "
+                      f"scaled by cells/total to a full application"}
+
+
+def solve_benchmarks(steps):
+    """Time-to-1e-10 of the multigrid and CG solvers on the Q3 128^3 curved problem."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    out = {}
+    mesh = mfq.Mesh(128, 0.1)
+    space = mfq.Space(mesh, 3, mfq.MFQ_BC_DIRICHLET0)
+    op = mfq.Operator(space, 0.5, mfq.MFQ_FP64)
+    b = op.rhs_manufactured()
+    for name, kind in [("gmg_mixed", mfq.MFQ_SOLVER_GMG_MIXED), ("gmg_mixed_ir", mfq.MFQ_SOLVER_GMG_MIXED_IR),
+                       ("gmg_fp64", mfq.MFQ_SOLVER_GMG_FP64), ("cg_fp64", mfq.MFQ_SOLVER_CG)]:
+        s = mfq.Solver(op, kind)
+        x, info, st = s.solve(b, rtol=1e-10, max_iter=20000, check=False)
+        out[name] = {"seconds": info.seconds, "iterations": info.iterations, "outer": info.outer_iterations,
+                     "rel_residual": info.rel_residual, "status": st, "levels": info.n_levels}
+        del s
+        torch.cuda.synchronize()
+    return out
+
+
+def main():
+    ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--solves", action="store_true", help="add time-to-1e-10 of the Q3 128^3 solvers")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how it "
+              "would shard); run with --gpus 1", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    import paper_1910_13247_amd as mfq
+    from synthetic import VARCOEF_Q4_64, uniform_vector
+
+    pr = VARCOEF_Q4_64
+    p, n = pr.degree, pr.cells_1d
+    torch.cuda.set_device(0)
+    mesh = mfq.Mesh(n, pr.amplitude)
+    space = mfq.Space(mesh, p, mfq.MFQ_BC_DIRICHLET0)
+    op64 = mfq.Operator(space, pr.alpha, mfq.MFQ_FP64)
+    x_np = uniform_vector(space.n_dofs, seed=0)
+    x64 = torch.from_numpy(x_np).cuda()
+    print(f"# workload {pr.name}: {space.n_dofs} DoFs, {space.n_cells} cells", file=sys.stderr, flush=True)
+    wall64, kern64, y64 = time_vmult(op64, x64, args.steps, args.warmup)
+    print(f"# fp64: {wall64 * 1e3:.3f} ms/step, cell kernel {kern64 * 1e3:.3f} ms", file=sys.stderr, flush=True)
+
+    op32 = mfq.Operator(space, pr.alpha, mfq.MFQ_FP32)
+    x32 = x64.float()
+    wall32, kern32, y32 = time_vmult(op32, x32, args.steps, args.warmup)
+    rel32 = ((y32.double() - y64).abs().max() / y64.abs().max()).item()
+    print(f"# fp32: {wall32 * 1e3:.3f} ms/step, cell kernel {kern32 * 1e3:.3f} ms", file=sys.stderr, flush=True)
+    del op32, x32, y32
+    torch.cuda.synchronize()
+
+    N = space.n_dofs
+    bytes64 = algorithmic_bytes(p, n, 8)
+    bytes32 = algorithmic_bytes(p, n, 4)
+    achieved = bytes64 / kern64 / 1e9
+    rec = {
+        "metric": METRIC,
+        "value": N / wall64,
+        "unit": "DoFs/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": wall64 * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {"workload": "Q4 variable-coefficient Laplacian, curved 64^3 hex mesh, FP64 matrix-free vmult",
+                   "degree": p, "cells": space.n_cells, "dofs": N, "amplitude": pr.amplitude, "alpha": pr.alpha,
+                   "input": "uniform[-1,1) seed 0, resident in HBM"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "vmult_kernel<4,double> (cell loop)", "kernel_ms": kern64 * 1e3,
+                     "algorithmic_bytes": bytes64,
+                     "algorithmic_tflops": algorithmic_flops(p, n) / kern64 / 1e12},
+        "fp32": {"value": N / wall32, "unit": "DoFs/s", "ms_per_step": wall32 * 1e3, "kernel_ms": kern32 * 1e3,
+                 "achieved_GBs": bytes32 / kern32 / 1e9, "frac": bytes32 / kern32 / 1e9 / HBM_PEAK_GBS,
+                 "normwise_rel_err_vs_fp64": rel32},
+    }
+    if args.solves:
+        rec["solves_q3_128"] = solve_benchmarks(args.steps)
+    if not args.no_cpu_baseline:
+        print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
+        rec["cpu_baseline"] = cpu_baseline(p, n, pr.amplitude, pr.alpha, x_np)
+    print(json.dumps(rec), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,198 @@
+/*
+ * mfq.h — C ABI of the matrix-free Q_p finite element library for AMD MI355X (gfx950).
+ *
+ * What it computes (section numbers refer to the deal.II paper, arXiv 1910.13247):
+ *   The action y = A x of the operator of the weak form of eq. (1), generalised to a
+ *   variable coefficient, a(u,v) = int a(x) grad u . grad v dx, discretised with continuous
+ *   tensor-product Lagrange elements Q_p on a hexahedral mesh (Sec. 3.1, 3.4), integrated
+ *   with shape-function gradients and JxW at quadrature points as in the cell loop of
+ *   Sec. 2.4, and applied without assembling a matrix, by evaluating the integrals on the
+ *   fly with the tensor-product (sum factorisation) structure of the shape functions
+ *   (Sec. 3.6) on the GPU (Sec. 3.7).  The operator is used inside conjugate gradients and a
+ *   geometric multigrid preconditioner with Chebyshev smoothing (Sec. 3.5) whose V-cycle runs
+ *   in single precision under a double-precision correction (Sec. 6.1).
+ *
+ * Problem statement fixed by this library (readings where the paper is silent):
+ *   - mesh: n^3 cells on the unit cube, optionally deformed by the exact map
+ *     x = X + A*sin(pi X1) sin(pi X2) sin(pi X3)*(1,1,1) evaluated at every quadrature point;
+ *   - element: Q_p, p = 1..8, nodes at the Gauss-Lobatto-Legendre points, lexicographic
+ *     numbering (x fastest) of the (p*n+1)^3 lattice nodes;
+ *   - quadrature: (p+1)^3-point tensor Gauss-Legendre;
+ *   - coefficient: a(x) = 1 + alpha*sin(2 pi x1) sin(2 pi x2) sin(2 pi x3) at the physical point;
+ *   - Dirichlet (bc = MFQ_BC_DIRICHLET0): y = m*A(m*x) + (1-m)*x with m = 0 on boundary nodes.
+ *
+ * Conventions
+ *   - Every function returns an mfq_status (0 = MFQ_OK, < 0 = error).  On error the
+ *     out-parameters are left untouched and mfq_last_error() returns a message
+ *     (thread-local).  Arguments are validated on the host before any launch.
+ *   - Device memory is owned by the caller.  Objects that need device storage report its size
+ *     (*_device_bytes) and are bound to a caller-provided buffer (*_bind); the library never
+ *     allocates device memory on the hot path.  The buffer must stay alive and unmodified while
+ *     the object is used.  All device pointers are plain device addresses (e.g. torch
+ *     data_ptr()); alignment of 256 bytes is required for bound buffers and 16 bytes for vectors.
+ *   - Streams are hipStream_t passed as void* (NULL = the null stream).  Launch functions are
+ *     asynchronous and do not synchronise the host unless stated.  Kernel faults surface at
+ *     the next synchronising call as MFQ_EHIP.
+ *   - Handles are not thread-safe.  Host handles are owned by the caller and freed with the
+ *     matching *_destroy (NULL is accepted).
+ *   - Vectors have length mfq_space_n_dofs() and hold boundary entries.  Their element type is
+ *     the precision of the object that consumes them: double for MFQ_FP64, float for MFQ_FP32.
+ */
+#ifndef MFQ_H
+#define MFQ_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MFQ_OK = 0,
+  MFQ_EINVAL = -1,      /* invalid argument (sizes, degree, NULL, unbound object, ...) */
+  MFQ_ENOMEM = -2,      /* caller buffer too small / host allocation failed */
+  MFQ_EHIP = -3,        /* HIP runtime error (message in mfq_last_error) */
+  MFQ_ENOCONV = -4,     /* solver did not reach the tolerance within max_iter (info is valid) */
+  MFQ_ENONFINITE = -5,  /* NaN or Inf met in a solver residual */
+  MFQ_EBUSY = -6        /* object in use by an unfinished batched solve */
+} mfq_status;
+
+typedef enum { MFQ_FP64 = 0, MFQ_FP32 = 1 } mfq_precision;
+typedef enum { MFQ_BC_NONE = 0, MFQ_BC_DIRICHLET0 = 1 } mfq_bc;
+
+typedef struct mfq_mesh mfq_mesh;
+typedef struct mfq_space mfq_space;
+typedef struct mfq_op mfq_op;
+typedef struct mfq_transfer mfq_transfer;
+typedef struct mfq_solver mfq_solver;
+
+/* Library version string and the message of the last failed call on this thread. */
+const char* mfq_version(void);
+const char* mfq_last_error(void);
+
+/* Host copies of the 1D reference data of Q_p (Sec. 3.4: reference-cell data computed once and
+ * cached): GLL nodes xi[p+1], Gauss points zeta[p+1] and weights omega[p+1] on [0,1] (weights sum
+ * to 1), S[q*(p+1)+a] = l_a(zeta_q), D[q*(p+1)+a] = l_a'(zeta_q).  Host pointers, caller-owned. */
+int mfq_reference_tables(int degree, double* xi, double* zeta, double* omega, double* S, double* D);
+
+/* ---------------------------------------------------------------- mesh / space (Sec. 3.1, 3.4)
+ * Mesh of n_cells_1d^3 cells on [0,1]^3 (1 <= n_cells_1d <= 1024), deformed with the given
+ * amplitude (0 = affine; |amplitude| < 1/(3 pi) keeps the map invertible). */
+int mfq_mesh_create(int n_cells_1d, double amplitude, mfq_mesh** out);
+void mfq_mesh_destroy(mfq_mesh* mesh);
+
+/* Q_p space on a mesh: degree 1..8, bc one of mfq_bc.  The space keeps a reference to the
+ * mesh, which must outlive it.  Fails with MFQ_EINVAL when (p*n+1)^3 >= 2^31. */
+int mfq_space_create(const mfq_mesh* mesh, int degree, int bc, mfq_space** out);
+void mfq_space_destroy(mfq_space* space);
+int64_t mfq_space_n_dofs(const mfq_space* space);   /* (p*n+1)^3, -1 on NULL */
+int64_t mfq_space_n_cells(const mfq_space* space);  /* n^3, -1 on NULL */
+
+/* b = m*x in place on `n_dofs` entries (zero on Dirichlet nodes): the algebraic right-hand side
+ * of a nodal load vector.  precision selects double/float. */
+int mfq_space_apply_mask(const mfq_space* space, int precision, void* x, void* hip_stream);
+
+/* ---------------------------------------------------------------- operator (Sec. 3.6, 3.7)
+ * The variable-coefficient operator on a space, computed in `precision` (MFQ_FP64 or MFQ_FP32).
+ * Device storage: the cell index maps (int32, (p+1)^3 per cell) and the merged
+ * quadrature-point tensor G_q = w_q a(x_q) det(J_q) J_q^{-1} J_q^{-T} (6 values per quadrature
+ * point, stored in `precision`, always computed in FP64 from the analytic Jacobian). */
+int mfq_op_create(const mfq_space* space, double alpha, int precision, mfq_op** out);
+void mfq_op_destroy(mfq_op* op);
+int mfq_op_device_bytes(const mfq_op* op, size_t* bytes);
+/* Binds `bytes` of device memory at dev_buf (256-byte aligned) and fills the index maps and
+ * G on the stream (asynchronous). */
+int mfq_op_bind(mfq_op* op, void* dev_buf, size_t bytes, void* hip_stream);
+
+/* dst = A src (Dirichlet rows as identity).  src, dst: device vectors of n_dofs elements of
+ * the operator's precision; they must not overlap.  Asynchronous, no host synchronisation. */
+int mfq_vmult(const mfq_op* op, const void* src, void* dst, void* hip_stream);
+
+/* dst += A src (same operator, Dirichlet rows add src): the cell loop alone, without clearing dst.
+ * mfq_vmult is a clear of dst followed by this.  Atomic accumulation: the order of the additions
+ * into a shared node is not fixed, so results may differ from run to run by rounding. */
+int mfq_vmult_add(const mfq_op* op, const void* src, void* dst, void* hip_stream);
+
+/* diag = diagonal of A (1 on Dirichlet rows), computed matrix-free from the same quadrature. */
+int mfq_op_diagonal(const mfq_op* op, void* diag, void* hip_stream);
+
+/* Copies G to out as double [n_cells][(p+1)^3][6] in the order (xx, xy, xz, yy, yz, zz),
+ * quadrature points lexicographic (x fastest).  For tests of the geometry precompute. */
+int mfq_op_geometry(const mfq_op* op, double* out_device, void* hip_stream);
+
+/* b_i = sum_K sum_q f(x_q) phi_i(x_q) JxW_q (Sec. 2.4 right-hand-side term) for the manufactured
+ * solution u* = sin(pi x1) sin(pi x2) sin(pi x3), f = -div(a grad u*); zero on Dirichlet rows.
+ * b is a double device vector; computed in FP64 for either operator precision. */
+int mfq_rhs_manufactured(const mfq_op* op, double* b, void* hip_stream);
+
+/* ---------------------------------------------------------------- transfer (Sec. 3.5, 3.1)
+ * Interpolation between nested spaces on the same domain: either the fine mesh halves the
+ * coarse cells (same degree) or the meshes agree and the fine degree is higher.  Both spaces
+ * must have the same bc and amplitude.  No device storage. */
+int mfq_transfer_create(const mfq_space* coarse, const mfq_space* fine, mfq_transfer** out);
+void mfq_transfer_destroy(mfq_transfer* t);
+/* fine = P coarse (overwrites fine; zero on Dirichlet nodes). */
+int mfq_prolongate(const mfq_transfer* t, int precision, const void* coarse, void* fine, void* hip_stream);
+/* coarse = P^T fine (overwrites coarse; zero on Dirichlet nodes). */
+int mfq_restrict(const mfq_transfer* t, int precision, const void* fine, void* coarse, void* hip_stream);
+
+/* ---------------------------------------------------------------- smoother (Sec. 3.5, 6.1)
+ * `degree` Chebyshev updates of x for A x = b with the Jacobi preconditioner inv_diag on the
+ * interval [lmin, lmax] of D^{-1}A (Chebyshev semi-iteration).  x_is_zero != 0 starts from
+ * x = 0 (x is overwritten).  work must hold 3*n_dofs elements of the operator's precision. */
+int mfq_chebyshev(const mfq_op* op, const void* inv_diag, const void* b, void* x, int x_is_zero,
+                  int degree, double lmin, double lmax, void* work, void* hip_stream);
+
+/* ---------------------------------------------------------------- solvers (Sec. 3.5, 6.1)
+ * Kinds: CG: unpreconditioned FP64 CG.  GMG_FP64: FP64 CG preconditioned by an FP64 V-cycle.
+ * GMG_MIXED: FP64 CG (FP64 operator, vectors and dot products) preconditioned by an FP32
+ * V-cycle.  GMG_MIXED_IR: FP64 iterative refinement (FP64 residual and correction) around an
+ * inner CG on FP32 operators preconditioned by the FP32 V-cycle.
+ * The solver is built on an FP64 operator with MFQ_BC_DIRICHLET0; the hierarchy halves n
+ * while n is even and the level has more than 4096 free DoFs, then lowers p to ceil(p/2)
+ * while more than 4096 free DoFs remain.  The coarsest level is solved in FP64 by a dense
+ * inverse (<= 4096 free DoFs) or by Jacobi-CG to 1e-12. */
+typedef enum { MFQ_SOLVER_CG = 0, MFQ_SOLVER_GMG_FP64 = 1, MFQ_SOLVER_GMG_MIXED = 2,
+               MFQ_SOLVER_GMG_MIXED_IR = 3 } mfq_solver_kind;
+
+typedef struct {
+  int smoother_degree;     /* Chebyshev degree (default 3) */
+  int lanczos_iters;       /* CG-Lanczos steps for the largest eigenvalue (default 12) */
+  double lambda_factor;    /* lmax = factor * estimate (default 1.2) */
+  double lambda_ratio;     /* lmin = lmax / ratio (default 15) */
+  double inner_rtol;       /* inner tolerance of GMG_MIXED_IR (default 1e-4) */
+  int check_every;         /* host convergence poll period in iterations (default 4) */
+  int n_lambda_override;   /* if > 0: lmax of levels 1..n (finest last) taken from lambda_override */
+  const double* lambda_override;
+} mfq_solver_params;
+
+typedef struct {
+  int iterations;          /* CG iterations (summed over inner solves for IR) */
+  int outer_iterations;    /* IR steps (1 for non-IR kinds) */
+  double rel_residual;     /* final true relative residual ||b - A x|| / ||b||, FP64 */
+  double seconds;          /* wall time of mfq_solve */
+  int n_levels;
+} mfq_solve_info;
+
+void mfq_solver_default_params(mfq_solver_params* params);
+int mfq_solver_create(const mfq_op* op_fp64, int kind, const mfq_solver_params* params, mfq_solver** out);
+void mfq_solver_destroy(mfq_solver* s);
+int mfq_solver_device_bytes(const mfq_solver* s, size_t* bytes);
+/* Binds the buffer; builds the level operators, diagonals, eigenvalue bounds and the coarse
+ * inverse.  Synchronises the stream. */
+int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream);
+/* Solves A x = b to ||b - A x||_2 <= rtol ||b||_2 from x = 0 (x overwritten).  b, x: double
+ * device vectors.  Blocks until done.  MFQ_ENOCONV when max_iter is reached (info valid). */
+int mfq_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_iter,
+              void* hip_stream, mfq_solve_info* info);
+/* z = M r: one application of the solver's preconditioner (the V-cycle; identity for CG) to
+ * the double device vector r.  Asynchronous. */
+int mfq_solver_precondition(mfq_solver* s, const double* r, double* z, void* hip_stream);
+/* Largest-eigenvalue estimates of D^{-1}A per level (finest last); n_out >= n_levels - 1. */
+int mfq_solver_lambdas(const mfq_solver* s, double* out, int n_out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* MFQ_H */

@@ -1,0 +1,212 @@
+"""Matrix-free Q_p finite elements on AMD MI355X (gfx950).
+
+The compute path is libmfq.so (hand-written HIP kernels behind a C ABI, see include/mfq.h);
+this package is its Python binding.  ``_lib`` has one function per C entry point with the
+same name; the classes below only add ownership: device memory comes from PyTorch (caching
+allocator, current stream), the library works inside those buffers.
+
+Objects mirror the problem statement of the deal.II paper (arXiv 1910.13247, Fig. 1 and
+Sec. 3.1-3.7): a mesh, a finite element space on it, the operator of the weak form applied
+matrix-free, level transfers, and solvers (CG, geometric multigrid).
+"""
+from . import _lib
+from ._lib import (MfqError, MFQ_FP64, MFQ_FP32, MFQ_BC_NONE, MFQ_BC_DIRICHLET0, MFQ_SOLVER_CG,
+                   MFQ_SOLVER_GMG_FP64, MFQ_SOLVER_GMG_MIXED, MFQ_SOLVER_GMG_MIXED_IR)
+
+__all__ = ["Mesh", "Space", "Operator", "Transfer", "Solver", "MfqError", "MFQ_FP64", "MFQ_FP32",
+           "MFQ_BC_NONE", "MFQ_BC_DIRICHLET0", "MFQ_SOLVER_CG", "MFQ_SOLVER_GMG_FP64",
+           "MFQ_SOLVER_GMG_MIXED", "MFQ_SOLVER_GMG_MIXED_IR"]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _stream(stream):
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return s.cuda_stream
+
+
+def _dtype(precision):
+    torch = _torch()
+    return torch.float64 if precision == MFQ_FP64 else torch.float32
+
+
+def _check_vec(t, n, precision, name):
+    torch = _torch()
+    if not t.is_cuda or t.dtype != _dtype(precision) or not t.is_contiguous() or t.numel() != n:
+        raise ValueError(f"{name}: need a contiguous CUDA tensor of {n} {_dtype(precision)} values")
+    return t.data_ptr()
+
+
+class Mesh:
+    """n^3 cells on the unit cube, deformed by x + A*sin(pi x)sin(pi y)sin(pi z)*(1,1,1)."""
+
+    def __init__(self, n_cells_1d, amplitude=0.0):
+        self.n = int(n_cells_1d)
+        self.amplitude = float(amplitude)
+        self.handle = _lib.mfq_mesh_create(self.n, self.amplitude)
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.mfq_mesh_destroy(self.handle)
+            self.handle = None
+
+
+class Space:
+    """Continuous Q_p space (GLL nodes) on a mesh, optionally with homogeneous Dirichlet rows."""
+
+    def __init__(self, mesh, degree, bc=MFQ_BC_DIRICHLET0):
+        self.mesh = mesh
+        self.degree = int(degree)
+        self.bc = int(bc)
+        self.handle = _lib.mfq_space_create(mesh.handle, self.degree, self.bc)
+        self.n_dofs = _lib.mfq_space_n_dofs(self.handle)
+        self.n_cells = _lib.mfq_space_n_cells(self.handle)
+
+    def apply_mask(self, x, precision=MFQ_FP64, stream=None):
+        _lib.mfq_space_apply_mask(self.handle, precision, _check_vec(x, self.n_dofs, precision, "x"), _stream(stream))
+        return x
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.mfq_space_destroy(self.handle)
+            self.handle = None
+
+
+class Operator:
+    """Matrix-free variable-coefficient Laplacian on a space; device data in a torch buffer."""
+
+    def __init__(self, space, alpha=0.0, precision=MFQ_FP64, device="cuda", stream=None):
+        torch = _torch()
+        self.space = space
+        self.alpha = float(alpha)
+        self.precision = int(precision)
+        self.dtype = _dtype(self.precision)
+        self.handle = _lib.mfq_op_create(space.handle, self.alpha, self.precision)
+        self.device_bytes = _lib.mfq_op_device_bytes(self.handle)
+        self.buffer = torch.empty(self.device_bytes, dtype=torch.uint8, device=device)
+        _lib.mfq_op_bind(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream(stream))
+
+    @property
+    def n_dofs(self):
+        return self.space.n_dofs
+
+    def new_vector(self):
+        torch = _torch()
+        return torch.empty(self.n_dofs, dtype=self.dtype, device=self.buffer.device)
+
+    def vmult(self, src, dst=None, stream=None):
+        if dst is None:
+            dst = self.new_vector()
+        _lib.mfq_vmult(self.handle, _check_vec(src, self.n_dofs, self.precision, "src"),
+                       _check_vec(dst, self.n_dofs, self.precision, "dst"), _stream(stream))
+        return dst
+
+    def vmult_add(self, src, dst, stream=None):
+        _lib.mfq_vmult_add(self.handle, _check_vec(src, self.n_dofs, self.precision, "src"),
+                           _check_vec(dst, self.n_dofs, self.precision, "dst"), _stream(stream))
+        return dst
+
+    def diagonal(self, stream=None):
+        d = self.new_vector()
+        _lib.mfq_op_diagonal(self.handle, d.data_ptr(), _stream(stream))
+        return d
+
+    def geometry(self, stream=None):
+        torch = _torch()
+        out = torch.empty((self.space.n_cells, (self.space.degree + 1) ** 3, 6), dtype=torch.float64,
+                          device=self.buffer.device)
+        _lib.mfq_op_geometry(self.handle, out.data_ptr(), _stream(stream))
+        return out
+
+    def rhs_manufactured(self, stream=None):
+        torch = _torch()
+        b = torch.empty(self.n_dofs, dtype=torch.float64, device=self.buffer.device)
+        _lib.mfq_rhs_manufactured(self.handle, b.data_ptr(), _stream(stream))
+        return b
+
+    def chebyshev(self, inv_diag, b, x, x_is_zero, degree, lmin, lmax, work=None, stream=None):
+        torch = _torch()
+        if work is None:
+            work = torch.empty(3 * self.n_dofs, dtype=self.dtype, device=self.buffer.device)
+        _lib.mfq_chebyshev(self.handle, _check_vec(inv_diag, self.n_dofs, self.precision, "inv_diag"),
+                           _check_vec(b, self.n_dofs, self.precision, "b"),
+                           _check_vec(x, self.n_dofs, self.precision, "x"), x_is_zero, degree, lmin, lmax,
+                           work.data_ptr(), _stream(stream))
+        return x
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.mfq_op_destroy(self.handle)
+            self.handle = None
+
+
+class Transfer:
+    """Interpolation between nested spaces (h: fine mesh halves coarse cells; p: lower degree)."""
+
+    def __init__(self, coarse, fine):
+        self.coarse, self.fine = coarse, fine
+        self.handle = _lib.mfq_transfer_create(coarse.handle, fine.handle)
+
+    def prolongate(self, coarse_vec, fine_vec, precision=MFQ_FP64, stream=None):
+        _lib.mfq_prolongate(self.handle, precision, _check_vec(coarse_vec, self.coarse.n_dofs, precision, "coarse"),
+                            _check_vec(fine_vec, self.fine.n_dofs, precision, "fine"), _stream(stream))
+        return fine_vec
+
+    def restrict(self, fine_vec, coarse_vec, precision=MFQ_FP64, stream=None):
+        _lib.mfq_restrict(self.handle, precision, _check_vec(fine_vec, self.fine.n_dofs, precision, "fine"),
+                          _check_vec(coarse_vec, self.coarse.n_dofs, precision, "coarse"), _stream(stream))
+        return coarse_vec
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.mfq_transfer_destroy(self.handle)
+            self.handle = None
+
+
+class Solver:
+    """CG / GMG-preconditioned CG on an FP64 operator (see mfq_solver_kind)."""
+
+    def __init__(self, op64, kind=MFQ_SOLVER_GMG_MIXED, stream=None, lambda_override=None, **params):
+        torch = _torch()
+        import ctypes
+        self.op = op64
+        self.kind = int(kind)
+        prm = _lib.mfq_solver_default_params()
+        for k, v in params.items():
+            setattr(prm, k, v)
+        if lambda_override is not None:
+            self._lam = (ctypes.c_double * len(lambda_override))(*lambda_override)
+            prm.n_lambda_override = len(lambda_override)
+            prm.lambda_override = ctypes.cast(self._lam, ctypes.POINTER(ctypes.c_double))
+        self.params = prm
+        self.handle = _lib.mfq_solver_create(op64.handle, self.kind, prm)
+        self.device_bytes = _lib.mfq_solver_device_bytes(self.handle)
+        self.buffer = torch.empty(max(self.device_bytes, 256), dtype=torch.uint8, device=op64.buffer.device)
+        _lib.mfq_solver_bind(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream(stream))
+
+    def solve(self, b, x=None, rtol=1e-10, max_iter=10000, stream=None, check=True):
+        if x is None:
+            x = self.op.new_vector()
+        st, info = _lib.mfq_solve(self.handle, _check_vec(b, self.op.n_dofs, MFQ_FP64, "b"),
+                                  _check_vec(x, self.op.n_dofs, MFQ_FP64, "x"), rtol, max_iter, _stream(stream),
+                                  check=check)
+        return x, info, st
+
+    def precondition(self, r, z=None, stream=None):
+        if z is None:
+            z = self.op.new_vector()
+        _lib.mfq_solver_precondition(self.handle, _check_vec(r, self.op.n_dofs, MFQ_FP64, "r"),
+                                     _check_vec(z, self.op.n_dofs, MFQ_FP64, "z"), _stream(stream))
+        return z
+
+    def lambdas(self, n_levels):
+        return _lib.mfq_solver_lambdas(self.handle, max(n_levels - 1, 0))
+
+    def __del__(self):
+        if getattr(self, "handle", None):
+            _lib.mfq_solver_destroy(self.handle)
+            self.handle = None

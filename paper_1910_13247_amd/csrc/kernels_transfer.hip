@@ -1,0 +1,166 @@
+// Level transfer of the geometric multigrid (Sec. 3.5): interpolation between nested Q_p spaces.
+//
+// Isotropic refinement (Sec. 3.1) makes each coarse cell the union of 2^3 fine cells, and the
+// hierarchy may also switch to a lower degree on the same mesh (as the paper's Sec. 6.1
+// hierarchy switches spaces).  Prolongation evaluates the coarse function at the fine nodes
+// inside each coarse cell: a tensor product of one 1D matrix P1 [nf1 x (pc+1)] applied in x, y
+// and z.  Nodes on coarse-cell faces are written by every adjacent coarse cell with bitwise
+// equal values (the 1D matrix is exactly the identity there), so plain stores suffice.
+// Restriction is the transpose: fine values are weighted by 1 / (number of coarse cells
+// containing the node) so the per-cell transposes sum to P^T, then added atomically.
+#include "kernels_common.hpp"
+
+namespace mfq {
+
+namespace {
+
+template <int PC, int NF1>
+struct Transfer1D {
+  double P[NF1 * (PC + 1)];  // P[i*(PC+1)+a]
+};
+
+constexpr int kTBlock = 128;
+
+template <int PC, int NF1, typename Real>
+__global__ __launch_bounds__(kTBlock) void prolongate_kernel(const Real* __restrict__ coarse, Real* __restrict__ fine,
+                                                             int nc, int bc, Transfer1D<PC, NF1> tr) {
+  constexpr int M = PC + 1;
+  __shared__ Real u[M * M * M];
+  __shared__ Real t1[NF1 * M * M];
+  __shared__ Real t2[NF1 * NF1 * M];
+  const int64_t cell = blockIdx.x;
+  const int ic = (int)(cell % nc), jc = (int)((cell / nc) % nc), kc = (int)(cell / ((int64_t)nc * nc));
+  const int64_t N1c = (int64_t)PC * nc + 1;
+  const int stride = NF1 - 1;
+  const int64_t N1f = (int64_t)stride * nc + 1;
+  for (int k = threadIdx.x; k < M * M * M; k += kTBlock) {
+    const int a = k % M, b = (k / M) % M, c = k / (M * M);
+    const int64_t I = (int64_t)PC * ic + a, J = (int64_t)PC * jc + b, K = (int64_t)PC * kc + c;
+    const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1c - 1 || J == N1c - 1 || K == N1c - 1);
+    u[k] = bnd ? (Real)0 : coarse[I + N1c * (J + N1c * K)];
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NF1 * M * M; k += kTBlock) {  // t1[i][b][c]
+    const int i = k % NF1, bc2 = k / NF1;
+    Real s = 0;
+#pragma unroll
+    for (int a = 0; a < M; ++a) s += (Real)tr.P[i * M + a] * u[a + M * bc2];
+    t1[k] = s;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NF1 * NF1 * M; k += kTBlock) {  // t2[i][j][c]
+    const int i = k % NF1, j = (k / NF1) % NF1, c = k / (NF1 * NF1);
+    Real s = 0;
+#pragma unroll
+    for (int b = 0; b < M; ++b) s += (Real)tr.P[j * M + b] * t1[i + NF1 * (b + M * c)];
+    t2[k] = s;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < NF1 * NF1 * NF1; k += kTBlock) {
+    const int i = k % NF1, j = (k / NF1) % NF1, l = k / (NF1 * NF1);
+    Real s = 0;
+#pragma unroll
+    for (int c = 0; c < M; ++c) s += (Real)tr.P[l * M + c] * t2[i + NF1 * (j + NF1 * c)];
+    const int64_t I = (int64_t)stride * ic + i, J = (int64_t)stride * jc + j, K = (int64_t)stride * kc + l;
+    const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1f - 1 || J == N1f - 1 || K == N1f - 1);
+    fine[I + N1f * (J + N1f * K)] = bnd ? (Real)0 : s;
+  }
+}
+
+template <int PC, int NF1, typename Real>
+__global__ __launch_bounds__(kTBlock) void restrict_kernel(const Real* __restrict__ fine, Real* __restrict__ coarse,
+                                                           int nc, int bc, Transfer1D<PC, NF1> tr) {
+  constexpr int M = PC + 1;
+  __shared__ Real t1[M * NF1 * NF1];  // t1[a][j][l]
+  __shared__ Real t2[M * M * NF1];    // t2[a][b][l]
+  const int64_t cell = blockIdx.x;
+  const int ic = (int)(cell % nc), jc = (int)((cell / nc) % nc), kc = (int)(cell / ((int64_t)nc * nc));
+  const int64_t N1c = (int64_t)PC * nc + 1;
+  const int stride = NF1 - 1;
+  const int64_t N1f = (int64_t)stride * nc + 1;
+  auto shared_factor = [&](int i, int icell) -> Real {
+    return ((i == 0 && icell > 0) || (i == NF1 - 1 && icell < nc - 1)) ? (Real)0.5 : (Real)1;
+  };
+  for (int k = threadIdx.x; k < M * NF1 * NF1; k += kTBlock) {
+    const int a = k % M, j = (k / M) % NF1, l = k / (M * NF1);
+    const int64_t J = (int64_t)stride * jc + j, K = (int64_t)stride * kc + l;
+    const Real wjl = shared_factor(j, jc) * shared_factor(l, kc);
+    Real s = 0;
+    for (int i = 0; i < NF1; ++i) {
+      const int64_t I = (int64_t)stride * ic + i;
+      const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1f - 1 || J == N1f - 1 || K == N1f - 1);
+      const Real v = bnd ? (Real)0 : fine[I + N1f * (J + N1f * K)];
+      s += (Real)tr.P[i * M + a] * shared_factor(i, ic) * v;
+    }
+    t1[k] = s * wjl;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < M * M * NF1; k += kTBlock) {
+    const int a = k % M, b = (k / M) % M, l = k / (M * M);
+    Real s = 0;
+    for (int j = 0; j < NF1; ++j) s += (Real)tr.P[j * M + b] * t1[a + M * (j + NF1 * l)];
+    t2[k] = s;
+  }
+  __syncthreads();
+  for (int k = threadIdx.x; k < M * M * M; k += kTBlock) {
+    const int a = k % M, b = (k / M) % M, c = k / (M * M);
+    Real s = 0;
+    for (int l = 0; l < NF1; ++l) s += (Real)tr.P[l * M + c] * t2[a + M * (b + M * l)];
+    const int64_t I = (int64_t)PC * ic + a, J = (int64_t)PC * jc + b, K = (int64_t)PC * kc + c;
+    const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1c - 1 || J == N1c - 1 || K == N1c - 1);
+    if (!bnd) atomic_add(coarse + I + N1c * (J + N1c * K), s);
+  }
+}
+
+template <int PC, int NF1>
+hipError_t transfer_pn(const mfq_transfer* t, int precision, bool prolongate, const void* in, void* out,
+                       hipStream_t st) {
+  Transfer1D<PC, NF1> tr;
+  for (int k = 0; k < NF1 * (PC + 1); ++k) tr.P[k] = t->P1[k];
+  const int nc = t->coarse->mesh->n;
+  const int bc = t->coarse->bc;
+  const unsigned grid = (unsigned)t->coarse->n_cells;
+  if (prolongate) {
+    if (precision == MFQ_FP64)
+      prolongate_kernel<PC, NF1, double><<<grid, kTBlock, 0, st>>>((const double*)in, (double*)out, nc, bc, tr);
+    else
+      prolongate_kernel<PC, NF1, float><<<grid, kTBlock, 0, st>>>((const float*)in, (float*)out, nc, bc, tr);
+  } else {
+    hipError_t e = launch_fill(precision, out, t->coarse->n_dofs, 0.0, st);
+    if (e != hipSuccess) return e;
+    if (precision == MFQ_FP64)
+      restrict_kernel<PC, NF1, double><<<grid, kTBlock, 0, st>>>((const double*)in, (double*)out, nc, bc, tr);
+    else
+      restrict_kernel<PC, NF1, float><<<grid, kTBlock, 0, st>>>((const float*)in, (float*)out, nc, bc, tr);
+  }
+  return hipGetLastError();
+}
+
+}  // namespace
+
+hipError_t launch_transfer(const mfq_transfer* t, int precision, bool prolongate, const void* in, void* out,
+                           hipStream_t st) {
+  const int pc = t->coarse->p;
+  if (t->h_transfer) {
+    switch (pc) {
+      case 1: return transfer_pn<1, 3>(t, precision, prolongate, in, out, st);
+      case 2: return transfer_pn<2, 5>(t, precision, prolongate, in, out, st);
+      case 3: return transfer_pn<3, 7>(t, precision, prolongate, in, out, st);
+      case 4: return transfer_pn<4, 9>(t, precision, prolongate, in, out, st);
+      case 5: return transfer_pn<5, 11>(t, precision, prolongate, in, out, st);
+      case 6: return transfer_pn<6, 13>(t, precision, prolongate, in, out, st);
+      case 7: return transfer_pn<7, 15>(t, precision, prolongate, in, out, st);
+      case 8: return transfer_pn<8, 17>(t, precision, prolongate, in, out, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  const int pf = t->fine->p;
+  // degree switches of the hierarchy rule: p -> ceil(p/2)
+#define MFQ_PT(a, b) \
+  if (pc == a && pf == b) return transfer_pn<a, b + 1>(t, precision, prolongate, in, out, st);
+  MFQ_PT(1, 2) MFQ_PT(2, 3) MFQ_PT(2, 4) MFQ_PT(3, 5) MFQ_PT(3, 6) MFQ_PT(4, 7) MFQ_PT(4, 8)
+#undef MFQ_PT
+  return hipErrorInvalidValue;
+}
+
+}  // namespace mfq

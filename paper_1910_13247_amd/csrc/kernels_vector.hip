@@ -1,0 +1,479 @@
+// Vector kernels of the Krylov solvers and smoothers (CDNA4, wave64).
+//
+// The paper leaves the solvers' vector algebra unspecified beyond running the library's own
+// iterative solvers with all operations on the GPU (Sec. 3.7).  Design here: every CG / PCG
+// step is a handful of fused streaming kernels; the scalars (alpha, beta, residual norms) live
+// in device memory and are produced by the last workgroup of each reduction kernel
+// (deterministic: partial sums per workgroup, then a fixed-order tree over the partials), so the
+// host never waits inside an iteration.  Convergence is decided on the device; the host polls a
+// flag every few iterations.
+#include "kernels_common.hpp"
+#include "solver_state.hpp"
+
+namespace mfq {
+
+namespace {
+
+constexpr int kVBlock = 256;
+constexpr int kMaxRedBlocks = 1024;  // partial-sum slots (fixed grid => deterministic sums)
+
+inline int vgrid(int64_t n) {
+  int64_t g = (n + kVBlock * 4 - 1) / (kVBlock * 4);
+  if (g > kMaxRedBlocks) g = kMaxRedBlocks;
+  if (g < 1) g = 1;
+  return (int)g;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+// Block sum (fixed order); result valid in thread 0.
+__device__ __forceinline__ double block_sum(double v, double* sh) {
+  v = wave_sum(v);
+  const int w = threadIdx.x >> 6, l = threadIdx.x & 63;
+  if (l == 0) sh[w] = v;
+  __syncthreads();
+  double s = 0;
+  if (threadIdx.x == 0)
+    for (int k = 0; k < kVBlock / 64; ++k) s += sh[k];
+  __syncthreads();
+  return s;
+}
+
+// Stores this block's partial; returns true in the (single) last block to finish, where
+// `total` then holds the fixed-order sum of all partials (valid in thread 0).
+__device__ bool grid_reduce(double part, double* partials, unsigned* counter, double& total, double* sh) {
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    partials[blockIdx.x] = part;
+    __threadfence();
+    const unsigned prev = atomicAdd(counter, 1u);
+    last = (prev == gridDim.x - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double v = 0;
+  for (int k = threadIdx.x; k < (int)gridDim.x; k += kVBlock) v += __hip_atomic_load(partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  total = block_sum(v, sh);
+  if (threadIdx.x == 0) *counter = 0u;
+  return true;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void fill_kernel(Real* __restrict__ x, int64_t n, Real v) {
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) x[i] = v;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void mask_kernel(Real* __restrict__ x, int64_t N1) {
+  const int64_t n = N1 * N1 * N1;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
+    const int64_t I = i % N1, J = (i / N1) % N1, K = i / (N1 * N1);
+    if (I == 0 || J == 0 || K == 0 || I == N1 - 1 || J == N1 - 1 || K == N1 - 1) x[i] = (Real)0;
+  }
+}
+
+template <typename In, typename Out>
+__global__ __launch_bounds__(kVBlock) void cast_kernel(const In* __restrict__ in, Out* __restrict__ out, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    out[i] = (Out)in[i];
+}
+
+// ---------------------------------------------------------------- CG / PCG (FP64 vectors)
+// start: r = b, x = 0, p = z = r (unpreconditioned) ; bb = rr = r.r
+__global__ __launch_bounds__(kVBlock) void cg_start_kernel(const double* __restrict__ b, double* __restrict__ x,
+                                                           double* __restrict__ r, double* __restrict__ p, int64_t n,
+                                                           SolverState* st, int copy_p, double tol2) {
+  __shared__ double sh[kVBlock / 64];
+  double part = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
+    const double v = b[i];
+    r[i] = v;
+    x[i] = 0.0;
+    if (copy_p) p[i] = v;
+    part += v * v;
+  }
+  part = block_sum(part, sh);
+  double tot;
+  if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) {
+    st->bb = tot;
+    st->tol2 = tol2;
+    st->rr = tot;
+    st->rz = tot;
+    st->iter = 0;
+    st->done = (tot == 0.0) ? 1 : 0;
+    st->converged_iter = 0;
+    st->nonfinite = (tot == tot && tot < 1e308) ? 0 : 1;
+    if (st->nonfinite) st->done = 1;
+  }
+}
+
+// pAp = p.Ap ; alpha = rz / pAp
+__global__ __launch_bounds__(kVBlock) void cg_alpha_kernel(const double* __restrict__ p, const double* __restrict__ Ap,
+                                                           int64_t n, SolverState* st) {
+  __shared__ double sh[kVBlock / 64];
+  if (st->done) return;
+  double part = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    part += p[i] * Ap[i];
+  part = block_sum(part, sh);
+  double tot;
+  if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) {
+    st->pAp = tot;
+    st->alpha = (tot != 0.0) ? st->rz / tot : 0.0;
+  }
+}
+
+// x += alpha p ; r -= alpha Ap ; rr = r.r ; convergence test rr <= tol2 * bb.
+// Unpreconditioned (z = r): also beta = rr_new / rr_old, rz = rr_new.
+__global__ __launch_bounds__(kVBlock) void cg_update_kernel(double* __restrict__ x, double* __restrict__ r,
+                                                            const double* __restrict__ p, const double* __restrict__ Ap,
+                                                            int64_t n, SolverState* st, int unpreconditioned) {
+  __shared__ double sh[kVBlock / 64];
+  if (st->done) return;
+  const double alpha = st->alpha;
+  double part = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
+    x[i] += alpha * p[i];
+    const double v = r[i] - alpha * Ap[i];
+    r[i] = v;
+    part += v * v;
+  }
+  part = block_sum(part, sh);
+  double tot;
+  if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) {
+    st->rr = tot;
+    st->iter += 1;
+    if (!(tot == tot) || tot > 1e308) {
+      st->nonfinite = 1;
+      st->done = 1;
+    } else if (tot <= st->tol2 * st->bb) {
+      st->done = 1;
+      st->converged_iter = st->iter;
+    }
+    if (unpreconditioned) {
+      st->beta = (st->rz != 0.0) ? tot / st->rz : 0.0;
+      st->rz = tot;
+    }
+  }
+}
+
+// rz_new = r.z ; beta = rz_new / rz
+__global__ __launch_bounds__(kVBlock) void cg_beta_kernel(const double* __restrict__ r, const double* __restrict__ z,
+                                                          int64_t n, SolverState* st) {
+  __shared__ double sh[kVBlock / 64];
+  if (st->done) return;
+  double part = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    part += r[i] * z[i];
+  part = block_sum(part, sh);
+  double tot;
+  if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) {
+    st->beta = (st->rz != 0.0) ? tot / st->rz : 0.0;
+    st->rz = tot;
+  }
+}
+
+// p = z + beta p  (first iteration: beta_first selects p = z)
+__global__ __launch_bounds__(kVBlock) void cg_direction_kernel(const double* __restrict__ z, double* __restrict__ p,
+                                                               int64_t n, SolverState* st, int first) {
+  if (st->done) return;
+  const double beta = first ? 0.0 : st->beta;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    p[i] = z[i] + beta * p[i];
+}
+
+// r = b - t (true residual), rr = r.r ; used by iterative refinement and final certificates.
+__global__ __launch_bounds__(kVBlock) void residual_norm_kernel(const double* __restrict__ b, const double* __restrict__ t,
+                                                                double* __restrict__ r, int64_t n, SolverState* st,
+                                                                double* out) {
+  __shared__ double sh[kVBlock / 64];
+  double part = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
+    const double v = b[i] - t[i];
+    if (r) r[i] = v;
+    part += v * v;
+  }
+  part = block_sum(part, sh);
+  double tot;
+  if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) *out = tot;
+}
+
+// x += c
+template <typename Real, typename Cor>
+__global__ __launch_bounds__(kVBlock) void add_kernel(Real* __restrict__ x, const Cor* __restrict__ c, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    x[i] += (Real)c[i];
+}
+
+// ---------------------------------------------------------------- Chebyshev smoother
+// first step: r = b - t (t = A x, or r = b when x = 0), d = dinv r / theta, x (+)= d
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void cheb_first_kernel(const Real* __restrict__ b, const Real* __restrict__ t,
+                                                             const Real* __restrict__ dinv, Real* __restrict__ x,
+                                                             Real* __restrict__ r, Real* __restrict__ d, int64_t n,
+                                                             Real inv_theta, int x_is_zero) {
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
+    const Real rv = x_is_zero ? b[i] : b[i] - t[i];
+    const Real dv = dinv[i] * rv * inv_theta;
+    r[i] = rv;
+    d[i] = dv;
+    x[i] = x_is_zero ? dv : x[i] + dv;
+  }
+}
+
+// r -= Ad ; d = c1 d + c2 dinv r ; x += d
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void cheb_step_kernel(const Real* __restrict__ Ad, const Real* __restrict__ dinv,
+                                                            Real* __restrict__ x, Real* __restrict__ r,
+                                                            Real* __restrict__ d, int64_t n, Real c1, Real c2) {
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
+    const Real rv = r[i] - Ad[i];
+    const Real dv = c1 * d[i] + c2 * dinv[i] * rv;
+    r[i] = rv;
+    d[i] = dv;
+    x[i] += dv;
+  }
+}
+
+// r = b - t
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void sub_kernel(const Real* __restrict__ b, const Real* __restrict__ t,
+                                                      Real* __restrict__ r, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    r[i] = b[i] - t[i];
+}
+
+// coarse solve on the free (interior) lattice nodes: x_f = Ainv b_f, FP64 accumulation, one wave
+// per row.  Free index f <-> node (I,J,K) = (f%m+1, (f/m)%m+1, f/m^2+1), m = N1-2.
+__device__ __forceinline__ int64_t free_to_global(int64_t f, int64_t N1) {
+  const int64_t m = N1 - 2;
+  return (f % m + 1) + N1 * ((f / m) % m + 1) + N1 * N1 * (f / (m * m) + 1);
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void dense_solve_kernel(const double* __restrict__ Ainv, int nf, int64_t N1,
+                                                              const Real* __restrict__ b, Real* __restrict__ x) {
+  const int wave = (blockIdx.x * kVBlock + threadIdx.x) >> 6;
+  const int l = threadIdx.x & 63;
+  if (wave >= nf) return;
+  const double* row = Ainv + (int64_t)wave * nf;
+  double s = 0;
+  for (int j = l; j < nf; j += 64) s += row[j] * (double)b[free_to_global(j, N1)];
+  s = wave_sum(s);
+  if (l == 0) x[free_to_global(wave, N1)] = (Real)s;
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void dot_kernel(const Real* __restrict__ x, const Real* __restrict__ y, int64_t n,
+                                                      SolverState* st, double* out) {
+  __shared__ double sh[kVBlock / 64];
+  double part = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    part += (double)x[i] * (double)y[i];
+  part = block_sum(part, sh);
+  double tot;
+  if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) *out = tot;
+}
+
+// y = a x + b y
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void axpby_kernel(Real a, const Real* __restrict__ x, Real b, Real* __restrict__ y,
+                                                        int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    y[i] = a * x[i] + b * y[i];
+}
+
+// z = d * r
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void mul_kernel(const Real* __restrict__ d, const Real* __restrict__ r,
+                                                      Real* __restrict__ z, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    z[i] = d[i] * r[i];
+}
+
+// x = 1 / x
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void reciprocal_kernel(Real* __restrict__ x, int64_t n) {
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    x[i] = (Real)1 / x[i];
+}
+
+// Counter-based start vector: SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) of counter i,
+// z = seed + (i+1)*0x9E3779B97F4A7C15, two xor-shift-multiply rounds, final xor-shift; the top
+// 53 bits give u in [0,1), v = 2u - 1; zero on boundary nodes of the (N1)^3 lattice when masked.
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void splitmix_kernel(Real* __restrict__ x, int64_t N1, uint64_t seed, int masked) {
+  const int64_t n = N1 * N1 * N1;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
+    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+    z = z ^ (z >> 31);
+    const double u = (double)(z >> 11) * 0x1.0p-53;
+    double v = 2.0 * u - 1.0;
+    if (masked) {
+      const int64_t I = i % N1, J = (i / N1) % N1, K = i / (N1 * N1);
+      if (I == 0 || J == 0 || K == 0 || I == N1 - 1 || J == N1 - 1 || K == N1 - 1) v = 0.0;
+    }
+    x[i] = (Real)v;
+  }
+}
+
+}  // namespace
+
+hipError_t launch_fill(int precision, void* x, int64_t n, double value, hipStream_t st) {
+  if (n <= 0) return hipSuccess;
+  const int g = vgrid(n) * 4;
+  if (precision == MFQ_FP64)
+    fill_kernel<double><<<g, kVBlock, 0, st>>>((double*)x, n, value);
+  else
+    fill_kernel<float><<<g, kVBlock, 0, st>>>((float*)x, n, (float)value);
+  return hipGetLastError();
+}
+
+hipError_t launch_mask(int precision, int p, int n, void* x, hipStream_t st) {
+  const int64_t N1 = (int64_t)p * n + 1;
+  const int g = vgrid(N1 * N1 * N1) * 4;
+  if (precision == MFQ_FP64)
+    mask_kernel<double><<<g, kVBlock, 0, st>>>((double*)x, N1);
+  else
+    mask_kernel<float><<<g, kVBlock, 0, st>>>((float*)x, N1);
+  return hipGetLastError();
+}
+
+hipError_t launch_cast(int from, const void* in, int to, void* out, int64_t n, hipStream_t st) {
+  const int g = vgrid(n) * 4;
+  if (from == MFQ_FP64 && to == MFQ_FP32)
+    cast_kernel<double, float><<<g, kVBlock, 0, st>>>((const double*)in, (float*)out, n);
+  else if (from == MFQ_FP32 && to == MFQ_FP64)
+    cast_kernel<float, double><<<g, kVBlock, 0, st>>>((const float*)in, (double*)out, n);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+
+hipError_t launch_cg_start(const double* b, double* x, double* r, double* p, int64_t n, SolverState* s, bool copy_p,
+                           double tol2, hipStream_t st) {
+  cg_start_kernel<<<vgrid(n), kVBlock, 0, st>>>(b, x, r, p, n, s, copy_p ? 1 : 0, tol2);
+  return hipGetLastError();
+}
+hipError_t launch_cg_alpha(const double* p, const double* Ap, int64_t n, SolverState* s, hipStream_t st) {
+  cg_alpha_kernel<<<vgrid(n), kVBlock, 0, st>>>(p, Ap, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* Ap, int64_t n, SolverState* s,
+                            bool unprec, hipStream_t st) {
+  cg_update_kernel<<<vgrid(n), kVBlock, 0, st>>>(x, r, p, Ap, n, s, unprec ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_cg_beta(const double* r, const double* z, int64_t n, SolverState* s, hipStream_t st) {
+  cg_beta_kernel<<<vgrid(n), kVBlock, 0, st>>>(r, z, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_cg_direction(const double* z, double* p, int64_t n, SolverState* s, bool first, hipStream_t st) {
+  cg_direction_kernel<<<vgrid(n) * 4, kVBlock, 0, st>>>(z, p, n, s, first ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_residual_norm(const double* b, const double* t, double* r, int64_t n, SolverState* s, double* out,
+                                hipStream_t st) {
+  residual_norm_kernel<<<vgrid(n), kVBlock, 0, st>>>(b, t, r, n, s, out);
+  return hipGetLastError();
+}
+hipError_t launch_add(int precision, void* x, int cor_precision, const void* c, int64_t n, hipStream_t st) {
+  const int g = vgrid(n) * 4;
+  if (precision == MFQ_FP64 && cor_precision == MFQ_FP64)
+    add_kernel<double, double><<<g, kVBlock, 0, st>>>((double*)x, (const double*)c, n);
+  else if (precision == MFQ_FP64 && cor_precision == MFQ_FP32)
+    add_kernel<double, float><<<g, kVBlock, 0, st>>>((double*)x, (const float*)c, n);
+  else if (precision == MFQ_FP32 && cor_precision == MFQ_FP32)
+    add_kernel<float, float><<<g, kVBlock, 0, st>>>((float*)x, (const float*)c, n);
+  else
+    return hipErrorInvalidValue;
+  return hipGetLastError();
+}
+hipError_t launch_cheb_first(int precision, const void* b, const void* t, const void* dinv, void* x, void* r, void* d,
+                             int64_t n, double inv_theta, bool x_is_zero, hipStream_t st) {
+  const int g = vgrid(n) * 4;
+  if (precision == MFQ_FP64)
+    cheb_first_kernel<double><<<g, kVBlock, 0, st>>>((const double*)b, (const double*)t, (const double*)dinv, (double*)x,
+                                                     (double*)r, (double*)d, n, inv_theta, x_is_zero ? 1 : 0);
+  else
+    cheb_first_kernel<float><<<g, kVBlock, 0, st>>>((const float*)b, (const float*)t, (const float*)dinv, (float*)x,
+                                                    (float*)r, (float*)d, n, (float)inv_theta, x_is_zero ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_cheb_step(int precision, const void* Ad, const void* dinv, void* x, void* r, void* d, int64_t n,
+                            double c1, double c2, hipStream_t st) {
+  const int g = vgrid(n) * 4;
+  if (precision == MFQ_FP64)
+    cheb_step_kernel<double><<<g, kVBlock, 0, st>>>((const double*)Ad, (const double*)dinv, (double*)x, (double*)r,
+                                                    (double*)d, n, c1, c2);
+  else
+    cheb_step_kernel<float><<<g, kVBlock, 0, st>>>((const float*)Ad, (const float*)dinv, (float*)x, (float*)r,
+                                                   (float*)d, n, (float)c1, (float)c2);
+  return hipGetLastError();
+}
+hipError_t launch_sub(int precision, const void* b, const void* t, void* r, int64_t n, hipStream_t st) {
+  const int g = vgrid(n) * 4;
+  if (precision == MFQ_FP64)
+    sub_kernel<double><<<g, kVBlock, 0, st>>>((const double*)b, (const double*)t, (double*)r, n);
+  else
+    sub_kernel<float><<<g, kVBlock, 0, st>>>((const float*)b, (const float*)t, (float*)r, n);
+  return hipGetLastError();
+}
+hipError_t launch_dense_solve(int precision, const double* Ainv, int nf, int64_t N1, const void* b, void* x,
+                              hipStream_t st) {
+  const int g = (int)(((int64_t)nf * 64 + kVBlock - 1) / kVBlock);
+  if (precision == MFQ_FP64)
+    dense_solve_kernel<double><<<g, kVBlock, 0, st>>>(Ainv, nf, N1, (const double*)b, (double*)x);
+  else
+    dense_solve_kernel<float><<<g, kVBlock, 0, st>>>(Ainv, nf, N1, (const float*)b, (float*)x);
+  return hipGetLastError();
+}
+hipError_t launch_dot(int precision, const void* x, const void* y, int64_t n, SolverState* s, double* out,
+                      hipStream_t st) {
+  if (precision == MFQ_FP64)
+    dot_kernel<double><<<vgrid(n), kVBlock, 0, st>>>((const double*)x, (const double*)y, n, s, out);
+  else
+    dot_kernel<float><<<vgrid(n), kVBlock, 0, st>>>((const float*)x, (const float*)y, n, s, out);
+  return hipGetLastError();
+}
+hipError_t launch_axpby(int precision, double a, const void* x, double b, void* y, int64_t n, hipStream_t st) {
+  const int g = vgrid(n) * 4;
+  if (precision == MFQ_FP64)
+    axpby_kernel<double><<<g, kVBlock, 0, st>>>(a, (const double*)x, b, (double*)y, n);
+  else
+    axpby_kernel<float><<<g, kVBlock, 0, st>>>((float)a, (const float*)x, (float)b, (float*)y, n);
+  return hipGetLastError();
+}
+hipError_t launch_mul(int precision, const void* d, const void* r, void* z, int64_t n, hipStream_t st) {
+  const int g = vgrid(n) * 4;
+  if (precision == MFQ_FP64)
+    mul_kernel<double><<<g, kVBlock, 0, st>>>((const double*)d, (const double*)r, (double*)z, n);
+  else
+    mul_kernel<float><<<g, kVBlock, 0, st>>>((const float*)d, (const float*)r, (float*)z, n);
+  return hipGetLastError();
+}
+hipError_t launch_reciprocal(int precision, void* x, int64_t n, hipStream_t st) {
+  const int g = vgrid(n) * 4;
+  if (precision == MFQ_FP64)
+    reciprocal_kernel<double><<<g, kVBlock, 0, st>>>((double*)x, n);
+  else
+    reciprocal_kernel<float><<<g, kVBlock, 0, st>>>((float*)x, n);
+  return hipGetLastError();
+}
+hipError_t launch_splitmix(int precision, void* x, int64_t N1, uint64_t seed, bool masked, hipStream_t st) {
+  const int g = vgrid(N1 * N1 * N1) * 4;
+  if (precision == MFQ_FP64)
+    splitmix_kernel<double><<<g, kVBlock, 0, st>>>((double*)x, N1, seed, masked ? 1 : 0);
+  else
+    splitmix_kernel<float><<<g, kVBlock, 0, st>>>((float*)x, N1, seed, masked ? 1 : 0);
+  return hipGetLastError();
+}
+
+}  // namespace mfq

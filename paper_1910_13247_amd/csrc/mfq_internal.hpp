@@ -1,0 +1,151 @@
+// Internal declarations of the matrix-free Q_p library (host side + kernel launchers).
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "../../include/mfq.h"
+
+namespace mfq {
+
+constexpr int kMaxDegree = 8;
+constexpr int kBlock = 256;  // threads per workgroup of the cell kernels
+
+// ---------------------------------------------------------------- errors
+void set_error(const char* fmt, ...);
+int fail(int code, const char* fmt, ...);
+#define MFQ_HIP(call)                                                                       \
+  do {                                                                                      \
+    hipError_t e_ = (call);                                                                 \
+    if (e_ != hipSuccess)                                                                   \
+      return ::mfq::fail(MFQ_EHIP, "%s failed: %s (%s:%d)", #call, hipGetErrorString(e_), \
+                         __FILE__, __LINE__);                                               \
+  } while (0)
+
+// ---------------------------------------------------------------- 1D tables (host, FP64)
+// Nodes of Q_p: Gauss-Lobatto-Legendre points on [0,1]; quadrature: (p+1)-point Gauss on [0,1].
+struct Tables1D {
+  int p = 0;
+  std::vector<double> xi;     // p+1 nodes
+  std::vector<double> zeta;   // p+1 Gauss points
+  std::vector<double> omega;  // p+1 Gauss weights (sum 1)
+  std::vector<double> S;      // S[q*(p+1)+a] = l_a(zeta_q)
+  std::vector<double> D;      // D[q*(p+1)+a] = l_a'(zeta_q)
+};
+const Tables1D& tables(int p);
+std::vector<double> gll_points(int p);
+void gauss_points(int nq, std::vector<double>& x, std::vector<double>& w);
+double lagrange_value(const std::vector<double>& nodes, int a, double t);
+double lagrange_derivative(const std::vector<double>& nodes, int a, double t);
+// 1D transfer matrix [nf1][pc+1]: coarse basis (degree pc) at the fine nodes lying in one coarse
+// cell: h-transfer (fine degree pc, two fine cells) when h_transfer, else the GLL nodes of pf.
+std::vector<double> transfer_matrix_1d(int pc, int pf, bool h_transfer, int* nf1);
+
+// Kernel geometry of the cell kernels: (p+1)^2 threads per cell, cells packed into 256 lanes.
+inline int threads_per_cell(int p) { return (p + 1) * (p + 1); }
+inline int cells_per_block(int p) { return kBlock / threads_per_cell(p); }
+inline int lanes_per_block(int p) { return cells_per_block(p) * threads_per_cell(p); }
+
+}  // namespace mfq
+
+// ---------------------------------------------------------------- opaque handles
+struct mfq_mesh {
+  int n;
+  double amplitude;
+};
+
+struct mfq_space {
+  const mfq_mesh* mesh;
+  int p;
+  int bc;
+  int64_t n_dofs;
+  int64_t n_cells;
+};
+
+struct mfq_op {
+  const mfq_space* space;
+  double alpha;
+  int precision;
+  int64_t n_blocks;
+  size_t idx_bytes, geo_bytes;
+  void* buf = nullptr;        // caller-owned device memory
+  int* idx = nullptr;         // [n_blocks][p+1][lanes] global DoF, ~g on Dirichlet nodes
+  void* geo = nullptr;        // [n_blocks][p+1][3][lanes][2] of the precision's type
+};
+
+struct mfq_transfer {
+  const mfq_space* coarse;
+  const mfq_space* fine;
+  bool h_transfer;
+  int nf1;
+  std::vector<double> P1;     // [nf1][pc+1]
+};
+
+namespace mfq {
+
+// Plain-struct view of an operator handed to launchers.
+struct OpView {
+  int p, n, bc;
+  int64_t n_cells, n_blocks, n_dofs;
+  double amplitude, alpha;
+  const int* idx;
+  const void* geo;
+};
+inline OpView view(const mfq_op* op) {
+  const mfq_space* s = op->space;
+  return OpView{s->p, s->mesh->n, s->bc, s->n_cells, op->n_blocks, s->n_dofs,
+                s->mesh->amplitude, op->alpha, op->idx, op->geo};
+}
+
+// ---------------------------------------------------------------- launchers (kernels_*.hip)
+hipError_t launch_fill_index(const OpView& v, int* idx, hipStream_t st);
+hipError_t launch_geometry(const OpView& v, int precision, void* geo, hipStream_t st);
+hipError_t launch_geometry_export(const OpView& v, int precision, double* out, hipStream_t st);
+// Cell-loop parts (they add into dst/diag/b, which the callers zero first).
+hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, void* dst, hipStream_t st);
+hipError_t launch_diagonal_cells(const OpView& v, int precision, void* diag, hipStream_t st);
+hipError_t launch_rhs_cells(const OpView& v, double* b, hipStream_t st);
+hipError_t launch_assemble_dense(const OpView& v, double* mat, int64_t ld, hipStream_t st);
+hipError_t launch_transfer(const mfq_transfer* t, int precision, bool prolongate, const void* in,
+                           void* out, hipStream_t st);
+
+// vector kernels (kernels_vector.hip)
+hipError_t launch_fill(int precision, void* x, int64_t n, double value, hipStream_t st);
+hipError_t launch_mask(int precision, int p, int n, void* x, hipStream_t st);
+hipError_t launch_cast(int from_precision, const void* in, int to_precision, void* out, int64_t n,
+                       hipStream_t st);
+
+struct SolverState;
+hipError_t launch_cg_start(const double* b, double* x, double* r, double* p, int64_t n, SolverState* s, bool copy_p,
+                           double tol2, hipStream_t st);
+hipError_t launch_cg_alpha(const double* p, const double* Ap, int64_t n, SolverState* s, hipStream_t st);
+hipError_t launch_cg_update(double* x, double* r, const double* p, const double* Ap, int64_t n, SolverState* s,
+                            bool unprec, hipStream_t st);
+hipError_t launch_cg_beta(const double* r, const double* z, int64_t n, SolverState* s, hipStream_t st);
+hipError_t launch_cg_direction(const double* z, double* p, int64_t n, SolverState* s, bool first, hipStream_t st);
+hipError_t launch_residual_norm(const double* b, const double* t, double* r, int64_t n, SolverState* s, double* out,
+                                hipStream_t st);
+hipError_t launch_add(int precision, void* x, int cor_precision, const void* c, int64_t n, hipStream_t st);
+hipError_t launch_cheb_first(int precision, const void* b, const void* t, const void* dinv, void* x, void* r, void* d,
+                             int64_t n, double inv_theta, bool x_is_zero, hipStream_t st);
+hipError_t launch_cheb_step(int precision, const void* Ad, const void* dinv, void* x, void* r, void* d, int64_t n,
+                            double c1, double c2, hipStream_t st);
+hipError_t launch_sub(int precision, const void* b, const void* t, void* r, int64_t n, hipStream_t st);
+hipError_t launch_dense_solve(int precision, const double* Ainv, int nf, int64_t N1, const void* b, void* x,
+                              hipStream_t st);
+hipError_t launch_dot(int precision, const void* x, const void* y, int64_t n, SolverState* s, double* out,
+                      hipStream_t st);
+hipError_t launch_axpby(int precision, double a, const void* x, double b, void* y, int64_t n, hipStream_t st);
+hipError_t launch_mul(int precision, const void* d, const void* r, void* z, int64_t n, hipStream_t st);
+hipError_t launch_reciprocal(int precision, void* x, int64_t n, hipStream_t st);
+hipError_t launch_splitmix(int precision, void* x, int64_t N1, uint64_t seed, bool masked, hipStream_t st);
+
+// ---------------------------------------------------------------- host-side operator helpers (api.cpp)
+int op_vmult(const mfq_op* op, const void* src, void* dst, hipStream_t st);      // zero dst + cell loop
+int op_diagonal(const mfq_op* op, void* diag, hipStream_t st);
+const char* last_error_cstr();
+
+}  // namespace mfq

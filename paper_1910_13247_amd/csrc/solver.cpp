@@ -1,0 +1,671 @@
+// Solvers: CG, and CG preconditioned by a geometric-multigrid V-cycle (Sec. 3.5) with Chebyshev
+// smoothing, matrix-free level operators and transfers, in FP64 or in FP32 under an FP64
+// outer iteration (Sec. 6.1: single-precision V-cycle combined with a double-precision
+// correction).  Host code only orchestrates launches; every vector operation runs on the device.
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <functional>
+#include <new>
+#include <thread>
+#include <vector>
+
+#include "mfq_internal.hpp"
+#include "solver_state.hpp"
+
+using namespace mfq;
+
+namespace {
+
+constexpr int64_t kDenseCoarseLimit = 4096;
+
+size_t round_up(size_t x, size_t a) { return (x + a - 1) / a * a; }
+size_t rsize(int prec) { return prec == MFQ_FP64 ? 8 : 4; }
+int64_t n_free(int p, int n) {
+  const int64_t m = (int64_t)p * n - 1;
+  return m > 0 ? m * m * m : 0;
+}
+
+struct Level {
+  mfq_mesh* mesh = nullptr;      // owned (nullptr for the finest level: the user's)
+  mfq_space* space = nullptr;    // owned (nullptr for the finest level)
+  const mfq_space* sp = nullptr; // the level's space
+  mfq_op* op = nullptr;          // owned V-cycle operator (precision prec_v); finest FP64 kind: user op
+  bool owns_op = true;
+  mfq_transfer* to_fine = nullptr;  // owned, coarse->next finer (nullptr on finest)
+  int64_t n = 0;
+  // offsets / pointers of level vectors (precision prec_v)
+  size_t off_op = 0, off_b = 0, off_x = 0, off_r = 0, off_d = 0, off_t = 0, off_dinv = 0;
+  void *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *dinv = nullptr;
+  double lhat = 0, lmin = 0, lmax = 0;
+};
+
+}  // namespace
+
+struct mfq_solver {
+  const mfq_op* op64 = nullptr;
+  int kind = 0;
+  mfq_solver_params prm{};
+  int prec_v = MFQ_FP64;
+  std::vector<Level> lv;  // coarsest first; empty for plain CG
+  // coarse level solver (FP64)
+  bool dense = false;
+  int64_t nf = 0;
+  mfq_op* coarse64 = nullptr;  // FP64 operator of the coarsest level (dense assembly or coarse CG)
+  size_t off_coarse64 = 0, off_ainv = 0, off_cvec = 0, off_cstate = 0;
+  double* ainv = nullptr;
+  double *cb = nullptr, *cx = nullptr, *cr = nullptr, *cp = nullptr, *cAp = nullptr, *cz = nullptr, *cdinv = nullptr;
+  SolverState* cstate = nullptr;
+  // Krylov vectors (FP64, finest)
+  size_t off_kry = 0, off_state = 0, off_aux = 0;
+  double *r = nullptr, *p = nullptr, *Ap = nullptr, *z = nullptr, *rout = nullptr, *c = nullptr;
+  SolverState* state = nullptr;
+  SolverState* aux = nullptr;  // reductions of the setup phase
+  double* scal = nullptr;      // device scalars for setup dots
+  size_t bytes = 0;
+  void* buf = nullptr;
+  ~mfq_solver() {
+    for (Level& l : lv) {
+      if (l.owns_op) mfq_op_destroy(l.op);
+      mfq_transfer_destroy(l.to_fine);
+      mfq_space_destroy(l.space);
+      mfq_mesh_destroy(l.mesh);
+    }
+    mfq_op_destroy(coarse64);
+  }
+};
+
+namespace {
+
+// Dense SPD inverse on the host: Cholesky A = L L^T, then A^{-1} = L^{-T} L^{-1}.
+// Rows of the triangular inverse are independent, so that step runs on several threads.
+bool spd_inverse(std::vector<double>& A, int64_t n) {
+  for (int64_t j = 0; j < n; ++j) {
+    double d = A[j * n + j];
+    for (int64_t k = 0; k < j; ++k) d -= A[j * n + k] * A[j * n + k];
+    if (!(d > 0)) return false;
+    const double ljj = std::sqrt(d);
+    A[j * n + j] = ljj;
+    const double inv = 1.0 / ljj;
+    auto work = [&](int64_t i0, int64_t i1) {
+      for (int64_t i = i0; i < i1; ++i) {
+        double s = A[i * n + j];
+        const double* ai = &A[i * n];
+        const double* aj = &A[j * n];
+        for (int64_t k = 0; k < j; ++k) s -= ai[k] * aj[k];
+        A[i * n + j] = s * inv;
+      }
+    };
+    const int64_t rows = n - j - 1;
+    const int nt = rows > 256 ? (int)std::min<unsigned>(8u, std::max(1u, std::thread::hardware_concurrency())) : 1;
+    if (nt == 1) {
+      work(j + 1, n);
+    } else {
+      std::vector<std::thread> th;
+      const int64_t chunk = (rows + nt - 1) / nt;
+      for (int t = 0; t < nt; ++t) {
+        const int64_t a = j + 1 + t * chunk, b = std::min(n, a + chunk);
+        if (a < b) th.emplace_back(work, a, b);
+      }
+      for (auto& x : th) x.join();
+    }
+  }
+  // W = L^{-1} (lower triangular), by forward substitution per column
+  std::vector<double> W((size_t)n * n, 0.0);
+  auto inv_cols = [&](int64_t c0, int64_t c1) {
+    for (int64_t c = c0; c < c1; ++c) {
+      W[c * n + c] = 1.0 / A[c * n + c];
+      for (int64_t i = c + 1; i < n; ++i) {
+        double s = 0;
+        for (int64_t k = c; k < i; ++k) s -= A[i * n + k] * W[k * n + c];
+        W[i * n + c] = s / A[i * n + i];
+      }
+    }
+  };
+  auto inv_full = [&](int64_t r0, int64_t r1) {
+    // A^{-1}[i][j] = sum_{k >= max(i,j)} W[k][i] W[k][j]
+    for (int64_t i = r0; i < r1; ++i)
+      for (int64_t j = 0; j < n; ++j) {
+        double s = 0;
+        for (int64_t k = std::max(i, j); k < n; ++k) s += W[k * n + i] * W[k * n + j];
+        A[i * n + j] = s;
+      }
+  };
+  const int nt = (int)std::min<unsigned>(8u, std::max(1u, std::thread::hardware_concurrency()));
+  for (int pass = 0; pass < 2; ++pass) {
+    std::vector<std::thread> th;
+    const int64_t chunk = (n + nt - 1) / nt;
+    for (int t = 0; t < nt; ++t) {
+      const int64_t a = t * chunk, b = std::min(n, a + chunk);
+      if (a >= b) continue;
+      if (pass == 0)
+        th.emplace_back(inv_cols, a, b);
+      else
+        th.emplace_back(inv_full, a, b);
+    }
+    for (auto& x : th) x.join();
+  }
+  return true;
+}
+
+// Largest eigenvalue of a small symmetric matrix (cyclic Jacobi rotations).
+double sym_max_eig(std::vector<double> T, int k) {
+  for (int sweep = 0; sweep < 100; ++sweep) {
+    double off = 0;
+    for (int i = 0; i < k; ++i)
+      for (int j = i + 1; j < k; ++j) off += T[i * k + j] * T[i * k + j];
+    if (off < 1e-30) break;
+    for (int pI = 0; pI < k; ++pI)
+      for (int q = pI + 1; q < k; ++q) {
+        const double apq = T[pI * k + q];
+        if (std::fabs(apq) < 1e-300) continue;
+        const double theta = (T[q * k + q] - T[pI * k + pI]) / (2 * apq);
+        const double t = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1));
+        const double c = 1 / std::sqrt(t * t + 1), s = t * c;
+        for (int r = 0; r < k; ++r) {
+          const double arp = T[r * k + pI], arq = T[r * k + q];
+          T[r * k + pI] = c * arp - s * arq;
+          T[r * k + q] = s * arp + c * arq;
+        }
+        for (int r = 0; r < k; ++r) {
+          const double apr = T[pI * k + r], aqr = T[q * k + r];
+          T[pI * k + r] = c * apr - s * aqr;
+          T[q * k + r] = s * apr + c * aqr;
+        }
+      }
+  }
+  double m = -1e300;
+  for (int i = 0; i < k; ++i) m = std::max(m, T[i * k + i]);
+  return m;
+}
+
+int poll(SolverState* dev, SolverState& host, hipStream_t st) {
+  MFQ_HIP(hipMemcpyAsync(&host, dev, offsetof(SolverState, partials), hipMemcpyDeviceToHost, st));
+  MFQ_HIP(hipStreamSynchronize(st));
+  return MFQ_OK;
+}
+
+using Apply = std::function<int(const double* in, double* out)>;
+
+struct PcgResult {
+  int iters = 0;
+  bool converged = false, nonfinite = false;
+  double rr = 0, bb = 0;
+};
+
+// CG / PCG on FP64 vectors from x = 0.  All scalars stay on the device.
+int pcg(const Apply& apply, const Apply* prec, const double* b, double* x, double* r, double* p, double* Ap, double* z,
+        int64_t n, SolverState* st, double rtol, int maxit, int check_every, hipStream_t stream, PcgResult& res) {
+  MFQ_HIP(launch_cg_start(b, x, r, p, n, st, prec == nullptr, rtol * rtol, stream));
+  if (prec) {
+    if (int rc = (*prec)(r, z)) return rc;
+    MFQ_HIP(launch_cg_beta(r, z, n, st, stream));
+    MFQ_HIP(launch_cg_direction(z, p, n, st, true, stream));
+  }
+  SolverState h{};
+  if (int rc = poll(st, h, stream)) return rc;
+  if (!h.done) {
+    for (int it = 0; it < maxit; ++it) {
+      if (int rc = apply(p, Ap)) return rc;
+      MFQ_HIP(launch_cg_alpha(p, Ap, n, st, stream));
+      MFQ_HIP(launch_cg_update(x, r, p, Ap, n, st, prec == nullptr, stream));
+      if (prec) {
+        if (int rc = (*prec)(r, z)) return rc;
+        MFQ_HIP(launch_cg_beta(r, z, n, st, stream));
+        MFQ_HIP(launch_cg_direction(z, p, n, st, false, stream));
+      } else {
+        MFQ_HIP(launch_cg_direction(r, p, n, st, false, stream));
+      }
+      if ((it + 1) % check_every == 0 || it + 1 == maxit) {
+        if (int rc = poll(st, h, stream)) return rc;
+        if (h.done) break;
+      }
+    }
+  }
+  res.iters = h.done ? h.converged_iter : h.iter;
+  res.converged = h.done && !h.nonfinite;
+  res.nonfinite = h.nonfinite != 0;
+  res.rr = h.rr;
+  res.bb = h.bb;
+  if (h.bb == 0.0) res.converged = true;
+  return MFQ_OK;
+}
+
+// ---------------------------------------------------------------- V-cycle
+int coarse_solve(mfq_solver* s, const void* b, void* x, hipStream_t st) {
+  Level& L = s->lv[0];
+  const int prec = s->prec_v;
+  if (s->dense) {
+    MFQ_HIP(launch_fill(prec, x, L.n, 0.0, st));
+    MFQ_HIP(launch_dense_solve(prec, s->ainv, (int)s->nf, (int64_t)L.sp->p * L.sp->mesh->n + 1, b, x, st));
+    return MFQ_OK;
+  }
+  // Jacobi-CG on the FP64 coarse operator to 1e-12
+  const double* b64 = (const double*)b;
+  double* x64 = (double*)x;
+  if (prec != MFQ_FP64) {
+    MFQ_HIP(launch_cast(prec, b, MFQ_FP64, s->cb, L.n, st));
+    b64 = s->cb;
+    x64 = s->cx;
+  }
+  Apply A = [s, st](const double* in, double* out) { return op_vmult(s->coarse64, in, out, st); };
+  Apply M = [s, st, &L](const double* in, double* out) -> int {
+    MFQ_HIP(launch_mul(MFQ_FP64, s->cdinv, in, out, L.n, st));
+    return MFQ_OK;
+  };
+  PcgResult res;
+  if (int rc = pcg(A, &M, b64, x64, s->cr, s->cp, s->cAp, s->cz, L.n, s->cstate, 1e-12, 10000, 8, st, res)) return rc;
+  if (prec != MFQ_FP64) MFQ_HIP(launch_cast(MFQ_FP64, x64, prec, x, L.n, st));
+  return MFQ_OK;
+}
+
+int vcycle(mfq_solver* s, int l, hipStream_t st) {
+  Level& L = s->lv[l];
+  if (l == 0) return coarse_solve(s, L.b, L.x, st);
+  const int prec = s->prec_v;
+  const int deg = s->prm.smoother_degree;
+  char* work = (char*)L.r;  // r, d, t are contiguous
+  if (int rc = mfq_chebyshev(L.op, L.dinv, L.b, L.x, 1, deg, L.lmin, L.lmax, work, st)) return rc;
+  if (int rc = op_vmult(L.op, L.x, L.t, st)) return rc;
+  MFQ_HIP(launch_sub(prec, L.b, L.t, L.r, L.n, st));
+  Level& C = s->lv[l - 1];
+  MFQ_HIP(launch_transfer(C.to_fine, prec, false, L.r, C.b, st));
+  if (int rc = vcycle(s, l - 1, st)) return rc;
+  MFQ_HIP(launch_transfer(C.to_fine, prec, true, C.x, L.t, st));
+  MFQ_HIP(launch_add(prec, L.x, prec, L.t, L.n, st));
+  return mfq_chebyshev(L.op, L.dinv, L.b, L.x, 0, deg, L.lmin, L.lmax, work, st);
+}
+
+// z = V(r) on the finest level, FP64 in and out.
+int precondition(mfq_solver* s, const double* r, double* z, hipStream_t st) {
+  Level& F = s->lv.back();
+  if (s->prec_v == MFQ_FP64) {
+    F.b = const_cast<double*>(r);
+    F.x = z;
+    return vcycle(s, (int)s->lv.size() - 1, st);
+  }
+  MFQ_HIP(launch_cast(MFQ_FP64, r, MFQ_FP32, F.b, F.n, st));
+  if (int rc = vcycle(s, (int)s->lv.size() - 1, st)) return rc;
+  MFQ_HIP(launch_cast(MFQ_FP32, F.x, MFQ_FP64, z, F.n, st));
+  return MFQ_OK;
+}
+
+// lhat of D^{-1} A_l: Lanczos matrix of `iters` Jacobi-PCG steps on A_l x = v0 (v0 counter-based)
+int estimate_lambda(mfq_solver* s, Level& L, hipStream_t st) {
+  const int prec = s->prec_v;
+  const int64_t n = L.n;
+  void *r = L.r, *zz = L.d, *p = L.t, *Ap = L.x;
+  const int64_t N1 = (int64_t)L.sp->p * L.sp->mesh->n + 1;
+  MFQ_HIP(launch_splitmix(prec, r, N1, 0, true, st));
+  MFQ_HIP(launch_mul(prec, L.dinv, r, zz, n, st));
+  MFQ_HIP(hipMemcpyAsync(p, zz, n * rsize(prec), hipMemcpyDeviceToDevice, st));
+  double rz = 0, pAp = 0;
+  MFQ_HIP(launch_dot(prec, r, zz, n, s->aux, s->scal, st));
+  MFQ_HIP(hipMemcpyAsync(&rz, s->scal, 8, hipMemcpyDeviceToHost, st));
+  MFQ_HIP(hipStreamSynchronize(st));
+  const int k = s->prm.lanczos_iters;
+  std::vector<double> alphas, betas;
+  for (int it = 0; it < k; ++it) {
+    if (int rc = op_vmult(L.op, p, Ap, st)) return rc;
+    MFQ_HIP(launch_dot(prec, p, Ap, n, s->aux, s->scal, st));
+    MFQ_HIP(hipMemcpyAsync(&pAp, s->scal, 8, hipMemcpyDeviceToHost, st));
+    MFQ_HIP(hipStreamSynchronize(st));
+    if (!(pAp > 0) || !(rz > 0)) break;
+    const double alpha = rz / pAp;
+    MFQ_HIP(launch_axpby(prec, -alpha, Ap, 1.0, r, n, st));
+    MFQ_HIP(launch_mul(prec, L.dinv, r, zz, n, st));
+    double rz_new = 0;
+    MFQ_HIP(launch_dot(prec, r, zz, n, s->aux, s->scal, st));
+    MFQ_HIP(hipMemcpyAsync(&rz_new, s->scal, 8, hipMemcpyDeviceToHost, st));
+    MFQ_HIP(hipStreamSynchronize(st));
+    const double beta = rz_new / rz;
+    alphas.push_back(alpha);
+    betas.push_back(beta);
+    MFQ_HIP(launch_axpby(prec, 1.0, zz, beta, p, n, st));
+    rz = rz_new;
+    if (!(rz > 0)) break;
+  }
+  const int m = (int)alphas.size();
+  if (m == 0) return fail(MFQ_ENONFINITE, "eigenvalue estimate failed on level p=%d n=%d", L.sp->p, L.sp->mesh->n);
+  std::vector<double> T((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) {
+    T[i * m + i] = 1.0 / alphas[i] + (i > 0 ? betas[i - 1] / alphas[i - 1] : 0.0);
+    if (i + 1 < m) T[i * m + i + 1] = T[(i + 1) * m + i] = std::sqrt(betas[i]) / alphas[i];
+  }
+  L.lhat = sym_max_eig(T, m);
+  return MFQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void mfq_solver_default_params(mfq_solver_params* p) {
+  if (!p) return;
+  p->smoother_degree = 3;
+  p->lanczos_iters = 12;
+  p->lambda_factor = 1.2;
+  p->lambda_ratio = 15.0;
+  p->inner_rtol = 1e-4;
+  p->check_every = 4;
+  p->n_lambda_override = 0;
+  p->lambda_override = nullptr;
+}
+
+int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* params, mfq_solver** out) {
+  if (!op64 || !out) return fail(MFQ_EINVAL, "op or out is NULL");
+  if (op64->precision != MFQ_FP64) return fail(MFQ_EINVAL, "solver needs an FP64 operator");
+  if (kind < MFQ_SOLVER_CG || kind > MFQ_SOLVER_GMG_MIXED_IR) return fail(MFQ_EINVAL, "unknown solver kind %d", kind);
+  const mfq_space* fs = op64->space;
+  if (kind != MFQ_SOLVER_CG && fs->bc != MFQ_BC_DIRICHLET0)
+    return fail(MFQ_EINVAL, "multigrid solvers need Dirichlet boundary conditions");
+  mfq_solver_params prm;
+  mfq_solver_default_params(&prm);
+  if (params) prm = *params;
+  if (prm.smoother_degree < 1 || prm.smoother_degree > 32) return fail(MFQ_EINVAL, "smoother degree out of range");
+  if (prm.lanczos_iters < 1 || prm.lanczos_iters > 200) return fail(MFQ_EINVAL, "lanczos_iters out of range");
+  if (prm.check_every < 1) prm.check_every = 1;
+  if (!(prm.lambda_ratio > 1) || !(prm.lambda_factor > 0)) return fail(MFQ_EINVAL, "bad Chebyshev interval parameters");
+  if (!(prm.inner_rtol > 0 && prm.inner_rtol < 1)) return fail(MFQ_EINVAL, "inner_rtol must be in (0,1)");
+  mfq_solver* s = new (std::nothrow) mfq_solver();
+  if (!s) return fail(MFQ_ENOMEM, "host allocation failed");
+  s->op64 = op64;
+  s->kind = kind;
+  s->prm = prm;
+  s->prec_v = (kind == MFQ_SOLVER_GMG_MIXED || kind == MFQ_SOLVER_GMG_MIXED_IR) ? MFQ_FP32 : MFQ_FP64;
+
+  size_t off = 0;
+  auto take = [&off](size_t bytes) {
+    size_t o = off;
+    off += round_up(bytes, 256);
+    return o;
+  };
+  const int64_t N = fs->n_dofs;
+  s->off_state = take(sizeof(SolverState));
+  s->off_aux = take(sizeof(SolverState) + 64);
+  s->off_kry = take(6 * round_up(N * 8, 256));
+
+  if (kind != MFQ_SOLVER_CG) {
+    // hierarchy: halve n while even and > 4096 free DoFs, then p -> ceil(p/2) while > 4096
+    std::vector<std::pair<int, int>> spec;
+    int p = fs->p, n = fs->mesh->n;
+    spec.push_back({p, n});
+    while (n % 2 == 0 && n_free(p, n) > kDenseCoarseLimit) {
+      n /= 2;
+      spec.push_back({p, n});
+    }
+    while (p > 1 && n_free(p, n) > kDenseCoarseLimit) {
+      p = (p + 1) / 2;
+      spec.push_back({p, n});
+    }
+    std::reverse(spec.begin(), spec.end());
+    s->lv.resize(spec.size());
+    const int prec = s->prec_v;
+    for (size_t l = 0; l < spec.size(); ++l) {
+      Level& L = s->lv[l];
+      int rc = MFQ_OK;
+      if (l + 1 == spec.size()) {
+        L.sp = fs;
+      } else {
+        const mfq_mesh* m0 = fs->mesh;
+        rc = mfq_mesh_create(spec[l].second, m0->amplitude, &L.mesh);
+        if (!rc) rc = mfq_space_create(L.mesh, spec[l].first, fs->bc, &L.space);
+        L.sp = L.space;
+      }
+      if (rc) {
+        delete s;
+        return rc;
+      }
+      L.n = L.sp->n_dofs;
+      if (l + 1 == spec.size() && prec == MFQ_FP64) {
+        L.op = const_cast<mfq_op*>(op64);
+        L.owns_op = false;
+      } else if (l > 0 || (l + 1 == spec.size() && kind == MFQ_SOLVER_GMG_MIXED_IR)) {
+        if (int rc2 = mfq_op_create(L.sp, op64->alpha, prec, &L.op)) {
+          delete s;
+          return rc2;
+        }
+        size_t ob;
+        mfq_op_device_bytes(L.op, &ob);
+        L.off_op = take(ob);
+      } else {
+        L.op = nullptr;
+        L.owns_op = false;
+      }
+      const size_t vb = round_up(L.n * rsize(prec), 256);
+      L.off_b = take(vb);
+      L.off_x = take(vb);
+      L.off_r = take(3 * vb);  // r, d, t contiguous (Chebyshev work)
+      L.off_dinv = take(vb);
+      if (l > 0) {
+        if (int rc2 = mfq_transfer_create(s->lv[l - 1].sp, L.sp, &s->lv[l - 1].to_fine)) {
+          delete s;
+          return rc2;
+        }
+      }
+    }
+    // coarse level
+    Level& C = s->lv[0];
+    s->nf = n_free(C.sp->p, C.sp->mesh->n);
+    s->dense = s->nf <= kDenseCoarseLimit;
+    if (int rc = mfq_op_create(C.sp, op64->alpha, MFQ_FP64, &s->coarse64)) {
+      delete s;
+      return rc;
+    }
+    size_t cb;
+    mfq_op_device_bytes(s->coarse64, &cb);
+    s->off_coarse64 = take(cb);
+    if (s->dense) {
+      s->off_ainv = take((size_t)s->nf * s->nf * 8);
+    } else {
+      s->off_cvec = take(7 * round_up(C.n * 8, 256));
+      s->off_cstate = take(sizeof(SolverState));
+    }
+  }
+  s->bytes = off;
+  *out = s;
+  return MFQ_OK;
+}
+
+void mfq_solver_destroy(mfq_solver* s) { delete s; }
+
+int mfq_solver_device_bytes(const mfq_solver* s, size_t* bytes) {
+  if (!s || !bytes) return fail(MFQ_EINVAL, "solver or bytes is NULL");
+  *bytes = s->bytes;
+  return MFQ_OK;
+}
+
+int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream) {
+  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
+  if (!s->op64->buf) return fail(MFQ_EINVAL, "the solver's FP64 operator is not bound");
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) % 256)) return fail(MFQ_EINVAL, "buffer NULL or misaligned");
+  if (bytes < s->bytes) return fail(MFQ_ENOMEM, "buffer of %zu bytes, solver needs %zu", bytes, s->bytes);
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* base = (char*)dev_buf;
+  s->buf = dev_buf;
+  s->state = (SolverState*)(base + s->off_state);
+  s->aux = (SolverState*)(base + s->off_aux);
+  s->scal = (double*)(base + s->off_aux + sizeof(SolverState));
+  MFQ_HIP(launch_fill(MFQ_FP64, s->state, sizeof(SolverState) / 8, 0.0, st));
+  MFQ_HIP(launch_fill(MFQ_FP64, s->aux, (sizeof(SolverState) + 64) / 8, 0.0, st));
+  const int64_t N = s->op64->space->n_dofs;
+  const size_t vb = round_up(N * 8, 256);
+  double* k = (double*)(base + s->off_kry);
+  s->r = k;
+  s->p = (double*)((char*)k + vb);
+  s->Ap = (double*)((char*)k + 2 * vb);
+  s->z = (double*)((char*)k + 3 * vb);
+  s->rout = (double*)((char*)k + 4 * vb);
+  s->c = (double*)((char*)k + 5 * vb);
+  if (s->kind == MFQ_SOLVER_CG) return MFQ_OK;
+
+  const int prec = s->prec_v;
+  for (size_t l = 0; l < s->lv.size(); ++l) {
+    Level& L = s->lv[l];
+    const size_t lb = round_up(L.n * rsize(prec), 256);
+    L.b = base + L.off_b;
+    L.x = base + L.off_x;
+    L.r = base + L.off_r;
+    L.d = base + L.off_r + lb;
+    L.t = base + L.off_r + 2 * lb;
+    L.dinv = base + L.off_dinv;
+    if (L.op && L.owns_op) {
+      size_t ob;
+      mfq_op_device_bytes(L.op, &ob);
+      if (int rc = mfq_op_bind(L.op, base + L.off_op, ob, st)) return rc;
+    }
+  }
+  size_t cb;
+  mfq_op_device_bytes(s->coarse64, &cb);
+  if (int rc = mfq_op_bind(s->coarse64, base + s->off_coarse64, cb, st)) return rc;
+
+  // diagonals and eigenvalue bounds of the smoothed levels
+  for (size_t l = 1; l < s->lv.size(); ++l) {
+    Level& L = s->lv[l];
+    if (int rc = op_diagonal(L.op, L.dinv, st)) return rc;
+    MFQ_HIP(launch_reciprocal(prec, L.dinv, L.n, st));
+    if (int rc = estimate_lambda(s, L, st)) return rc;
+    const int idx = (int)l - 1;
+    double lmax = s->prm.lambda_factor * L.lhat;
+    if (s->prm.n_lambda_override > idx && s->prm.lambda_override) lmax = s->prm.lambda_override[idx];
+    L.lmax = lmax;
+    L.lmin = lmax / s->prm.lambda_ratio;
+  }
+  // coarse level
+  Level& C = s->lv[0];
+  const int64_t nf = s->nf;
+  if (s->dense) {
+    s->ainv = (double*)(base + s->off_ainv);
+    if (nf > 0) {
+      MFQ_HIP(launch_fill(MFQ_FP64, s->ainv, nf * nf, 0.0, st));
+      MFQ_HIP(launch_assemble_dense(view(s->coarse64), s->ainv, nf, st));
+      std::vector<double> A((size_t)nf * nf);
+      MFQ_HIP(hipMemcpyAsync(A.data(), s->ainv, A.size() * 8, hipMemcpyDeviceToHost, st));
+      MFQ_HIP(hipStreamSynchronize(st));
+      if (!spd_inverse(A, nf)) return fail(MFQ_ENONFINITE, "coarse matrix is not SPD");
+      MFQ_HIP(hipMemcpyAsync(s->ainv, A.data(), A.size() * 8, hipMemcpyHostToDevice, st));
+    }
+  } else {
+    const size_t cvb = round_up(C.n * 8, 256);
+    char* cv = base + s->off_cvec;
+    double** ptrs[7] = {&s->cb, &s->cx, &s->cr, &s->cp, &s->cAp, &s->cz, &s->cdinv};
+    for (int i = 0; i < 7; ++i) *ptrs[i] = (double*)(cv + i * cvb);
+    s->cstate = (SolverState*)(base + s->off_cstate);
+    MFQ_HIP(launch_fill(MFQ_FP64, s->cstate, sizeof(SolverState) / 8, 0.0, st));
+    if (int rc = op_diagonal(s->coarse64, s->cdinv, st)) return rc;
+    MFQ_HIP(launch_reciprocal(MFQ_FP64, s->cdinv, C.n, st));
+  }
+  MFQ_HIP(hipStreamSynchronize(st));
+  return MFQ_OK;
+}
+
+int mfq_solver_precondition(mfq_solver* s, const double* r, double* z, void* hip_stream) {
+  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
+  if (!s->buf) return fail(MFQ_EINVAL, "solver is not bound");
+  if (!r || !z || (reinterpret_cast<uintptr_t>(r) % 16) || (reinterpret_cast<uintptr_t>(z) % 16))
+    return fail(MFQ_EINVAL, "r or z NULL or misaligned");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const int64_t N = s->op64->space->n_dofs;
+  if (s->kind == MFQ_SOLVER_CG) {
+    MFQ_HIP(hipMemcpyAsync(z, r, N * 8, hipMemcpyDeviceToDevice, st));
+    return MFQ_OK;
+  }
+  return precondition(s, r, z, st);
+}
+
+int mfq_solver_lambdas(const mfq_solver* s, double* out, int n_out) {
+  if (!s || !out) return fail(MFQ_EINVAL, "solver or out is NULL");
+  const int m = s->lv.empty() ? 0 : (int)s->lv.size() - 1;
+  if (n_out < m) return fail(MFQ_EINVAL, "need room for %d values", m);
+  for (int i = 0; i < m; ++i) out[i] = s->lv[i + 1].lhat;
+  return MFQ_OK;
+}
+
+int mfq_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_iter, void* hip_stream,
+              mfq_solve_info* info) {
+  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
+  if (!s->buf) return fail(MFQ_EINVAL, "solver is not bound");
+  if (!b || !x || (reinterpret_cast<uintptr_t>(b) % 16) || (reinterpret_cast<uintptr_t>(x) % 16))
+    return fail(MFQ_EINVAL, "b or x NULL or misaligned");
+  if (!(rtol > 0 && rtol < 1)) return fail(MFQ_EINVAL, "rtol must be in (0,1)");
+  if (max_iter < 1) return fail(MFQ_EINVAL, "max_iter must be >= 1");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  const int64_t N = s->op64->space->n_dofs;
+  Apply A64 = [s, st](const double* in, double* out) { return op_vmult(s->op64, in, out, st); };
+  Apply M = [s, st](const double* in, double* out) { return precondition(s, in, out, st); };
+  mfq_solve_info inf{};
+  inf.n_levels = (int)s->lv.size();
+  int status = MFQ_OK;
+  PcgResult res;
+  if (s->kind != MFQ_SOLVER_GMG_MIXED_IR) {
+    const Apply* prec = (s->kind == MFQ_SOLVER_CG) ? nullptr : &M;
+    if (int rc = pcg(A64, prec, b, x, s->r, s->p, s->Ap, s->z, N, s->state, rtol, max_iter, s->prm.check_every, st, res))
+      return rc;
+    inf.iterations = res.iters;
+    inf.outer_iterations = 1;
+    if (res.nonfinite) status = MFQ_ENONFINITE;
+    else if (!res.converged) status = MFQ_ENOCONV;
+  } else {
+    // iterative refinement: r = b - A64 x (FP64); inner CG on FP32 operators, FP64 vectors
+    Level& F = s->lv.back();
+    Apply A32 = [s, st, &F](const double* in, double* out) -> int {
+      MFQ_HIP(launch_cast(MFQ_FP64, in, MFQ_FP32, F.r, F.n, st));
+      if (int rc = op_vmult(F.op, F.r, F.d, st)) return rc;
+      MFQ_HIP(launch_cast(MFQ_FP32, F.d, MFQ_FP64, out, F.n, st));
+      return MFQ_OK;
+    };
+    MFQ_HIP(launch_fill(MFQ_FP64, x, N, 0.0, st));
+    double bb = -1, rr = 0;
+    int total = 0, outer = 0;
+    for (;;) {
+      if (outer == 0) {
+        MFQ_HIP(launch_fill(MFQ_FP64, s->Ap, N, 0.0, st));
+      } else if (int rc = op_vmult(s->op64, x, s->Ap, st)) {
+        return rc;
+      }
+      MFQ_HIP(launch_residual_norm(b, s->Ap, s->rout, N, s->aux, s->scal, st));
+      MFQ_HIP(hipMemcpyAsync(&rr, s->scal, 8, hipMemcpyDeviceToHost, st));
+      MFQ_HIP(hipStreamSynchronize(st));
+      if (bb < 0) bb = rr;
+      if (!std::isfinite(rr)) {
+        status = MFQ_ENONFINITE;
+        break;
+      }
+      if (rr <= rtol * rtol * bb || bb == 0) break;
+      if (total >= max_iter) {
+        status = MFQ_ENOCONV;
+        break;
+      }
+      if (int rc = pcg(A32, &M, s->rout, s->c, s->r, s->p, s->Ap, s->z, N, s->state, s->prm.inner_rtol,
+                       max_iter - total, s->prm.check_every, st, res))
+        return rc;
+      total += std::max(res.iters, 1);
+      if (res.nonfinite) {
+        status = MFQ_ENONFINITE;
+        break;
+      }
+      MFQ_HIP(launch_add(MFQ_FP64, x, MFQ_FP64, s->c, N, st));
+      ++outer;
+    }
+    inf.iterations = total;
+    inf.outer_iterations = outer;
+  }
+  // true residual certificate
+  if (int rc = op_vmult(s->op64, x, s->Ap, st)) return rc;
+  MFQ_HIP(launch_residual_norm(b, s->Ap, nullptr, N, s->aux, s->scal, st));
+  double rr = 0, bb = 0;
+  MFQ_HIP(hipMemcpyAsync(&rr, s->scal, 8, hipMemcpyDeviceToHost, st));
+  MFQ_HIP(launch_dot(MFQ_FP64, b, b, N, s->aux, s->scal, st));
+  MFQ_HIP(hipMemcpyAsync(&bb, s->scal, 8, hipMemcpyDeviceToHost, st));
+  MFQ_HIP(hipStreamSynchronize(st));
+  inf.rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  if (info) *info = inf;
+  if (status == MFQ_ENOCONV) return fail(MFQ_ENOCONV, "no convergence to %g within %d iterations", rtol, max_iter);
+  if (status == MFQ_ENONFINITE) return fail(MFQ_ENONFINITE, "non-finite residual");
+  return MFQ_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,103 @@
+"""CPU checks of the C ABI: every declared symbol is exported, and host-side validation errors
+(no device needed) come back as documented status codes."""
+import ctypes
+import os
+import re
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "mfq.h")
+
+
+def _declared():
+    src = open(HEADER).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(mfq_[a-z0-9_]+)\s*\(", src)))
+
+
+def _lib():
+    from paper_1910_13247_amd import _lib
+    return _lib
+
+
+def test_library_exports_every_declared_symbol():
+    L = _lib().lib()
+    names = _declared()
+    assert len(names) >= 25
+    missing = [n for n in names if not hasattr(L, n)]
+    assert not missing, missing
+    assert set(names) == set(_lib().EXPORTED)
+
+
+def test_host_validation_errors():
+    lib = _lib()
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_mesh_create(0, 0.0)
+    assert e.value.status == lib.MFQ_EINVAL
+    with pytest.raises(lib.MfqError):
+        lib.mfq_mesh_create(4, 0.2)          # non-invertible deformation
+    m = lib.mfq_mesh_create(4, 0.1)
+    with pytest.raises(lib.MfqError):
+        lib.mfq_space_create(m, 9, 1)
+    with pytest.raises(lib.MfqError):
+        lib.mfq_space_create(m, 2, 7)
+    s = lib.mfq_space_create(m, 4, 1)
+    assert lib.mfq_space_n_dofs(s) == 17 ** 3 and lib.mfq_space_n_cells(s) == 64
+    with pytest.raises(lib.MfqError):
+        lib.mfq_op_create(s, 1.5, 0)
+    with pytest.raises(lib.MfqError):
+        lib.mfq_op_create(s, 0.5, 5)
+    op = lib.mfq_op_create(s, 0.5, 0)
+    nbytes = lib.mfq_op_device_bytes(op)
+    # index map (p+1)*256-lane blocks of int32 plus 6 doubles per quadrature point
+    cpb = 256 // 25
+    nblk = -(-64 // cpb)
+    assert nbytes >= nblk * 5 * 250 * 4 + nblk * 5 * 3 * 250 * 2 * 8
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_vmult(op, 256, 512, None)   # unbound operator: rejected before any launch
+    assert e.value.status == lib.MFQ_EINVAL
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_op_bind(op, 256, nbytes - 1, None)
+    assert e.value.status == lib.MFQ_ENOMEM
+    with pytest.raises(lib.MfqError):
+        lib.mfq_op_bind(op, 3, nbytes, None)  # misaligned
+    # transfer pairs must be nested
+    m2 = lib.mfq_mesh_create(8, 0.1)
+    s2 = lib.mfq_space_create(m2, 4, 1)
+    t = lib.mfq_transfer_create(s, s2)
+    lib.mfq_transfer_destroy(t)
+    with pytest.raises(lib.MfqError):
+        lib.mfq_transfer_create(s2, s)
+    s3 = lib.mfq_space_create(m, 2, 1)
+    t = lib.mfq_transfer_create(s3, s)       # p-coarsening 4 -> 2 on the same mesh
+    lib.mfq_transfer_destroy(t)
+    # solver kinds and precision
+    with pytest.raises(lib.MfqError):
+        lib.mfq_solver_create(op, 9)
+    op32 = lib.mfq_op_create(s, 0.5, 1)
+    with pytest.raises(lib.MfqError):
+        lib.mfq_solver_create(op32, 0)
+    sv = lib.mfq_solver_create(op, 2)
+    assert lib.mfq_solver_device_bytes(sv) > 0
+    with pytest.raises(lib.MfqError):
+        lib.mfq_solve(sv, 256, 512, 1e-10, 10, None)   # not bound
+    for h, f in [(sv, lib.mfq_solver_destroy), (op32, lib.mfq_op_destroy), (op, lib.mfq_op_destroy),
+                 (s3, lib.mfq_space_destroy), (s2, lib.mfq_space_destroy), (s, lib.mfq_space_destroy),
+                 (m2, lib.mfq_mesh_destroy), (m, lib.mfq_mesh_destroy)]:
+        f(h)
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_library_tables_agree_with_oracle_tables(p):
+    # the library's tables (Newton on the Legendre recurrence) and the oracle's (numpy companion
+    # roots, leggauss) are independent codes; both feed every parity test
+    import numpy as np
+    from oracle.tables import shape_1d
+    xi, z, w, S, D = _lib().mfq_reference_tables(p)
+    xo, zo, wo, So, Do = shape_1d(p)
+    np.testing.assert_allclose(xi, xo, atol=2e-16)
+    np.testing.assert_allclose(z, zo, atol=2e-16)
+    np.testing.assert_allclose(w, wo, atol=2e-16)
+    np.testing.assert_allclose(S, So, atol=1e-14)
+    np.testing.assert_allclose(D, Do, atol=1e-12 * np.abs(Do).max())
