@@ -110,8 +110,8 @@ int mfq_op_bind(mfq_op* op, void* dev_buf, size_t bytes, void* hip_stream);
 int mfq_vmult(const mfq_op* op, const void* src, void* dst, void* hip_stream);
 
 /* dst += A src (same operator, Dirichlet rows add src): the cell loop alone, without clearing dst.
- * mfq_vmult is a clear of dst followed by this.  Atomic accumulation: the order of the additions
- * into a shared node is not fixed, so results may differ from run to run by rounding. */
+ * Both are deterministic (fixed summation order, no atomics): equal inputs give bitwise equal
+ * outputs.  Eight launches on the stream (one per brick colour). */
 int mfq_vmult_add(const mfq_op* op, const void* src, void* dst, void* hip_stream);
 
 /* diag = diagonal of A (1 on Dirichlet rows), computed matrix-free from the same quadrature. */

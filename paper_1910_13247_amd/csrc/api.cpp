@@ -31,8 +31,7 @@ namespace mfq {
 
 int op_vmult(const mfq_op* op, const void* src, void* dst, hipStream_t st) {
   const OpView v = view(op);
-  MFQ_HIP(launch_fill(op->precision, dst, v.n_dofs, 0.0, st));
-  MFQ_HIP(launch_vmult_cells(v, op->precision, src, dst, st));
+  MFQ_HIP(launch_vmult_cells(v, op->precision, src, dst, false, st));
   return MFQ_OK;
 }
 
@@ -114,11 +113,11 @@ int mfq_op_create(const mfq_space* space, double alpha, int precision, mfq_op** 
   op->alpha = alpha;
   op->precision = precision;
   const int p = space->p;
-  const int cpb = cells_per_block(p);
-  op->n_blocks = (space->n_cells + cpb - 1) / cpb;
-  const size_t lanes = (size_t)lanes_per_block(p);
-  op->idx_bytes = round_up((size_t)op->n_blocks * (p + 1) * lanes * sizeof(int), 256);
-  op->geo_bytes = round_up((size_t)op->n_blocks * (p + 1) * 3 * lanes * 2 * real_size(precision), 256);
+  op->bricks = make_bricks(p, space->mesh->n);
+  const size_t nb = (size_t)op->bricks.n_bricks;
+  const size_t lanes = (size_t)lanes_per_brick(p);
+  op->idx_bytes = round_up(nb * (size_t)lattice_per_brick(p) * sizeof(int), 256);
+  op->geo_bytes = round_up(nb * (p + 1) * 3 * lanes * 2 * real_size(precision), 256);
   *out = op;
   return MFQ_OK;
 }
@@ -169,7 +168,7 @@ int mfq_vmult_add(const mfq_op* op, const void* src, void* dst, void* hip_stream
   const char* s = (const char*)src;
   const char* d = (const char*)dst;
   if (s < d + bytes && d < s + bytes) return fail(MFQ_EINVAL, "src and dst overlap");
-  MFQ_HIP(launch_vmult_cells(view(op), op->precision, src, dst, (hipStream_t)hip_stream));
+  MFQ_HIP(launch_vmult_cells(view(op), op->precision, src, dst, true, (hipStream_t)hip_stream));
   return MFQ_OK;
 }
 

@@ -5,43 +5,50 @@
 // applied without a matrix (Sec. 3.6): gather the cell's DoFs, evaluate reference gradients at
 // the quadrature points by sum factorisation, multiply by the stored quadrature-point tensor
 // G_q = w_q a(x_q) det(J_q) J_q^{-1} J_q^{-T}, test with the reference gradients (transposed sum
-// factorisation), scatter-add.
+// factorisation), add into the result.
 //
-// Work decomposition (MI355X-first): one lane per 1D pencil of a cell ((p+1)^2 lanes per cell,
-// 256 // (p+1)^2 cells per workgroup), each lane contracting its pencil in registers; the
-// pencils change direction through LDS.  Gradients are formed directly from the 1D value and
-// derivative tables in the order x (S, D) -> y (S, D on the S-branch) -> z, so all three
-// components arrive at the same lane and point without extra transposes; the backward pass is
-// the exact transpose.  The G stream (the dominant HBM traffic) is laid out so that every wave
-// load is 1 KiB contiguous and is issued at kernel start to overlap the forward contractions.
+// Work decomposition (MI355X-first):
+//  * one workgroup per brick of cells (e.g. 2x2x2 at p=4), one lane per 1D pencil of a cell,
+//    each lane contracting its pencil in registers; pencils change direction through LDS.
+//    Gradients are formed from the 1D value and derivative tables in the order x (S, D) ->
+//    y (S, D on the S-branch) -> z, so all three components arrive at the same lane and
+//    quadrature point without extra transposes; the backward pass is the exact transpose.
+//  * the brick's node lattice is gathered once into LDS (shared nodes of neighbouring cells
+//    read once) and the cells' results are summed per lattice node in LDS in a fixed order;
+//  * bricks are coloured by the parities of their coordinates: one launch per colour, colours
+//    in order, so a workgroup owns its lattice nodes during its launch and writes them with plain
+//    stores (the first colour touching a node stores, later colours add).  No atomics (device
+//    atomics across the 8 XCDs are resolved at the memory side and cost several times the
+//    whole operator), no clearing of the result, bitwise reproducible.
+//  * per-brick data (index lattice, G) is stored colour-major so each launch streams a
+//    contiguous range; every wave's G load is 1 KiB contiguous and issued at kernel start.
+#include <climits>
+
 #include "kernels_common.hpp"
 
 namespace mfq {
 
 namespace {
 
-// ---------------------------------------------------------------- index maps
-// idx[blk][a][lane]: lane = lc*T + e, e = e0 + N1*e1, holds the global DoF of local DoF
-// (a, e0, e1) of cell blk*CPB + lc; Dirichlet nodes are stored as ~g (negative).
+constexpr int kAbsent = INT_MIN;  // lattice node outside the mesh (ragged last bricks)
+
+// ---------------------------------------------------------------- index lattices
+// idx[ord][k]: global node of lattice node k = li + LX*(lj + LY*lk) of brick `ord`;
+// ~g on Dirichlet nodes, kAbsent outside the mesh.
 template <int P>
-__global__ __launch_bounds__(kBlock) void fill_index_kernel(int* __restrict__ idx, int64_t n_cells, int64_t n_blocks,
-                                                            int n, int bc) {
+__global__ __launch_bounds__(kBlock) void fill_index_kernel(int* __restrict__ idx, Bricks bk, int n, int bc) {
   using C = Cell<P>;
-  const int64_t total = n_blocks * C::N1 * C::NT;
+  const int64_t total = bk.n_bricks * C::NL;
   const int64_t N1g = (int64_t)P * n + 1;
   for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < total; L += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t blk = L / (C::N1 * C::NT);
-    const int rem = (int)(L - blk * (C::N1 * C::NT));
-    const int a = rem / C::NT;
-    const int lane = rem - a * C::NT;
-    const int lc = lane / C::T;
-    const int e = lane - lc * C::T;
-    const int e0 = e % C::N1, e1 = e / C::N1;
-    const int64_t cell = blk * C::CPB + lc;
-    int val = 0;
-    if (cell < n_cells) {
-      const int64_t ci = cell % n, cj = (cell / n) % n, ck = cell / ((int64_t)n * n);
-      const int64_t I = P * ci + a, J = P * cj + e0, K = P * ck + e1;
+    const int64_t ord = L / C::NL;
+    const int k = (int)(L - ord * C::NL);
+    const int li = k % C::LX, lj = (k / C::LX) % C::LY, lk = k / (C::LX * C::LY);
+    int bi, bj, bz;
+    brick_of_ordinal(bk, ord, bi, bj, bz);
+    const int64_t I = (int64_t)bi * C::BX * P + li, J = (int64_t)bj * C::BY * P + lj, K = (int64_t)bz * C::BZ * P + lk;
+    int val = kAbsent;
+    if (I < N1g && J < N1g && K < N1g) {
       const int64_t g = I + N1g * (J + N1g * K);
       const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1g - 1 || J == N1g - 1 || K == N1g - 1);
       val = bnd ? ~(int)g : (int)g;
@@ -50,9 +57,17 @@ __global__ __launch_bounds__(kBlock) void fill_index_kernel(int* __restrict__ id
   }
 }
 
+// lattice index of local node (a, b, c) of cell lc of a brick
+template <int P>
+__host__ __device__ inline int lattice_of(int lc, int a, int b, int c) {
+  using C = Cell<P>;
+  const int cx = lc % C::BX, cy = (lc / C::BX) % C::BY, cz = lc / (C::BX * C::BY);
+  return (cx * P + a) + C::LX * ((cy * P + b) + C::LY * (cz * P + c));
+}
+
 // ---------------------------------------------------------------- geometry precompute (FP64)
-// geo[blk][t][m][lane][2]: for lane = lc*T + (r + N1*s), quadrature point (r, s, t) of cell
-// blk*CPB+lc; pairs m = (G00,G01), (G02,G11), (G12,G22).
+// geo[ord][t][m][lane][2]: for lane = lc*T + (r + N1*s), quadrature point (r, s, t) of cell lc of
+// brick ord; pairs m = (G00,G01), (G02,G11), (G12,G22); zero for cells outside the mesh.
 template <int P>
 struct QuadRule {
   double z[P + 1];
@@ -86,27 +101,39 @@ __device__ __forceinline__ void merged_tensor(const QGeo& g, double wa, double (
   G[5] = f * K[2][2];
 }
 
-template <int P, typename Real>
-__global__ __launch_bounds__(kBlock) void geometry_kernel(Real* __restrict__ geo, int64_t n_cells, int64_t n_blocks,
-                                                          int n, double amp, double alpha, QuadRule<P> qr) {
+// global cell (ci, cj, ck) of cell lc in brick (bi, bj, bz); false when outside the mesh
+template <int P>
+__device__ __forceinline__ bool cell_of(int bi, int bj, int bz, int lc, int n, int64_t& ci, int64_t& cj, int64_t& ck) {
   using C = Cell<P>;
-  const int64_t total = n_blocks * C::N1 * C::NT;
+  ci = (int64_t)bi * C::BX + lc % C::BX;
+  cj = (int64_t)bj * C::BY + (lc / C::BX) % C::BY;
+  ck = (int64_t)bz * C::BZ + lc / (C::BX * C::BY);
+  return ci < n && cj < n && ck < n;
+}
+
+template <int P, typename Real>
+__global__ __launch_bounds__(kBlock) void geometry_kernel(Real* __restrict__ geo, Bricks bk, int n, double amp,
+                                                          double alpha, QuadRule<P> qr) {
+  using C = Cell<P>;
+  const int64_t total = bk.n_bricks * C::N1 * C::NT;
   for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < total; L += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t blk = L / (C::N1 * C::NT);
-    const int rem = (int)(L - blk * (C::N1 * C::NT));
+    const int64_t ord = L / (C::N1 * C::NT);
+    const int rem = (int)(L - ord * (C::N1 * C::NT));
     const int t = rem / C::NT;
     const int lane = rem - t * C::NT;
     const int lc = lane / C::T;
     const int e = lane - lc * C::T;
     const int r = e % C::N1, s = e / C::N1;
-    const int64_t cell = blk * C::CPB + lc;
+    int bi, bj, bz;
+    brick_of_ordinal(bk, ord, bi, bj, bz);
+    int64_t ci, cj, ck;
     double G[6] = {0, 0, 0, 0, 0, 0};
-    if (cell < n_cells) {
+    if (cell_of<P>(bi, bj, bz, lc, n, ci, cj, ck)) {
       QGeo g;
-      qpoint_geometry(n, amp, cell, qr.z[r], qr.z[s], qr.z[t], g);
+      qpoint_geometry(n, amp, ci + (int64_t)n * (cj + (int64_t)n * ck), qr.z[r], qr.z[s], qr.z[t], g);
       merged_tensor(g, qr.w[r] * qr.w[s] * qr.w[t] * coefficient(alpha, g.x), G);
     }
-    Real2<Real>* out = reinterpret_cast<Real2<Real>*>(geo) + (blk * C::N1 + t) * 3 * C::NT + lane;
+    Real2<Real>* out = reinterpret_cast<Real2<Real>*>(geo) + (ord * C::N1 + t) * 3 * C::NT + lane;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       Real2<Real> v;
@@ -119,16 +146,16 @@ __global__ __launch_bounds__(kBlock) void geometry_kernel(Real* __restrict__ geo
 
 template <int P, typename Real>
 __global__ __launch_bounds__(kBlock) void geometry_export_kernel(const Real* __restrict__ geo, double* __restrict__ out,
-                                                                 int64_t n_cells) {
+                                                                 Bricks bk, int n) {
   using C = Cell<P>;
-  const int64_t total = n_cells * C::NQ;
+  const int64_t total = (int64_t)n * n * n * C::NQ;
   for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < total; L += (int64_t)gridDim.x * blockDim.x) {
     const int64_t cell = L / C::NQ;
     const int q = (int)(L - cell * C::NQ);
     const int t = q / C::T, e = q - t * C::T;
-    const int64_t blk = cell / C::CPB;
-    const int lc = (int)(cell - blk * C::CPB);
-    const Real2<Real>* in = reinterpret_cast<const Real2<Real>*>(geo) + (blk * C::N1 + t) * 3 * C::NT + lc * C::T + e;
+    int lc;
+    const int64_t ord = ordinal_of_cell(bk, cell % n, (cell / n) % n, cell / ((int64_t)n * n), lc);
+    const Real2<Real>* in = reinterpret_cast<const Real2<Real>*>(geo) + (ord * C::N1 + t) * 3 * C::NT + lc * C::T + e;
 #pragma unroll
     for (int m = 0; m < 3; ++m) {
       Real2<Real> v = in[m * C::NT];
@@ -139,62 +166,86 @@ __global__ __launch_bounds__(kBlock) void geometry_export_kernel(const Real* __r
 }
 
 // ---------------------------------------------------------------- operator application
-template <int P, typename Real>
+// One launch per colour, one workgroup per brick; ACC adds A src into dst instead of overwriting
+// it.  Lanes beyond the brick's pencils work on a spare LDS slot so no branch is needed around
+// LDS stores or loads (their results are never read).
+template <int P, typename Real, bool ACC>
 __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
-                                                       const Real* __restrict__ src, Real* __restrict__ dst,
-                                                       int64_t n_cells, int n1d, Shape<P, Real> sh) {
+                                                       const Real* __restrict__ src, Real* __restrict__ dst, Bricks bk,
+                                                       int colour, ShapeEO<P, Real> sh) {
   using C = Cell<P>;
-  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, CPB = C::CPB, NT = C::NT;
-  constexpr bool kPrefetch = (P <= 5);
-  __shared__ Real lds[CPB * 3 * NQ];
+  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NCELL = C::NCELL, NT = C::NT, LX = C::LX, LY = C::LY, NL = C::NL;
+  constexpr int KPT = (NL + kBlock - 1) / kBlock;  // lattice nodes per thread
+  __shared__ Real lds[(NCELL + 1) * 3 * NQ];
+  // cell arrays stored array-major: [L0 of every cell][L1 ...][L2 ...]; the node lattice is only
+  // read before the first write of an L2 array, so it lives in the L2 block
+  static_assert(KPT * kBlock <= (NCELL + 1) * NQ, "lattice must fit the L2 block");
+  Real* const lat = lds + 2 * (NCELL + 1) * NQ;
 
   const int tid = threadIdx.x;
-  const int lc = tid / T;
-  const int e = tid - lc * T;
+  const bool lane_ok = tid < NT;
+  const int lc = lane_ok ? tid / T : NCELL;           // spare slot for the idle lanes
+  const int e = lane_ok ? tid - lc * T : (tid - NT) % T;
   const int e0 = e % N1, e1 = e / N1;
-  const int64_t blk = blockIdx.x;
-  const bool lane_ok = lc < CPB;
-  const bool active = lane_ok && (blk * CPB + lc) < n_cells;
-  const int lane = lane_ok ? lc * T + e : 0;
-  Real* L0 = lds + (lane_ok ? lc : 0) * 3 * NQ;
-  Real* L1 = L0 + NQ;
-  Real* L2 = L1 + NQ;
+  const int64_t ord = bk.offset[colour] + blockIdx.x;
+  int bi, bj, bz;
+  brick_of(bk, colour, blockIdx.x, bi, bj, bz);
+  Real* L0 = lds + lc * NQ;
+  Real* L1 = L0 + (NCELL + 1) * NQ;
+  Real* L2 = L1 + (NCELL + 1) * NQ;
 
-  // quadrature-point tensor of this lane's z-pencil (points (e0, e1, t))
-  const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + blk * (int64_t)(N1 * 3 * NT) + lane;
-  Real2<Real> g[kPrefetch ? N1 : 1][3];
+  // quadrature-point tensors of this lane's z-pencil (points (e0, e1, t)), issued first
+  const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + (lane_ok ? tid : 0);
+  Real2<Real> g[N1][3];
 #pragma unroll
-  for (int t = 0; t < (kPrefetch ? N1 : 1); ++t)
+  for (int t = 0; t < N1; ++t)
 #pragma unroll
-    for (int m = 0; m < 3; ++m) g[t][m] = (kPrefetch && active) ? __builtin_nontemporal_load(gp + (t * 3 + m) * NT)
-                                                                 : Real2<Real>{0, 0};
+    for (int m = 0; m < 3; ++m) g[t][m] = __builtin_nontemporal_load(gp + (t * 3 + m) * NT);
 
-  // gather the x-pencil (a, e0, e1); Dirichlet nodes enter as zero
-  int gi[N1];
-  Real u[N1];
-  const int* ip = idx + blk * (int64_t)(N1 * NT) + lane;
+  // this thread's lattice nodes: global index, first-touch flag (the first colour touching a node
+  // stores: the brick that is even in every direction in which the node is shared with a
+  // neighbouring brick), source value, and the dst value this launch adds to
+  const int* ip = idx + ord * (int64_t)NL;
+  int gk[KPT];
+  bool first[KPT];
+  Real dv[KPT];
 #pragma unroll
-  for (int a = 0; a < N1; ++a) {
-    gi[a] = active ? ip[a * NT] : 0;
+  for (int j = 0; j < KPT; ++j) {
+    const int k = tid + j * kBlock;
+    const int kk = k < NL ? k : NL - 1;
+    const int gl = ip[kk];
+    gk[j] = k < NL ? gl : kAbsent;
+    const int li = kk % LX, lj = (kk / LX) % LY, lk = kk / (LX * LY);
+    const bool sx = (li == 0 && bi > 0) || (li == LX - 1 && bi < bk.nbx - 1);
+    const bool sy = (lj == 0 && bj > 0) || (lj == LY - 1 && bj < bk.nby - 1);
+    const bool sz = (lk == 0 && bz > 0) || (lk == C::LZ - 1 && bz < bk.nbz - 1);
+    first[j] = (!sx || !(bi & 1)) && (!sy || !(bj & 1)) && (!sz || !(bz & 1));
   }
 #pragma unroll
-  for (int a = 0; a < N1; ++a) {
-    Real v = 0;
-    if (active && gi[a] >= 0) v = src[gi[a]];
-    u[a] = v;
+  for (int j = 0; j < KPT; ++j) {
+    const int g0 = gk[j];
+    const int gs = g0 >= 0 ? g0 : 0;
+    const Real s = src[gs];
+    const Real d = dst[gs];
+    lat[tid + j * kBlock] = g0 >= 0 ? s : (Real)0;
+    dv[j] = (g0 >= 0 && (ACC || !first[j])) ? d : (Real)0;
   }
+  lds_barrier();
 
-  // x: values and x-derivatives at (q, e0, e1)
+  // x: values and x-derivatives at (q, e0, e1) from the lane's x-pencil
   {
-    Real A[N1], B[N1];
-    apply<N1>(sh.S, u, A);
-    apply<N1>(sh.D, u, B);
-    if (lane_ok) {
+    const int cl = lc < NCELL ? lc : 0;
+    const int cx = cl % C::BX, cy = (cl / C::BX) % C::BY, cz = cl / (C::BX * C::BY);
+    const Real* up = lat + cx * P + LX * ((cy * P + e0) + LY * (cz * P + e1));
+    Real u[N1], A[N1], B[N1];
 #pragma unroll
-      for (int q = 0; q < N1; ++q) {
-        L0[q + N1 * e] = A[q];
-        L1[q + N1 * e] = B[q];
-      }
+    for (int a = 0; a < N1; ++a) u[a] = up[a];
+    eo_apply<N1, 1, false>(sh.S, u, A);
+    eo_apply<N1, -1, false>(sh.D, u, B);
+#pragma unroll
+    for (int q = 0; q < N1; ++q) {
+      L0[q + N1 * e] = A[q];
+      L1[q + N1 * e] = B[q];
     }
   }
   lds_barrier();
@@ -207,17 +258,15 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
       b1[b] = L1[e0 + N1 * b + T * e1];
     }
     Real A2[N1], B2[N1], C2[N1];
-    apply<N1>(sh.S, a1, A2);
-    apply<N1>(sh.D, a1, C2);
-    apply<N1>(sh.S, b1, B2);
+    eo_apply<N1, 1, false>(sh.S, a1, A2);
+    eo_apply<N1, -1, false>(sh.D, a1, C2);
+    eo_apply<N1, 1, false>(sh.S, b1, B2);
     lds_barrier();
-    if (lane_ok) {
 #pragma unroll
-      for (int s = 0; s < N1; ++s) {
-        L0[e0 + N1 * s + T * e1] = A2[s];
-        L1[e0 + N1 * s + T * e1] = B2[s];
-        L2[e0 + N1 * s + T * e1] = C2[s];
-      }
+    for (int s = 0; s < N1; ++s) {
+      L0[e0 + N1 * s + T * e1] = A2[s];
+      L1[e0 + N1 * s + T * e1] = B2[s];
+      L2[e0 + N1 * s + T * e1] = C2[s];
     }
   }
   lds_barrier();
@@ -230,77 +279,54 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
       b2[c] = L1[e + T * c];
       c2[c] = L2[e + T * c];
     }
-    Real Az[N1], Bz[N1], Cz[N1];
-#pragma unroll
-    for (int c = 0; c < N1; ++c) Az[c] = Bz[c] = Cz[c] = 0;
+    Real gx[N1], gy[N1], gz[N1];
+    eo_apply<N1, 1, false>(sh.S, b2, gx);
+    eo_apply<N1, 1, false>(sh.S, c2, gy);
+    eo_apply<N1, -1, false>(sh.D, a2, gz);
+    Real vx[N1], vy[N1], vz[N1];
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
-      Real gx = 0, gy = 0, gz = 0;
-#pragma unroll
-      for (int c = 0; c < N1; ++c) {
-        gx = __builtin_fma(sh.S[t * N1 + c], b2[c], gx);
-        gy = __builtin_fma(sh.S[t * N1 + c], c2[c], gy);
-        gz = __builtin_fma(sh.D[t * N1 + c], a2[c], gz);
-      }
-      Real2<Real> G0, G1, G2;
-      if constexpr (kPrefetch) {
-        G0 = g[t][0];
-        G1 = g[t][1];
-        G2 = g[t][2];
-      } else {
-        if (active) {
-          G0 = __builtin_nontemporal_load(gp + (t * 3 + 0) * NT);
-          G1 = __builtin_nontemporal_load(gp + (t * 3 + 1) * NT);
-          G2 = __builtin_nontemporal_load(gp + (t * 3 + 2) * NT);
-        } else {
-          G0 = G1 = G2 = Real2<Real>{0, 0};
-        }
-      }
       // (G00 G01 G02; G01 G11 G12; G02 G12 G22) = (G0.x G0.y G1.x; . G1.y G2.x; . . G2.y)
-      const Real vx = G0.x * gx + G0.y * gy + G1.x * gz;
-      const Real vy = G0.y * gx + G1.y * gy + G2.x * gz;
-      const Real vz = G1.x * gx + G2.x * gy + G2.y * gz;
-#pragma unroll
-      for (int c = 0; c < N1; ++c) {
-        Bz[c] = __builtin_fma(sh.S[t * N1 + c], vx, Bz[c]);
-        Cz[c] = __builtin_fma(sh.S[t * N1 + c], vy, Cz[c]);
-        Az[c] = __builtin_fma(sh.D[t * N1 + c], vz, Az[c]);
-      }
+      const Real2<Real> G0 = g[t][0], G1 = g[t][1], G2 = g[t][2];
+      vx[t] = G0.x * gx[t] + G0.y * gy[t] + G1.x * gz[t];
+      vy[t] = G0.y * gx[t] + G1.y * gy[t] + G2.x * gz[t];
+      vz[t] = G1.x * gx[t] + G2.x * gy[t] + G2.y * gz[t];
     }
+    Real Az[N1], Bz[N1], Cz[N1];
+    eo_apply<N1, 1, true>(sh.S, vx, Bz);
+    eo_apply<N1, 1, true>(sh.S, vy, Cz);
+    eo_apply<N1, -1, true>(sh.D, vz, Az);
     lds_barrier();
-    if (lane_ok) {
 #pragma unroll
-      for (int c = 0; c < N1; ++c) {
-        L0[e + T * c] = Az[c];
-        L1[e + T * c] = Bz[c];
-        L2[e + T * c] = Cz[c];
-      }
+    for (int c = 0; c < N1; ++c) {
+      L0[e + T * c] = Az[c];
+      L1[e + T * c] = Bz[c];
+      L2[e + T * c] = Cz[c];
     }
   }
   lds_barrier();
   // transposed y: lane (r=e0, c=e1)
   {
-    Real az[N1], bz[N1], cz[N1];
+    Real az[N1], bz2[N1], cz[N1];
 #pragma unroll
     for (int s = 0; s < N1; ++s) {
       az[s] = L0[e0 + N1 * s + T * e1];
-      bz[s] = L1[e0 + N1 * s + T * e1];
+      bz2[s] = L1[e0 + N1 * s + T * e1];
       cz[s] = L2[e0 + N1 * s + T * e1];
     }
     Real Ap[N1], Bp[N1];
-    apply_t2<N1>(sh.S, az, sh.D, cz, Ap);
-    apply_t<N1>(sh.S, bz, Bp);
+    eo_apply_t2<N1>(sh.S, az, sh.D, cz, Ap);
+    eo_apply<N1, 1, true>(sh.S, bz2, Bp);
     lds_barrier();
-    if (lane_ok) {
 #pragma unroll
-      for (int b = 0; b < N1; ++b) {
-        L0[e0 + N1 * b + T * e1] = Ap[b];
-        L1[e0 + N1 * b + T * e1] = Bp[b];
-      }
+    for (int b = 0; b < N1; ++b) {
+      L0[e0 + N1 * b + T * e1] = Ap[b];
+      L1[e0 + N1 * b + T * e1] = Bp[b];
     }
   }
   lds_barrier();
-  // transposed x: lane (b=e0, c=e1) owns the DoFs it gathered
+  // transposed x: lane (b=e0, c=e1) gets the cell result of its x-pencil, kept in L0 in local
+  // lexicographic order (each lane rewrites exactly the entries it read)
   {
     Real ap[N1], bp[N1], y[N1];
 #pragma unroll
@@ -308,44 +334,56 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
       ap[r] = L0[r + N1 * e];
       bp[r] = L1[r + N1 * e];
     }
-    apply_t2<N1>(sh.S, ap, sh.D, bp, y);
-    if (active) {
-      // Dirichlet rows add src once: by the cell that holds the node at a non-lower face in
-      // every direction (no lower-indexed neighbour shares it)
-      const int64_t cell = blk * CPB + lc;
-      const int64_t ci = cell % n1d, cj = (cell / n1d) % n1d, ck = cell / ((int64_t)n1d * n1d);
-      const bool own_yz = (e0 > 0 || cj == 0) && (e1 > 0 || ck == 0);
+    eo_apply_t2<N1>(sh.S, ap, sh.D, bp, y);
 #pragma unroll
-      for (int a = 0; a < N1; ++a) {
-        if (gi[a] >= 0)
-          atomic_add(dst + gi[a], y[a]);
-        else if (own_yz && (a > 0 || ci == 0))
-          atomic_add(dst + ~gi[a], src[~gi[a]]);
-      }
+    for (int a = 0; a < N1; ++a) L0[a + N1 * e] = y[a];
+  }
+  lds_barrier();
+  // sum the cells' results per lattice node (fixed order) and write the brick's nodes
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    const int k = tid + j * kBlock;
+    const int g0 = gk[j];
+    if (g0 == kAbsent) continue;
+    const int li = k % LX, lj = (k / LX) % LY, lk = k / (LX * LY);
+    const int xhi = min(li / P, C::BX - 1), xlo = (li % P == 0 && li > 0) ? li / P - 1 : xhi;
+    const int yhi = min(lj / P, C::BY - 1), ylo = (lj % P == 0 && lj > 0) ? lj / P - 1 : yhi;
+    const int zhi = min(lk / P, C::BZ - 1), zlo = (lk % P == 0 && lk > 0) ? lk / P - 1 : zhi;
+    Real sum = 0;
+    for (int cz = zlo; cz <= zhi; ++cz)
+      for (int cy = ylo; cy <= yhi; ++cy)
+        for (int cx = xlo; cx <= xhi; ++cx) {
+          const int cell = cx + C::BX * (cy + C::BY * cz);
+          sum += lds[cell * NQ + (li - cx * P) + N1 * ((lj - cy * P) + N1 * (lk - cz * P))];
+        }
+    if (g0 >= 0) {
+      dst[g0] = (ACC || !first[j]) ? dv[j] + sum : sum;
+    } else if (first[j]) {
+      const int gg = ~g0;
+      dst[gg] = ACC ? dst[gg] + src[gg] : src[gg];
     }
   }
 }
 
 // ---------------------------------------------------------------- diagonal
-// diag_i = sum_K sum_q grad phi_i(q)^T G_q grad phi_i(q); one thread per (cell, i).
+// diag_i = sum_K sum_q grad phi_i(q)^T G_q grad phi_i(q); one thread per (cell, i), atomics.
 template <int P, typename Real>
 __global__ __launch_bounds__(kBlock) void diagonal_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
-                                                          Real* __restrict__ diag, int64_t n_cells, Shape<P, Real> sh) {
+                                                          Real* __restrict__ diag, Bricks bk, Shape<P, Real> sh) {
   using C = Cell<P>;
-  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, CPB = C::CPB, NT = C::NT;
-  const int64_t blk = blockIdx.x;
-  for (int k = threadIdx.x; k < CPB * NQ; k += kBlock) {
+  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NT = C::NT;
+  const int64_t ord = blockIdx.x;
+  for (int k = threadIdx.x; k < C::NCELL * NQ; k += kBlock) {
     const int lc = k / NQ;
     const int i = k - lc * NQ;
-    if (blk * CPB + lc >= n_cells) continue;
     const int a = i % N1, b = (i / N1) % N1, c = i / T;
-    // idx layout: local DoF (a, b, c) is lane lc*T + (b + N1*c), row a
-    const int g = idx[blk * (int64_t)(N1 * NT) + a * NT + lc * T + b + N1 * c];
+    const int g = idx[ord * (int64_t)C::NL + lattice_of<P>(lc, a, b, c)];
+    if (g == kAbsent) continue;
     if (g < 0) {
       diag[~g] = (Real)1;
       continue;
     }
-    const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + blk * (int64_t)(N1 * 3 * NT) + lc * T;
+    const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + lc * T;
     Real sum = 0;
     for (int t = 0; t < N1; ++t)
       for (int s = 0; s < N1; ++s)
@@ -365,28 +403,30 @@ __global__ __launch_bounds__(kBlock) void diagonal_kernel(const int* __restrict_
 // ---------------------------------------------------------------- right-hand side
 // b_i += sum_q f(x_q) JxW_q phi_i(q) for u* = sin(pi x) sin(pi y) sin(pi z), f = -div(a grad u*).
 template <int P>
-__global__ __launch_bounds__(kBlock) void rhs_kernel(const int* __restrict__ idx, double* __restrict__ b, int64_t n_cells,
+__global__ __launch_bounds__(kBlock) void rhs_kernel(const int* __restrict__ idx, double* __restrict__ b, Bricks bk,
                                                      int n, double amp, double alpha, Shape<P, double> sh,
                                                      QuadRule<P> qr) {
   using C = Cell<P>;
-  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, CPB = C::CPB, NT = C::NT;
-  __shared__ double lds[CPB * NQ];
+  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NT = C::NT;
+  __shared__ double lds[C::NCELL * NQ];
   const int tid = threadIdx.x;
-  const int lc = tid / T;
-  const int e = tid - lc * T;
+  const bool lane_ok = tid < NT;
+  const int lc = lane_ok ? tid / T : 0;
+  const int e = lane_ok ? tid - lc * T : 0;
   const int e0 = e % N1, e1 = e / N1;
-  const int64_t blk = blockIdx.x;
-  const bool lane_ok = lc < CPB;
-  const int64_t cell = blk * CPB + lc;
-  const bool active = lane_ok && cell < n_cells;
-  double* L0 = lds + (lane_ok ? lc : 0) * NQ;
+  const int64_t ord = blockIdx.x;
+  int bi, bj, bz;
+  brick_of_ordinal(bk, ord, bi, bj, bz);
+  int64_t ci, cj, ck;
+  const bool active = lane_ok && cell_of<P>(bi, bj, bz, lc, n, ci, cj, ck);
+  double* L0 = lds + lc * NQ;
   // z-pencil of f*JxW at points (e0, e1, t), tested with S^T in z
   double fz[N1];
   for (int t = 0; t < N1; ++t) {
     double v = 0;
     if (active) {
       QGeo g;
-      qpoint_geometry(n, amp, cell, qr.z[e0], qr.z[e1], qr.z[t], g);
+      qpoint_geometry(n, amp, ci + (int64_t)n * (cj + (int64_t)n * ck), qr.z[e0], qr.z[e1], qr.z[t], g);
       const double* x = g.x;
       double s1[3], c1[3], s2[3], c2[3];
       for (int d = 0; d < 3; ++d) {
@@ -403,10 +443,10 @@ __global__ __launch_bounds__(kBlock) void rhs_kernel(const int* __restrict__ idx
     }
     fz[t] = v;
   }
-  double bz[N1];
-  apply_t<N1>(sh.S, fz, bz);
+  double bzv[N1];
+  apply_t<N1>(sh.S, fz, bzv);
   if (lane_ok)
-    for (int c = 0; c < N1; ++c) L0[e + T * c] = bz[c];
+    for (int c = 0; c < N1; ++c) L0[e + T * c] = bzv[c];
   lds_barrier();
   double by[N1], tmp[N1];
   for (int s = 0; s < N1; ++s) tmp[s] = L0[e0 + N1 * s + T * e1];
@@ -419,9 +459,8 @@ __global__ __launch_bounds__(kBlock) void rhs_kernel(const int* __restrict__ idx
   for (int r = 0; r < N1; ++r) tmp[r] = L0[r + N1 * e];
   apply_t<N1>(sh.S, tmp, bx);
   if (active) {
-    const int* ip = idx + blk * (int64_t)(N1 * NT) + lc * T + e;
     for (int a = 0; a < N1; ++a) {
-      const int g = ip[a * NT];
+      const int g = idx[ord * (int64_t)C::NL + lattice_of<P>(lc, a, e0, e1)];
       if (g >= 0) atomic_add(b + g, bx[a]);
     }
   }
@@ -432,24 +471,24 @@ __global__ __launch_bounds__(kBlock) void rhs_kernel(const int* __restrict__ idx
 // (I-1) + m*((J-1) + m*(K-1)), m = N1-2.  One thread per (cell, i, j).
 template <int P>
 __global__ __launch_bounds__(kBlock) void assemble_dense_kernel(const int* __restrict__ idx, const double* __restrict__ geo,
-                                                                double* __restrict__ mat, int64_t ld, int64_t n_cells,
+                                                                double* __restrict__ mat, int64_t ld, Bricks bk,
                                                                 int64_t N1g, Shape<P, double> sh) {
   using C = Cell<P>;
-  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, CPB = C::CPB, NT = C::NT;
-  const int64_t total = n_cells * NQ * NQ;
+  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NT = C::NT;
+  const int64_t total = bk.n_bricks * C::NCELL * NQ * NQ;
   const int64_t m = N1g - 2;
   for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < total; L += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t cell = L / (NQ * NQ);
-    const int ij = (int)(L - cell * NQ * NQ);
+    const int64_t cellord = L / (NQ * NQ);
+    const int ij = (int)(L - cellord * NQ * NQ);
     const int i = ij / NQ, j = ij - (ij / NQ) * NQ;
-    const int64_t blk = cell / CPB;
-    const int lc = (int)(cell - blk * CPB);
+    const int64_t ord = cellord / C::NCELL;
+    const int lc = (int)(cellord - ord * C::NCELL);
     const int ai = i % N1, bi = (i / N1) % N1, ci = i / T;
     const int aj = j % N1, bj = (j / N1) % N1, cj = j / T;
-    const int gi = idx[blk * (int64_t)(N1 * NT) + ai * NT + lc * T + bi + N1 * ci];
-    const int gj = idx[blk * (int64_t)(N1 * NT) + aj * NT + lc * T + bj + N1 * cj];
-    if (gi < 0 || gj < 0) continue;
-    const Real2<double>* gp = reinterpret_cast<const Real2<double>*>(geo) + blk * (int64_t)(N1 * 3 * NT) + lc * T;
+    const int gi = idx[ord * (int64_t)C::NL + lattice_of<P>(lc, ai, bi, ci)];
+    const int gj = idx[ord * (int64_t)C::NL + lattice_of<P>(lc, aj, bj, cj)];
+    if (gi < 0 || gj < 0) continue;  // Dirichlet or absent
+    const Real2<double>* gp = reinterpret_cast<const Real2<double>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + lc * T;
     double sum = 0;
     for (int t = 0; t < N1; ++t)
       for (int s = 0; s < N1; ++s)
@@ -484,20 +523,18 @@ int grid_for(int64_t work) {
 template <int P>
 hipError_t fill_index_p(const OpView& v, int* idx, hipStream_t st) {
   using C = Cell<P>;
-  fill_index_kernel<P><<<grid_for(v.n_blocks * C::N1 * C::NT), kBlock, 0, st>>>(idx, v.n_cells, v.n_blocks, v.n, v.bc);
+  fill_index_kernel<P><<<grid_for(v.bricks.n_bricks * C::NL), kBlock, 0, st>>>(idx, v.bricks, v.n, v.bc);
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t geometry_p(const OpView& v, int precision, void* geo, hipStream_t st) {
   using C = Cell<P>;
-  const int g = grid_for(v.n_blocks * C::N1 * C::NT);
+  const int g = grid_for(v.bricks.n_bricks * C::N1 * C::NT);
   if (precision == MFQ_FP64)
-    geometry_kernel<P, double><<<g, kBlock, 0, st>>>((double*)geo, v.n_cells, v.n_blocks, v.n, v.amplitude, v.alpha,
-                                                     make_rule<P>());
+    geometry_kernel<P, double><<<g, kBlock, 0, st>>>((double*)geo, v.bricks, v.n, v.amplitude, v.alpha, make_rule<P>());
   else
-    geometry_kernel<P, float><<<g, kBlock, 0, st>>>((float*)geo, v.n_cells, v.n_blocks, v.n, v.amplitude, v.alpha,
-                                                    make_rule<P>());
+    geometry_kernel<P, float><<<g, kBlock, 0, st>>>((float*)geo, v.bricks, v.n, v.amplitude, v.alpha, make_rule<P>());
   return hipGetLastError();
 }
 
@@ -506,49 +543,80 @@ hipError_t geometry_export_p(const OpView& v, int precision, double* out, hipStr
   using C = Cell<P>;
   const int g = grid_for(v.n_cells * C::NQ);
   if (precision == MFQ_FP64)
-    geometry_export_kernel<P, double><<<g, kBlock, 0, st>>>((const double*)v.geo, out, v.n_cells);
+    geometry_export_kernel<P, double><<<g, kBlock, 0, st>>>((const double*)v.geo, out, v.bricks, v.n);
   else
-    geometry_export_kernel<P, float><<<g, kBlock, 0, st>>>((const float*)v.geo, out, v.n_cells);
+    geometry_export_kernel<P, float><<<g, kBlock, 0, st>>>((const float*)v.geo, out, v.bricks, v.n);
+  return hipGetLastError();
+}
+
+// Resident workgroups per CU of a kernel and the device's CU count (cached per device).
+template <typename K>
+int resident_grid(K kernel) {
+  static thread_local int cached_dev = -1, cached = 0;
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) return 0;
+  if (dev == cached_dev) return cached;
+  int cus = 0, per_cu = 0;
+  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
+  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
+  cached_dev = dev;
+  cached = cus * per_cu;
+  return cached;
+}
+
+// Grid for nb bricks: at most one resident wave of workgroups, each taking the same number of bricks.
+inline unsigned balanced_grid(int64_t nb, int resident) {
+  if (resident <= 0 || nb <= resident) return (unsigned)nb;
+  const int64_t per = (nb + resident - 1) / resident;
+  return (unsigned)((nb + per - 1) / per);
+}
+
+template <int P, typename Real>
+hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipStream_t st) {
+  static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
+  for (int c = 0; c < 8; ++c) {
+    const int64_t nb = v.bricks.count[c];
+    if (nb == 0) continue;
+    if (acc)
+      vmult_kernel<P, Real, true><<<(unsigned)nb, kBlock, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
+                                                                   (Real*)dst, v.bricks, c, sh);
+    else
+      vmult_kernel<P, Real, false><<<(unsigned)nb, kBlock, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
+                                                                    (Real*)dst, v.bricks, c, sh);
+  }
   return hipGetLastError();
 }
 
 template <int P>
-hipError_t vmult_p(const OpView& v, int precision, const void* src, void* dst, hipStream_t st) {
-  if (v.n_blocks == 0) return hipSuccess;
-  if (precision == MFQ_FP64)
-    vmult_kernel<P, double><<<(unsigned)v.n_blocks, kBlock, 0, st>>>(v.idx, (const double*)v.geo, (const double*)src,
-                                                                   (double*)dst, v.n_cells, v.n, make_shape<P, double>());
-  else
-    vmult_kernel<P, float><<<(unsigned)v.n_blocks, kBlock, 0, st>>>(v.idx, (const float*)v.geo, (const float*)src,
-                                                                  (float*)dst, v.n_cells, v.n, make_shape<P, float>());
-  return hipGetLastError();
+hipError_t vmult_p(const OpView& v, int precision, const void* src, void* dst, bool acc, hipStream_t st) {
+  if (precision == MFQ_FP64) return vmult_pr<P, double>(v, src, dst, acc, st);
+  return vmult_pr<P, float>(v, src, dst, acc, st);
 }
 
 template <int P>
 hipError_t diagonal_p(const OpView& v, int precision, void* diag, hipStream_t st) {
-  if (v.n_blocks == 0) return hipSuccess;
+  const unsigned g = (unsigned)v.bricks.n_bricks;
   if (precision == MFQ_FP64)
-    diagonal_kernel<P, double><<<(unsigned)v.n_blocks, kBlock, 0, st>>>(v.idx, (const double*)v.geo, (double*)diag,
-                                                                      v.n_cells, make_shape<P, double>());
+    diagonal_kernel<P, double><<<g, kBlock, 0, st>>>(v.idx, (const double*)v.geo, (double*)diag, v.bricks,
+                                                     make_shape<P, double>());
   else
-    diagonal_kernel<P, float><<<(unsigned)v.n_blocks, kBlock, 0, st>>>(v.idx, (const float*)v.geo, (float*)diag,
-                                                                     v.n_cells, make_shape<P, float>());
+    diagonal_kernel<P, float><<<g, kBlock, 0, st>>>(v.idx, (const float*)v.geo, (float*)diag, v.bricks,
+                                                    make_shape<P, float>());
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t rhs_p(const OpView& v, double* b, hipStream_t st) {
-  if (v.n_blocks == 0) return hipSuccess;
-  rhs_kernel<P><<<(unsigned)v.n_blocks, kBlock, 0, st>>>(v.idx, b, v.n_cells, v.n, v.amplitude, v.alpha,
-                                                         make_shape<P, double>(), make_rule<P>());
+  rhs_kernel<P><<<(unsigned)v.bricks.n_bricks, kBlock, 0, st>>>(v.idx, b, v.bricks, v.n, v.amplitude, v.alpha,
+                                                                make_shape<P, double>(), make_rule<P>());
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t assemble_dense_p(const OpView& v, double* mat, int64_t ld, hipStream_t st) {
   using C = Cell<P>;
-  assemble_dense_kernel<P><<<grid_for(v.n_cells * C::NQ * C::NQ), kBlock, 0, st>>>(
-      v.idx, (const double*)v.geo, mat, ld, v.n_cells, (int64_t)P * v.n + 1, make_shape<P, double>());
+  assemble_dense_kernel<P><<<grid_for(v.bricks.n_bricks * C::NCELL * C::NQ * C::NQ), kBlock, 0, st>>>(
+      v.idx, (const double*)v.geo, mat, ld, v.bricks, (int64_t)P * v.n + 1, make_shape<P, double>());
   return hipGetLastError();
 }
 
@@ -577,8 +645,9 @@ hipError_t launch_geometry_export(const OpView& v, int precision, double* out, h
   MFQ_DISPATCH(v.p, geometry_export_p, v, precision, out, st);
 }
 
-hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, void* dst, hipStream_t st) {
-  MFQ_DISPATCH(v.p, vmult_p, v, precision, src, dst, st);
+hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, void* dst, bool accumulate,
+                              hipStream_t st) {
+  MFQ_DISPATCH(v.p, vmult_p, v, precision, src, dst, accumulate, st);
 }
 
 hipError_t launch_diagonal_cells(const OpView& v, int precision, void* diag, hipStream_t st) {

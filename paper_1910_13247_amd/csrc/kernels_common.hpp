@@ -6,8 +6,13 @@
 #include <cstdint>
 
 #include "mfq_internal.hpp"
+#include "tables_ct.hpp"
 
 namespace mfq {
+
+// fused multiply-add in the operand's own precision (no promotion of float to double)
+__device__ __forceinline__ double fmad(double a, double b, double c) { return __builtin_fma(a, b, c); }
+__device__ __forceinline__ float fmad(float a, float b, float c) { return __builtin_fmaf(a, b, c); }
 
 // 1D shape tables at the Gauss points, S[q*(P+1)+a] = l_a(zeta_q), D[q*(P+1)+a] = l_a'(zeta_q).
 // Passed by value as a kernel argument: with fully unrolled loops every entry is a
@@ -19,26 +24,154 @@ struct Shape {
 };
 
 template <int P, typename Real>
-Shape<P, Real> make_shape() {
-  Shape<P, Real> sh;
-  const Tables1D& t = tables(P);
+constexpr Shape<P, Real> make_shape() {
+  Shape<P, Real> sh{};
   for (int k = 0; k < (P + 1) * (P + 1); ++k) {
-    sh.S[k] = (Real)t.S[k];
-    sh.D[k] = (Real)t.D[k];
+    sh.S[k] = (Real)ct::kTab<P>.S[k];
+    sh.D[k] = (Real)ct::kTab<P>.D[k];
   }
   return sh;
 }
 
-// Compile-time geometry of the cell kernels: one thread per 1D pencil ((P+1)^2 per cell),
-// CPB cells per 256-lane workgroup, NT lanes carry work (the rest idle).
+// Even-odd form of a 1D table M (N1 x N1) with M[N1-1-q][N1-1-a] = sgn M[q][a]: S is symmetric
+// and D antisymmetric under this reflection because the nodes and the Gauss points are symmetric
+// about 1/2.  With e_k = x_k + x_{N1-1-k}, o_k = x_k - x_{N1-1-k} (k < H = N1/2):
+//   y_q = E_q + O_q,  y_{N1-1-q} = sgn (E_q - O_q),  E_q = sum_k A[q][k] e_k (+ mc[q] x_H),
+//   O_q = sum_k B[q][k] o_k, A = (M[q][k] + M[q][N1-1-k])/2, B = (M[q][k] - M[q][N1-1-k])/2, and
+//   for odd N1 the middle row y_H = sum_k mr[k] e_k + cc x_H (sgn +1) or sum_k mr[k] o_k (sgn -1).
+// The transpose reuses the same numbers (A^T, B^T, mid row <-> mid column; A and B swap for the
+// antisymmetric table), so one set of about N1^2/2 constants per table serves both directions:
+// few enough to stay in scalar registers for p <= 5 in FP64.
+template <int N1, typename Real>
+struct EvenOdd {
+  static constexpr int H = N1 / 2;
+  Real A[H * H];
+  Real B[H * H];
+  Real mc[H];
+  Real mr[H];
+  Real cc;
+};
+
+template <int P, typename Real>
+struct ShapeEO {
+  EvenOdd<P + 1, Real> S, D;
+};
+
+template <int N1, typename Real>
+EvenOdd<N1, Real> make_even_odd(const double* M) {
+  EvenOdd<N1, Real> t{};
+  constexpr int H = N1 / 2;
+  for (int q = 0; q < H; ++q)
+    for (int k = 0; k < H; ++k) {
+      t.A[q * H + k] = (Real)(0.5 * (M[q * N1 + k] + M[q * N1 + N1 - 1 - k]));
+      t.B[q * H + k] = (Real)(0.5 * (M[q * N1 + k] - M[q * N1 + N1 - 1 - k]));
+    }
+  if (N1 % 2 == 1) {
+    for (int q = 0; q < H; ++q) {
+      t.mc[q] = (Real)M[q * N1 + H];
+      t.mr[q] = (Real)M[H * N1 + q];
+    }
+    t.cc = (Real)M[H * N1 + H];
+  }
+  return t;
+}
+
+template <int P, typename Real>
+ShapeEO<P, Real> make_shape_eo() {
+  ShapeEO<P, Real> s;
+  s.S = make_even_odd<P + 1, Real>(ct::kTab<P>.S);
+  s.D = make_even_odd<P + 1, Real>(ct::kTab<P>.D);
+  return s;
+}
+
+// y = M x (TR = false) or y = M^T x (TR = true) for a table in even-odd form; SGN = +1 for S,
+// -1 for D.
+template <int N1, int SGN, bool TR, typename Real>
+__device__ __forceinline__ void eo_apply(const EvenOdd<N1, Real>& m, const Real (&x)[N1], Real (&y)[N1]) {
+  constexpr int H = N1 / 2;
+  constexpr bool odd = (N1 % 2) == 1;
+  Real e[H > 0 ? H : 1], o[H > 0 ? H : 1];
+#pragma unroll
+  for (int k = 0; k < H; ++k) {
+    e[k] = x[k] + x[N1 - 1 - k];
+    o[k] = x[k] - x[N1 - 1 - k];
+  }
+#pragma unroll
+  for (int q = 0; q < H; ++q) {
+    Real E = 0, O = 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) {
+      const Real a = !TR ? m.A[q * H + k] : (SGN > 0 ? m.A[k * H + q] : m.B[k * H + q]);
+      const Real b = !TR ? m.B[q * H + k] : (SGN > 0 ? m.B[k * H + q] : m.A[k * H + q]);
+      E = fmad(a, e[k], E);
+      O = fmad(b, o[k], O);
+    }
+    if constexpr (odd) E = fmad(TR ? m.mr[q] : m.mc[q], x[H], E);
+    y[q] = E + O;
+    y[N1 - 1 - q] = SGN > 0 ? E - O : O - E;
+  }
+  if constexpr (odd) {
+    Real s = 0;
+#pragma unroll
+    for (int k = 0; k < H; ++k) s = fmad(TR ? m.mc[k] : m.mr[k], SGN > 0 ? e[k] : o[k], s);
+    if constexpr (SGN > 0) s = fmad(m.cc, x[H], s);
+    y[H] = s;
+  }
+}
+
+// y = S^T x1 + D^T x2 in even-odd form
+template <int N1, typename Real>
+__device__ __forceinline__ void eo_apply_t2(const EvenOdd<N1, Real>& S, const Real (&x1)[N1],
+                                            const EvenOdd<N1, Real>& D, const Real (&x2)[N1], Real (&y)[N1]) {
+  Real y1[N1], y2[N1];
+  eo_apply<N1, 1, true>(S, x1, y1);
+  eo_apply<N1, -1, true>(D, x2, y2);
+#pragma unroll
+  for (int a = 0; a < N1; ++a) y[a] = y1[a] + y2[a];
+}
+
+// Compile-time geometry of the cell kernels: one workgroup per brick of BX*BY*BZ cells, one
+// lane per 1D pencil of a cell (T = (P+1)^2 lanes per cell, NT lanes carry work), and the brick's
+// node lattice LX*LY*LZ (shared nodes of neighbouring cells appear once).
 template <int P>
 struct Cell {
   static constexpr int N1 = P + 1;
   static constexpr int T = N1 * N1;
   static constexpr int NQ = N1 * T;
-  static constexpr int CPB = kBlock / T;
-  static constexpr int NT = CPB * T;
+  static constexpr BrickDims BD = brick_dims(P);
+  static constexpr int BX = BD.bx, BY = BD.by, BZ = BD.bz;
+  static constexpr int NCELL = BX * BY * BZ;
+  static constexpr int NT = NCELL * T;
+  static constexpr int LX = BX * P + 1, LY = BY * P + 1, LZ = BZ * P + 1;
+  static constexpr int NL = LX * LY * LZ;
+  static_assert(NT <= kBlock, "a brick must fit one workgroup");
 };
+
+// Brick coordinates of brick `b` of colour `c` (colour = parity of x + 2*y + 4*z brick indices).
+__host__ __device__ inline void brick_of(const Bricks& bk, int c, int64_t b64, int& bi, int& bj, int& bz) {
+  const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
+  const unsigned b = (unsigned)b64, cxn = (unsigned)bk.cxn[c], cyn = (unsigned)bk.cyn[c];
+  const unsigned q = b / cxn;
+  bi = 2 * (int)(b - q * cxn) + px;
+  bj = 2 * (int)(q % cyn) + py;
+  bz = 2 * (int)(q / cyn) + pz;
+}
+
+// Colour and brick coordinates of a storage ordinal (colour-major order).
+__host__ __device__ inline void brick_of_ordinal(const Bricks& bk, int64_t ord, int& bi, int& bj, int& bz) {
+  int c = 0;
+  while (c < 7 && ord >= bk.offset[c] + bk.count[c]) ++c;
+  brick_of(bk, c, ord - bk.offset[c], bi, bj, bz);
+}
+
+// Storage ordinal of the brick holding cell (ci, cj, ck), and the cell's index inside it.
+__host__ __device__ inline int64_t ordinal_of_cell(const Bricks& bk, int64_t ci, int64_t cj, int64_t ck, int& lc) {
+  const int bi = (int)(ci / bk.bx), bj = (int)(cj / bk.by), bz = (int)(ck / bk.bz);
+  lc = (int)(ci - (int64_t)bi * bk.bx) + bk.bx * ((int)(cj - (int64_t)bj * bk.by) + bk.by * (int)(ck - (int64_t)bz * bk.bz));
+  const int c = (bi & 1) + 2 * (bj & 1) + 4 * (bz & 1);
+  const int64_t cxn = (bk.nbx + 1 - (c & 1)) / 2, cyn = (bk.nby + 1 - ((c >> 1) & 1)) / 2;
+  return bk.offset[c] + (bi / 2) + cxn * ((bj / 2) + cyn * (int64_t)(bz / 2));
+}
 
 // Workgroup barrier that orders LDS only: global loads issued before it stay in flight.
 __device__ __forceinline__ void lds_barrier() {
@@ -57,7 +190,7 @@ __device__ __forceinline__ void apply(const Real* M, const Real (&in)[N1], Real 
   for (int q = 0; q < N1; ++q) {
     Real s = M[q * N1] * in[0];
 #pragma unroll
-    for (int a = 1; a < N1; ++a) s = __builtin_fma(M[q * N1 + a], in[a], s);
+    for (int a = 1; a < N1; ++a) s = fmad(M[q * N1 + a], in[a], s);
     out[q] = s;
   }
 }
@@ -69,7 +202,7 @@ __device__ __forceinline__ void apply_t(const Real* M, const Real (&in)[N1], Rea
   for (int a = 0; a < N1; ++a) {
     Real s = M[a] * in[0];
 #pragma unroll
-    for (int q = 1; q < N1; ++q) s = __builtin_fma(M[q * N1 + a], in[q], s);
+    for (int q = 1; q < N1; ++q) s = fmad(M[q * N1 + a], in[q], s);
     out[a] = s;
   }
 }
@@ -81,11 +214,11 @@ __device__ __forceinline__ void apply_t2(const Real* M1, const Real (&in1)[N1], 
 #pragma unroll
   for (int a = 0; a < N1; ++a) {
     Real s = M1[a] * in1[0];
-    s = __builtin_fma(M2[a], in2[0], s);
+    s = fmad(M2[a], in2[0], s);
 #pragma unroll
     for (int q = 1; q < N1; ++q) {
-      s = __builtin_fma(M1[q * N1 + a], in1[q], s);
-      s = __builtin_fma(M2[q * N1 + a], in2[q], s);
+      s = fmad(M1[q * N1 + a], in1[q], s);
+      s = fmad(M2[q * N1 + a], in2[q], s);
     }
     out[a] = s;
   }

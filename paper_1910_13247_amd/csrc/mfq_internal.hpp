@@ -37,17 +37,92 @@ struct Tables1D {
 };
 const Tables1D& tables(int p);
 std::vector<double> gll_points(int p);
-void gauss_points(int nq, std::vector<double>& x, std::vector<double>& w);
 double lagrange_value(const std::vector<double>& nodes, int a, double t);
 double lagrange_derivative(const std::vector<double>& nodes, int a, double t);
 // 1D transfer matrix [nf1][pc+1]: coarse basis (degree pc) at the fine nodes lying in one coarse
 // cell: h-transfer (fine degree pc, two fine cells) when h_transfer, else the GLL nodes of pf.
 std::vector<double> transfer_matrix_1d(int pc, int pf, bool h_transfer, int* nf1);
 
-// Kernel geometry of the cell kernels: (p+1)^2 threads per cell, cells packed into 256 lanes.
+// Work decomposition of the cell kernels: one workgroup per brick of bx*by*bz cells, one lane per
+// 1D pencil of a cell ((p+1)^2 lanes per cell).  Bricks are coloured by the parities of their
+// brick coordinates; bricks of one colour share no node, so a colour is one launch whose
+// workgroups write their brick's nodes without atomics, and colours run in order 0..7.
+struct BrickDims {
+  int bx, by, bz;
+};
+// Brick shapes (cells in x, y, z); a build can override one degree, e.g. -DMFQ_BRICK_P4=4,2,1.
+#ifndef MFQ_BRICK_P1
+#define MFQ_BRICK_P1 4, 4, 4
+#endif
+#ifndef MFQ_BRICK_P2
+#define MFQ_BRICK_P2 3, 3, 3
+#endif
+#ifndef MFQ_BRICK_P3
+#define MFQ_BRICK_P3 4, 2, 2
+#endif
+#ifndef MFQ_BRICK_P4
+#define MFQ_BRICK_P4 2, 2, 2
+#endif
+#ifndef MFQ_BRICK_P5
+#define MFQ_BRICK_P5 3, 2, 1
+#endif
+#ifndef MFQ_BRICK_P6
+#define MFQ_BRICK_P6 2, 2, 1
+#endif
+#ifndef MFQ_BRICK_P7
+#define MFQ_BRICK_P7 2, 2, 1
+#endif
+#ifndef MFQ_BRICK_P8
+#define MFQ_BRICK_P8 3, 1, 1
+#endif
+constexpr BrickDims brick_dims(int p) {
+  return p == 1 ? BrickDims{MFQ_BRICK_P1} : p == 2 ? BrickDims{MFQ_BRICK_P2} : p == 3 ? BrickDims{MFQ_BRICK_P3}
+       : p == 4 ? BrickDims{MFQ_BRICK_P4} : p == 5 ? BrickDims{MFQ_BRICK_P5} : p == 6 ? BrickDims{MFQ_BRICK_P6}
+       : p == 7 ? BrickDims{MFQ_BRICK_P7} : BrickDims{MFQ_BRICK_P8};
+}
 inline int threads_per_cell(int p) { return (p + 1) * (p + 1); }
-inline int cells_per_block(int p) { return kBlock / threads_per_cell(p); }
-inline int lanes_per_block(int p) { return cells_per_block(p) * threads_per_cell(p); }
+inline int cells_per_brick(int p) {
+  const BrickDims b = brick_dims(p);
+  return b.bx * b.by * b.bz;
+}
+inline int lanes_per_brick(int p) { return cells_per_brick(p) * threads_per_cell(p); }
+inline int64_t lattice_per_brick(int p) {
+  const BrickDims b = brick_dims(p);
+  return (int64_t)(b.bx * p + 1) * (b.by * p + 1) * (b.bz * p + 1);
+}
+
+// Brick grid of a mesh: bricks per direction, bricks per colour and the first brick ordinal of
+// each colour (storage of per-brick data is colour-major, so each launch streams a contiguous range).
+struct Bricks {
+  int bx, by, bz;
+  int nbx, nby, nbz;
+  int cxn[8], cyn[8];  // bricks of colour c along x and y
+  int64_t count[8];
+  int64_t offset[8];
+  int64_t n_bricks;
+};
+inline Bricks make_bricks(int p, int n) {
+  Bricks b{};
+  const BrickDims d = brick_dims(p);
+  b.bx = d.bx;
+  b.by = d.by;
+  b.bz = d.bz;
+  b.nbx = (n + d.bx - 1) / d.bx;
+  b.nby = (n + d.by - 1) / d.by;
+  b.nbz = (n + d.bz - 1) / d.bz;
+  int64_t off = 0;
+  for (int c = 0; c < 8; ++c) {
+    const int cx = (b.nbx + 1 - (c & 1)) / 2, cy = (b.nby + 1 - ((c >> 1) & 1)) / 2,
+              cz = (b.nbz + 1 - (c >> 2)) / 2;
+    b.cxn[c] = cx;
+    b.cyn[c] = cy;
+    b.count[c] = (int64_t)cx * cy * cz;
+    b.offset[c] = off;
+    off += b.count[c];
+  }
+  b.n_bricks = off;
+  return b;
+}
 
 }  // namespace mfq
 
@@ -69,11 +144,12 @@ struct mfq_op {
   const mfq_space* space;
   double alpha;
   int precision;
-  int64_t n_blocks;
+  mfq::Bricks bricks;
   size_t idx_bytes, geo_bytes;
   void* buf = nullptr;        // caller-owned device memory
-  int* idx = nullptr;         // [n_blocks][p+1][lanes] global DoF, ~g on Dirichlet nodes
-  void* geo = nullptr;        // [n_blocks][p+1][3][lanes][2] of the precision's type
+  int* idx = nullptr;         // [n_bricks][lattice]: global node of each brick-lattice node,
+                              // ~g on Dirichlet nodes, INT_MIN outside the mesh
+  void* geo = nullptr;        // [n_bricks][p+1][3][lanes][2] of the precision's type
 };
 
 struct mfq_transfer {
@@ -89,23 +165,26 @@ namespace mfq {
 // Plain-struct view of an operator handed to launchers.
 struct OpView {
   int p, n, bc;
-  int64_t n_cells, n_blocks, n_dofs;
+  int64_t n_cells, n_dofs;
   double amplitude, alpha;
+  Bricks bricks;
   const int* idx;
   const void* geo;
 };
 inline OpView view(const mfq_op* op) {
   const mfq_space* s = op->space;
-  return OpView{s->p, s->mesh->n, s->bc, s->n_cells, op->n_blocks, s->n_dofs,
-                s->mesh->amplitude, op->alpha, op->idx, op->geo};
+  return OpView{s->p, s->mesh->n, s->bc, s->n_cells, s->n_dofs, s->mesh->amplitude, op->alpha, op->bricks,
+                op->idx, op->geo};
 }
 
 // ---------------------------------------------------------------- launchers (kernels_*.hip)
 hipError_t launch_fill_index(const OpView& v, int* idx, hipStream_t st);
 hipError_t launch_geometry(const OpView& v, int precision, void* geo, hipStream_t st);
 hipError_t launch_geometry_export(const OpView& v, int precision, double* out, hipStream_t st);
-// Cell-loop parts (they add into dst/diag/b, which the callers zero first).
-hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, void* dst, hipStream_t st);
+// dst = A src (accumulate = false: every node written, no clearing needed) or dst += A src.
+hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, void* dst, bool accumulate,
+                              hipStream_t st);
+// Setup-time cell loops (they add into diag/b/mat, which the callers zero first).
 hipError_t launch_diagonal_cells(const OpView& v, int precision, void* diag, hipStream_t st);
 hipError_t launch_rhs_cells(const OpView& v, double* b, hipStream_t st);
 hipError_t launch_assemble_dense(const OpView& v, double* mat, int64_t ld, hipStream_t st);

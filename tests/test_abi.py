@@ -50,10 +50,10 @@ def test_host_validation_errors():
         lib.mfq_op_create(s, 0.5, 5)
     op = lib.mfq_op_create(s, 0.5, 0)
     nbytes = lib.mfq_op_device_bytes(op)
-    # index map (p+1)*256-lane blocks of int32 plus 6 doubles per quadrature point
-    cpb = 256 // 25
-    nblk = -(-64 // cpb)
-    assert nbytes >= nblk * 5 * 250 * 4 + nblk * 5 * 3 * 250 * 2 * 8
+    # 2x2x2-cell bricks at p=4: a 9^3 int32 node lattice per brick plus 6 doubles per quadrature point
+    nbricks = 2 * 2 * 2
+    rnd = lambda b: -(-b // 256) * 256
+    assert nbytes == rnd(nbricks * 9 ** 3 * 4) + rnd(nbricks * 8 * 125 * 6 * 8)
     with pytest.raises(lib.MfqError) as e:
         lib.mfq_vmult(op, 256, 512, None)   # unbound operator: rejected before any launch
     assert e.value.status == lib.MFQ_EINVAL
