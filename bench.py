@@ -8,7 +8,7 @@ DoFs/s of the step, the roofline of the dominant kernel (the cell loop, timed wi
 on its stream), an FP32 figure of the same operator, and the CPU oracle on a bounded sample of
 the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--solves]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--solves] [--copy-probe]
 """
 import argparse
 import json
@@ -21,6 +21,38 @@ sys.path.insert(0, ROOT)
 
 METRIC = "DoFs/s matrix-free vmult FP64 vs FP32; solves/s + p99 latency at 1e-10"
 HBM_PEAK_GBS = 8000.0
+# sources that define the cell-loop kernel; HBM counter figures are used only while they match
+KERNEL_SOURCES = ["paper_1910_13247_amd/csrc/kernels_cell.hip", "paper_1910_13247_amd/csrc/kernels_common.hpp",
+                  "paper_1910_13247_amd/csrc/mfq_internal.hpp", "paper_1910_13247_amd/csrc/tables_ct.hpp"]
+TRAFFIC_PROFILE = "profiles/vmult_q4_64_fp64_hbm_counters.md"
+
+
+def kernel_source_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in KERNEL_SOURCES:
+        with open(os.path.join(ROOT, f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic():
+    """HBM bytes per cell-loop launch from the committed counter summary (FETCH_SIZE + WRITE_SIZE,
+    each scaled by a copy kernel's reading), or None when the kernel changed since it was taken."""
+    path = os.path.join(ROOT, TRAFFIC_PROFILE)
+    if not os.path.exists(path):
+        return None
+    fields = {}
+    for line in open(path):
+        if ":" in line and line.startswith("- "):
+            k, v = line[2:].split(":", 1)
+            fields[k.strip()] = v.strip().strip("`")
+    if fields.get("kernel source sha256/16") != kernel_source_hash():
+        return None
+    try:
+        return float(fields["hbm bytes per launch"])
+    except (KeyError, ValueError):
+        return None
 
 
 def algorithmic_bytes(p, n, real_bytes):
@@ -37,7 +69,7 @@ def algorithmic_flops(p, n):
 
 
 def time_vmult(op, x, steps, warmup):
-    """(wall s per step for clear+cell loop, event-timed s per cell-loop kernel)."""
+    """(wall s per step, event-timed s of the cell-loop launches of one step)."""
     import torch
     y = op.new_vector()
     for _ in range(warmup):
@@ -48,7 +80,8 @@ def time_vmult(op, x, steps, warmup):
         op.vmult(x, y)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    # dominant kernel alone: back-to-back cell-loop launches (accumulating) between two events
+    # dominant kernel alone: back-to-back cell-loop launches (accumulating) between two events on
+    # the stream they are launched on (torch's current stream)
     acc = torch.zeros_like(y)
     op.vmult_add(x, acc)
     e0 = torch.cuda.Event(enable_timing=True)
@@ -120,6 +153,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solves", action="store_true", help="add time-to-1e-10 of the Q3 128^3 solvers")
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run 3 plain device copies of 1 GiB (reference reading for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how it "
@@ -152,9 +187,14 @@ def main():
     torch.cuda.synchronize()
 
     N = space.n_dofs
+    lay = op64.layout()
+    launches = lay["launches"]
     bytes64 = algorithmic_bytes(p, n, 8)
     bytes32 = algorithmic_bytes(p, n, 4)
-    achieved = bytes64 / kern64 / 1e9
+    # per launch: the colours split the cells evenly on this mesh (64 rows of bricks per direction)
+    per_launch64 = bytes64 / launches
+    launch_s = kern64 / launches
+    achieved = per_launch64 / launch_s / 1e9
     rec = {
         "metric": METRIC,
         "value": N / wall64,
@@ -172,14 +212,23 @@ def main():
                    "degree": p, "cells": space.n_cells, "dofs": N, "amplitude": pr.amplitude, "alpha": pr.alpha,
                    "input": "uniform[-1,1) seed 0, resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
-                     "kernel": "vmult_kernel<4,double> (cell loop)", "kernel_ms": kern64 * 1e3,
-                     "algorithmic_bytes": bytes64,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
+                     "kernel": "vmult_kernel<4,double,true> (cell loop)", "launches_per_step": launches,
+                     "launch_ms": launch_s * 1e3, "algorithmic_bytes_per_launch": per_launch64,
+                     "layout": lay, "kernel_source": kernel_source_hash(),
                      "algorithmic_tflops": algorithmic_flops(p, n) / kern64 / 1e12},
-        "fp32": {"value": N / wall32, "unit": "DoFs/s", "ms_per_step": wall32 * 1e3, "kernel_ms": kern32 * 1e3,
+        "fp32": {"value": N / wall32, "unit": "DoFs/s", "ms_per_step": wall32 * 1e3, "cell_loop_ms": kern32 * 1e3,
                  "achieved_GBs": bytes32 / kern32 / 1e9, "frac": bytes32 / kern32 / 1e9 / HBM_PEAK_GBS,
                  "normwise_rel_err_vs_fp64": rel32},
     }
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").uniform_()
+        b = torch.empty_like(a)
+        for _ in range(3):
+            b.copy_(a)
+        torch.cuda.synchronize()
+        rec["copy_probe_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
+        del a, b
     if args.solves:
         rec["solves_q3_128"] = solve_benchmarks(args.steps)
     if not args.no_cpu_baseline:

@@ -111,8 +111,19 @@ int mfq_vmult(const mfq_op* op, const void* src, void* dst, void* hip_stream);
 
 /* dst += A src (same operator, Dirichlet rows add src): the cell loop alone, without clearing dst.
  * Both are deterministic (fixed summation order, no atomics): equal inputs give bitwise equal
- * outputs.  Eight launches on the stream (one per brick colour). */
+ * outputs.  One launch per non-empty colour of the work decomposition (mfq_op_get_layout). */
 int mfq_vmult_add(const mfq_op* op, const void* src, void* dst, void* hip_stream);
+
+/* Work decomposition of the cell loop, for callers that time or profile it: the mesh is cut into
+ * bricks of brick[0] x brick[1] x brick[2] cells, one workgroup each; `launches` kernel launches
+ * (one per non-empty brick colour) make one mfq_vmult or mfq_vmult_add, with `workgroups`
+ * workgroups (bricks) over all of them.  Host only; valid before mfq_op_bind. */
+typedef struct {
+  int brick[3];
+  int launches;
+  int64_t workgroups;
+} mfq_op_layout;
+int mfq_op_get_layout(const mfq_op* op, mfq_op_layout* out);
 
 /* diag = diagonal of A (1 on Dirichlet rows), computed matrix-free from the same quadrature. */
 int mfq_op_diagonal(const mfq_op* op, void* diag, void* hip_stream);

@@ -105,6 +105,10 @@ class Operator:
                        _check_vec(dst, self.n_dofs, self.precision, "dst"), _stream(stream))
         return dst
 
+    def layout(self):
+        """Work decomposition of the cell loop: brick shape, launches per vmult, workgroups."""
+        return _lib.mfq_op_get_layout(self.handle)
+
     def vmult_add(self, src, dst, stream=None):
         _lib.mfq_vmult_add(self.handle, _check_vec(src, self.n_dofs, self.precision, "src"),
                            _check_vec(dst, self.n_dofs, self.precision, "dst"), _stream(stream))

@@ -31,6 +31,10 @@ class SolverParams(C.Structure):
                 ("n_lambda_override", C.c_int), ("lambda_override", C.POINTER(C.c_double))]
 
 
+class OpLayout(C.Structure):
+    _fields_ = [("brick", C.c_int * 3), ("launches", C.c_int), ("workgroups", C.c_int64)]
+
+
 class SolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int), ("outer_iterations", C.c_int), ("rel_residual", C.c_double),
                 ("seconds", C.c_double), ("n_levels", C.c_int)]
@@ -62,6 +66,7 @@ _SIGS = {
     "mfq_op_bind": ([P, P, SZ, P], I),
     "mfq_vmult": ([P, P, P, P], I),
     "mfq_vmult_add": ([P, P, P, P], I),
+    "mfq_op_get_layout": ([P, C.POINTER(OpLayout)], I),
     "mfq_op_diagonal": ([P, P, P], I),
     "mfq_op_geometry": ([P, P, P], I),
     "mfq_rhs_manufactured": ([P, P, P], I),
@@ -182,6 +187,13 @@ def mfq_vmult(op, src, dst, stream):
 
 def mfq_vmult_add(op, src, dst, stream):
     _check(lib().mfq_vmult_add(op, src, dst, stream))
+
+
+def mfq_op_get_layout(op):
+    """Work decomposition of the cell loop as a dict (brick, launches, workgroups)."""
+    r = OpLayout()
+    _check(lib().mfq_op_get_layout(op, C.byref(r)))
+    return {"brick": tuple(r.brick), "launches": r.launches, "workgroups": r.workgroups}
 
 
 def mfq_op_diagonal(op, diag, stream):

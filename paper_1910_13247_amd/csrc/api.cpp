@@ -130,6 +130,21 @@ int mfq_op_device_bytes(const mfq_op* op, size_t* bytes) {
   return MFQ_OK;
 }
 
+int mfq_op_get_layout(const mfq_op* op, mfq_op_layout* out) {
+  if (!op || !out) return fail(MFQ_EINVAL, "op or out is NULL");
+  const Bricks& b = op->bricks;
+  mfq_op_layout r{};
+  r.brick[0] = b.bx;
+  r.brick[1] = b.by;
+  r.brick[2] = b.bz;
+  for (int c = 0; c < kColours; ++c) {
+    r.launches += b.count[c] > 0 ? 1 : 0;
+    r.workgroups += b.count[c];
+  }
+  *out = r;
+  return MFQ_OK;
+}
+
 int mfq_op_bind(mfq_op* op, void* dev_buf, size_t bytes, void* hip_stream) {
   if (!op) return fail(MFQ_EINVAL, "op is NULL");
   if (!dev_buf || !aligned(dev_buf, 256)) return fail(MFQ_EINVAL, "buffer NULL or not 256-byte aligned");

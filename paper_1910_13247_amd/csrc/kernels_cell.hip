@@ -8,8 +8,8 @@
 // factorisation), add into the result.
 //
 // Work decomposition (MI355X-first):
-//  * one workgroup per brick of cells (e.g. 2x2x2 at p=4), one lane per 1D pencil of a cell,
-//    each lane contracting its pencil in registers; pencils change direction through LDS.
+//  * one workgroup per brick of cells (e.g. 5x2x1 at p=4), one lane per 1D pencil of a
+//    cell, each lane contracting its pencil in registers; pencils change direction through LDS.
 //    Gradients are formed from the 1D value and derivative tables in the order x (S, D) ->
 //    y (S, D on the S-branch) -> z, so all three components arrive at the same lane and
 //    quadrature point without extra transposes; the backward pass is the exact transpose.
@@ -169,6 +169,10 @@ __global__ __launch_bounds__(kBlock) void geometry_export_kernel(const Real* __r
 // One launch per colour, one workgroup per brick; ACC adds A src into dst instead of overwriting
 // it.  Lanes beyond the brick's pencils work on a spare LDS slot so no branch is needed around
 // LDS stores or loads (their results are never read).
+//
+// A lattice node shared with neighbouring bricks is written by each of them, each in its own
+// launch: the brick that is even in every direction in which the node is shared stores (its colour
+// comes first), the others add to what is there.
 template <int P, typename Real, bool ACC>
 __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
                                                        const Real* __restrict__ src, Real* __restrict__ dst, Bricks bk,
@@ -176,38 +180,51 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
   using C = Cell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NCELL = C::NCELL, NT = C::NT, LX = C::LX, LY = C::LY, NL = C::NL;
   constexpr int KPT = (NL + kBlock - 1) / kBlock;  // lattice nodes per thread
-  __shared__ Real lds[(NCELL + 1) * 3 * NQ];
+  constexpr int SLOT = (NCELL + 1) * NQ;           // one array per cell plus the spare slot
+  constexpr int L2SZ = SLOT > KPT * kBlock ? SLOT : KPT * kBlock;
   // cell arrays stored array-major: [L0 of every cell][L1 ...][L2 ...]; the node lattice is only
-  // read before the first write of an L2 array, so it lives in the L2 block
-  static_assert(KPT * kBlock <= (NCELL + 1) * NQ, "lattice must fit the L2 block");
-  Real* const lat = lds + 2 * (NCELL + 1) * NQ;
+  // read before the first write of an L2 array, so it shares the L2 block
+  __shared__ Real lds[2 * SLOT + L2SZ];
+  Real* const lat = lds + 2 * SLOT;
 
   const int tid = threadIdx.x;
   const bool lane_ok = tid < NT;
-  const int lc = lane_ok ? tid / T : NCELL;           // spare slot for the idle lanes
+  const int lc = lane_ok ? tid / T : NCELL;  // spare slot for the idle lanes
   const int e = lane_ok ? tid - lc * T : (tid - NT) % T;
   const int e0 = e % N1, e1 = e / N1;
+  const int cl = lc < NCELL ? lc : 0;
+  const int cx = cl % C::BX, cy = (cl / C::BX) % C::BY, cz = cl / (C::BX * C::BY);
   const int64_t ord = bk.offset[colour] + blockIdx.x;
   int bi, bj, bz;
   brick_of(bk, colour, blockIdx.x, bi, bj, bz);
   Real* L0 = lds + lc * NQ;
-  Real* L1 = L0 + (NCELL + 1) * NQ;
-  Real* L2 = L1 + (NCELL + 1) * NQ;
+  Real* L1 = L0 + SLOT;
+  Real* L2 = L1 + SLOT;
 
-  // quadrature-point tensors of this lane's z-pencil (points (e0, e1, t)), issued first
-  const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + (lane_ok ? tid : 0);
+  // quadrature-point tensors of this lane's z-pencil (points (e0, e1, t)), issued first; lanes
+  // of cells outside the mesh (ragged last bricks) load nothing
   Real2<Real> g[N1][3];
+  {
+    const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + tid;
+    if (lane_ok && bi * C::BX + cx < bk.n && bj * C::BY + cy < bk.n && bz * C::BZ + cz < bk.n) {
 #pragma unroll
-  for (int t = 0; t < N1; ++t)
+      for (int t = 0; t < N1; ++t)
 #pragma unroll
-    for (int m = 0; m < 3; ++m) g[t][m] = __builtin_nontemporal_load(gp + (t * 3 + m) * NT);
+        for (int m = 0; m < 3; ++m) g[t][m] = __builtin_nontemporal_load(gp + (t * 3 + m) * NT);
+    } else {
+#pragma unroll
+      for (int t = 0; t < N1; ++t)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) g[t][m] = Real2<Real>{0, 0};
+    }
+  }
 
-  // this thread's lattice nodes: global index, first-touch flag (the first colour touching a node
-  // stores: the brick that is even in every direction in which the node is shared with a
-  // neighbouring brick), source value, and the dst value this launch adds to
+  // this thread's lattice nodes: global index from the index lattice (~g on Dirichlet nodes,
+  // kAbsent outside the mesh), store/add bit (one bit per node, in a vector register), source
+  // value, and the dst value this launch adds to
   const int* ip = idx + ord * (int64_t)NL;
   int gk[KPT];
-  bool first[KPT];
+  unsigned first = 0;
   Real dv[KPT];
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
@@ -219,23 +236,23 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
     const bool sx = (li == 0 && bi > 0) || (li == LX - 1 && bi < bk.nbx - 1);
     const bool sy = (lj == 0 && bj > 0) || (lj == LY - 1 && bj < bk.nby - 1);
     const bool sz = (lk == 0 && bz > 0) || (lk == C::LZ - 1 && bz < bk.nbz - 1);
-    first[j] = (!sx || !(bi & 1)) && (!sy || !(bj & 1)) && (!sz || !(bz & 1));
+    const bool fj = (!sx || !(bi & 1)) && (!sy || !(bj & 1)) && (!sz || !(bz & 1));
+    first |= fj ? 1u << j : 0u;
   }
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
     const int g0 = gk[j];
-    const int gs = g0 >= 0 ? g0 : 0;
+    const bool live = g0 >= 0;
+    const int gs = live ? g0 : 0;
     const Real s = src[gs];
     const Real d = dst[gs];
-    lat[tid + j * kBlock] = g0 >= 0 ? s : (Real)0;
-    dv[j] = (g0 >= 0 && (ACC || !first[j])) ? d : (Real)0;
+    lat[tid + j * kBlock] = live ? s : (Real)0;
+    dv[j] = (live && (ACC || !(first >> j & 1u))) ? d : (Real)0;
   }
   lds_barrier();
 
   // x: values and x-derivatives at (q, e0, e1) from the lane's x-pencil
   {
-    const int cl = lc < NCELL ? lc : 0;
-    const int cx = cl % C::BX, cy = (cl / C::BX) % C::BY, cz = cl / (C::BX * C::BY);
     const Real* up = lat + cx * P + LX * ((cy * P + e0) + LY * (cz * P + e1));
     Real u[N1], A[N1], B[N1];
 #pragma unroll
@@ -307,15 +324,15 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
   lds_barrier();
   // transposed y: lane (r=e0, c=e1)
   {
-    Real az[N1], bz2[N1], cz[N1];
+    Real az[N1], bz2[N1], cz2[N1];
 #pragma unroll
     for (int s = 0; s < N1; ++s) {
       az[s] = L0[e0 + N1 * s + T * e1];
       bz2[s] = L1[e0 + N1 * s + T * e1];
-      cz[s] = L2[e0 + N1 * s + T * e1];
+      cz2[s] = L2[e0 + N1 * s + T * e1];
     }
     Real Ap[N1], Bp[N1];
-    eo_apply_t2<N1>(sh.S, az, sh.D, cz, Ap);
+    eo_apply_t2<N1>(sh.S, az, sh.D, cz2, Ap);
     eo_apply<N1, 1, true>(sh.S, bz2, Bp);
     lds_barrier();
 #pragma unroll
@@ -350,15 +367,16 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
     const int yhi = min(lj / P, C::BY - 1), ylo = (lj % P == 0 && lj > 0) ? lj / P - 1 : yhi;
     const int zhi = min(lk / P, C::BZ - 1), zlo = (lk % P == 0 && lk > 0) ? lk / P - 1 : zhi;
     Real sum = 0;
-    for (int cz = zlo; cz <= zhi; ++cz)
-      for (int cy = ylo; cy <= yhi; ++cy)
-        for (int cx = xlo; cx <= xhi; ++cx) {
-          const int cell = cx + C::BX * (cy + C::BY * cz);
-          sum += lds[cell * NQ + (li - cx * P) + N1 * ((lj - cy * P) + N1 * (lk - cz * P))];
+    for (int ccz = zlo; ccz <= zhi; ++ccz)
+      for (int ccy = ylo; ccy <= yhi; ++ccy)
+        for (int ccx = xlo; ccx <= xhi; ++ccx) {
+          const int cell = ccx + C::BX * (ccy + C::BY * ccz);
+          sum += lds[cell * NQ + (li - ccx * P) + N1 * ((lj - ccy * P) + N1 * (lk - ccz * P))];
         }
+    const bool fj = first >> j & 1u;
     if (g0 >= 0) {
-      dst[g0] = (ACC || !first[j]) ? dv[j] + sum : sum;
-    } else if (first[j]) {
+      dst[g0] = (ACC || !fj) ? dv[j] + sum : sum;
+    } else if (fj) {
       const int gg = ~g0;
       dst[gg] = ACC ? dst[gg] + src[gg] : src[gg];
     }
@@ -549,32 +567,10 @@ hipError_t geometry_export_p(const OpView& v, int precision, double* out, hipStr
   return hipGetLastError();
 }
 
-// Resident workgroups per CU of a kernel and the device's CU count (cached per device).
-template <typename K>
-int resident_grid(K kernel) {
-  static thread_local int cached_dev = -1, cached = 0;
-  int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) return 0;
-  if (dev == cached_dev) return cached;
-  int cus = 0, per_cu = 0;
-  if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess) return 0;
-  if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kernel, kBlock, 0) != hipSuccess || per_cu < 1) per_cu = 1;
-  cached_dev = dev;
-  cached = cus * per_cu;
-  return cached;
-}
-
-// Grid for nb bricks: at most one resident wave of workgroups, each taking the same number of bricks.
-inline unsigned balanced_grid(int64_t nb, int resident) {
-  if (resident <= 0 || nb <= resident) return (unsigned)nb;
-  const int64_t per = (nb + resident - 1) / resident;
-  return (unsigned)((nb + per - 1) / per);
-}
-
 template <int P, typename Real>
 hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipStream_t st) {
   static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
-  for (int c = 0; c < 8; ++c) {
+  for (int c = 0; c < kColours; ++c) {
     const int64_t nb = v.bricks.count[c];
     if (nb == 0) continue;
     if (acc)

@@ -130,7 +130,7 @@ __device__ __forceinline__ void eo_apply_t2(const EvenOdd<N1, Real>& S, const Re
   for (int a = 0; a < N1; ++a) y[a] = y1[a] + y2[a];
 }
 
-// Compile-time geometry of the cell kernels: one workgroup per brick of BX*BY*BZ cells, one
+// Compile-time geometry of the cell kernels: a workgroup works on a brick of BX*BY*BZ cells, one
 // lane per 1D pencil of a cell (T = (P+1)^2 lanes per cell, NT lanes carry work), and the brick's
 // node lattice LX*LY*LZ (shared nodes of neighbouring cells appear once).
 template <int P>
@@ -147,20 +147,19 @@ struct Cell {
   static_assert(NT <= kBlock, "a brick must fit one workgroup");
 };
 
-// Brick coordinates of brick `b` of colour `c` (colour = parity of x + 2*y + 4*z brick indices).
+// Brick coordinates of brick b (counted within colour c, x fastest).
 __host__ __device__ inline void brick_of(const Bricks& bk, int c, int64_t b64, int& bi, int& bj, int& bz) {
-  const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
   const unsigned b = (unsigned)b64, cxn = (unsigned)bk.cxn[c], cyn = (unsigned)bk.cyn[c];
-  const unsigned q = b / cxn;
-  bi = 2 * (int)(b - q * cxn) + px;
-  bj = 2 * (int)(q % cyn) + py;
-  bz = 2 * (int)(q / cyn) + pz;
+  const unsigned r = b / cxn, q = r / cyn;
+  bi = 2 * (int)(b - r * cxn) + (c & 1);
+  bj = 2 * (int)(r - q * cyn) + ((c >> 1) & 1);
+  bz = 2 * (int)q + (c >> 2);
 }
 
-// Colour and brick coordinates of a storage ordinal (colour-major order).
+// Brick coordinates of a storage ordinal (colour-major order).
 __host__ __device__ inline void brick_of_ordinal(const Bricks& bk, int64_t ord, int& bi, int& bj, int& bz) {
   int c = 0;
-  while (c < 7 && ord >= bk.offset[c] + bk.count[c]) ++c;
+  while (c < kColours - 1 && ord >= bk.offset[c] + bk.count[c]) ++c;
   brick_of(bk, c, ord - bk.offset[c], bi, bj, bz);
 }
 
@@ -169,8 +168,7 @@ __host__ __device__ inline int64_t ordinal_of_cell(const Bricks& bk, int64_t ci,
   const int bi = (int)(ci / bk.bx), bj = (int)(cj / bk.by), bz = (int)(ck / bk.bz);
   lc = (int)(ci - (int64_t)bi * bk.bx) + bk.bx * ((int)(cj - (int64_t)bj * bk.by) + bk.by * (int)(ck - (int64_t)bz * bk.bz));
   const int c = (bi & 1) + 2 * (bj & 1) + 4 * (bz & 1);
-  const int64_t cxn = (bk.nbx + 1 - (c & 1)) / 2, cyn = (bk.nby + 1 - ((c >> 1) & 1)) / 2;
-  return bk.offset[c] + (bi / 2) + cxn * ((bj / 2) + cyn * (int64_t)(bz / 2));
+  return bk.offset[c] + (bi / 2) + (int64_t)bk.cxn[c] * ((bj / 2) + (int64_t)bk.cyn[c] * (bz / 2));
 }
 
 // Workgroup barrier that orders LDS only: global loads issued before it stay in flight.

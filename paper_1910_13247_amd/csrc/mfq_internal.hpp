@@ -43,34 +43,36 @@ double lagrange_derivative(const std::vector<double>& nodes, int a, double t);
 // cell: h-transfer (fine degree pc, two fine cells) when h_transfer, else the GLL nodes of pf.
 std::vector<double> transfer_matrix_1d(int pc, int pf, bool h_transfer, int* nf1);
 
-// Work decomposition of the cell kernels: one workgroup per brick of bx*by*bz cells, one lane per
-// 1D pencil of a cell ((p+1)^2 lanes per cell).  Bricks are coloured by the parities of their
-// brick coordinates; bricks of one colour share no node, so a colour is one launch whose
-// workgroups write their brick's nodes without atomics, and colours run in order 0..7.
+// Work decomposition of the cell kernels: the mesh is cut into bricks of bx x by x bz cells, one
+// workgroup per brick and one lane per 1D pencil of a cell ((p+1)^2 lanes per cell).  Bricks are
+// coloured by the parities of their (x, y, z) brick coordinates: bricks of one colour share no
+// node, so a colour is one launch whose workgroups write their nodes without atomics, and the
+// colours run in order 0..7.
 struct BrickDims {
   int bx, by, bz;
 };
-// Brick shapes (cells in x, y, z); a build can override one degree, e.g. -DMFQ_BRICK_P4=4,2,1.
+// Brick shapes (cells in x, y, z) per degree, chosen by timing the operator on MI355X among the
+// shapes that fill a 256-lane workgroup; a build can override one, e.g. -DMFQ_BRICK_P4=4,1,2.
 #ifndef MFQ_BRICK_P1
-#define MFQ_BRICK_P1 4, 4, 4
+#define MFQ_BRICK_P1 32, 2, 1
 #endif
 #ifndef MFQ_BRICK_P2
-#define MFQ_BRICK_P2 3, 3, 3
+#define MFQ_BRICK_P2 14, 2, 1
 #endif
 #ifndef MFQ_BRICK_P3
-#define MFQ_BRICK_P3 4, 2, 2
+#define MFQ_BRICK_P3 16, 1, 1
 #endif
 #ifndef MFQ_BRICK_P4
-#define MFQ_BRICK_P4 2, 2, 2
+#define MFQ_BRICK_P4 5, 2, 1
 #endif
 #ifndef MFQ_BRICK_P5
-#define MFQ_BRICK_P5 3, 2, 1
+#define MFQ_BRICK_P5 7, 1, 1
 #endif
 #ifndef MFQ_BRICK_P6
-#define MFQ_BRICK_P6 2, 2, 1
+#define MFQ_BRICK_P6 4, 1, 1
 #endif
 #ifndef MFQ_BRICK_P7
-#define MFQ_BRICK_P7 2, 2, 1
+#define MFQ_BRICK_P7 4, 1, 1
 #endif
 #ifndef MFQ_BRICK_P8
 #define MFQ_BRICK_P8 3, 1, 1
@@ -91,19 +93,25 @@ inline int64_t lattice_per_brick(int p) {
   return (int64_t)(b.bx * p + 1) * (b.by * p + 1) * (b.bz * p + 1);
 }
 
-// Brick grid of a mesh: bricks per direction, bricks per colour and the first brick ordinal of
-// each colour (storage of per-brick data is colour-major, so each launch streams a contiguous range).
+constexpr int kColours = 8;
+
+// Brick grid of a mesh.  Colour c = (x parity) + 2 (y parity) + 4 (z parity) of the brick
+// coordinates.  Per-brick data is stored colour-major, bricks of a colour x-fastest, so each
+// launch streams one contiguous range.
 struct Bricks {
-  int bx, by, bz;
-  int nbx, nby, nbz;
-  int cxn[8], cyn[8];  // bricks of colour c along x and y
-  int64_t count[8];
-  int64_t offset[8];
+  int n;                     // cells per direction of the mesh
+  int bx, by, bz;            // cells per brick
+  int nbx, nby, nbz;         // bricks per direction
+  int cxn[kColours];         // bricks of colour c along x
+  int cyn[kColours];         // bricks of colour c along y
+  int64_t count[kColours];   // bricks of colour c
+  int64_t offset[kColours];  // first brick ordinal of colour c
   int64_t n_bricks;
 };
 inline Bricks make_bricks(int p, int n) {
   Bricks b{};
   const BrickDims d = brick_dims(p);
+  b.n = n;
   b.bx = d.bx;
   b.by = d.by;
   b.bz = d.bz;
@@ -111,9 +119,8 @@ inline Bricks make_bricks(int p, int n) {
   b.nby = (n + d.by - 1) / d.by;
   b.nbz = (n + d.bz - 1) / d.bz;
   int64_t off = 0;
-  for (int c = 0; c < 8; ++c) {
-    const int cx = (b.nbx + 1 - (c & 1)) / 2, cy = (b.nby + 1 - ((c >> 1) & 1)) / 2,
-              cz = (b.nbz + 1 - (c >> 2)) / 2;
+  for (int c = 0; c < kColours; ++c) {
+    const int cx = (b.nbx + 1 - (c & 1)) / 2, cy = (b.nby + 1 - ((c >> 1) & 1)) / 2, cz = (b.nbz + 1 - (c >> 2)) / 2;
     b.cxn[c] = cx;
     b.cyn[c] = cy;
     b.count[c] = (int64_t)cx * cy * cz;

@@ -50,10 +50,11 @@ def test_host_validation_errors():
         lib.mfq_op_create(s, 0.5, 5)
     op = lib.mfq_op_create(s, 0.5, 0)
     nbytes = lib.mfq_op_device_bytes(op)
-    # 2x2x2-cell bricks at p=4: a 9^3 int32 node lattice per brick plus 6 doubles per quadrature point
-    nbricks = 2 * 2 * 2
+    # 5x2x1-cell bricks at p=4 (one ragged brick spans x of the 4^3 mesh, 2x4 bricks in y and z):
+    # a 21x9x5 int32 node lattice per brick plus 6 doubles per quadrature point of its 250 pencils
+    nbricks = 1 * 2 * 4
     rnd = lambda b: -(-b // 256) * 256
-    assert nbytes == rnd(nbricks * 9 ** 3 * 4) + rnd(nbricks * 8 * 125 * 6 * 8)
+    assert nbytes == rnd(nbricks * 21 * 9 * 5 * 4) + rnd(nbricks * 5 * 250 * 6 * 8)
     with pytest.raises(lib.MfqError) as e:
         lib.mfq_vmult(op, 256, 512, None)   # unbound operator: rejected before any launch
     assert e.value.status == lib.MFQ_EINVAL
@@ -101,3 +102,24 @@ def test_library_tables_agree_with_oracle_tables(p):
     np.testing.assert_allclose(w, wo, atol=2e-16)
     np.testing.assert_allclose(S, So, atol=1e-14)
     np.testing.assert_allclose(D, Do, atol=1e-12 * np.abs(Do).max())
+
+
+@pytest.mark.parametrize("p,n,brick,launches,groups", [
+    (4, 64, (5, 2, 1), 8, 13 * 32 * 64),
+    (4, 4, (5, 2, 1), 4, 8),                  # one (ragged) brick along x: the odd-x colours are empty
+    (8, 24, (3, 1, 1), 8, 8 * 24 * 24),
+    (3, 128, (16, 1, 1), 8, 8 * 128 * 128),
+    (1, 1, (32, 2, 1), 1, 1),                 # a single ragged brick
+])
+def test_operator_layout(p, n, brick, launches, groups):
+    """The cell loop's work decomposition: brick shape per degree, one workgroup per brick, one
+    launch per non-empty colour of the brick grid."""
+    lib = _lib()
+    m = lib.mfq_mesh_create(n, 0.1 if n > 1 else 0.0)
+    s = lib.mfq_space_create(m, p, 1)
+    op = lib.mfq_op_create(s, 0.5, 0)
+    lay = lib.mfq_op_get_layout(op)
+    assert lay == {"brick": brick, "launches": launches, "workgroups": groups}
+    lib.mfq_op_destroy(op)
+    lib.mfq_space_destroy(s)
+    lib.mfq_mesh_destroy(m)
