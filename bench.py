@@ -8,7 +8,7 @@ DoFs/s of the step, the roofline of the dominant kernel (the cell loop, timed wi
 on its stream), an FP32 figure of the same operator, and the CPU oracle on a bounded sample of
 the same workload.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--solves] [--copy-probe]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--solves] [--serve N] [--copy-probe]
 """
 import argparse
 import json
@@ -146,6 +146,32 @@ def solve_benchmarks(steps):
     return out
 
 
+def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=4):
+    """The serving stream: Poisson arrivals at `rate`/s, degree U{1..6}, n U{4..48}, alpha
+    U[0,0.9], right-hand side from the request's seed; each solved to relative residual 1e-10."""
+    import torch
+    from synthetic import serving_stream
+    from paper_1910_13247_amd.serve import DeviceExecutor, Request, Server, run_stream
+    stream = serving_stream(n_requests, rate, seed)
+    reqs = [Request(degree=d["degree"], n=d["cells_1d"], alpha=d["alpha"], seed=d["rhs_seed"]) for d in stream]
+    arrivals = [d["arrival"] for d in stream]
+    free, _ = torch.cuda.mem_get_info()
+    budget = int(min(0.75 * free, 160e9))
+    srv = Server(DeviceExecutor(n_streams=n_streams), budget, iters_per_step=iters_per_step)
+    t0 = time.perf_counter()
+    st = run_stream(srv, reqs, arrivals)
+    torch.cuda.synchronize()
+    st["wall_s"] = time.perf_counter() - t0
+    st["budget_bytes"] = budget
+    st["iters_per_step"] = iters_per_step
+    st["streams"] = n_streams
+    st["rate_per_s"] = rate
+    st["dofs_total"] = sum((r.degree * r.n + 1) ** 3 for r in reqs)
+    st["iterations_mean"] = sum(r.iterations for r in srv.done) / max(len(srv.done), 1)
+    st["not_converged"] = sum(1 for r in srv.done if r.status != 0)
+    return st
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__, formatter_class=argparse.RawDescriptionHelpFormatter)
     ap.add_argument("--gpus", type=int, default=1)
@@ -153,6 +179,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--solves", action="store_true", help="add time-to-1e-10 of the Q3 128^3 solvers")
+    ap.add_argument("--serve", type=int, default=0, metavar="N",
+                    help="also replay N requests of the serving stream (200 requests/s) and report solves/s, p50/p99")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run 3 plain device copies of 1 GiB (reference reading for HBM byte counters)")
     args = ap.parse_args()
@@ -231,6 +259,9 @@ def main():
         del a, b
     if args.solves:
         rec["solves_q3_128"] = solve_benchmarks(args.steps)
+    if args.serve:
+        print(f"# serving {args.serve} requests", file=sys.stderr, flush=True)
+        rec["serving"] = serve_benchmark(args.serve)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, n, pr.amplitude, pr.alpha, x_np)

@@ -93,6 +93,12 @@ int64_t mfq_space_n_cells(const mfq_space* space);  /* n^3, -1 on NULL */
  * of a nodal load vector.  precision selects double/float. */
 int mfq_space_apply_mask(const mfq_space* space, int precision, void* x, void* hip_stream);
 
+/* x_i = 2 u_i - 1 with u_i = (z_i >> 11) 2^-53 and z_i the SplitMix64 output (Steele, Lea and
+ * Flood, OOPSLA 2014) of the state seed + (i+1) 0x9E3779B97F4A7C15, for i = 0..n_dofs-1; zero on
+ * Dirichlet nodes when the space has MFQ_BC_DIRICHLET0.  A counter-based random load vector
+ * (independent of launch shape), e.g. the right-hand sides of a stream of solve requests. */
+int mfq_space_random(const mfq_space* space, int precision, void* x, uint64_t seed, void* hip_stream);
+
 /* ---------------------------------------------------------------- operator (Sec. 3.6, 3.7)
  * The variable-coefficient operator on a space, computed in `precision` (MFQ_FP64 or MFQ_FP32).
  * Device storage: the cell index maps (int32, (p+1)^3 per cell) and the merged
@@ -161,9 +167,15 @@ int mfq_chebyshev(const mfq_op* op, const void* inv_diag, const void* b, void* x
  * V-cycle.  GMG_MIXED_IR: FP64 iterative refinement (FP64 residual and correction) around an
  * inner CG on FP32 operators preconditioned by the FP32 V-cycle.
  * The solver is built on an FP64 operator with MFQ_BC_DIRICHLET0; the hierarchy halves n
- * while n is even and the level has more than 4096 free DoFs, then lowers p to ceil(p/2)
- * while more than 4096 free DoFs remain.  The coarsest level is solved in FP64 by a dense
- * inverse (<= 4096 free DoFs) or by Jacobi-CG to 1e-12. */
+ * while n is even and the level has more than coarse_dofs free DoFs (default 4096), then
+ * lowers p to ceil(p/2) while more than coarse_dofs free DoFs remain.  Coarsest level:
+ *   coarse_mode 0 (default): solved in FP64 by a dense inverse (<= coarse_dofs free DoFs) or by
+ *     Jacobi-CG to 1e-12 (which polls the host);
+ *   coarse_mode 1: coarse_degree Chebyshev updates from zero on [lmax/coarse_ratio, lmax] with
+ *     the V-cycle's precision, so a V-cycle never waits on the host (used when many solves share
+ *     the device, see mfq_batch_step).
+ * Every solve ends with an FP64 true-residual check; while it exceeds rtol, another CG pass on
+ * the residual equation (FP64 correction) follows, within max_iter iterations in total. */
 typedef enum { MFQ_SOLVER_CG = 0, MFQ_SOLVER_GMG_FP64 = 1, MFQ_SOLVER_GMG_MIXED = 2,
                MFQ_SOLVER_GMG_MIXED_IR = 3 } mfq_solver_kind;
 
@@ -176,6 +188,10 @@ typedef struct {
   int check_every;         /* host convergence poll period in iterations (default 4) */
   int n_lambda_override;   /* if > 0: lmax of levels 1..n (finest last) taken from lambda_override */
   const double* lambda_override;
+  int coarse_mode;         /* 0: dense inverse or Jacobi-CG; 1: Chebyshev, no host round trip */
+  int coarse_degree;       /* Chebyshev degree on the coarsest level in coarse_mode 1 (default 16) */
+  double coarse_ratio;     /* its interval [lmax/coarse_ratio, lmax] (default 30) */
+  int coarse_dofs;         /* coarsening stops at this many free DoFs (default 4096, at most 4096) */
 } mfq_solver_params;
 
 typedef struct {
@@ -194,9 +210,29 @@ int mfq_solver_device_bytes(const mfq_solver* s, size_t* bytes);
  * inverse.  Synchronises the stream. */
 int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream);
 /* Solves A x = b to ||b - A x||_2 <= rtol ||b||_2 from x = 0 (x overwritten).  b, x: double
- * device vectors.  Blocks until done.  MFQ_ENOCONV when max_iter is reached (info valid). */
+ * device vectors.  Blocks until done.  MFQ_ENOCONV when max_iter is reached (info valid).
+ * Equivalent to mfq_solve_begin, mfq_batch_step on this solver alone (check_every iterations
+ * per step) until it reports done, and mfq_solve_end. */
 int mfq_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_iter,
               void* hip_stream, mfq_solve_info* info);
+
+/* Resumable solves, for serving many requests on one device (continuous batching; not in the
+ * paper).  mfq_solve_begin validates the arguments like mfq_solve and enqueues the start of the
+ * solve on hip_stream (asynchronous); the solver remembers b, x and the stream, which must stay
+ * valid until mfq_solve_end.  A solver runs one solve at a time (MFQ_EBUSY otherwise). */
+int mfq_solve_begin(mfq_solver* s, const double* b, double* x, double rtol, int max_iter, void* hip_stream);
+
+/* One step of `count` running solves: enqueues up to `iters` CG iterations of each (or its
+ * residual check) on its own stream, then waits once for all of them and reads every solve's
+ * convergence state from pinned host memory (one device-to-host copy per solve per step).
+ * done[i] is set to 1 once solve i has finished (converged, out of iterations or non-finite).
+ * Solves on different streams overlap on the device. */
+int mfq_batch_step(mfq_solver* const* solvers, int count, int iters, int* done);
+
+/* Finishes a solve that mfq_batch_step reported done: fills info and returns the solve's status
+ * (MFQ_OK, MFQ_ENOCONV or MFQ_ENONFINITE); the solver can then begin another solve.
+ * MFQ_EINVAL if no solve has finished. */
+int mfq_solve_end(mfq_solver* s, mfq_solve_info* info);
 /* z = M r: one application of the solver's preconditioner (the V-cycle; identity for CG) to
  * the double device vector r.  Asynchronous. */
 int mfq_solver_precondition(mfq_solver* s, const double* r, double* z, void* hip_stream);

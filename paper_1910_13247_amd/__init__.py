@@ -11,11 +11,13 @@ matrix-free, level transfers, and solvers (CG, geometric multigrid).
 """
 from . import _lib
 from ._lib import (MfqError, MFQ_FP64, MFQ_FP32, MFQ_BC_NONE, MFQ_BC_DIRICHLET0, MFQ_SOLVER_CG,
-                   MFQ_SOLVER_GMG_FP64, MFQ_SOLVER_GMG_MIXED, MFQ_SOLVER_GMG_MIXED_IR)
+                   MFQ_SOLVER_GMG_FP64, MFQ_SOLVER_GMG_MIXED, MFQ_SOLVER_GMG_MIXED_IR, MFQ_OK, MFQ_EINVAL,
+                   MFQ_ENOMEM, MFQ_EHIP, MFQ_ENOCONV, MFQ_ENONFINITE, MFQ_EBUSY)
 
 __all__ = ["Mesh", "Space", "Operator", "Transfer", "Solver", "MfqError", "MFQ_FP64", "MFQ_FP32",
            "MFQ_BC_NONE", "MFQ_BC_DIRICHLET0", "MFQ_SOLVER_CG", "MFQ_SOLVER_GMG_FP64",
-           "MFQ_SOLVER_GMG_MIXED", "MFQ_SOLVER_GMG_MIXED_IR"]
+           "MFQ_SOLVER_GMG_MIXED", "MFQ_SOLVER_GMG_MIXED_IR", "MFQ_OK", "MFQ_EINVAL", "MFQ_ENOMEM",
+           "MFQ_EHIP", "MFQ_ENOCONV", "MFQ_ENONFINITE", "MFQ_EBUSY", "batch_step"]
 
 
 def _torch():
@@ -65,6 +67,16 @@ class Space:
         self.handle = _lib.mfq_space_create(mesh.handle, self.degree, self.bc)
         self.n_dofs = _lib.mfq_space_n_dofs(self.handle)
         self.n_cells = _lib.mfq_space_n_cells(self.handle)
+
+    def random(self, seed, precision=MFQ_FP64, x=None, stream=None):
+        """Counter-based (SplitMix64) uniform[-1,1) vector, zero on Dirichlet nodes."""
+        torch = _torch()
+        if x is None:
+            x = torch.empty(self.n_dofs, dtype=torch.float64 if precision == MFQ_FP64 else torch.float32,
+                            device="cuda")
+        _lib.mfq_space_random(self.handle, precision, _check_vec(x, self.n_dofs, precision, "x"), int(seed),
+                              _stream(stream))
+        return x
 
     def apply_mask(self, x, precision=MFQ_FP64, stream=None):
         _lib.mfq_space_apply_mask(self.handle, precision, _check_vec(x, self.n_dofs, precision, "x"), _stream(stream))
@@ -171,6 +183,12 @@ class Transfer:
             self.handle = None
 
 
+def batch_step(solvers, iters=2):
+    """Advance every running solve in `solvers` by up to `iters` CG iterations (each on the stream
+    it was begun on), wait once for all of them, and return their done flags."""
+    return _lib.mfq_batch_step([s.handle for s in solvers], iters)
+
+
 class Solver:
     """CG / GMG-preconditioned CG on an FP64 operator (see mfq_solver_kind)."""
 
@@ -199,6 +217,15 @@ class Solver:
                                   _check_vec(x, self.op.n_dofs, MFQ_FP64, "x"), rtol, max_iter, _stream(stream),
                                   check=check)
         return x, info, st
+
+    def begin(self, b, x, rtol=1e-10, max_iter=10000, stream=None):
+        """Start a resumable solve (advance it with batch_step, finish with end)."""
+        _lib.mfq_solve_begin(self.handle, _check_vec(b, self.op.n_dofs, MFQ_FP64, "b"),
+                             _check_vec(x, self.op.n_dofs, MFQ_FP64, "x"), rtol, max_iter, _stream(stream))
+
+    def end(self, check=True):
+        """(status, SolveInfo) of a solve that batch_step reported done."""
+        return _lib.mfq_solve_end(self.handle, check=check)
 
     def precondition(self, r, z=None, stream=None):
         if z is None:

@@ -28,7 +28,9 @@ class MfqError(RuntimeError):
 class SolverParams(C.Structure):
     _fields_ = [("smoother_degree", C.c_int), ("lanczos_iters", C.c_int), ("lambda_factor", C.c_double),
                 ("lambda_ratio", C.c_double), ("inner_rtol", C.c_double), ("check_every", C.c_int),
-                ("n_lambda_override", C.c_int), ("lambda_override", C.POINTER(C.c_double))]
+                ("n_lambda_override", C.c_int), ("lambda_override", C.POINTER(C.c_double)),
+                ("coarse_mode", C.c_int), ("coarse_degree", C.c_int), ("coarse_ratio", C.c_double),
+                ("coarse_dofs", C.c_int)]
 
 
 class OpLayout(C.Structure):
@@ -60,6 +62,7 @@ _SIGS = {
     "mfq_space_n_dofs": ([P], I64),
     "mfq_space_n_cells": ([P], I64),
     "mfq_space_apply_mask": ([P, I, P, P], I),
+    "mfq_space_random": ([P, I, P, C.c_uint64, P], I),
     "mfq_op_create": ([P, D, I, PP], I),
     "mfq_op_destroy": ([P], None),
     "mfq_op_device_bytes": ([P, C.POINTER(SZ)], I),
@@ -81,6 +84,9 @@ _SIGS = {
     "mfq_solver_device_bytes": ([P, C.POINTER(SZ)], I),
     "mfq_solver_bind": ([P, P, SZ, P], I),
     "mfq_solve": ([P, P, P, D, I, P, C.POINTER(SolveInfo)], I),
+    "mfq_solve_begin": ([P, P, P, D, I, P], I),
+    "mfq_batch_step": ([C.POINTER(C.c_void_p), I, I, C.POINTER(C.c_int)], I),
+    "mfq_solve_end": ([P, C.POINTER(SolveInfo)], I),
     "mfq_solver_lambdas": ([P, C.POINTER(D), I], I),
     "mfq_solver_precondition": ([P, P, P, P], I),
 }
@@ -157,6 +163,10 @@ def mfq_space_n_dofs(space):
 
 def mfq_space_n_cells(space):
     return lib().mfq_space_n_cells(space)
+
+
+def mfq_space_random(space, precision, x, seed, stream):
+    _check(lib().mfq_space_random(space, precision, x, seed, stream))
 
 
 def mfq_space_apply_mask(space, precision, x, stream):
@@ -256,6 +266,28 @@ def mfq_solve(s, b, x, rtol, max_iter, stream, check=True):
     """Returns (status, SolveInfo).  With check=True a status other than MFQ_OK raises."""
     info = SolveInfo()
     st = lib().mfq_solve(s, b, x, rtol, max_iter, stream, C.byref(info))
+    if check:
+        _check(st)
+    return st, info
+
+
+def mfq_solve_begin(s, b, x, rtol, max_iter, stream):
+    _check(lib().mfq_solve_begin(s, b, x, rtol, max_iter, stream))
+
+
+def mfq_batch_step(solvers, iters):
+    """One step of the running solves `solvers` (handles); returns their done flags."""
+    n = len(solvers)
+    arr = (C.c_void_p * max(n, 1))(*solvers)
+    done = (C.c_int * max(n, 1))()
+    _check(lib().mfq_batch_step(arr, n, iters, done))
+    return [bool(done[i]) for i in range(n)]
+
+
+def mfq_solve_end(s, check=True):
+    """Returns (status, SolveInfo) of a finished solve; check=True raises on a status other than MFQ_OK."""
+    info = SolveInfo()
+    st = lib().mfq_solve_end(s, C.byref(info))
     if check:
         _check(st)
     return st, info

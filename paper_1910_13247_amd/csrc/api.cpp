@@ -102,6 +102,15 @@ int mfq_space_apply_mask(const mfq_space* space, int precision, void* x, void* h
   return MFQ_OK;
 }
 
+int mfq_space_random(const mfq_space* space, int precision, void* x, uint64_t seed, void* hip_stream) {
+  if (!space) return fail(MFQ_EINVAL, "space is NULL");
+  if (precision != MFQ_FP64 && precision != MFQ_FP32) return fail(MFQ_EINVAL, "unknown precision %d", precision);
+  if (int rc = check_vec(x, "x")) return rc;
+  const int64_t N1 = (int64_t)space->p * space->mesh->n + 1;
+  MFQ_HIP(launch_splitmix(precision, x, N1, seed, space->bc == MFQ_BC_DIRICHLET0, (hipStream_t)hip_stream));
+  return MFQ_OK;
+}
+
 int mfq_op_create(const mfq_space* space, double alpha, int precision, mfq_op** out) {
   if (!space || !out) return fail(MFQ_EINVAL, "space or out is NULL");
   if (precision != MFQ_FP64 && precision != MFQ_FP32) return fail(MFQ_EINVAL, "unknown precision %d", precision);

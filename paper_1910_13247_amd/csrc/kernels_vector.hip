@@ -178,13 +178,13 @@ __global__ __launch_bounds__(kVBlock) void cg_beta_kernel(const double* __restri
   }
 }
 
-// p = z + beta p  (first iteration: beta_first selects p = z)
+// p = z + beta p; the first direction is p = z, without reading p (which holds no value yet)
 __global__ __launch_bounds__(kVBlock) void cg_direction_kernel(const double* __restrict__ z, double* __restrict__ p,
                                                                int64_t n, SolverState* st, int first) {
   if (st->done) return;
-  const double beta = first ? 0.0 : st->beta;
+  const double beta = st->beta;
   for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
-    p[i] = z[i] + beta * p[i];
+    p[i] = first ? z[i] : z[i] + beta * p[i];
 }
 
 // r = b - t (true residual), rr = r.r ; used by iterative refinement and final certificates.
@@ -285,7 +285,7 @@ template <typename Real>
 __global__ __launch_bounds__(kVBlock) void axpby_kernel(Real a, const Real* __restrict__ x, Real b, Real* __restrict__ y,
                                                         int64_t n) {
   for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
-    y[i] = a * x[i] + b * y[i];
+    y[i] = b == (Real)0 ? a * x[i] : a * x[i] + b * y[i];  // b = 0 never reads y
 }
 
 // z = d * r

@@ -65,7 +65,31 @@ struct mfq_solver {
   double* scal = nullptr;      // device scalars for setup dots
   size_t bytes = 0;
   void* buf = nullptr;
+  // resumable solve (mfq_solve_begin / mfq_batch_step / mfq_solve_end)
+  struct HostStatus {
+    SolverState head;  // copy of the device state up to (excluding) the reduction partials
+    double cert;       // ||b - A x||^2 of the last residual check
+  };
+  HostStatus* hstat = nullptr;  // pinned host memory
+  struct Run {
+    enum Phase { kIdle, kInner, kCheck, kDone };
+    Phase phase = kIdle;
+    const double* b = nullptr;
+    double* x = nullptr;
+    double* sol = nullptr;      // solution vector of the current CG pass (x or the correction c)
+    double rtol = 0;
+    int max_iter = 0;
+    hipStream_t st = nullptr;
+    int pass = 0;               // CG passes started
+    int iters = 0;              // iterations of finished passes
+    int enqueued = 0, budget = 0;  // iterations enqueued / allowed in the current pass
+    double bb = -1, rr = 0;
+    int status = MFQ_OK;
+    std::chrono::steady_clock::time_point t0;
+    double seconds = 0;
+  } run;
   ~mfq_solver() {
+    if (hstat) (void)hipHostFree(hstat);
     for (Level& l : lv) {
       if (l.owns_op) mfq_op_destroy(l.op);
       mfq_transfer_destroy(l.to_fine);
@@ -236,6 +260,8 @@ int pcg(const Apply& apply, const Apply* prec, const double* b, double* x, doubl
 int coarse_solve(mfq_solver* s, const void* b, void* x, hipStream_t st) {
   Level& L = s->lv[0];
   const int prec = s->prec_v;
+  if (s->prm.coarse_mode == 1)
+    return mfq_chebyshev(L.op, L.dinv, b, x, 1, s->prm.coarse_degree, L.lmin, L.lmax, L.r, st);
   if (s->dense) {
     MFQ_HIP(launch_fill(prec, x, L.n, 0.0, st));
     MFQ_HIP(launch_dense_solve(prec, s->ainv, (int)s->nf, (int64_t)L.sp->p * L.sp->mesh->n + 1, b, x, st));
@@ -337,6 +363,146 @@ int estimate_lambda(mfq_solver* s, Level& L, hipStream_t st) {
   return MFQ_OK;
 }
 
+// ---------------------------------------------------------------- resumable solve
+// A solve is a sequence of CG passes.  Pass 0 solves A x = b from x = 0 (for GMG_MIXED_IR: the
+// FP32-operator inner system A c = b, then x = c).  Every pass ends with an FP64 true-residual
+// check r = b - A x; while ||r|| > rtol ||b|| another pass solves the residual equation A c = r
+// and adds c to x (FP64 iterative refinement).  Steps enqueue work asynchronously; the host
+// decides between passes after reading the pinned status copy.
+using Run = mfq_solver::Run;
+
+bool preconditioned(const mfq_solver* s) { return s->kind != MFQ_SOLVER_CG; }
+
+// operator of the inner CG: the FP64 operator, or the finest FP32 operator for GMG_MIXED_IR
+int inner_apply(mfq_solver* s, const double* in, double* out, hipStream_t st) {
+  if (s->kind != MFQ_SOLVER_GMG_MIXED_IR) return op_vmult(s->op64, in, out, st);
+  Level& F = s->lv.back();
+  MFQ_HIP(launch_cast(MFQ_FP64, in, MFQ_FP32, F.r, F.n, st));
+  if (int rc = op_vmult(F.op, F.r, F.d, st)) return rc;
+  MFQ_HIP(launch_cast(MFQ_FP32, F.d, MFQ_FP64, out, F.n, st));
+  return MFQ_OK;
+}
+
+int pass_start(mfq_solver* s, const double* rhs, double* sol, double tol2) {
+  Run& R = s->run;
+  const int64_t N = s->op64->space->n_dofs;
+  const bool pre = preconditioned(s);
+  MFQ_HIP(launch_cg_start(rhs, sol, s->r, s->p, N, s->state, !pre, tol2, R.st));
+  if (pre) {
+    if (int rc = precondition(s, s->r, s->z, R.st)) return rc;
+    MFQ_HIP(launch_cg_beta(s->r, s->z, N, s->state, R.st));
+    MFQ_HIP(launch_cg_direction(s->z, s->p, N, s->state, true, R.st));
+  }
+  R.sol = sol;
+  R.enqueued = 0;
+  R.budget = R.max_iter - R.iters;
+  R.pass += 1;
+  R.phase = Run::kInner;
+  return MFQ_OK;
+}
+
+// CG iterations; once the device state says done, the remaining ones are no-ops
+int pass_iterate(mfq_solver* s, int k) {
+  Run& R = s->run;
+  const int64_t N = s->op64->space->n_dofs;
+  const bool pre = preconditioned(s);
+  for (int i = 0; i < k; ++i) {
+    if (int rc = inner_apply(s, s->p, s->Ap, R.st)) return rc;
+    MFQ_HIP(launch_cg_alpha(s->p, s->Ap, N, s->state, R.st));
+    MFQ_HIP(launch_cg_update(R.sol, s->r, s->p, s->Ap, N, s->state, !pre, R.st));
+    if (pre) {
+      if (int rc = precondition(s, s->r, s->z, R.st)) return rc;
+      MFQ_HIP(launch_cg_beta(s->r, s->z, N, s->state, R.st));
+      MFQ_HIP(launch_cg_direction(s->z, s->p, N, s->state, false, R.st));
+    } else {
+      MFQ_HIP(launch_cg_direction(s->r, s->p, N, s->state, false, R.st));
+    }
+  }
+  return MFQ_OK;
+}
+
+void finish(mfq_solver* s, int status) {
+  Run& R = s->run;
+  R.status = status;
+  R.phase = Run::kDone;
+  R.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - R.t0).count();
+}
+
+// first half of a step: enqueue work and the device-to-host copy of its outcome
+int step_enqueue(mfq_solver* s, int iters) {
+  Run& R = s->run;
+  const int64_t N = s->op64->space->n_dofs;
+  if (R.phase == Run::kInner) {
+    const int m = std::max(0, std::min(iters, R.budget - R.enqueued));
+    if (int rc = pass_iterate(s, m)) return rc;
+    R.enqueued += m;
+    MFQ_HIP(hipMemcpyAsync(&s->hstat->head, s->state, offsetof(SolverState, partials), hipMemcpyDeviceToHost, R.st));
+  } else if (R.phase == Run::kCheck) {
+    if (R.sol != R.x) MFQ_HIP(launch_add(MFQ_FP64, R.x, MFQ_FP64, R.sol, N, R.st));
+    if (int rc = op_vmult(s->op64, R.x, s->Ap, R.st)) return rc;
+    MFQ_HIP(launch_residual_norm(R.b, s->Ap, s->rout, N, s->aux, s->scal, R.st));
+    MFQ_HIP(hipMemcpyAsync(&s->hstat->cert, s->scal, 8, hipMemcpyDeviceToHost, R.st));
+  }
+  return MFQ_OK;
+}
+
+// second half, after the stream has been synchronised: read the outcome, pick the next phase
+int step_collect(mfq_solver* s) {
+  Run& R = s->run;
+  if (R.phase == Run::kInner) {
+    const SolverState& h = s->hstat->head;
+    if (R.pass == 1 && R.bb < 0) R.bb = h.bb;  // pass 1 runs on b itself
+    if (h.nonfinite) {
+      R.iters += h.iter;
+      finish(s, MFQ_ENONFINITE);
+    } else if (h.done || R.enqueued >= R.budget) {
+      R.iters += h.done ? h.converged_iter : h.iter;
+      R.phase = Run::kCheck;
+    }
+  } else if (R.phase == Run::kCheck) {
+    const double rr = s->hstat->cert;
+    R.rr = rr;
+    if (!std::isfinite(rr)) {
+      finish(s, MFQ_ENONFINITE);
+    } else if (rr <= R.rtol * R.rtol * R.bb || R.bb == 0) {
+      finish(s, MFQ_OK);
+    } else if (R.iters >= R.max_iter) {
+      finish(s, MFQ_ENOCONV);
+    } else {
+      // correction pass on A c = r: the inner system of GMG_MIXED_IR to inner_rtol, the others
+      // to half the remaining distance to rtol ||b||
+      const double tol2 = s->kind == MFQ_SOLVER_GMG_MIXED_IR ? s->prm.inner_rtol * s->prm.inner_rtol
+                                                              : std::min(0.25, 0.25 * R.rtol * R.rtol * R.bb / rr);
+      if (int rc = pass_start(s, s->rout, s->c, tol2)) return rc;
+    }
+  }
+  return MFQ_OK;
+}
+
+int begin_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_iter, hipStream_t st) {
+  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
+  if (!s->buf) return fail(MFQ_EINVAL, "solver is not bound");
+  if (s->run.phase == Run::kInner || s->run.phase == Run::kCheck) return fail(MFQ_EBUSY, "a solve is running");
+  if (!b || !x || (reinterpret_cast<uintptr_t>(b) % 16) || (reinterpret_cast<uintptr_t>(x) % 16))
+    return fail(MFQ_EINVAL, "b or x NULL or misaligned");
+  if (!(rtol > 0 && rtol < 1)) return fail(MFQ_EINVAL, "rtol must be in (0,1)");
+  if (max_iter < 1) return fail(MFQ_EINVAL, "max_iter must be >= 1");
+  Run& R = s->run;
+  R = Run{};
+  R.b = b;
+  R.x = x;
+  R.rtol = rtol;
+  R.max_iter = max_iter;
+  R.st = st;
+  R.t0 = std::chrono::steady_clock::now();
+  const int64_t N = s->op64->space->n_dofs;
+  if (s->kind == MFQ_SOLVER_GMG_MIXED_IR) {
+    MFQ_HIP(launch_fill(MFQ_FP64, x, N, 0.0, st));
+    return pass_start(s, b, s->c, s->prm.inner_rtol * s->prm.inner_rtol);
+  }
+  return pass_start(s, b, x, rtol * rtol);
+}
+
 }  // namespace
 
 extern "C" {
@@ -351,6 +517,10 @@ void mfq_solver_default_params(mfq_solver_params* p) {
   p->check_every = 4;
   p->n_lambda_override = 0;
   p->lambda_override = nullptr;
+  p->coarse_mode = 0;
+  p->coarse_degree = 16;
+  p->coarse_ratio = 30.0;
+  p->coarse_dofs = (int)kDenseCoarseLimit;
 }
 
 int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* params, mfq_solver** out) {
@@ -368,6 +538,11 @@ int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* par
   if (prm.check_every < 1) prm.check_every = 1;
   if (!(prm.lambda_ratio > 1) || !(prm.lambda_factor > 0)) return fail(MFQ_EINVAL, "bad Chebyshev interval parameters");
   if (!(prm.inner_rtol > 0 && prm.inner_rtol < 1)) return fail(MFQ_EINVAL, "inner_rtol must be in (0,1)");
+  if (prm.coarse_mode != 0 && prm.coarse_mode != 1) return fail(MFQ_EINVAL, "coarse_mode must be 0 or 1");
+  if (prm.coarse_degree < 1 || prm.coarse_degree > 256) return fail(MFQ_EINVAL, "coarse_degree out of range");
+  if (!(prm.coarse_ratio > 1)) return fail(MFQ_EINVAL, "coarse_ratio must exceed 1");
+  if (prm.coarse_dofs < 1 || prm.coarse_dofs > kDenseCoarseLimit)
+    return fail(MFQ_EINVAL, "coarse_dofs must be in [1, %d]", (int)kDenseCoarseLimit);
   mfq_solver* s = new (std::nothrow) mfq_solver();
   if (!s) return fail(MFQ_ENOMEM, "host allocation failed");
   s->op64 = op64;
@@ -391,11 +566,12 @@ int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* par
     std::vector<std::pair<int, int>> spec;
     int p = fs->p, n = fs->mesh->n;
     spec.push_back({p, n});
-    while (n % 2 == 0 && n_free(p, n) > kDenseCoarseLimit) {
+    const int64_t limit = prm.coarse_dofs;
+    while (n % 2 == 0 && n_free(p, n) > limit) {
       n /= 2;
       spec.push_back({p, n});
     }
-    while (p > 1 && n_free(p, n) > kDenseCoarseLimit) {
+    while (p > 1 && n_free(p, n) > limit) {
       p = (p + 1) / 2;
       spec.push_back({p, n});
     }
@@ -421,7 +597,7 @@ int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* par
       if (l + 1 == spec.size() && prec == MFQ_FP64) {
         L.op = const_cast<mfq_op*>(op64);
         L.owns_op = false;
-      } else if (l > 0 || (l + 1 == spec.size() && kind == MFQ_SOLVER_GMG_MIXED_IR)) {
+      } else if (l > 0 || prm.coarse_mode == 1 || (l + 1 == spec.size() && kind == MFQ_SOLVER_GMG_MIXED_IR)) {
         if (int rc2 = mfq_op_create(L.sp, op64->alpha, prec, &L.op)) {
           delete s;
           return rc2;
@@ -448,7 +624,13 @@ int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* par
     // coarse level
     Level& C = s->lv[0];
     s->nf = n_free(C.sp->p, C.sp->mesh->n);
-    s->dense = s->nf <= kDenseCoarseLimit;
+    s->dense = s->nf <= limit;
+    if (prm.coarse_mode == 1) {
+      s->dense = false;
+      s->bytes = off;
+      *out = s;
+      return MFQ_OK;
+    }
     if (int rc = mfq_op_create(C.sp, op64->alpha, MFQ_FP64, &s->coarse64)) {
       delete s;
       return rc;
@@ -482,6 +664,10 @@ int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream
   if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) % 256)) return fail(MFQ_EINVAL, "buffer NULL or misaligned");
   if (bytes < s->bytes) return fail(MFQ_ENOMEM, "buffer of %zu bytes, solver needs %zu", bytes, s->bytes);
   hipStream_t st = (hipStream_t)hip_stream;
+  if (!s->hstat) {
+    MFQ_HIP(hipHostMalloc((void**)&s->hstat, sizeof(mfq_solver::HostStatus), hipHostMallocDefault));
+    std::memset(s->hstat, 0, sizeof(mfq_solver::HostStatus));
+  }
   char* base = (char*)dev_buf;
   s->buf = dev_buf;
   s->state = (SolverState*)(base + s->off_state);
@@ -516,21 +702,33 @@ int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream
       if (int rc = mfq_op_bind(L.op, base + L.off_op, ob, st)) return rc;
     }
   }
-  size_t cb;
-  mfq_op_device_bytes(s->coarse64, &cb);
-  if (int rc = mfq_op_bind(s->coarse64, base + s->off_coarse64, cb, st)) return rc;
+  if (s->coarse64) {
+    size_t cb;
+    mfq_op_device_bytes(s->coarse64, &cb);
+    if (int rc = mfq_op_bind(s->coarse64, base + s->off_coarse64, cb, st)) return rc;
+  }
 
-  // diagonals and eigenvalue bounds of the smoothed levels
-  for (size_t l = 1; l < s->lv.size(); ++l) {
+  // diagonals and eigenvalue bounds of the smoothed levels (and of the Chebyshev coarse level)
+  const size_t l0 = s->prm.coarse_mode == 1 ? 0 : 1;
+  for (size_t l = l0; l < s->lv.size(); ++l) {
     Level& L = s->lv[l];
     if (int rc = op_diagonal(L.op, L.dinv, st)) return rc;
     MFQ_HIP(launch_reciprocal(prec, L.dinv, L.n, st));
     if (int rc = estimate_lambda(s, L, st)) return rc;
-    const int idx = (int)l - 1;
     double lmax = s->prm.lambda_factor * L.lhat;
+    if (l == 0) {
+      L.lmax = lmax;
+      L.lmin = lmax / s->prm.coarse_ratio;
+      continue;
+    }
+    const int idx = (int)l - 1;
     if (s->prm.n_lambda_override > idx && s->prm.lambda_override) lmax = s->prm.lambda_override[idx];
     L.lmax = lmax;
     L.lmin = lmax / s->prm.lambda_ratio;
+  }
+  if (s->prm.coarse_mode == 1) {
+    MFQ_HIP(hipStreamSynchronize(st));
+    return MFQ_OK;
   }
   // coarse level
   Level& C = s->lv[0];
@@ -584,86 +782,65 @@ int mfq_solver_lambdas(const mfq_solver* s, double* out, int n_out) {
 
 int mfq_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_iter, void* hip_stream,
               mfq_solve_info* info) {
-  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
-  if (!s->buf) return fail(MFQ_EINVAL, "solver is not bound");
-  if (!b || !x || (reinterpret_cast<uintptr_t>(b) % 16) || (reinterpret_cast<uintptr_t>(x) % 16))
-    return fail(MFQ_EINVAL, "b or x NULL or misaligned");
-  if (!(rtol > 0 && rtol < 1)) return fail(MFQ_EINVAL, "rtol must be in (0,1)");
-  if (max_iter < 1) return fail(MFQ_EINVAL, "max_iter must be >= 1");
-  hipStream_t st = (hipStream_t)hip_stream;
-  const auto t0 = std::chrono::steady_clock::now();
-  const int64_t N = s->op64->space->n_dofs;
-  Apply A64 = [s, st](const double* in, double* out) { return op_vmult(s->op64, in, out, st); };
-  Apply M = [s, st](const double* in, double* out) { return precondition(s, in, out, st); };
-  mfq_solve_info inf{};
-  inf.n_levels = (int)s->lv.size();
-  int status = MFQ_OK;
-  PcgResult res;
-  if (s->kind != MFQ_SOLVER_GMG_MIXED_IR) {
-    const Apply* prec = (s->kind == MFQ_SOLVER_CG) ? nullptr : &M;
-    if (int rc = pcg(A64, prec, b, x, s->r, s->p, s->Ap, s->z, N, s->state, rtol, max_iter, s->prm.check_every, st, res))
+  if (int rc = begin_solve(s, b, x, rtol, max_iter, (hipStream_t)hip_stream)) return rc;
+  mfq_solver* const one[1] = {s};
+  int done = 0;
+  while (!done)
+    if (int rc = mfq_batch_step(one, 1, s->prm.check_every, &done)) {
+      s->run.phase = Run::kIdle;
       return rc;
-    inf.iterations = res.iters;
-    inf.outer_iterations = 1;
-    if (res.nonfinite) status = MFQ_ENONFINITE;
-    else if (!res.converged) status = MFQ_ENOCONV;
-  } else {
-    // iterative refinement: r = b - A64 x (FP64); inner CG on FP32 operators, FP64 vectors
-    Level& F = s->lv.back();
-    Apply A32 = [s, st, &F](const double* in, double* out) -> int {
-      MFQ_HIP(launch_cast(MFQ_FP64, in, MFQ_FP32, F.r, F.n, st));
-      if (int rc = op_vmult(F.op, F.r, F.d, st)) return rc;
-      MFQ_HIP(launch_cast(MFQ_FP32, F.d, MFQ_FP64, out, F.n, st));
-      return MFQ_OK;
-    };
-    MFQ_HIP(launch_fill(MFQ_FP64, x, N, 0.0, st));
-    double bb = -1, rr = 0;
-    int total = 0, outer = 0;
-    for (;;) {
-      if (outer == 0) {
-        MFQ_HIP(launch_fill(MFQ_FP64, s->Ap, N, 0.0, st));
-      } else if (int rc = op_vmult(s->op64, x, s->Ap, st)) {
-        return rc;
-      }
-      MFQ_HIP(launch_residual_norm(b, s->Ap, s->rout, N, s->aux, s->scal, st));
-      MFQ_HIP(hipMemcpyAsync(&rr, s->scal, 8, hipMemcpyDeviceToHost, st));
-      MFQ_HIP(hipStreamSynchronize(st));
-      if (bb < 0) bb = rr;
-      if (!std::isfinite(rr)) {
-        status = MFQ_ENONFINITE;
-        break;
-      }
-      if (rr <= rtol * rtol * bb || bb == 0) break;
-      if (total >= max_iter) {
-        status = MFQ_ENOCONV;
-        break;
-      }
-      if (int rc = pcg(A32, &M, s->rout, s->c, s->r, s->p, s->Ap, s->z, N, s->state, s->prm.inner_rtol,
-                       max_iter - total, s->prm.check_every, st, res))
-        return rc;
-      total += std::max(res.iters, 1);
-      if (res.nonfinite) {
-        status = MFQ_ENONFINITE;
-        break;
-      }
-      MFQ_HIP(launch_add(MFQ_FP64, x, MFQ_FP64, s->c, N, st));
-      ++outer;
     }
-    inf.iterations = total;
-    inf.outer_iterations = outer;
+  return mfq_solve_end(s, info);
+}
+
+int mfq_solve_begin(mfq_solver* s, const double* b, double* x, double rtol, int max_iter, void* hip_stream) {
+  return begin_solve(s, b, x, rtol, max_iter, (hipStream_t)hip_stream);
+}
+
+int mfq_batch_step(mfq_solver* const* solvers, int count, int iters, int* done) {
+  if (count < 0 || (count > 0 && (!solvers || !done))) return fail(MFQ_EINVAL, "bad solver list");
+  if (iters < 1) return fail(MFQ_EINVAL, "iters must be >= 1");
+  for (int i = 0; i < count; ++i) {
+    mfq_solver* s = solvers[i];
+    if (!s || s->run.phase == Run::kIdle) return fail(MFQ_EINVAL, "solver %d has no running solve", i);
   }
-  // true residual certificate
-  if (int rc = op_vmult(s->op64, x, s->Ap, st)) return rc;
-  MFQ_HIP(launch_residual_norm(b, s->Ap, nullptr, N, s->aux, s->scal, st));
-  double rr = 0, bb = 0;
-  MFQ_HIP(hipMemcpyAsync(&rr, s->scal, 8, hipMemcpyDeviceToHost, st));
-  MFQ_HIP(launch_dot(MFQ_FP64, b, b, N, s->aux, s->scal, st));
-  MFQ_HIP(hipMemcpyAsync(&bb, s->scal, 8, hipMemcpyDeviceToHost, st));
-  MFQ_HIP(hipStreamSynchronize(st));
-  inf.rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
-  inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+  for (int i = 0; i < count; ++i) {
+    mfq_solver* s = solvers[i];
+    if (s->run.phase != Run::kDone)
+      if (int rc = step_enqueue(s, iters)) return rc;
+  }
+  // one wait per distinct stream, then every solve's outcome is in pinned host memory
+  std::vector<hipStream_t> seen;
+  for (int i = 0; i < count; ++i) {
+    mfq_solver* s = solvers[i];
+    if (s->run.phase == Run::kDone) continue;
+    if (std::find(seen.begin(), seen.end(), s->run.st) != seen.end()) continue;
+    seen.push_back(s->run.st);
+    MFQ_HIP(hipStreamSynchronize(s->run.st));
+  }
+  for (int i = 0; i < count; ++i) {
+    mfq_solver* s = solvers[i];
+    if (s->run.phase != Run::kDone)
+      if (int rc = step_collect(s)) return rc;
+    done[i] = s->run.phase == Run::kDone ? 1 : 0;
+  }
+  return MFQ_OK;
+}
+
+int mfq_solve_end(mfq_solver* s, mfq_solve_info* info) {
+  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
+  Run& R = s->run;
+  if (R.phase != Run::kDone) return fail(MFQ_EINVAL, "no finished solve");
+  mfq_solve_info inf{};
+  inf.iterations = R.iters;
+  inf.outer_iterations = R.pass;
+  inf.rel_residual = R.bb > 0 ? std::sqrt(R.rr / R.bb) : 0.0;
+  inf.seconds = R.seconds;
+  inf.n_levels = (int)s->lv.size();
   if (info) *info = inf;
-  if (status == MFQ_ENOCONV) return fail(MFQ_ENOCONV, "no convergence to %g within %d iterations", rtol, max_iter);
+  const int status = R.status;
+  R.phase = Run::kIdle;
+  if (status == MFQ_ENOCONV) return fail(MFQ_ENOCONV, "no convergence to %g within %d iterations", R.rtol, R.max_iter);
   if (status == MFQ_ENONFINITE) return fail(MFQ_ENONFINITE, "non-finite residual");
   return MFQ_OK;
 }

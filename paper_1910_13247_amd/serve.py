@@ -1,0 +1,246 @@
+"""Serving loop: continuous batching of solve requests on one device.
+
+Requests (degree, mesh size, coefficient, right-hand-side seed) arrive as host events.  The
+scheduler admits them first come, first served while the sum of the admitted requests' device
+footprints stays within a byte budget, and keeps every admitted request's mesh, geometry,
+multigrid hierarchy and Krylov state on the device until it finishes.  Each scheduler step
+advances all running solves together (``mfq_batch_step``: a few CG iterations of each on its own
+stream, one wait and one device-to-host status copy per request), retires the finished ones and
+frees their memory, so requests that arrive while others run join at the next step.
+
+The solver of a request is GMG_MIXED (FP64 CG, FP64 operator and dot products, FP32 multigrid
+V-cycle) with an FP64 true-residual check and refinement passes until the relative residual is
+at most ``rtol``; its coarsest level uses the Chebyshev mode, so no solve ever waits on the host
+between steps.  This batching of independent requests is a serving pattern, not part of the
+paper's method.
+"""
+import dataclasses
+import math
+import time
+from typing import List, Optional
+
+from . import _lib
+from ._lib import MFQ_BC_DIRICHLET0, MFQ_FP64, MFQ_SOLVER_GMG_MIXED, MFQ_OK
+
+
+@dataclasses.dataclass
+class Request:
+    degree: int
+    n: int
+    alpha: float
+    seed: int
+    amplitude: float = 0.0
+    rtol: float = 1e-10
+    max_iter: int = 1000
+    # filled in by the server
+    id: int = -1
+    arrival: float = math.nan
+    admitted: float = math.nan
+    finished: float = math.nan
+    status: Optional[int] = None
+    iterations: int = 0
+    rel_residual: float = math.nan
+    footprint: int = 0
+    result: object = None  # solution (device tensor) when the server keeps results
+
+    @property
+    def latency(self):
+        return self.finished - self.arrival
+
+
+class DeviceExecutor:
+    """Builds and runs requests with the library; device memory comes from torch."""
+
+    def __init__(self, n_streams=4, keep_results=False, solver_kind=MFQ_SOLVER_GMG_MIXED, **solver_params):
+        import torch
+        self.torch = torch
+        # default-priority streams; requests are spread over them round-robin
+        self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
+        self.keep_results = keep_results
+        self.kind = solver_kind
+        self.params = dict(coarse_mode=1)
+        self.params.update(solver_params)
+        self._next_stream = 0
+
+    def prepare(self, req):
+        """Host-side handles and the device footprint in bytes (nothing allocated on the device)."""
+        h = {}
+        h["mesh"] = _lib.mfq_mesh_create(req.n, req.amplitude)
+        h["space"] = _lib.mfq_space_create(h["mesh"], req.degree, MFQ_BC_DIRICHLET0)
+        h["op"] = _lib.mfq_op_create(h["space"], req.alpha, MFQ_FP64)
+        prm = _lib.mfq_solver_default_params()
+        for k, v in self.params.items():
+            setattr(prm, k, v)
+        h["prm"] = prm
+        h["solver"] = _lib.mfq_solver_create(h["op"], self.kind, prm)
+        h["N"] = _lib.mfq_space_n_dofs(h["space"])
+        h["op_bytes"] = _lib.mfq_op_device_bytes(h["op"])
+        h["solver_bytes"] = _lib.mfq_solver_device_bytes(h["solver"])
+        vec = -(-h["N"] * 8 // 256) * 256
+        h["bytes"] = h["op_bytes"] + h["solver_bytes"] + 2 * vec
+        return h
+
+    def start(self, req, h):
+        """Allocate, set up (geometry, hierarchy, eigenvalue estimates) and begin the solve."""
+        torch = self.torch
+        st = self.streams[self._next_stream % len(self.streams)]
+        self._next_stream += 1
+        h["stream"] = st
+        with torch.cuda.stream(st):
+            h["op_buf"] = torch.empty(max(h["op_bytes"], 256), dtype=torch.uint8, device="cuda")
+            h["solver_buf"] = torch.empty(max(h["solver_bytes"], 256), dtype=torch.uint8, device="cuda")
+            h["b"] = torch.empty(h["N"], dtype=torch.float64, device="cuda")
+            h["x"] = torch.empty(h["N"], dtype=torch.float64, device="cuda")
+        sp = st.cuda_stream
+        _lib.mfq_op_bind(h["op"], h["op_buf"].data_ptr(), h["op_bytes"], sp)
+        _lib.mfq_solver_bind(h["solver"], h["solver_buf"].data_ptr(), h["solver_bytes"], sp)
+        _lib.mfq_space_random(h["space"], MFQ_FP64, h["b"].data_ptr(), req.seed, sp)
+        _lib.mfq_solve_begin(h["solver"], h["b"].data_ptr(), h["x"].data_ptr(), req.rtol, req.max_iter, sp)
+
+    def step(self, handles, iters):
+        return _lib.mfq_batch_step([h["solver"] for h in handles], iters)
+
+    def finish(self, req, h):
+        status, info = _lib.mfq_solve_end(h["solver"], check=False)
+        req.status = status
+        req.iterations = info.iterations
+        req.rel_residual = info.rel_residual
+        if self.keep_results:
+            req.result = h["x"]
+
+    def release(self, h):
+        if h.get("solver"):
+            _lib.mfq_solver_destroy(h["solver"])
+        if h.get("op"):
+            _lib.mfq_op_destroy(h["op"])
+        if h.get("space"):
+            _lib.mfq_space_destroy(h["space"])
+        if h.get("mesh"):
+            _lib.mfq_mesh_destroy(h["mesh"])
+        h.clear()
+
+
+class Server:
+    """FIFO admission by device footprint, continuous batching, latency accounting."""
+
+    def __init__(self, executor, budget_bytes, iters_per_step=2, max_active=256, clock=time.perf_counter):
+        self.ex = executor
+        self.budget = int(budget_bytes)
+        self.iters = int(iters_per_step)
+        self.max_active = int(max_active)
+        self.clock = clock
+        self.queue: List[Request] = []      # arrived, waiting for admission (FIFO)
+        self.active = []                    # (request, handles)
+        self.done: List[Request] = []
+        self.rejected: List[Request] = []
+        self.used = 0
+        self.steps = 0
+        self.peak_used = 0
+        self.peak_active = 0
+        self._next_id = 0
+        self._head = None  # prepared handles of the request at the head of the queue
+
+    def submit(self, req, now=None):
+        req.id = self._next_id
+        self._next_id += 1
+        req.arrival = self.clock() if now is None else now
+        self.queue.append(req)
+        return req.id
+
+    def _admit(self):
+        while self.queue and len(self.active) < self.max_active:
+            req = self.queue[0]
+            if self._head is None:
+                self._head = self.ex.prepare(req)
+            h = self._head
+            if h["bytes"] > self.budget:
+                # can never fit: reject instead of blocking the queue
+                self.queue.pop(0)
+                self._head = None
+                self.ex.release(h)
+                req.status = _lib.MFQ_ENOMEM
+                req.finished = self.clock()
+                self.rejected.append(req)
+                continue
+            if self.used + h["bytes"] > self.budget:
+                break  # waits (with its prepared handles) until memory frees up
+            self.queue.pop(0)
+            self._head = None
+            req.footprint = h["bytes"]
+            self.used += h["bytes"]
+            req.admitted = self.clock()
+            self.ex.start(req, h)
+            self.active.append((req, h))
+        self.peak_used = max(self.peak_used, self.used)
+        self.peak_active = max(self.peak_active, len(self.active))
+
+    def step(self):
+        """Admit what fits, advance every running solve once, retire the finished ones.
+        Returns the requests finished in this step."""
+        self._admit()
+        if not self.active:
+            return []
+        flags = self.ex.step([h for _, h in self.active], self.iters)
+        self.steps += 1
+        now = self.clock()
+        finished, still = [], []
+        for (req, h), d in zip(self.active, flags):
+            if d:
+                self.ex.finish(req, h)
+                req.finished = now
+                self.used -= req.footprint
+                self.ex.release(h)
+                finished.append(req)
+            else:
+                still.append((req, h))
+        self.active = still
+        self.done.extend(finished)
+        return finished
+
+    @property
+    def idle(self):
+        return not self.queue and not self.active
+
+    def drain(self):
+        while not self.idle:
+            self.step()
+
+    def stats(self):
+        lat = sorted(r.latency for r in self.done)
+        ok = [r for r in self.done if r.status == MFQ_OK]
+        out = {"requests": len(self.done), "converged": len(ok), "rejected": len(self.rejected),
+               "steps": self.steps, "peak_active": self.peak_active, "peak_bytes": self.peak_used}
+        if lat:
+            first = min(r.arrival for r in self.done)
+            last = max(r.finished for r in self.done)
+            out["solves_per_s"] = len(self.done) / max(last - first, 1e-9)
+            out["p50_s"] = percentile(lat, 50)
+            out["p99_s"] = percentile(lat, 99)
+            out["max_rel_residual"] = max(r.rel_residual for r in self.done)
+        return out
+
+
+def percentile(sorted_values, q):
+    """Nearest-rank percentile of an ascending list."""
+    if not sorted_values:
+        return math.nan
+    k = max(0, min(len(sorted_values) - 1, math.ceil(q / 100.0 * len(sorted_values)) - 1))
+    return sorted_values[k]
+
+
+def run_stream(server, requests, arrivals, sleep=time.sleep):
+    """Replays `requests` arriving at offsets `arrivals` (seconds from now): submits each when its
+    time has come, steps the server meanwhile, and returns when all have finished."""
+    t0 = server.clock()
+    i = 0
+    n = len(requests)
+    while i < n or not server.idle:
+        now = server.clock() - t0
+        while i < n and arrivals[i] <= now:
+            server.submit(requests[i], now=t0 + arrivals[i])
+            i += 1
+        if server.idle and i < n:
+            sleep(max(0.0, arrivals[i] - (server.clock() - t0)))
+            continue
+        server.step()
+    return server.stats()

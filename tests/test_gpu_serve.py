@@ -1,0 +1,170 @@
+"""Resumable solves and the serving loop on the GPU: the batch step equals the blocking solve,
+each request's result is the same alone and in a mix, served solutions match the oracle, and
+admission respects a tight memory budget."""
+import numpy as np
+import pytest
+
+from oracle import assemble, gmg, mesh, solve
+
+pytestmark = pytest.mark.gpu
+
+# a mix of degrees and mesh sizes, even and odd n (odd n: no h-coarsening, p-levels only)
+MIX = [(1, 9, 0.7), (2, 6, 0.3), (3, 5, 0.0), (4, 4, 0.9), (2, 11, 0.5), (3, 8, 0.2)]
+
+
+def _mfq():
+    import paper_1910_13247_amd as mfq
+    return mfq
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _requests(rtol=1e-10):
+    from paper_1910_13247_amd.serve import Request
+    return [Request(degree=p, n=n, alpha=a, seed=100 + i, rtol=rtol) for i, (p, n, a) in enumerate(MIX)]
+
+
+def _serve(reqs, budget=8 << 30, **kw):
+    from paper_1910_13247_amd.serve import DeviceExecutor, Server
+    srv = Server(DeviceExecutor(keep_results=True), budget, **kw)
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    _torch().cuda.synchronize()
+    return srv
+
+
+def test_space_random_matches_counter_definition():
+    mfq = _mfq()
+    m = mfq.Mesh(3, 0.0)
+    s = mfq.Space(m, 2, mfq.MFQ_BC_DIRICHLET0)
+    x = s.random(12345).cpu().numpy()
+    ref = gmg.splitmix64_uniform(s.n_dofs, 12345) * mesh.boundary_mask(2, 3)
+    np.testing.assert_array_equal(x, ref)
+
+
+def test_batch_step_equals_blocking_solve():
+    """Same solver driven by mfq_solve and by begin / batch_step / end with the step length equal
+    to the poll period (the same launches in the same order): equal iteration counts, solutions
+    equal up to the rounding of the restriction's atomic sums."""
+    mfq = _mfq()
+    torch = _torch()
+    print("batch step vs blocking", flush=True)
+    m = mfq.Mesh(8, 0.1)
+    s = mfq.Space(m, 3, mfq.MFQ_BC_DIRICHLET0)
+    op = mfq.Operator(s, 0.5, mfq.MFQ_FP64)
+    b = op.rhs_manufactured()
+    sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, check_every=3)
+    x1, info1, st1 = sv.solve(b, rtol=1e-10, max_iter=200)
+    x2 = op.new_vector()
+    sv.begin(b, x2, rtol=1e-10, max_iter=200)
+    steps = 0
+    while not mfq.batch_step([sv], iters=3)[0]:
+        steps += 1
+        assert steps < 1000
+    st2, info2 = sv.end()
+    torch.cuda.synchronize()
+    assert st1 == st2 == mfq.MFQ_OK
+    assert info1.iterations == info2.iterations and info1.outer_iterations == info2.outer_iterations
+    assert info1.rel_residual <= 1e-10 and info2.rel_residual <= 1e-10
+    assert (x1 - x2).abs().max().item() <= 1e-8 * x1.abs().max().item()
+
+
+def test_resumable_errors():
+    mfq = _mfq()
+    _lib = mfq._lib
+    m = mfq.Mesh(4, 0.0)
+    s = mfq.Space(m, 2, mfq.MFQ_BC_DIRICHLET0)
+    op = mfq.Operator(s, 0.0, mfq.MFQ_FP64)
+    b = s.random(1)
+    x = op.new_vector()
+    sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED)
+    with pytest.raises(_lib.MfqError) as e:
+        sv.end()
+    assert e.value.status == mfq.MFQ_EINVAL
+    sv.begin(b, x)
+    with pytest.raises(_lib.MfqError) as e:
+        sv.begin(b, x)
+    assert e.value.status == mfq.MFQ_EBUSY
+    while not mfq.batch_step([sv], iters=2)[0]:
+        pass
+    st, info = sv.end()
+    assert st == mfq.MFQ_OK and info.rel_residual <= 1e-10
+    sv.begin(b, x)  # a finished solver can run the next solve
+    while not mfq.batch_step([sv], iters=2)[0]:
+        pass
+    assert sv.end()[0] == mfq.MFQ_OK
+
+
+def test_cg_true_residual_certified():
+    """Plain CG stops on its recurred residual; the residual check adds FP64 correction passes
+    until the true residual meets rtol."""
+    mfq = _mfq()
+    print("cg certified", flush=True)
+    m = mfq.Mesh(12, 0.1)
+    s = mfq.Space(m, 3, mfq.MFQ_BC_DIRICHLET0)
+    op = mfq.Operator(s, 0.5, mfq.MFQ_FP64)
+    b = op.rhs_manufactured()
+    sv = mfq.Solver(op, mfq.MFQ_SOLVER_CG)
+    x, info, st = sv.solve(b, rtol=1e-10, max_iter=20000)
+    assert st == mfq.MFQ_OK and info.rel_residual <= 1e-10
+    At = assemble.operator_csr(3, 12, 0.1, 0.5, 1)
+    assert solve.rel_residual(lambda v: At @ v, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10
+
+
+def test_served_results_match_oracle():
+    """Each served request solves its own system: the solution agrees with a sparse direct solve
+    of the oracle's assembled operator for the same counter-based right-hand side."""
+    print("serve vs oracle", flush=True)
+    reqs = _requests()
+    srv = _serve(reqs)
+    assert len(srv.done) == len(reqs)
+    for r in reqs:
+        assert r.status == 0 and r.rel_residual <= 1e-10, (r.degree, r.n, r.rel_residual)
+        A = assemble.operator_csr(r.degree, r.n, 0.0, r.alpha, 1)
+        N = A.shape[0]
+        b = gmg.splitmix64_uniform(N, r.seed) * mesh.boundary_mask(r.degree, r.n)
+        x = r.result.cpu().numpy()
+        assert solve.rel_residual(lambda v: A @ v, b, x) <= 1e-10
+        xd = solve.direct_solve(A, b)
+        # relative residual 1e-10 bounds the error by cond(A) * 1e-10; cond < 1e4 here
+        assert np.abs(x - xd).max() <= 1e-6 * np.abs(xd).max(), (r.degree, r.n)
+
+
+def test_alone_and_in_mix_agree():
+    """The same request alone and among others: equal iteration counts and solutions equal
+    within what the 1e-10 residual tolerance allows (both are certified)."""
+    print("alone vs mix", flush=True)
+    mixed = _requests()
+    _serve(mixed)
+    for i, p in enumerate(MIX):
+        alone = _requests()[i]
+        _serve([alone])
+        m = mixed[i]
+        assert alone.status == m.status == 0
+        assert abs(alone.iterations - m.iterations) <= 1, (p, alone.iterations, m.iterations)
+        xa, xm = alone.result.cpu().numpy(), m.result.cpu().numpy()
+        assert np.abs(xa - xm).max() <= 1e-7 * np.abs(xa).max(), p
+
+
+def test_tight_budget_serialises_admission():
+    """With a budget that holds only the largest request, no two large requests are resident at
+    once, and every request still finishes, in FIFO admission order."""
+    from paper_1910_13247_amd.serve import DeviceExecutor
+    print("tight budget", flush=True)
+    reqs = _requests()
+    ex = DeviceExecutor()
+    sizes = []
+    for r in reqs:
+        h = ex.prepare(r)
+        sizes.append(h["bytes"])
+        ex.release(h)
+    budget = max(sizes) + min(sizes) - 1
+    srv = _serve(reqs, budget=budget)
+    assert srv.peak_used <= budget
+    assert all(r.status == 0 for r in reqs)
+    adm = sorted(reqs, key=lambda r: r.admitted)
+    assert [r.id for r in adm] == sorted(r.id for r in reqs)

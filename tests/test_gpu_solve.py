@@ -130,3 +130,39 @@ def test_zero_rhs_gives_zero_solution():
     for kind in (0, 2, 3):
         x, info, _ = mfq.Solver(op, kind).solve(b, rtol=1e-10)
         assert x.abs().max().item() == 0.0
+
+
+@pytest.mark.parametrize("kind", [0, 1, 2, 3])
+def test_solvers_need_no_initialised_memory(kind):
+    """Operator, solver and solution buffers filled with NaN bit patterns before binding: every
+    value the solve reads must have been written by the library first (regression: the first CG
+    direction once read the previous contents of p)."""
+    mfq = _mfq()
+    torch = _torch()
+    _lib = mfq._lib
+    print(f"nan-filled buffers kind={kind}", flush=True)
+    p, n = 3, 8
+    m = _lib.mfq_mesh_create(n, 0.1)
+    s = _lib.mfq_space_create(m, p, mfq.MFQ_BC_DIRICHLET0)
+    op = _lib.mfq_op_create(s, 0.5, mfq.MFQ_FP64)
+    ob = _lib.mfq_op_device_bytes(op)
+    obuf = torch.full((ob,), 0xFF, dtype=torch.uint8, device="cuda")
+    st = torch.cuda.current_stream().cuda_stream
+    _lib.mfq_op_bind(op, obuf.data_ptr(), ob, st)
+    prm = _lib.mfq_solver_default_params()
+    sv = _lib.mfq_solver_create(op, kind, prm)
+    sb = _lib.mfq_solver_device_bytes(sv)
+    sbuf = torch.full((sb,), 0xFF, dtype=torch.uint8, device="cuda")
+    _lib.mfq_solver_bind(sv, sbuf.data_ptr(), sb, st)
+    N = _lib.mfq_space_n_dofs(s)
+    b = torch.full((N,), float("nan"), dtype=torch.float64, device="cuda")
+    x = torch.full((N,), float("nan"), dtype=torch.float64, device="cuda")
+    _lib.mfq_rhs_manufactured(op, b.data_ptr(), st)
+    status, info = _lib.mfq_solve(sv, b.data_ptr(), x.data_ptr(), 1e-10, 5000, st)
+    torch.cuda.synchronize()
+    assert status == mfq.MFQ_OK and info.rel_residual <= 1e-10
+    assert bool(torch.isfinite(x).all())
+    _lib.mfq_solver_destroy(sv)
+    _lib.mfq_op_destroy(op)
+    _lib.mfq_space_destroy(s)
+    _lib.mfq_mesh_destroy(m)
