@@ -192,6 +192,9 @@ typedef struct {
   int coarse_degree;       /* Chebyshev degree on the coarsest level in coarse_mode 1 (default 16) */
   double coarse_ratio;     /* its interval [lmax/coarse_ratio, lmax] (default 30) */
   int coarse_dofs;         /* coarsening stops at this many free DoFs (default 4096, at most 4096) */
+  int use_graphs;          /* 1 (default): on a non-default stream, each CG iteration is captured
+                              once as a HIP graph and replayed (not when a Jacobi-CG coarse solve
+                              must poll the host); 0: launches issued one by one */
 } mfq_solver_params;
 
 typedef struct {

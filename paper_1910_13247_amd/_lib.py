@@ -30,7 +30,7 @@ class SolverParams(C.Structure):
                 ("lambda_ratio", C.c_double), ("inner_rtol", C.c_double), ("check_every", C.c_int),
                 ("n_lambda_override", C.c_int), ("lambda_override", C.POINTER(C.c_double)),
                 ("coarse_mode", C.c_int), ("coarse_degree", C.c_int), ("coarse_ratio", C.c_double),
-                ("coarse_dofs", C.c_int)]
+                ("coarse_dofs", C.c_int), ("use_graphs", C.c_int)]
 
 
 class OpLayout(C.Structure):

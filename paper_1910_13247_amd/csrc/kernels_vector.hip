@@ -324,6 +324,91 @@ __global__ __launch_bounds__(kVBlock) void splitmix_kernel(Real* __restrict__ x,
   }
 }
 
+// ---------------------------------------------------------------- device-side Lanczos
+// Largest-eigenvalue estimate of D^{-1} A from k steps of Jacobi-preconditioned CG (the CG
+// coefficients give the Lanczos tridiagonal matrix).  Scalars stay in a SolverState (rz, alpha,
+// beta, iter, done); step j records trace[2j] = alpha_j, trace[2j+1] = beta_j and the count of
+// completed steps in trace[count_slot], so the host reads the whole run once at the end.
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void lz_init_kernel(const Real* __restrict__ r, const Real* __restrict__ dinv,
+                                                          Real* __restrict__ z, Real* __restrict__ p, int64_t n,
+                                                          SolverState* st, double* trace, int count_slot) {
+  __shared__ double sh[kVBlock / 64];
+  double part = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
+    const Real zv = dinv[i] * r[i];
+    z[i] = zv;
+    p[i] = zv;
+    part += (double)r[i] * (double)zv;
+  }
+  part = block_sum(part, sh);
+  double tot;
+  if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) {
+    st->rz = tot;
+    st->iter = 0;
+    st->done = (tot > 0) ? 0 : 1;
+    trace[count_slot] = 0.0;
+  }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void lz_alpha_kernel(const Real* __restrict__ p, const Real* __restrict__ Ap,
+                                                           int64_t n, SolverState* st, double* trace) {
+  __shared__ double sh[kVBlock / 64];
+  if (st->done) return;
+  double part = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    part += (double)p[i] * (double)Ap[i];
+  part = block_sum(part, sh);
+  double tot;
+  if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) {
+    if (tot > 0) {
+      st->alpha = st->rz / tot;
+      trace[2 * st->iter] = st->alpha;
+    } else {
+      st->done = 1;
+    }
+  }
+}
+
+// r -= alpha Ap ; z = dinv r ; beta = r.z / rz ; rz = r.z
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void lz_update_kernel(Real* __restrict__ r, Real* __restrict__ z,
+                                                            const Real* __restrict__ Ap, const Real* __restrict__ dinv,
+                                                            int64_t n, SolverState* st, double* trace, int count_slot) {
+  __shared__ double sh[kVBlock / 64];
+  if (st->done) return;
+  const Real alpha = (Real)st->alpha;
+  double part = 0;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
+    const Real rv = r[i] - alpha * Ap[i];
+    const Real zv = dinv[i] * rv;
+    r[i] = rv;
+    z[i] = zv;
+    part += (double)rv * (double)zv;
+  }
+  part = block_sum(part, sh);
+  double tot;
+  if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) {
+    const double beta = tot / st->rz;
+    trace[2 * st->iter + 1] = beta;
+    st->beta = beta;
+    st->rz = tot;
+    st->iter += 1;
+    trace[count_slot] = (double)st->iter;
+    if (!(tot > 0)) st->done = 1;
+  }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(kVBlock) void lz_direction_kernel(const Real* __restrict__ z, Real* __restrict__ p,
+                                                               int64_t n, SolverState* st) {
+  if (st->done) return;
+  const Real beta = (Real)st->beta;
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    p[i] = z[i] + beta * p[i];
+}
+
 }  // namespace
 
 hipError_t launch_fill(int precision, void* x, int64_t n, double value, hipStream_t st) {
@@ -467,6 +552,42 @@ hipError_t launch_reciprocal(int precision, void* x, int64_t n, hipStream_t st) 
     reciprocal_kernel<float><<<g, kVBlock, 0, st>>>((float*)x, n);
   return hipGetLastError();
 }
+hipError_t launch_lz_init(int precision, const void* r, const void* dinv, void* z, void* p, int64_t n, SolverState* s,
+                          double* trace, int count_slot, hipStream_t st) {
+  if (precision == MFQ_FP64)
+    lz_init_kernel<double><<<vgrid(n), kVBlock, 0, st>>>((const double*)r, (const double*)dinv, (double*)z, (double*)p,
+                                                         n, s, trace, count_slot);
+  else
+    lz_init_kernel<float><<<vgrid(n), kVBlock, 0, st>>>((const float*)r, (const float*)dinv, (float*)z, (float*)p, n,
+                                                        s, trace, count_slot);
+  return hipGetLastError();
+}
+hipError_t launch_lz_alpha(int precision, const void* p, const void* Ap, int64_t n, SolverState* s, double* trace,
+                           hipStream_t st) {
+  if (precision == MFQ_FP64)
+    lz_alpha_kernel<double><<<vgrid(n), kVBlock, 0, st>>>((const double*)p, (const double*)Ap, n, s, trace);
+  else
+    lz_alpha_kernel<float><<<vgrid(n), kVBlock, 0, st>>>((const float*)p, (const float*)Ap, n, s, trace);
+  return hipGetLastError();
+}
+hipError_t launch_lz_update(int precision, void* r, void* z, const void* Ap, const void* dinv, int64_t n,
+                            SolverState* s, double* trace, int count_slot, hipStream_t st) {
+  if (precision == MFQ_FP64)
+    lz_update_kernel<double><<<vgrid(n), kVBlock, 0, st>>>((double*)r, (double*)z, (const double*)Ap,
+                                                           (const double*)dinv, n, s, trace, count_slot);
+  else
+    lz_update_kernel<float><<<vgrid(n), kVBlock, 0, st>>>((float*)r, (float*)z, (const float*)Ap, (const float*)dinv, n,
+                                                          s, trace, count_slot);
+  return hipGetLastError();
+}
+hipError_t launch_lz_direction(int precision, const void* z, void* p, int64_t n, SolverState* s, hipStream_t st) {
+  if (precision == MFQ_FP64)
+    lz_direction_kernel<double><<<vgrid(n) * 4, kVBlock, 0, st>>>((const double*)z, (double*)p, n, s);
+  else
+    lz_direction_kernel<float><<<vgrid(n) * 4, kVBlock, 0, st>>>((const float*)z, (float*)p, n, s);
+  return hipGetLastError();
+}
+
 hipError_t launch_splitmix(int precision, void* x, int64_t N1, uint64_t seed, bool masked, hipStream_t st) {
   const int g = vgrid(N1 * N1 * N1) * 4;
   if (precision == MFQ_FP64)

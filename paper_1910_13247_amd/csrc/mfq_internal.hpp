@@ -228,6 +228,14 @@ hipError_t launch_axpby(int precision, double a, const void* x, double b, void* 
 hipError_t launch_mul(int precision, const void* d, const void* r, void* z, int64_t n, hipStream_t st);
 hipError_t launch_reciprocal(int precision, void* x, int64_t n, hipStream_t st);
 hipError_t launch_splitmix(int precision, void* x, int64_t N1, uint64_t seed, bool masked, hipStream_t st);
+// device-side Lanczos (Jacobi-PCG) steps; trace[2j], trace[2j+1] = alpha_j, beta_j; trace[count_slot] = steps
+hipError_t launch_lz_init(int precision, const void* r, const void* dinv, void* z, void* p, int64_t n, SolverState* s,
+                          double* trace, int count_slot, hipStream_t st);
+hipError_t launch_lz_alpha(int precision, const void* p, const void* Ap, int64_t n, SolverState* s, double* trace,
+                           hipStream_t st);
+hipError_t launch_lz_update(int precision, void* r, void* z, const void* Ap, const void* dinv, int64_t n,
+                            SolverState* s, double* trace, int count_slot, hipStream_t st);
+hipError_t launch_lz_direction(int precision, const void* z, void* p, int64_t n, SolverState* s, hipStream_t st);
 
 // ---------------------------------------------------------------- host-side operator helpers (api.cpp)
 int op_vmult(const mfq_op* op, const void* src, void* dst, hipStream_t st);      // zero dst + cell loop

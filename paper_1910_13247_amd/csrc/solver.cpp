@@ -88,7 +88,24 @@ struct mfq_solver {
     std::chrono::steady_clock::time_point t0;
     double seconds = 0;
   } run;
+  // one CG iteration captured as a HIP graph per (stream, solution vector): a step replays it
+  // instead of issuing the iteration's ~100-200 kernel launches one by one
+  struct IterGraph {
+    hipStream_t st = nullptr;
+    double* sol = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  IterGraph graphs[2];
+  int next_graph = 0;
+  // Lanczos traces of the eigenvalue estimates (device region in the buffer, pinned host copy)
+  size_t off_trace = 0;
+  double* trace = nullptr;
+  double* trace_host = nullptr;
+  int trace_stride = 0;  // doubles per level: 2 * lanczos_iters coefficients + the step count
   ~mfq_solver() {
+    if (trace_host) (void)hipHostFree(trace_host);
+    for (IterGraph& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (hstat) (void)hipHostFree(hstat);
     for (Level& l : lv) {
       if (l.owns_op) mfq_op_destroy(l.op);
@@ -317,47 +334,35 @@ int precondition(mfq_solver* s, const double* r, double* z, hipStream_t st) {
   return MFQ_OK;
 }
 
-// lhat of D^{-1} A_l: Lanczos matrix of `iters` Jacobi-PCG steps on A_l x = v0 (v0 counter-based)
-int estimate_lambda(mfq_solver* s, Level& L, hipStream_t st) {
+// lhat of D^{-1} A_l: largest eigenvalue of the Lanczos matrix of `iters` Jacobi-PCG steps on
+// A_l x = v0 (v0 counter-based).  The steps run on the device; their coefficients land in the
+// level's trace slot, read by the host once for all levels.
+int enqueue_lanczos(mfq_solver* s, Level& L, double* trace, hipStream_t st) {
   const int prec = s->prec_v;
   const int64_t n = L.n;
   void *r = L.r, *zz = L.d, *p = L.t, *Ap = L.x;
+  const int k = s->prm.lanczos_iters;
   const int64_t N1 = (int64_t)L.sp->p * L.sp->mesh->n + 1;
   MFQ_HIP(launch_splitmix(prec, r, N1, 0, true, st));
-  MFQ_HIP(launch_mul(prec, L.dinv, r, zz, n, st));
-  MFQ_HIP(hipMemcpyAsync(p, zz, n * rsize(prec), hipMemcpyDeviceToDevice, st));
-  double rz = 0, pAp = 0;
-  MFQ_HIP(launch_dot(prec, r, zz, n, s->aux, s->scal, st));
-  MFQ_HIP(hipMemcpyAsync(&rz, s->scal, 8, hipMemcpyDeviceToHost, st));
-  MFQ_HIP(hipStreamSynchronize(st));
-  const int k = s->prm.lanczos_iters;
-  std::vector<double> alphas, betas;
+  MFQ_HIP(launch_lz_init(prec, r, L.dinv, zz, p, n, s->aux, trace, 2 * k, st));
   for (int it = 0; it < k; ++it) {
     if (int rc = op_vmult(L.op, p, Ap, st)) return rc;
-    MFQ_HIP(launch_dot(prec, p, Ap, n, s->aux, s->scal, st));
-    MFQ_HIP(hipMemcpyAsync(&pAp, s->scal, 8, hipMemcpyDeviceToHost, st));
-    MFQ_HIP(hipStreamSynchronize(st));
-    if (!(pAp > 0) || !(rz > 0)) break;
-    const double alpha = rz / pAp;
-    MFQ_HIP(launch_axpby(prec, -alpha, Ap, 1.0, r, n, st));
-    MFQ_HIP(launch_mul(prec, L.dinv, r, zz, n, st));
-    double rz_new = 0;
-    MFQ_HIP(launch_dot(prec, r, zz, n, s->aux, s->scal, st));
-    MFQ_HIP(hipMemcpyAsync(&rz_new, s->scal, 8, hipMemcpyDeviceToHost, st));
-    MFQ_HIP(hipStreamSynchronize(st));
-    const double beta = rz_new / rz;
-    alphas.push_back(alpha);
-    betas.push_back(beta);
-    MFQ_HIP(launch_axpby(prec, 1.0, zz, beta, p, n, st));
-    rz = rz_new;
-    if (!(rz > 0)) break;
+    MFQ_HIP(launch_lz_alpha(prec, p, Ap, n, s->aux, trace, st));
+    MFQ_HIP(launch_lz_update(prec, r, zz, Ap, L.dinv, n, s->aux, trace, 2 * k, st));
+    MFQ_HIP(launch_lz_direction(prec, zz, p, n, s->aux, st));
   }
-  const int m = (int)alphas.size();
+  return MFQ_OK;
+}
+
+int lambda_from_trace(const mfq_solver* s, Level& L, const double* trace) {
+  const int k = s->prm.lanczos_iters;
+  const int m = std::min(k, std::max(0, (int)trace[2 * k]));
   if (m == 0) return fail(MFQ_ENONFINITE, "eigenvalue estimate failed on level p=%d n=%d", L.sp->p, L.sp->mesh->n);
   std::vector<double> T((size_t)m * m, 0.0);
   for (int i = 0; i < m; ++i) {
-    T[i * m + i] = 1.0 / alphas[i] + (i > 0 ? betas[i - 1] / alphas[i - 1] : 0.0);
-    if (i + 1 < m) T[i * m + i + 1] = T[(i + 1) * m + i] = std::sqrt(betas[i]) / alphas[i];
+    const double ai = trace[2 * i], bi = trace[2 * i + 1];
+    T[i * m + i] = 1.0 / ai + (i > 0 ? trace[2 * i - 1] / trace[2 * i - 2] : 0.0);
+    if (i + 1 < m) T[i * m + i + 1] = T[(i + 1) * m + i] = std::sqrt(bi) / ai;
   }
   L.lhat = sym_max_eig(T, m);
   return MFQ_OK;
@@ -401,8 +406,8 @@ int pass_start(mfq_solver* s, const double* rhs, double* sol, double tol2) {
   return MFQ_OK;
 }
 
-// CG iterations; once the device state says done, the remaining ones are no-ops
-int pass_iterate(mfq_solver* s, int k) {
+// CG iterations issued as launches; once the device state says done, they are no-ops
+int pass_iterate_direct(mfq_solver* s, int k) {
   Run& R = s->run;
   const int64_t N = s->op64->space->n_dofs;
   const bool pre = preconditioned(s);
@@ -418,6 +423,53 @@ int pass_iterate(mfq_solver* s, int k) {
       MFQ_HIP(launch_cg_direction(s->r, s->p, N, s->state, false, R.st));
     }
   }
+  return MFQ_OK;
+}
+
+// Graphs are used on a non-default stream when nothing in an iteration waits on the host (the
+// Jacobi-CG coarse solve polls the host, so it is launched directly).
+bool graphs_usable(const mfq_solver* s) {
+  if (!s->prm.use_graphs || s->run.st == nullptr) return false;
+  if (s->kind == MFQ_SOLVER_CG || s->prm.coarse_mode == 1 || s->dense) return true;
+  return false;
+}
+
+int iteration_graph(mfq_solver* s, hipGraphExec_t* out) {
+  Run& R = s->run;
+  for (auto& g : s->graphs)
+    if (g.exec && g.st == R.st && g.sol == R.sol) {
+      *out = g.exec;
+      return MFQ_OK;
+    }
+  hipGraph_t graph = nullptr;
+  MFQ_HIP(hipStreamBeginCapture(R.st, hipStreamCaptureModeThreadLocal));
+  const int rc = pass_iterate_direct(s, 1);
+  const hipError_t e = hipStreamEndCapture(R.st, &graph);
+  if (rc) {
+    if (graph) (void)hipGraphDestroy(graph);
+    return rc;
+  }
+  if (e != hipSuccess) return fail(MFQ_EHIP, "capture of a CG iteration failed: %s", hipGetErrorString(e));
+  hipGraphExec_t exec = nullptr;
+  const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+  (void)hipGraphDestroy(graph);
+  if (e2 != hipSuccess) return fail(MFQ_EHIP, "graph instantiation failed: %s", hipGetErrorString(e2));
+  auto& slot = s->graphs[s->next_graph];
+  s->next_graph = (s->next_graph + 1) % 2;
+  if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+  slot.st = R.st;
+  slot.sol = R.sol;
+  slot.exec = exec;
+  *out = exec;
+  return MFQ_OK;
+}
+
+int pass_iterate(mfq_solver* s, int k) {
+  if (k <= 0) return MFQ_OK;
+  if (!graphs_usable(s)) return pass_iterate_direct(s, k);
+  hipGraphExec_t exec = nullptr;
+  if (int rc = iteration_graph(s, &exec)) return rc;
+  for (int i = 0; i < k; ++i) MFQ_HIP(hipGraphLaunch(exec, s->run.st));
   return MFQ_OK;
 }
 
@@ -521,6 +573,7 @@ void mfq_solver_default_params(mfq_solver_params* p) {
   p->coarse_degree = 16;
   p->coarse_ratio = 30.0;
   p->coarse_dofs = (int)kDenseCoarseLimit;
+  p->use_graphs = 1;
 }
 
 int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* params, mfq_solver** out) {
@@ -560,6 +613,7 @@ int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* par
   s->off_state = take(sizeof(SolverState));
   s->off_aux = take(sizeof(SolverState) + 64);
   s->off_kry = take(6 * round_up(N * 8, 256));
+  s->trace_stride = 2 * prm.lanczos_iters + 1;
 
   if (kind != MFQ_SOLVER_CG) {
     // hierarchy: halve n while even and > 4096 free DoFs, then p -> ceil(p/2) while > 4096
@@ -621,6 +675,7 @@ int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* par
         }
       }
     }
+    s->off_trace = take(s->lv.size() * s->trace_stride * sizeof(double));
     // coarse level
     Level& C = s->lv[0];
     s->nf = n_free(C.sp->p, C.sp->mesh->n);
@@ -708,13 +763,24 @@ int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream
     if (int rc = mfq_op_bind(s->coarse64, base + s->off_coarse64, cb, st)) return rc;
   }
 
-  // diagonals and eigenvalue bounds of the smoothed levels (and of the Chebyshev coarse level)
+  // diagonals and eigenvalue bounds of the smoothed levels (and of the Chebyshev coarse level):
+  // all Lanczos runs are enqueued, then their traces come back in one copy
   const size_t l0 = s->prm.coarse_mode == 1 ? 0 : 1;
-  for (size_t l = l0; l < s->lv.size(); ++l) {
+  const size_t nlv = s->lv.size();
+  s->trace = (double*)(base + s->off_trace);
+  if (!s->trace_host)
+    MFQ_HIP(hipHostMalloc((void**)&s->trace_host, nlv * s->trace_stride * sizeof(double), hipHostMallocDefault));
+  for (size_t l = l0; l < nlv; ++l) {
     Level& L = s->lv[l];
     if (int rc = op_diagonal(L.op, L.dinv, st)) return rc;
     MFQ_HIP(launch_reciprocal(prec, L.dinv, L.n, st));
-    if (int rc = estimate_lambda(s, L, st)) return rc;
+    if (int rc = enqueue_lanczos(s, L, s->trace + l * s->trace_stride, st)) return rc;
+  }
+  MFQ_HIP(hipMemcpyAsync(s->trace_host, s->trace, nlv * s->trace_stride * sizeof(double), hipMemcpyDeviceToHost, st));
+  MFQ_HIP(hipStreamSynchronize(st));
+  for (size_t l = l0; l < nlv; ++l) {
+    Level& L = s->lv[l];
+    if (int rc = lambda_from_trace(s, L, s->trace_host + l * s->trace_stride)) return rc;
     double lmax = s->prm.lambda_factor * L.lhat;
     if (l == 0) {
       L.lmax = lmax;
@@ -726,10 +792,7 @@ int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream
     L.lmax = lmax;
     L.lmin = lmax / s->prm.lambda_ratio;
   }
-  if (s->prm.coarse_mode == 1) {
-    MFQ_HIP(hipStreamSynchronize(st));
-    return MFQ_OK;
-  }
+  if (s->prm.coarse_mode == 1) return MFQ_OK;
   // coarse level
   Level& C = s->lv[0];
   const int64_t nf = s->nf;

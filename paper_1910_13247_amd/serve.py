@@ -54,8 +54,11 @@ class DeviceExecutor:
     def __init__(self, n_streams=4, keep_results=False, solver_kind=MFQ_SOLVER_GMG_MIXED, **solver_params):
         import torch
         self.torch = torch
-        # default-priority streams; requests are spread over them round-robin
+        # default-priority streams: solves are spread over `streams` round-robin; set-up work
+        # (geometry, hierarchy, eigenvalue estimates, which wait on the host) runs on its own
+        # stream so its waits do not queue behind the running solves
         self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
+        self.setup_stream = torch.cuda.Stream()
         self.keep_results = keep_results
         self.kind = solver_kind
         self.params = dict(coarse_mode=1)
@@ -86,16 +89,19 @@ class DeviceExecutor:
         st = self.streams[self._next_stream % len(self.streams)]
         self._next_stream += 1
         h["stream"] = st
-        with torch.cuda.stream(st):
+        su = self.setup_stream
+        with torch.cuda.stream(su):
             h["op_buf"] = torch.empty(max(h["op_bytes"], 256), dtype=torch.uint8, device="cuda")
             h["solver_buf"] = torch.empty(max(h["solver_bytes"], 256), dtype=torch.uint8, device="cuda")
             h["b"] = torch.empty(h["N"], dtype=torch.float64, device="cuda")
             h["x"] = torch.empty(h["N"], dtype=torch.float64, device="cuda")
-        sp = st.cuda_stream
+        sp = su.cuda_stream
         _lib.mfq_op_bind(h["op"], h["op_buf"].data_ptr(), h["op_bytes"], sp)
-        _lib.mfq_solver_bind(h["solver"], h["solver_buf"].data_ptr(), h["solver_bytes"], sp)
         _lib.mfq_space_random(h["space"], MFQ_FP64, h["b"].data_ptr(), req.seed, sp)
-        _lib.mfq_solve_begin(h["solver"], h["b"].data_ptr(), h["x"].data_ptr(), req.rtol, req.max_iter, sp)
+        # synchronises the set-up stream: everything above is complete before the solve starts
+        _lib.mfq_solver_bind(h["solver"], h["solver_buf"].data_ptr(), h["solver_bytes"], sp)
+        _lib.mfq_solve_begin(h["solver"], h["b"].data_ptr(), h["x"].data_ptr(), req.rtol, req.max_iter,
+                             st.cuda_stream)
 
     def step(self, handles, iters):
         return _lib.mfq_batch_step([h["solver"] for h in handles], iters)
@@ -139,6 +145,8 @@ class Server:
         self.peak_active = 0
         self._next_id = 0
         self._head = None  # prepared handles of the request at the head of the queue
+        self.setup_s = 0.0   # host time in admission (handles, allocation, set-up on the device)
+        self.step_s = 0.0    # host time in batch steps (launches and the per-step wait)
 
     def submit(self, req, now=None):
         req.id = self._next_id
@@ -169,7 +177,9 @@ class Server:
             req.footprint = h["bytes"]
             self.used += h["bytes"]
             req.admitted = self.clock()
+            t = time.perf_counter()
             self.ex.start(req, h)
+            self.setup_s += time.perf_counter() - t
             self.active.append((req, h))
         self.peak_used = max(self.peak_used, self.used)
         self.peak_active = max(self.peak_active, len(self.active))
@@ -180,7 +190,9 @@ class Server:
         self._admit()
         if not self.active:
             return []
+        t = time.perf_counter()
         flags = self.ex.step([h for _, h in self.active], self.iters)
+        self.step_s += time.perf_counter() - t
         self.steps += 1
         now = self.clock()
         finished, still = [], []
@@ -209,7 +221,8 @@ class Server:
         lat = sorted(r.latency for r in self.done)
         ok = [r for r in self.done if r.status == MFQ_OK]
         out = {"requests": len(self.done), "converged": len(ok), "rejected": len(self.rejected),
-               "steps": self.steps, "peak_active": self.peak_active, "peak_bytes": self.peak_used}
+               "steps": self.steps, "peak_active": self.peak_active, "peak_bytes": self.peak_used,
+               "setup_host_s": self.setup_s, "step_host_s": self.step_s}
         if lat:
             first = min(r.arrival for r in self.done)
             last = max(r.finished for r in self.done)
