@@ -126,6 +126,36 @@ def cpu_baseline(p, n, amp, alpha, x_np, budget_s=12.0):
                       f"scaled by cells/total to a full application"}
 
 
+def high_degree_comparison(steps, warmup):
+    """Q8 on the curved 24^3 mesh (7,189,057 DoFs): the operator in FP64, FP32 (vector ALU) and
+    FP32 with the 1D contractions on the matrix cores; per-application times of the cell loop and
+    the FP32 forms' normwise error against the FP64 result."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    from synthetic import VARCOEF_Q8_24, uniform_vector
+    pr = VARCOEF_Q8_24
+    mesh = mfq.Mesh(pr.cells_1d, pr.amplitude)
+    space = mfq.Space(mesh, pr.degree, mfq.MFQ_BC_DIRICHLET0)
+    x64 = torch.from_numpy(uniform_vector(space.n_dofs, seed=0)).cuda()
+    out = {"workload": pr.name, "dofs": space.n_dofs}
+    ref = None
+    for name, prec in [("fp64", mfq.MFQ_FP64), ("fp32", mfq.MFQ_FP32), ("fp32_mfma", mfq.MFQ_FP32_MFMA)]:
+        op = mfq.Operator(space, pr.alpha, prec)
+        x = x64 if prec == mfq.MFQ_FP64 else x64.float()
+        wall, kern, y = time_vmult(op, x, steps, warmup)
+        rb = algorithmic_bytes(pr.degree, pr.cells_1d, 8 if prec == mfq.MFQ_FP64 else 4)
+        rec = {"ms": kern * 1e3, "GB_per_s": rb / kern / 1e9, "frac": rb / kern / 1e9 / HBM_PEAK_GBS,
+               "DoFs_per_s": space.n_dofs / kern}
+        if ref is None:
+            ref = y.clone()
+        else:
+            rec["normwise_rel_err_vs_fp64"] = ((y.double() - ref).abs().max() / ref.abs().max()).item()
+        out[name] = rec
+        del op, y
+        torch.cuda.synchronize()
+    return out
+
+
 def solve_benchmarks(steps):
     """Time-to-1e-10 of the multigrid and CG solvers on the Q3 128^3 curved problem."""
     import torch
@@ -257,6 +287,8 @@ def main():
         torch.cuda.synchronize()
         rec["copy_probe_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
         del a, b
+    print("# Q8 24^3: FP64 / FP32 / FP32 matrix cores", file=sys.stderr, flush=True)
+    rec["high_degree_q8_24"] = high_degree_comparison(min(args.steps, 20), args.warmup)
     if args.solves:
         rec["solves_q3_128"] = solve_benchmarks(args.steps)
     if args.serve:

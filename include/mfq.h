@@ -58,7 +58,10 @@ typedef enum {
   MFQ_EBUSY = -6        /* object in use by an unfinished batched solve */
 } mfq_status;
 
-typedef enum { MFQ_FP64 = 0, MFQ_FP32 = 1 } mfq_precision;
+/* MFQ_FP32_MFMA: an FP32 operator (FP32 storage and arithmetic, same results within the FP32
+ * bound) whose cell loop runs its 1D contractions on the matrix cores (v_mfma_f32_16x16x4f32);
+ * as a vector precision it means float, like MFQ_FP32. */
+typedef enum { MFQ_FP64 = 0, MFQ_FP32 = 1, MFQ_FP32_MFMA = 2 } mfq_precision;
 typedef enum { MFQ_BC_NONE = 0, MFQ_BC_DIRICHLET0 = 1 } mfq_bc;
 
 typedef struct mfq_mesh mfq_mesh;
@@ -100,7 +103,8 @@ int mfq_space_apply_mask(const mfq_space* space, int precision, void* x, void* h
 int mfq_space_random(const mfq_space* space, int precision, void* x, uint64_t seed, void* hip_stream);
 
 /* ---------------------------------------------------------------- operator (Sec. 3.6, 3.7)
- * The variable-coefficient operator on a space, computed in `precision` (MFQ_FP64 or MFQ_FP32).
+ * The variable-coefficient operator on a space, computed in `precision` (MFQ_FP64, MFQ_FP32 or
+ * MFQ_FP32_MFMA).
  * Device storage: the cell index maps (int32, (p+1)^3 per cell) and the merged
  * quadrature-point tensor G_q = w_q a(x_q) det(J_q) J_q^{-1} J_q^{-T} (6 values per quadrature
  * point, stored in `precision`, always computed in FP64 from the analytic Jacobian). */

@@ -10,11 +10,11 @@ Sec. 3.1-3.7): a mesh, a finite element space on it, the operator of the weak fo
 matrix-free, level transfers, and solvers (CG, geometric multigrid).
 """
 from . import _lib
-from ._lib import (MfqError, MFQ_FP64, MFQ_FP32, MFQ_BC_NONE, MFQ_BC_DIRICHLET0, MFQ_SOLVER_CG,
+from ._lib import (MfqError, MFQ_FP64, MFQ_FP32, MFQ_FP32_MFMA, MFQ_BC_NONE, MFQ_BC_DIRICHLET0, MFQ_SOLVER_CG,
                    MFQ_SOLVER_GMG_FP64, MFQ_SOLVER_GMG_MIXED, MFQ_SOLVER_GMG_MIXED_IR, MFQ_OK, MFQ_EINVAL,
                    MFQ_ENOMEM, MFQ_EHIP, MFQ_ENOCONV, MFQ_ENONFINITE, MFQ_EBUSY)
 
-__all__ = ["Mesh", "Space", "Operator", "Transfer", "Solver", "MfqError", "MFQ_FP64", "MFQ_FP32",
+__all__ = ["Mesh", "Space", "Operator", "Transfer", "Solver", "MfqError", "MFQ_FP64", "MFQ_FP32", "MFQ_FP32_MFMA",
            "MFQ_BC_NONE", "MFQ_BC_DIRICHLET0", "MFQ_SOLVER_CG", "MFQ_SOLVER_GMG_FP64",
            "MFQ_SOLVER_GMG_MIXED", "MFQ_SOLVER_GMG_MIXED_IR", "MFQ_OK", "MFQ_EINVAL", "MFQ_ENOMEM",
            "MFQ_EHIP", "MFQ_ENOCONV", "MFQ_ENONFINITE", "MFQ_EBUSY", "batch_step"]

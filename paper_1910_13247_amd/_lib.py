@@ -11,7 +11,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libmfq.so")
 
 MFQ_OK, MFQ_EINVAL, MFQ_ENOMEM, MFQ_EHIP, MFQ_ENOCONV, MFQ_ENONFINITE, MFQ_EBUSY = 0, -1, -2, -3, -4, -5, -6
-MFQ_FP64, MFQ_FP32 = 0, 1
+MFQ_FP64, MFQ_FP32, MFQ_FP32_MFMA = 0, 1, 2
 MFQ_BC_NONE, MFQ_BC_DIRICHLET0 = 0, 1
 MFQ_SOLVER_CG, MFQ_SOLVER_GMG_FP64, MFQ_SOLVER_GMG_MIXED, MFQ_SOLVER_GMG_MIXED_IR = 0, 1, 2, 3
 

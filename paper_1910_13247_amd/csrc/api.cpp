@@ -95,32 +95,35 @@ int64_t mfq_space_n_cells(const mfq_space* space) { return space ? space->n_cell
 
 int mfq_space_apply_mask(const mfq_space* space, int precision, void* x, void* hip_stream) {
   if (!space) return fail(MFQ_EINVAL, "space is NULL");
-  if (precision != MFQ_FP64 && precision != MFQ_FP32) return fail(MFQ_EINVAL, "unknown precision %d", precision);
+  const int vp = vector_precision(precision);
+  if (vp < 0) return fail(MFQ_EINVAL, "unknown precision %d", precision);
   if (int rc = check_vec(x, "x")) return rc;
   if (space->bc == MFQ_BC_NONE) return MFQ_OK;
-  MFQ_HIP(launch_mask(precision, space->p, space->mesh->n, x, (hipStream_t)hip_stream));
+  MFQ_HIP(launch_mask(vp, space->p, space->mesh->n, x, (hipStream_t)hip_stream));
   return MFQ_OK;
 }
 
 int mfq_space_random(const mfq_space* space, int precision, void* x, uint64_t seed, void* hip_stream) {
   if (!space) return fail(MFQ_EINVAL, "space is NULL");
-  if (precision != MFQ_FP64 && precision != MFQ_FP32) return fail(MFQ_EINVAL, "unknown precision %d", precision);
+  const int vp = vector_precision(precision);
+  if (vp < 0) return fail(MFQ_EINVAL, "unknown precision %d", precision);
   if (int rc = check_vec(x, "x")) return rc;
   const int64_t N1 = (int64_t)space->p * space->mesh->n + 1;
-  MFQ_HIP(launch_splitmix(precision, x, N1, seed, space->bc == MFQ_BC_DIRICHLET0, (hipStream_t)hip_stream));
+  MFQ_HIP(launch_splitmix(vp, x, N1, seed, space->bc == MFQ_BC_DIRICHLET0, (hipStream_t)hip_stream));
   return MFQ_OK;
 }
 
 int mfq_op_create(const mfq_space* space, double alpha, int precision, mfq_op** out) {
   if (!space || !out) return fail(MFQ_EINVAL, "space or out is NULL");
-  if (precision != MFQ_FP64 && precision != MFQ_FP32) return fail(MFQ_EINVAL, "unknown precision %d", precision);
+  if (vector_precision(precision) < 0) return fail(MFQ_EINVAL, "unknown precision %d", precision);
   if (!std::isfinite(alpha) || std::fabs(alpha) >= 1.0)
     return fail(MFQ_EINVAL, "alpha %g must satisfy |alpha| < 1 (coefficient stays positive)", alpha);
   mfq_op* op = new (std::nothrow) mfq_op();
   if (!op) return fail(MFQ_ENOMEM, "host allocation failed");
   op->space = space;
   op->alpha = alpha;
-  op->precision = precision;
+  op->precision = vector_precision(precision);
+  op->mfma = precision == MFQ_FP32_MFMA;
   const int p = space->p;
   op->bricks = make_bricks(p, space->mesh->n);
   const size_t nb = (size_t)op->bricks.n_bricks;
@@ -244,19 +247,21 @@ void mfq_transfer_destroy(mfq_transfer* t) { delete t; }
 
 int mfq_prolongate(const mfq_transfer* t, int precision, const void* coarse, void* fine, void* hip_stream) {
   if (!t) return fail(MFQ_EINVAL, "transfer is NULL");
-  if (precision != MFQ_FP64 && precision != MFQ_FP32) return fail(MFQ_EINVAL, "unknown precision %d", precision);
+  const int vp = vector_precision(precision);
+  if (vp < 0) return fail(MFQ_EINVAL, "unknown precision %d", precision);
   if (int rc = check_vec(coarse, "coarse")) return rc;
   if (int rc = check_vec(fine, "fine")) return rc;
-  MFQ_HIP(launch_transfer(t, precision, true, coarse, fine, (hipStream_t)hip_stream));
+  MFQ_HIP(launch_transfer(t, vp, true, coarse, fine, (hipStream_t)hip_stream));
   return MFQ_OK;
 }
 
 int mfq_restrict(const mfq_transfer* t, int precision, const void* fine, void* coarse, void* hip_stream) {
   if (!t) return fail(MFQ_EINVAL, "transfer is NULL");
-  if (precision != MFQ_FP64 && precision != MFQ_FP32) return fail(MFQ_EINVAL, "unknown precision %d", precision);
+  const int vp = vector_precision(precision);
+  if (vp < 0) return fail(MFQ_EINVAL, "unknown precision %d", precision);
   if (int rc = check_vec(coarse, "coarse")) return rc;
   if (int rc = check_vec(fine, "fine")) return rc;
-  MFQ_HIP(launch_transfer(t, precision, false, fine, coarse, (hipStream_t)hip_stream));
+  MFQ_HIP(launch_transfer(t, vp, false, fine, coarse, (hipStream_t)hip_stream));
   return MFQ_OK;
 }
 

@@ -166,22 +166,98 @@ __global__ __launch_bounds__(kBlock) void geometry_export_kernel(const Real* __r
 }
 
 // ---------------------------------------------------------------- operator application
+// Gather of a brick's node lattice by BLOCK threads (KPT nodes each): global index from the index
+// lattice (~g on Dirichlet nodes, kAbsent outside the mesh), store/add bit per node (bit j of
+// `first`, in a vector register), source values into `lat` (zero on Dirichlet and absent nodes)
+// and the dst values this launch adds to.  A node shared with neighbouring bricks is written by
+// each of them, each in its own launch: the brick that is even in every direction in which the
+// node is shared stores (its colour comes first), the others add to what is there.
+template <int P, typename Real, bool ACC, int BLOCK, int KPT>
+__device__ __forceinline__ void gather_lattice(const int* __restrict__ ip, const Real* __restrict__ src,
+                                               const Real* __restrict__ dst, const Bricks& bk, int bi, int bj,
+                                               int bz, Real* lat, int (&gk)[KPT], unsigned& first, Real (&dv)[KPT]) {
+  using C = Cell<P>;
+  constexpr int LX = C::LX, LY = C::LY, NL = C::NL;
+  const int tid = threadIdx.x;
+  first = 0;
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    const int k = tid + j * BLOCK;
+    const int kk = k < NL ? k : NL - 1;
+    const int gl = ip[kk];
+    gk[j] = k < NL ? gl : kAbsent;
+    const int li = kk % LX, lj = (kk / LX) % LY, lk = kk / (LX * LY);
+    const bool sx = (li == 0 && bi > 0) || (li == LX - 1 && bi < bk.nbx - 1);
+    const bool sy = (lj == 0 && bj > 0) || (lj == LY - 1 && bj < bk.nby - 1);
+    const bool sz = (lk == 0 && bz > 0) || (lk == C::LZ - 1 && bz < bk.nbz - 1);
+    const bool fj = (!sx || !(bi & 1)) && (!sy || !(bj & 1)) && (!sz || !(bz & 1));
+    first |= fj ? 1u << j : 0u;
+  }
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    const int g0 = gk[j];
+    const bool live = g0 >= 0;
+    const int gs = live ? g0 : 0;
+    const Real s = src[gs];
+    const Real d = dst[gs];
+    lat[tid + j * BLOCK] = live ? s : (Real)0;
+    dv[j] = (live && (ACC || !(first >> j & 1u))) ? d : (Real)0;
+  }
+}
+
+// Sum the cells' results per lattice node in a fixed order (cell c's result at res + c * cstride,
+// local lexicographic order) and write the brick's nodes: store or add per the `first` bit,
+// Dirichlet nodes get src (added to dst when accumulating) from the brick that stores.
+template <int P, typename Real, bool ACC, int BLOCK, int KPT>
+__device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, const Real* __restrict__ src,
+                                                Real* __restrict__ dst, const int (&gk)[KPT], unsigned first,
+                                                const Real (&dv)[KPT]) {
+  using C = Cell<P>;
+  constexpr int N1 = C::N1, LX = C::LX, LY = C::LY;
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    const int k = tid + j * BLOCK;
+    const int g0 = gk[j];
+    if (g0 == kAbsent) continue;
+    const int li = k % LX, lj = (k / LX) % LY, lk = k / (LX * LY);
+    const int xhi = min(li / P, C::BX - 1), xlo = (li % P == 0 && li > 0) ? li / P - 1 : xhi;
+    const int yhi = min(lj / P, C::BY - 1), ylo = (lj % P == 0 && lj > 0) ? lj / P - 1 : yhi;
+    const int zhi = min(lk / P, C::BZ - 1), zlo = (lk % P == 0 && lk > 0) ? lk / P - 1 : zhi;
+    Real sum = 0;
+    for (int ccz = zlo; ccz <= zhi; ++ccz)
+      for (int ccy = ylo; ccy <= yhi; ++ccy)
+        for (int ccx = xlo; ccx <= xhi; ++ccx) {
+          const int cell = ccx + C::BX * (ccy + C::BY * ccz);
+          sum += res[cell * cstride + (li - ccx * P) + N1 * ((lj - ccy * P) + N1 * (lk - ccz * P))];
+        }
+    const bool fj = first >> j & 1u;
+    if (g0 >= 0) {
+      dst[g0] = (ACC || !fj) ? dv[j] + sum : sum;
+    } else if (fj) {
+      const int gg = ~g0;
+      dst[gg] = ACC ? dst[gg] + src[gg] : src[gg];
+    }
+  }
+}
+
+#ifndef MFQ_G_STAGE
+#define MFQ_G_STAGE 0
+#endif
+
 // One launch per colour, one workgroup per brick; ACC adds A src into dst instead of overwriting
 // it.  Lanes beyond the brick's pencils work on a spare LDS slot so no branch is needed around
 // LDS stores or loads (their results are never read).
-//
-// A lattice node shared with neighbouring bricks is written by each of them, each in its own
-// launch: the brick that is even in every direction in which the node is shared stores (its colour
-// comes first), the others add to what is there.
 template <int P, typename Real, bool ACC>
-__global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
+__global__ __launch_bounds__(Cell<P>::BLOCK) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
                                                        const Real* __restrict__ src, Real* __restrict__ dst, Bricks bk,
                                                        int colour, ShapeEO<P, Real> sh) {
   using C = Cell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NCELL = C::NCELL, NT = C::NT, LX = C::LX, LY = C::LY, NL = C::NL;
-  constexpr int KPT = (NL + kBlock - 1) / kBlock;  // lattice nodes per thread
+  constexpr int BLOCK = C::BLOCK;
+  constexpr int KPT = (NL + BLOCK - 1) / BLOCK;    // lattice nodes per thread
   constexpr int SLOT = (NCELL + 1) * NQ;           // one array per cell plus the spare slot
-  constexpr int L2SZ = SLOT > KPT * kBlock ? SLOT : KPT * kBlock;
+  constexpr int L2SZ = SLOT > KPT * BLOCK ? SLOT : KPT * BLOCK;
   // cell arrays stored array-major: [L0 of every cell][L1 ...][L2 ...]; the node lattice is only
   // read before the first write of an L2 array, so it shares the L2 block
   __shared__ Real lds[2 * SLOT + L2SZ];
@@ -201,12 +277,15 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
   Real* L1 = L0 + SLOT;
   Real* L2 = L1 + SLOT;
 
-  // quadrature-point tensors of this lane's z-pencil (points (e0, e1, t)), issued first; lanes
-  // of cells outside the mesh (ragged last bricks) load nothing
+  // quadrature-point tensors of this lane's z-pencil (points (e0, e1, t)); lanes of cells outside
+  // the mesh (ragged last bricks) load nothing.  Issued at the stage MFQ_G_STAGE selects (0: kernel
+  // start, 1: after the x contraction, 2: after the y contraction): earlier hides more latency,
+  // later holds the 6(p+1) values in registers for a shorter time.
   Real2<Real> g[N1][3];
-  {
+  const bool cell_in = lane_ok && bi * C::BX + cx < bk.n && bj * C::BY + cy < bk.n && bz * C::BZ + cz < bk.n;
+  auto load_g = [&]() {
     const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + tid;
-    if (lane_ok && bi * C::BX + cx < bk.n && bj * C::BY + cy < bk.n && bz * C::BZ + cz < bk.n) {
+    if (cell_in) {
 #pragma unroll
       for (int t = 0; t < N1; ++t)
 #pragma unroll
@@ -217,38 +296,14 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
 #pragma unroll
         for (int m = 0; m < 3; ++m) g[t][m] = Real2<Real>{0, 0};
     }
-  }
+  };
+  if (MFQ_G_STAGE == 0) load_g();
 
-  // this thread's lattice nodes: global index from the index lattice (~g on Dirichlet nodes,
-  // kAbsent outside the mesh), store/add bit (one bit per node, in a vector register), source
-  // value, and the dst value this launch adds to
-  const int* ip = idx + ord * (int64_t)NL;
+  // this thread's lattice nodes
   int gk[KPT];
-  unsigned first = 0;
+  unsigned first;
   Real dv[KPT];
-#pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const int k = tid + j * kBlock;
-    const int kk = k < NL ? k : NL - 1;
-    const int gl = ip[kk];
-    gk[j] = k < NL ? gl : kAbsent;
-    const int li = kk % LX, lj = (kk / LX) % LY, lk = kk / (LX * LY);
-    const bool sx = (li == 0 && bi > 0) || (li == LX - 1 && bi < bk.nbx - 1);
-    const bool sy = (lj == 0 && bj > 0) || (lj == LY - 1 && bj < bk.nby - 1);
-    const bool sz = (lk == 0 && bz > 0) || (lk == C::LZ - 1 && bz < bk.nbz - 1);
-    const bool fj = (!sx || !(bi & 1)) && (!sy || !(bj & 1)) && (!sz || !(bz & 1));
-    first |= fj ? 1u << j : 0u;
-  }
-#pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const int g0 = gk[j];
-    const bool live = g0 >= 0;
-    const int gs = live ? g0 : 0;
-    const Real s = src[gs];
-    const Real d = dst[gs];
-    lat[tid + j * kBlock] = live ? s : (Real)0;
-    dv[j] = (live && (ACC || !(first >> j & 1u))) ? d : (Real)0;
-  }
+  gather_lattice<P, Real, ACC, BLOCK, KPT>(idx + ord * (int64_t)NL, src, dst, bk, bi, bj, bz, lat, gk, first, dv);
   lds_barrier();
 
   // x: values and x-derivatives at (q, e0, e1) from the lane's x-pencil
@@ -265,6 +320,7 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
       L1[q + N1 * e] = B[q];
     }
   }
+  if (MFQ_G_STAGE == 1) load_g();
   lds_barrier();
   // y: lane (r=e0, c=e1) holds y-pencils
   {
@@ -286,6 +342,7 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
       L2[e0 + N1 * s + T * e1] = C2[s];
     }
   }
+  if (MFQ_G_STAGE == 2) load_g();
   lds_barrier();
   // z: lane (r=e0, s=e1) holds z-pencils; gradient, G, and the transposed z contraction
   {
@@ -357,30 +414,335 @@ __global__ __launch_bounds__(kBlock) void vmult_kernel(const int* __restrict__ i
   }
   lds_barrier();
   // sum the cells' results per lattice node (fixed order) and write the brick's nodes
-#pragma unroll
-  for (int j = 0; j < KPT; ++j) {
-    const int k = tid + j * kBlock;
-    const int g0 = gk[j];
-    if (g0 == kAbsent) continue;
-    const int li = k % LX, lj = (k / LX) % LY, lk = k / (LX * LY);
-    const int xhi = min(li / P, C::BX - 1), xlo = (li % P == 0 && li > 0) ? li / P - 1 : xhi;
-    const int yhi = min(lj / P, C::BY - 1), ylo = (lj % P == 0 && lj > 0) ? lj / P - 1 : yhi;
-    const int zhi = min(lk / P, C::BZ - 1), zlo = (lk % P == 0 && lk > 0) ? lk / P - 1 : zhi;
-    Real sum = 0;
-    for (int ccz = zlo; ccz <= zhi; ++ccz)
-      for (int ccy = ylo; ccy <= yhi; ++ccy)
-        for (int ccx = xlo; ccx <= xhi; ++ccx) {
-          const int cell = ccx + C::BX * (ccy + C::BY * ccz);
-          sum += lds[cell * NQ + (li - ccx * P) + N1 * ((lj - ccy * P) + N1 * (lk - ccz * P))];
-        }
-    const bool fj = first >> j & 1u;
-    if (g0 >= 0) {
-      dst[g0] = (ACC || !fj) ? dv[j] + sum : sum;
-    } else if (fj) {
-      const int gg = ~g0;
-      dst[gg] = ACC ? dst[gg] + src[gg] : src[gg];
-    }
+  scatter_lattice<P, Real, ACC, BLOCK, KPT>(lds, NQ, src, dst, gk, first, dv);
+}
+
+// ---------------------------------------------------------------- operator application, MFMA (FP32)
+// The same operator with the 1D contractions on the matrix cores.  Each contraction of a cell is
+// Out[m][pencil] = sum_k M[m][k] In[k][pencil] over the (p+1)^2 pencils of one direction: the 1D
+// table M (S, D or their transposes, zero-padded to 16 x 4 KS) is the A operand of
+// v_mfma_f32_16x16x4f32, the cell data the B operand, read from LDS with the addressing that
+// transposes it to the next direction, so no explicit transposes are needed.  One wave works on one
+// cell at a time; the quadrature-point tensor is applied tile by tile right after the z contraction
+// and its transpose follows at once.  Brick layout, index lattice, G and the node ownership rules
+// are those of the FP32 operator.
+//
+// Lane layout of v_mfma_f32_16x16x4f32 (wave64): A operand lane l = A[l % 16][l / 16], B operand
+// lane l = B[l / 16][l % 16], result register r of lane l = D[4 (l / 16) + r][l % 16].
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+
+template <int P>
+struct MfmaTables {
+  float S[(P + 1) * (P + 1)];  // S[q][a] = l_a(zeta_q)
+  float D[(P + 1) * (P + 1)];  // D[q][a] = l_a'(zeta_q)
+};
+
+template <int P>
+MfmaTables<P> make_mfma_tables() {
+  MfmaTables<P> t;
+  for (int k = 0; k < (P + 1) * (P + 1); ++k) {
+    t.S[k] = (float)ct::kTab<P>.S[k];
+    t.D[k] = (float)ct::kTab<P>.D[k];
   }
+  return t;
+}
+
+template <int P>
+struct MCell {
+  using C = Cell<P>;
+  static constexpr int N1 = P + 1, NP = N1 * N1, NQ = N1 * NP;
+  static constexpr int KS = (N1 + 3) / 4;          // k-steps of 4 (K padded to 4 KS)
+  static constexpr int TILES = (NP + 15) / 16;     // pencil tiles of 16 columns
+  static constexpr int WAVES = C::NCELL < 8 ? C::NCELL : 8;
+  static constexpr int BLOCK = 64 * WAVES;
+  static constexpr int KPT = (C::NL + BLOCK - 1) / BLOCK;
+  static constexpr int VROWS = 4 * KS;
+  static constexpr int WORK = 3 * NQ + 3 * VROWS * 16;  // per-wave scratch (floats)
+  static constexpr int LDS = KPT * BLOCK + C::NCELL * NQ + WAVES * WORK;
+};
+
+__device__ __forceinline__ f32x4 mfma4(float a, float b, f32x4 c) {
+  return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+// Orders this wave's LDS accesses (data exchanged between lanes of one wave only).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront", "local");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront", "local");
+}
+
+// A operand of M (transpose = false) or M^T, row-major N1 x N1, zero outside N1 x N1
+template <int N1, int KS>
+__device__ __forceinline__ void a_operand(const float* M, bool transpose, int lane, float (&a)[KS]) {
+  const int i = lane & 15, kk = lane >> 4;
+#pragma unroll
+  for (int s = 0; s < KS; ++s) {
+    const int k = 4 * s + kk;
+    a[s] = (i < N1 && k < N1) ? (transpose ? M[k * N1 + i] : M[i * N1 + k]) : 0.0f;
+  }
+}
+
+template <int P, bool ACC>
+__global__ __launch_bounds__(MCell<P>::BLOCK) void vmult_mfma_kernel(MfmaTables<P> tab, const int* __restrict__ idx,
+                                                                     const float* __restrict__ geo,
+                                                                     const float* __restrict__ src,
+                                                                     float* __restrict__ dst, Bricks bk, int colour) {
+  using C = Cell<P>;
+  using M = MCell<P>;
+  constexpr int N1 = M::N1, NP = M::NP, NQ = M::NQ, KS = M::KS, TILES = M::TILES, WAVES = M::WAVES;
+  constexpr int BLOCK = M::BLOCK, KPT = M::KPT, VROWS = M::VROWS;
+  constexpr int NCELL = C::NCELL, T = C::T, NT = C::NT, LX = C::LX, LY = C::LY, NL = C::NL;
+  __shared__ float lds[M::LDS];
+  float* const lat = lds;
+  float* const res = lds + KPT * BLOCK;     // cell results, [cell][a + N1 (b + N1 c)]
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int col = lane & 15, kg = lane >> 4;
+  float* const A0 = res + NCELL * NQ + wave * M::WORK;
+  float* const A1 = A0 + NQ;
+  float* const A2 = A1 + NQ;
+  float* const V = A2 + NQ;  // [3][VROWS][16]
+  const int64_t ord = bk.offset[colour] + blockIdx.x;
+  int bi, bj, bz;
+  brick_of(bk, colour, blockIdx.x, bi, bj, bz);
+
+  int gk[KPT];
+  unsigned first;
+  float dv[KPT];
+  gather_lattice<P, float, ACC, BLOCK, KPT>(idx + ord * (int64_t)NL, src, dst, bk, bi, bj, bz, lat, gk, first, dv);
+
+  float aS[KS], aD[KS], aSt[KS], aDt[KS];
+  a_operand<N1, KS>(tab.S, false, lane, aS);
+  a_operand<N1, KS>(tab.D, false, lane, aD);
+  a_operand<N1, KS>(tab.S, true, lane, aSt);
+  a_operand<N1, KS>(tab.D, true, lane, aDt);
+  lds_barrier();
+
+  const Real2<float>* geo2 = reinterpret_cast<const Real2<float>*>(geo) + ord * (int64_t)(N1 * 3 * NT);
+  for (int lc = wave; lc < NCELL; lc += WAVES) {
+    const int cx = lc % C::BX, cy = (lc / C::BX) % C::BY, cz = lc / (C::BX * C::BY);
+    const bool cell_in = bi * C::BX + cx < bk.n && bj * C::BY + cy < bk.n && bz * C::BZ + cz < bk.n;
+    const float* ub = lat + cx * P + LX * (cy * P + LY * (cz * P));  // u[a][b][c] = ub[a + LX (b + LY c)]
+
+    // x: XA[q][b + N1 c] = sum_a S[q][a] u[a][b][c] -> A0, XB (D) -> A1
+    {
+      f32x4 xa[TILES], xb[TILES];
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) {
+        xa[t] = f32x4{0, 0, 0, 0};
+        xb[t] = f32x4{0, 0, 0, 0};
+        const int p = 16 * t + col;
+        const bool pok = p < NP;
+        const int pb = pok ? p % N1 : 0, pc = pok ? p / N1 : 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int k = 4 * s + kg;
+          const float bv = (pok && k < N1) ? ub[k + LX * (pb + LY * pc)] : 0.0f;
+          xa[t] = mfma4(aS[s], bv, xa[t]);
+          xb[t] = mfma4(aD[s], bv, xb[t]);
+        }
+      }
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) {
+        const int p = 16 * t + col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int q = 4 * kg + r;
+          if (p < NP && q < N1) {
+            A0[q * NP + p] = xa[t][r];
+            A1[q * NP + p] = xb[t][r];
+          }
+        }
+      }
+    }
+    wave_lds_sync();
+    // y: YA = S_y XA, YC = D_y XA, YB = S_y XB; Y[s][q + N1 c] (B operand k = b at q NP + b + N1 c)
+    {
+      f32x4 ya[TILES], yc[TILES], yb[TILES];
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) {
+        ya[t] = yc[t] = yb[t] = f32x4{0, 0, 0, 0};
+        const int p = 16 * t + col;
+        const bool pok = p < NP;
+        const int q = pok ? p % N1 : 0, c = pok ? p / N1 : 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int k = 4 * s + kg;
+          const bool ok = pok && k < N1;
+          const int ad = q * NP + k + N1 * c;
+          const float bA = ok ? A0[ad] : 0.0f;
+          const float bB = ok ? A1[ad] : 0.0f;
+          ya[t] = mfma4(aS[s], bA, ya[t]);
+          yc[t] = mfma4(aD[s], bA, yc[t]);
+          yb[t] = mfma4(aS[s], bB, yb[t]);
+        }
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) {
+        const int p = 16 * t + col;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int sr = 4 * kg + r;
+          if (p < NP && sr < N1) {
+            A2[sr * NP + p] = ya[t][r];
+            A0[sr * NP + p] = yc[t][r];
+            A1[sr * NP + p] = yb[t][r];
+          }
+        }
+      }
+    }
+    wave_lds_sync();
+    // z, quadrature point and transposed z, one tile of pencils (q, s) at a time:
+    // gz = D_z YA, gx = S_z YB, gy = S_z YC (B operand k = c at s NP + q + N1 c); v = G (gx, gy, gz);
+    // Az = D_z^T vz, Bz = S_z^T vx, Cz = S_z^T vy written back over the tile's Y entries
+    // quadrature tensors of a tile's points, zero outside the cell's points
+    Real2<float> gq[4][3];
+    auto load_gq = [&](int t, Real2<float> (&dst)[4][3]) {
+      const int p = 16 * t + col;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int tz = 4 * kg + r;
+        const bool ok = cell_in && p < NP && tz < N1;
+        const Real2<float>* gp = geo2 + (int64_t)(ok ? tz : 0) * 3 * NT + lc * T + (ok ? p : 0);
+#pragma unroll
+        for (int m = 0; m < 3; ++m) dst[r][m] = ok ? gp[m * NT] : Real2<float>{0, 0};
+      }
+    };
+#pragma unroll
+    for (int t = 0; t < TILES; ++t) {
+      load_gq(t, gq);
+      const int p = 16 * t + col;
+      const bool pok = p < NP;
+      const int q = pok ? p % N1 : 0, sy = pok ? p / N1 : 0;
+      f32x4 gx = {0, 0, 0, 0}, gy = {0, 0, 0, 0}, gz = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int k = 4 * s + kg;
+        const bool ok = pok && k < N1;
+        const int ad = sy * NP + q + N1 * k;
+        const float bA = ok ? A2[ad] : 0.0f;
+        const float bB = ok ? A1[ad] : 0.0f;
+        const float bC = ok ? A0[ad] : 0.0f;
+        gz = mfma4(aD[s], bA, gz);
+        gx = mfma4(aS[s], bB, gx);
+        gy = mfma4(aS[s], bC, gy);
+      }
+      f32x4 vx, vy, vz;
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // (G00 G01 G02; G01 G11 G12; G02 G12 G22) = (G0.x G0.y G1.x; . G1.y G2.x; . . G2.y); zero
+        // outside the cell's points
+        const Real2<float> G0 = gq[r][0], G1 = gq[r][1], G2 = gq[r][2];
+        vx[r] = G0.x * gx[r] + G0.y * gy[r] + G1.x * gz[r];
+        vy[r] = G0.y * gx[r] + G1.y * gy[r] + G2.x * gz[r];
+        vz[r] = G1.x * gx[r] + G2.x * gy[r] + G2.y * gz[r];
+      }
+      // the tile's v to scratch ([row tz][col], VROWS = 4 KS rows per component: the rows the
+      // transposed contraction reads as its K; rows N1..VROWS-1 hold zeros) and back as B operand
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = 4 * kg + r;
+        if (row < VROWS) {
+          V[row * 16 + col] = vx[r];
+          V[(VROWS + row) * 16 + col] = vy[r];
+          V[(2 * VROWS + row) * 16 + col] = vz[r];
+        }
+      }
+      wave_lds_sync();
+      f32x4 az = {0, 0, 0, 0}, bzv = {0, 0, 0, 0}, czv = {0, 0, 0, 0};
+#pragma unroll
+      for (int s = 0; s < KS; ++s) {
+        const int row = 4 * s + kg;
+        const float bvx = V[row * 16 + col];
+        const float bvy = V[(VROWS + row) * 16 + col];
+        const float bvz = V[(2 * VROWS + row) * 16 + col];
+        bzv = mfma4(aSt[s], bvx, bzv);
+        czv = mfma4(aSt[s], bvy, czv);
+        az = mfma4(aDt[s], bvz, az);
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int c = 4 * kg + r;
+        if (pok && c < N1) {
+          const int ad = sy * NP + q + N1 * c;
+          A2[ad] = az[r];
+          A1[ad] = bzv[r];
+          A0[ad] = czv[r];
+        }
+      }
+    }
+    wave_lds_sync();
+    // transposed y: A' = S_y^T Az + D_y^T Cz, B' = S_y^T Bz (B operand k = s at s NP + q + N1 c);
+    // written as X[q][b + N1 c]
+    {
+      f32x4 ap[TILES], bp[TILES];
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) {
+        ap[t] = bp[t] = f32x4{0, 0, 0, 0};
+        const int p = 16 * t + col;
+        const bool pok = p < NP;
+        const int q = pok ? p % N1 : 0, c = pok ? p / N1 : 0;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int k = 4 * s + kg;
+          const bool ok = pok && k < N1;
+          const int ad = k * NP + q + N1 * c;
+          const float bAz = ok ? A2[ad] : 0.0f;
+          const float bCz = ok ? A0[ad] : 0.0f;
+          const float bBz = ok ? A1[ad] : 0.0f;
+          ap[t] = mfma4(aSt[s], bAz, ap[t]);
+          ap[t] = mfma4(aDt[s], bCz, ap[t]);
+          bp[t] = mfma4(aSt[s], bBz, bp[t]);
+        }
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) {
+        const int p = 16 * t + col;
+        const int q = p % N1, c = p / N1;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int b = 4 * kg + r;
+          if (p < NP && b < N1) {
+            A2[q * NP + b + N1 * c] = ap[t][r];
+            A1[q * NP + b + N1 * c] = bp[t][r];
+          }
+        }
+      }
+    }
+    wave_lds_sync();
+    // transposed x: y[a][b + N1 c] = S_x^T A' + D_x^T B' (B operand k = q at q NP + b + N1 c)
+    {
+      float* out = res + lc * NQ;
+#pragma unroll
+      for (int t = 0; t < TILES; ++t) {
+        f32x4 y = {0, 0, 0, 0};
+        const int p = 16 * t + col;
+        const bool pok = p < NP;
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          const int k = 4 * s + kg;
+          const bool ok = pok && k < N1;
+          const int ad = k * NP + p;
+          const float bA = ok ? A2[ad] : 0.0f;
+          const float bB = ok ? A1[ad] : 0.0f;
+          y = mfma4(aSt[s], bA, y);
+          y = mfma4(aDt[s], bB, y);
+        }
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+          const int a = 4 * kg + r;
+          if (pok && a < N1) out[a + N1 * p] = y[r];
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+  lds_barrier();
+  scatter_lattice<P, float, ACC, BLOCK, KPT>(res, NQ, src, dst, gk, first, dv);
 }
 
 // ---------------------------------------------------------------- diagonal
@@ -421,7 +783,7 @@ __global__ __launch_bounds__(kBlock) void diagonal_kernel(const int* __restrict_
 // ---------------------------------------------------------------- right-hand side
 // b_i += sum_q f(x_q) JxW_q phi_i(q) for u* = sin(pi x) sin(pi y) sin(pi z), f = -div(a grad u*).
 template <int P>
-__global__ __launch_bounds__(kBlock) void rhs_kernel(const int* __restrict__ idx, double* __restrict__ b, Bricks bk,
+__global__ __launch_bounds__(Cell<P>::BLOCK) void rhs_kernel(const int* __restrict__ idx, double* __restrict__ b, Bricks bk,
                                                      int n, double amp, double alpha, Shape<P, double> sh,
                                                      QuadRule<P> qr) {
   using C = Cell<P>;
@@ -574,11 +936,27 @@ hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipSt
     const int64_t nb = v.bricks.count[c];
     if (nb == 0) continue;
     if (acc)
-      vmult_kernel<P, Real, true><<<(unsigned)nb, kBlock, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
+      vmult_kernel<P, Real, true><<<(unsigned)nb, Cell<P>::BLOCK, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
                                                                    (Real*)dst, v.bricks, c, sh);
     else
-      vmult_kernel<P, Real, false><<<(unsigned)nb, kBlock, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
+      vmult_kernel<P, Real, false><<<(unsigned)nb, Cell<P>::BLOCK, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
                                                                     (Real*)dst, v.bricks, c, sh);
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t vmult_mfma_p(const OpView& v, const void* src, void* dst, bool acc, hipStream_t st) {
+  static const MfmaTables<P> tab = make_mfma_tables<P>();
+  for (int c = 0; c < kColours; ++c) {
+    const int64_t nb = v.bricks.count[c];
+    if (nb == 0) continue;
+    if (acc)
+      vmult_mfma_kernel<P, true><<<(unsigned)nb, MCell<P>::BLOCK, 0, st>>>(tab, v.idx, (const float*)v.geo,
+                                                                          (const float*)src, (float*)dst, v.bricks, c);
+    else
+      vmult_mfma_kernel<P, false><<<(unsigned)nb, MCell<P>::BLOCK, 0, st>>>(tab, v.idx, (const float*)v.geo,
+                                                                           (const float*)src, (float*)dst, v.bricks, c);
   }
   return hipGetLastError();
 }
@@ -586,6 +964,7 @@ hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipSt
 template <int P>
 hipError_t vmult_p(const OpView& v, int precision, const void* src, void* dst, bool acc, hipStream_t st) {
   if (precision == MFQ_FP64) return vmult_pr<P, double>(v, src, dst, acc, st);
+  if (v.mfma) return vmult_mfma_p<P>(v, src, dst, acc, st);
   return vmult_pr<P, float>(v, src, dst, acc, st);
 }
 
@@ -603,7 +982,7 @@ hipError_t diagonal_p(const OpView& v, int precision, void* diag, hipStream_t st
 
 template <int P>
 hipError_t rhs_p(const OpView& v, double* b, hipStream_t st) {
-  rhs_kernel<P><<<(unsigned)v.bricks.n_bricks, kBlock, 0, st>>>(v.idx, b, v.bricks, v.n, v.amplitude, v.alpha,
+  rhs_kernel<P><<<(unsigned)v.bricks.n_bricks, Cell<P>::BLOCK, 0, st>>>(v.idx, b, v.bricks, v.n, v.amplitude, v.alpha,
                                                                 make_shape<P, double>(), make_rule<P>());
   return hipGetLastError();
 }

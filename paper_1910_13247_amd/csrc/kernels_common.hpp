@@ -144,7 +144,9 @@ struct Cell {
   static constexpr int NT = NCELL * T;
   static constexpr int LX = BX * P + 1, LY = BY * P + 1, LZ = BZ * P + 1;
   static constexpr int NL = LX * LY * LZ;
-  static_assert(NT <= kBlock, "a brick must fit one workgroup");
+  // workgroup of the per-brick kernels: 256 lanes, or 512 for bricks of more than 256 pencils
+  static constexpr int BLOCK = NT <= kBlock ? kBlock : 2 * kBlock;
+  static_assert(NT <= BLOCK, "a brick must fit one workgroup");
 };
 
 // Brick coordinates of brick b (counted within colour c, x fastest).

@@ -150,7 +150,8 @@ struct mfq_space {
 struct mfq_op {
   const mfq_space* space;
   double alpha;
-  int precision;
+  int precision;              // MFQ_FP64 or MFQ_FP32 (storage and arithmetic)
+  bool mfma = false;          // FP32 cell loop on the matrix cores (created as MFQ_FP32_MFMA)
   mfq::Bricks bricks;
   size_t idx_bytes, geo_bytes;
   void* buf = nullptr;        // caller-owned device memory
@@ -177,11 +178,18 @@ struct OpView {
   Bricks bricks;
   const int* idx;
   const void* geo;
+  bool mfma;
 };
 inline OpView view(const mfq_op* op) {
   const mfq_space* s = op->space;
   return OpView{s->p, s->mesh->n, s->bc, s->n_cells, s->n_dofs, s->mesh->amplitude, op->alpha, op->bricks,
-                op->idx, op->geo};
+                op->idx, op->geo, op->mfma};
+}
+
+// precision of a vector argument: MFQ_FP32_MFMA means float; -1 if unknown
+inline int vector_precision(int precision) {
+  if (precision == MFQ_FP32_MFMA) return MFQ_FP32;
+  return (precision == MFQ_FP64 || precision == MFQ_FP32) ? precision : -1;
 }
 
 // ---------------------------------------------------------------- launchers (kernels_*.hip)

@@ -72,6 +72,71 @@ def test_vmult_fp32_within_rounding_bound(p):
     print(f"p={p} fp32 normwise rel err {np.abs(y - yo).max() / np.abs(yo).max():.2e}")
 
 
+@pytest.mark.parametrize("p", range(1, 9))
+def test_vmult_fp32_mfma_within_rounding_bound(p):
+    """The matrix-core form of the FP32 operator: the same componentwise bound as the VALU FP32
+    path (each MFMA dot product sums at most p+1 terms in FP32, the padding adds exact zeros), and
+    both FP32 forms within twice that bound of each other."""
+    n = SIZES[p]
+    mfq = _mfq()
+    print(f"vmult fp32 mfma p={p} n={n}", flush=True)
+    opm = _op(p, n, 0.1, 0.5, 1, mfq.MFQ_FP32_MFMA)
+    opv = _op(p, n, 0.1, 0.5, 1, mfq.MFQ_FP32)
+    x = uniform_vector(opm.n_dofs, seed=20 + p)
+    x32 = x.astype(np.float32).astype(np.float64)
+    ym = _run(opm, x)
+    yv = _run(opv, x)
+    yo = assemble.operator_csr(p, n, 0.1, 0.5, 1) @ x32
+    mag = ebe.magnitude_bound(p, n, 0.1, 0.5, x32, 1)
+    k = 8 * (p + 1) + 16
+    assert np.all(np.abs(ym - yo) <= 2 * k * U32 * mag + 1e-30)
+    assert np.all(np.abs(ym - yv) <= 4 * k * U32 * mag + 1e-30)
+    print(f"p={p} fp32-mfma normwise rel err {np.abs(ym - yo).max() / np.abs(yo).max():.2e}")
+
+
+@pytest.mark.parametrize("p,n", [(8, 5), (6, 4), (3, 9)])
+def test_vmult_fp32_mfma_accumulate_and_dirichlet(p, n):
+    """dst += A src on the matrix-core path equals dst + A src of the VALU path (same bound)."""
+    mfq = _mfq()
+    torch = _torch()
+    opm = _op(p, n, 0.1, 0.5, 1, mfq.MFQ_FP32_MFMA)
+    x = torch.from_numpy(uniform_vector(opm.n_dofs, seed=3)).float().cuda()
+    d0 = torch.from_numpy(uniform_vector(opm.n_dofs, seed=4)).float().cuda()
+    d = d0.clone()
+    opm.vmult_add(x, d)
+    y = opm.vmult(x)
+    torch.cuda.synchronize()
+    ref = (d0.double() + y.double()).cpu().numpy()
+    got = d.double().cpu().numpy()
+    assert np.abs(got - ref).max() <= 1e-5 * np.abs(ref).max()
+    # Dirichlet rows: identity on the input
+    bmask = mesh.boundary_mask(p, n) == 0
+    np.testing.assert_array_equal(y.cpu().numpy()[bmask], x.cpu().numpy()[bmask])
+
+
+def test_sampled_parity_full_size_q8_24_mfma():
+    """The high-degree workload at full size (Q8 on the curved 24^3 mesh, 7,189,057 DoFs) on the
+    matrix cores: sampled rows recomputed by the oracle cell by cell, within the FP32 bound."""
+    mfq = _mfq()
+    torch = _torch()
+    p, n = 8, 24
+    print("full-size sampled parity Q8 24^3 fp32-mfma", flush=True)
+    op = _op(p, n, 0.1, 0.5, 1, mfq.MFQ_FP32_MFMA)
+    x_np = uniform_vector(op.n_dofs, seed=5)
+    x32 = x_np.astype(np.float32).astype(np.float64)
+    y = op.vmult(torch.from_numpy(x32).float().cuda())
+    torch.cuda.synchronize()
+    N1 = p * n + 1
+    rng = np.random.default_rng(2)
+    rows = np.concatenate([rng.integers(0, op.n_dofs, 8), [1 + N1 + N1 * N1, N1 * N1 * N1 // 2,
+                                                            8 + 8 * N1 + 8 * N1 * N1, 9 + 17 * N1 + 100 * N1 * N1]])
+    yo = ebe.ebe_rows(p, n, 0.1, 0.5, x32, 1, rows)
+    mag = ebe.ebe_rows(p, n, 0.1, 0.5, np.abs(x32), 1, rows, magnitude=True)
+    yg = y[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    k = 8 * (p + 1) + 16
+    assert np.all(np.abs(yg - yo) <= 2 * k * U32 * mag + 1e-30)
+
+
 def test_poisson_q2_8_vmult():
     # the small Poisson workload: Q2 on 8^3 affine cells (4,913 DoFs), applied to the seeded f
     mfq = _mfq()
