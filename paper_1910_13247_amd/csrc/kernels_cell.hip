@@ -166,36 +166,47 @@ __global__ __launch_bounds__(kBlock) void geometry_export_kernel(const Real* __r
 }
 
 // ---------------------------------------------------------------- operator application
-// Gather of a brick's node lattice by BLOCK threads (KPT nodes each): global index from the index
-// lattice (~g on Dirichlet nodes, kAbsent outside the mesh), store/add bit per node (bit j of
-// `first`, in a vector register), source values into `lat` (zero on Dirichlet and absent nodes)
-// and the dst values this launch adds to.  A node shared with neighbouring bricks is written by
-// each of them, each in its own launch: the brick that is even in every direction in which the
-// node is shared stores (its colour comes first), the others add to what is there.
-template <int P, typename Real, bool ACC, int BLOCK, int KPT>
-__device__ __forceinline__ void gather_lattice(const int* __restrict__ ip, const Real* __restrict__ src,
-                                               const Real* __restrict__ dst, const Bricks& bk, int bi, int bj,
-                                               int bz, Real* lat, int (&gk)[KPT], unsigned& first, Real (&dv)[KPT]) {
+// Gather of a brick's node lattice by BLOCK threads (KPT nodes each), in two steps so that other
+// loads can be issued in between (vector-memory loads complete in issue order, so a load issued
+// before the index lattice would delay the dependent source gather):
+//  lattice_index: global index of each node from the index lattice (~g on Dirichlet nodes,
+//    kAbsent outside the mesh) and its store/add bit (bit j of `first`, in a vector register);
+//  lattice_values: source values into `lat` (zero on Dirichlet and absent nodes) and the dst
+//    values this launch adds to.
+// A node shared with neighbouring bricks is written by each of them, each in its own launch: the
+// brick that is even in every direction in which the node is shared stores (its colour comes
+// first), the others add to what is there.
+template <int P, int BLOCK, int KPT>
+__device__ __forceinline__ void lattice_index(const int* __restrict__ ip, const Bricks& bk, int bi, int bj, int bz,
+                                              int (&gk)[KPT], unsigned& first) {
   using C = Cell<P>;
   constexpr int LX = C::LX, LY = C::LY, NL = C::NL;
   const int tid = threadIdx.x;
+  // loads only: the loaded indices are first used in lattice_values
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) gk[j] = __builtin_nontemporal_load(ip + min(tid + j * BLOCK, NL - 1));
+  // bitwise logic (no short-circuit branches: a branch here would also force a wait for the loads)
   first = 0;
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
-    const int k = tid + j * BLOCK;
-    const int kk = k < NL ? k : NL - 1;
-    const int gl = ip[kk];
-    gk[j] = k < NL ? gl : kAbsent;
+    const int kk = min(tid + j * BLOCK, NL - 1);
     const int li = kk % LX, lj = (kk / LX) % LY, lk = kk / (LX * LY);
-    const bool sx = (li == 0 && bi > 0) || (li == LX - 1 && bi < bk.nbx - 1);
-    const bool sy = (lj == 0 && bj > 0) || (lj == LY - 1 && bj < bk.nby - 1);
-    const bool sz = (lk == 0 && bz > 0) || (lk == C::LZ - 1 && bz < bk.nbz - 1);
-    const bool fj = (!sx || !(bi & 1)) && (!sy || !(bj & 1)) && (!sz || !(bz & 1));
+    const bool sx = ((li == 0) & (bi > 0)) | ((li == LX - 1) & (bi < bk.nbx - 1));
+    const bool sy = ((lj == 0) & (bj > 0)) | ((lj == LY - 1) & (bj < bk.nby - 1));
+    const bool sz = ((lk == 0) & (bz > 0)) | ((lk == C::LZ - 1) & (bz < bk.nbz - 1));
+    const bool fj = ((!sx) | !(bi & 1)) & ((!sy) | !(bj & 1)) & ((!sz) | !(bz & 1));
     first |= fj ? 1u << j : 0u;
   }
+}
+
+template <typename Real, bool ACC, int BLOCK, int KPT, int NL>
+__device__ __forceinline__ void lattice_values(const Real* __restrict__ src, const Real* __restrict__ dst,
+                                               int (&gk)[KPT], unsigned first, Real* lat, Real (&dv)[KPT]) {
+  const int tid = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
-    const int g0 = gk[j];
+    const int g0 = tid + j * BLOCK < NL ? gk[j] : kAbsent;
+    gk[j] = g0;
     const bool live = g0 >= 0;
     const int gs = live ? g0 : 0;
     const Real s = src[gs];
@@ -283,27 +294,28 @@ __global__ __launch_bounds__(Cell<P>::BLOCK) void vmult_kernel(const int* __rest
   // later holds the 6(p+1) values in registers for a shorter time.
   Real2<Real> g[N1][3];
   const bool cell_in = lane_ok && bi * C::BX + cx < bk.n && bj * C::BY + cy < bk.n && bz * C::BZ + cz < bk.n;
+  // Branch-free: lanes without a cell in the mesh read lane 0's entries (inside the brick, a line
+  // the wave fetches anyway) and zero them.  A branch around the loads would make the compiler wait
+  // for all outstanding loads at the join, G included, before the dependent source gather.
   auto load_g = [&]() {
-    const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + tid;
-    if (cell_in) {
+    const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + (cell_in ? tid : 0);
 #pragma unroll
-      for (int t = 0; t < N1; ++t)
+    for (int t = 0; t < N1; ++t)
 #pragma unroll
-        for (int m = 0; m < 3; ++m) g[t][m] = __builtin_nontemporal_load(gp + (t * 3 + m) * NT);
-    } else {
-#pragma unroll
-      for (int t = 0; t < N1; ++t)
-#pragma unroll
-        for (int m = 0; m < 3; ++m) g[t][m] = Real2<Real>{0, 0};
-    }
+      for (int m = 0; m < 3; ++m) {
+        const Real2<Real> v = __builtin_nontemporal_load(gp + (t * 3 + m) * NT);
+        g[t][m] = cell_in ? v : Real2<Real>{0, 0};
+      }
   };
-  if (MFQ_G_STAGE == 0) load_g();
 
-  // this thread's lattice nodes
+  // this thread's lattice nodes: index lattice first, then G (not needed before the z
+  // contraction), then the source and dst values that depend on the indices
   int gk[KPT];
   unsigned first;
   Real dv[KPT];
-  gather_lattice<P, Real, ACC, BLOCK, KPT>(idx + ord * (int64_t)NL, src, dst, bk, bi, bj, bz, lat, gk, first, dv);
+  lattice_index<P, BLOCK, KPT>(idx + ord * (int64_t)NL, bk, bi, bj, bz, gk, first);
+  if (MFQ_G_STAGE == 0) load_g();
+  lattice_values<Real, ACC, BLOCK, KPT, NL>(src, dst, gk, first, lat, dv);
   lds_barrier();
 
   // x: values and x-derivatives at (q, e0, e1) from the lane's x-pencil
@@ -510,7 +522,8 @@ __global__ __launch_bounds__(MCell<P>::BLOCK) void vmult_mfma_kernel(MfmaTables<
   int gk[KPT];
   unsigned first;
   float dv[KPT];
-  gather_lattice<P, float, ACC, BLOCK, KPT>(idx + ord * (int64_t)NL, src, dst, bk, bi, bj, bz, lat, gk, first, dv);
+  lattice_index<P, BLOCK, KPT>(idx + ord * (int64_t)NL, bk, bi, bj, bz, gk, first);
+  lattice_values<float, ACC, BLOCK, KPT, NL>(src, dst, gk, first, lat, dv);
 
   float aS[KS], aD[KS], aSt[KS], aDt[KS];
   a_operand<N1, KS>(tab.S, false, lane, aS);
