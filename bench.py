@@ -176,7 +176,7 @@ def solve_benchmarks(steps):
     return out
 
 
-def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=4):
+def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=4, mode="async"):
     """The serving stream: Poisson arrivals at `rate`/s, degree U{1..6}, n U{4..48}, alpha
     U[0,0.9], right-hand side from the request's seed; each solved to relative residual 1e-10."""
     import torch
@@ -187,7 +187,7 @@ def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=
     arrivals = [d["arrival"] for d in stream]
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(0.75 * free, 160e9))
-    srv = Server(DeviceExecutor(n_streams=n_streams), budget, iters_per_step=iters_per_step)
+    srv = Server(DeviceExecutor(n_streams=n_streams), budget, iters_per_step=iters_per_step, mode=mode)
     t0 = time.perf_counter()
     st = run_stream(srv, reqs, arrivals)
     torch.cuda.synchronize()
@@ -195,6 +195,7 @@ def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=
     st["budget_bytes"] = budget
     st["iters_per_step"] = iters_per_step
     st["streams"] = n_streams
+    st["mode"] = mode
     st["rate_per_s"] = rate
     st["dofs_total"] = sum((r.degree * r.n + 1) ** 3 for r in reqs)
     st["iterations_mean"] = sum(r.iterations for r in srv.done) / max(len(srv.done), 1)
@@ -211,6 +212,9 @@ def main():
     ap.add_argument("--solves", action="store_true", help="add time-to-1e-10 of the Q3 128^3 solvers")
     ap.add_argument("--serve", type=int, default=0, metavar="N",
                     help="also replay N requests of the serving stream (200 requests/s) and report solves/s, p50/p99")
+    ap.add_argument("--serve-mode", choices=["sync", "async"], default="async",
+                    help="serving steps: all solves together (sync) or each at its own pace (async)")
+    ap.add_argument("--serve-streams", type=int, default=4)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run 3 plain device copies of 1 GiB (reference reading for HBM byte counters)")
     args = ap.parse_args()
@@ -293,7 +297,7 @@ def main():
         rec["solves_q3_128"] = solve_benchmarks(args.steps)
     if args.serve:
         print(f"# serving {args.serve} requests", file=sys.stderr, flush=True)
-        rec["serving"] = serve_benchmark(args.serve)
+        rec["serving"] = serve_benchmark(args.serve, mode=args.serve_mode, n_streams=args.serve_streams)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, n, pr.amplitude, pr.alpha, x_np)

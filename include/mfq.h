@@ -236,9 +236,19 @@ int mfq_solve_begin(mfq_solver* s, const double* b, double* x, double rtol, int 
  * Solves on different streams overlap on the device. */
 int mfq_batch_step(mfq_solver* const* solvers, int count, int iters, int* done);
 
-/* Finishes a solve that mfq_batch_step reported done: fills info and returns the solve's status
- * (MFQ_OK, MFQ_ENOCONV or MFQ_ENONFINITE); the solver can then begin another solve.
- * MFQ_EINVAL if no solve has finished. */
+/* Non-blocking form of a step of one solve.  mfq_solve_step_async enqueues up to `iters` CG
+ * iterations (or the residual check) and the status copy on the solve's stream and records an
+ * event; MFQ_EBUSY while the previous asynchronous step has not been polled to completion, MFQ_OK
+ * without work once the solve is done.  mfq_solve_step_poll never waits: *ready = 0 while that
+ * work runs; otherwise it reads the outcome, sets *ready = 1 and *done = 1 once the solve has
+ * finished.  Lets a caller advance each solve at its own pace instead of waiting for all of them
+ * at every step.  Not to be mixed with mfq_batch_step on a solve with a step in flight. */
+int mfq_solve_step_async(mfq_solver* s, int iters);
+int mfq_solve_step_poll(mfq_solver* s, int* ready, int* done);
+
+/* Finishes a solve reported done (by mfq_batch_step or mfq_solve_step_poll): fills info and
+ * returns the solve's status (MFQ_OK, MFQ_ENOCONV or MFQ_ENONFINITE); the solver can then begin
+ * another solve.  MFQ_EINVAL if no solve has finished. */
 int mfq_solve_end(mfq_solver* s, mfq_solve_info* info);
 /* z = M r: one application of the solver's preconditioner (the V-cycle; identity for CG) to
  * the double device vector r.  Asynchronous. */

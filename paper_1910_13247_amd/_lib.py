@@ -87,6 +87,8 @@ _SIGS = {
     "mfq_solve_begin": ([P, P, P, D, I, P], I),
     "mfq_batch_step": ([C.POINTER(C.c_void_p), I, I, C.POINTER(C.c_int)], I),
     "mfq_solve_end": ([P, C.POINTER(SolveInfo)], I),
+    "mfq_solve_step_async": ([P, I], I),
+    "mfq_solve_step_poll": ([P, C.POINTER(C.c_int), C.POINTER(C.c_int)], I),
     "mfq_solver_lambdas": ([P, C.POINTER(D), I], I),
     "mfq_solver_precondition": ([P, P, P, P], I),
 }
@@ -282,6 +284,17 @@ def mfq_batch_step(solvers, iters):
     done = (C.c_int * max(n, 1))()
     _check(lib().mfq_batch_step(arr, n, iters, done))
     return [bool(done[i]) for i in range(n)]
+
+
+def mfq_solve_step_async(s, iters):
+    _check(lib().mfq_solve_step_async(s, iters))
+
+
+def mfq_solve_step_poll(s):
+    """(ready, done) of the solve's last asynchronous step; never waits."""
+    ready, done = C.c_int(), C.c_int()
+    _check(lib().mfq_solve_step_poll(s, C.byref(ready), C.byref(done)))
+    return bool(ready.value), bool(done.value)
 
 
 def mfq_solve_end(s, check=True):

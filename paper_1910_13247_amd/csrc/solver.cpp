@@ -97,12 +97,15 @@ struct mfq_solver {
   };
   IterGraph graphs[2];
   int next_graph = 0;
+  hipEvent_t step_event = nullptr;  // completion of the last asynchronous step
+  bool step_pending = false;
   // Lanczos traces of the eigenvalue estimates (device region in the buffer, pinned host copy)
   size_t off_trace = 0;
   double* trace = nullptr;
   double* trace_host = nullptr;
   int trace_stride = 0;  // doubles per level: 2 * lanczos_iters coefficients + the step count
   ~mfq_solver() {
+    if (step_event) (void)hipEventDestroy(step_event);
     if (trace_host) (void)hipHostFree(trace_host);
     for (IterGraph& g : graphs)
       if (g.exec) (void)hipGraphExecDestroy(g.exec);
@@ -534,7 +537,8 @@ int step_collect(mfq_solver* s) {
 int begin_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_iter, hipStream_t st) {
   if (!s) return fail(MFQ_EINVAL, "solver is NULL");
   if (!s->buf) return fail(MFQ_EINVAL, "solver is not bound");
-  if (s->run.phase == Run::kInner || s->run.phase == Run::kCheck) return fail(MFQ_EBUSY, "a solve is running");
+  if (s->run.phase == Run::kInner || s->run.phase == Run::kCheck || s->step_pending)
+    return fail(MFQ_EBUSY, "a solve is running");
   if (!b || !x || (reinterpret_cast<uintptr_t>(b) % 16) || (reinterpret_cast<uintptr_t>(x) % 16))
     return fail(MFQ_EINVAL, "b or x NULL or misaligned");
   if (!(rtol > 0 && rtol < 1)) return fail(MFQ_EINVAL, "rtol must be in (0,1)");
@@ -866,6 +870,7 @@ int mfq_batch_step(mfq_solver* const* solvers, int count, int iters, int* done) 
   for (int i = 0; i < count; ++i) {
     mfq_solver* s = solvers[i];
     if (!s || s->run.phase == Run::kIdle) return fail(MFQ_EINVAL, "solver %d has no running solve", i);
+    if (s->step_pending) return fail(MFQ_EBUSY, "solver %d has an asynchronous step in flight", i);
   }
   for (int i = 0; i < count; ++i) {
     mfq_solver* s = solvers[i];
@@ -890,10 +895,42 @@ int mfq_batch_step(mfq_solver* const* solvers, int count, int iters, int* done) 
   return MFQ_OK;
 }
 
+int mfq_solve_step_async(mfq_solver* s, int iters) {
+  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
+  if (iters < 1) return fail(MFQ_EINVAL, "iters must be >= 1");
+  if (s->run.phase == Run::kIdle) return fail(MFQ_EINVAL, "no running solve");
+  if (s->step_pending) return fail(MFQ_EBUSY, "the previous step has not been polled to completion");
+  if (s->run.phase == Run::kDone) return MFQ_OK;
+  if (!s->step_event) MFQ_HIP(hipEventCreateWithFlags(&s->step_event, hipEventDisableTiming));
+  if (int rc = step_enqueue(s, iters)) return rc;
+  MFQ_HIP(hipEventRecord(s->step_event, s->run.st));
+  s->step_pending = true;
+  return MFQ_OK;
+}
+
+int mfq_solve_step_poll(mfq_solver* s, int* ready, int* done) {
+  if (!s || !ready || !done) return fail(MFQ_EINVAL, "solver, ready or done is NULL");
+  *ready = 0;
+  *done = s->run.phase == Run::kDone ? 1 : 0;
+  if (s->run.phase == Run::kIdle) return fail(MFQ_EINVAL, "no running solve");
+  if (!s->step_pending) {
+    *ready = 1;
+    return MFQ_OK;
+  }
+  const hipError_t e = hipEventQuery(s->step_event);
+  if (e == hipErrorNotReady) return MFQ_OK;
+  if (e != hipSuccess) return fail(MFQ_EHIP, "hipEventQuery failed: %s", hipGetErrorString(e));
+  s->step_pending = false;
+  if (int rc = step_collect(s)) return rc;
+  *ready = 1;
+  *done = s->run.phase == Run::kDone ? 1 : 0;
+  return MFQ_OK;
+}
+
 int mfq_solve_end(mfq_solver* s, mfq_solve_info* info) {
   if (!s) return fail(MFQ_EINVAL, "solver is NULL");
   Run& R = s->run;
-  if (R.phase != Run::kDone) return fail(MFQ_EINVAL, "no finished solve");
+  if (R.phase != Run::kDone || s->step_pending) return fail(MFQ_EINVAL, "no finished solve");
   mfq_solve_info inf{};
   inf.iterations = R.iters;
   inf.outer_iterations = R.pass;

@@ -106,6 +106,12 @@ class DeviceExecutor:
     def step(self, handles, iters):
         return _lib.mfq_batch_step([h["solver"] for h in handles], iters)
 
+    def submit(self, h, iters):
+        _lib.mfq_solve_step_async(h["solver"], iters)
+
+    def poll(self, h):
+        return _lib.mfq_solve_step_poll(h["solver"])
+
     def finish(self, req, h):
         status, info = _lib.mfq_solve_end(h["solver"], check=False)
         req.status = status
@@ -127,9 +133,19 @@ class DeviceExecutor:
 
 
 class Server:
-    """FIFO admission by device footprint, continuous batching, latency accounting."""
+    """FIFO admission by device footprint, continuous batching, latency accounting.
 
-    def __init__(self, executor, budget_bytes, iters_per_step=2, max_active=256, clock=time.perf_counter):
+    mode "sync": every step advances all running solves together and waits for all of them
+    (mfq_batch_step).  mode "async": each solve's next few iterations are enqueued as soon as its
+    previous ones have been polled complete (mfq_solve_step_async / _poll), so a long request does
+    not hold back the others; a step is one pass over the running solves and never waits."""
+
+    def __init__(self, executor, budget_bytes, iters_per_step=2, max_active=256, clock=time.perf_counter,
+                 mode="sync", idle_sleep=2e-5):
+        if mode not in ("sync", "async"):
+            raise ValueError("mode must be 'sync' or 'async'")
+        self.mode = mode
+        self.idle_sleep = idle_sleep
         self.ex = executor
         self.budget = int(budget_bytes)
         self.iters = int(iters_per_step)
@@ -185,11 +201,13 @@ class Server:
         self.peak_active = max(self.peak_active, len(self.active))
 
     def step(self):
-        """Admit what fits, advance every running solve once, retire the finished ones.
+        """Admit what fits, advance the running solves, retire the finished ones.
         Returns the requests finished in this step."""
         self._admit()
         if not self.active:
             return []
+        if self.mode == "async":
+            return self._step_async()
         t = time.perf_counter()
         flags = self.ex.step([h for _, h in self.active], self.iters)
         self.step_s += time.perf_counter() - t
@@ -198,15 +216,48 @@ class Server:
         finished, still = [], []
         for (req, h), d in zip(self.active, flags):
             if d:
-                self.ex.finish(req, h)
-                req.finished = now
-                self.used -= req.footprint
-                self.ex.release(h)
+                self._retire(req, h, now)
                 finished.append(req)
             else:
                 still.append((req, h))
         self.active = still
-        self.done.extend(finished)
+        return finished
+
+    def _retire(self, req, h, now):
+        self.ex.finish(req, h)
+        req.finished = now
+        self.used -= req.footprint
+        self.ex.release(h)
+        self.done.append(req)
+
+    def _step_async(self):
+        t = time.perf_counter()
+        finished, still, progressed = [], [], False
+        for req, h in self.active:
+            if not h.get("inflight"):
+                self.ex.submit(h, self.iters)
+                h["inflight"] = True
+                progressed = True
+                still.append((req, h))
+                continue
+            ready, done = self.ex.poll(h)
+            if not ready:
+                still.append((req, h))
+                continue
+            progressed = True
+            h["inflight"] = False
+            if done:
+                self._retire(req, h, self.clock())
+                finished.append(req)
+            else:
+                self.ex.submit(h, self.iters)
+                h["inflight"] = True
+                still.append((req, h))
+        self.active = still
+        self.steps += 1
+        self.step_s += time.perf_counter() - t
+        if not progressed and self.idle_sleep:
+            time.sleep(self.idle_sleep)
         return finished
 
     @property

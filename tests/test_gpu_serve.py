@@ -29,6 +29,7 @@ def _requests(rtol=1e-10):
 
 def _serve(reqs, budget=8 << 30, **kw):
     from paper_1910_13247_amd.serve import DeviceExecutor, Server
+    kw.setdefault("idle_sleep", 0)
     srv = Server(DeviceExecutor(keep_results=True), budget, **kw)
     for r in reqs:
         srv.submit(r)
@@ -115,12 +116,13 @@ def test_cg_true_residual_certified():
     assert solve.rel_residual(lambda v: At @ v, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10
 
 
-def test_served_results_match_oracle():
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_served_results_match_oracle(mode):
     """Each served request solves its own system: the solution agrees with a sparse direct solve
     of the oracle's assembled operator for the same counter-based right-hand side."""
-    print("serve vs oracle", flush=True)
+    print(f"serve vs oracle ({mode})", flush=True)
     reqs = _requests()
-    srv = _serve(reqs)
+    srv = _serve(reqs, mode=mode)
     assert len(srv.done) == len(reqs)
     for r in reqs:
         assert r.status == 0 and r.rel_residual <= 1e-10, (r.degree, r.n, r.rel_residual)
@@ -134,15 +136,16 @@ def test_served_results_match_oracle():
         assert np.abs(x - xd).max() <= 1e-6 * np.abs(xd).max(), (r.degree, r.n)
 
 
-def test_alone_and_in_mix_agree():
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_alone_and_in_mix_agree(mode):
     """The same request alone and among others: equal iteration counts and solutions equal
     within what the 1e-10 residual tolerance allows (both are certified)."""
-    print("alone vs mix", flush=True)
+    print(f"alone vs mix ({mode})", flush=True)
     mixed = _requests()
-    _serve(mixed)
+    _serve(mixed, mode=mode)
     for i, p in enumerate(MIX):
         alone = _requests()[i]
-        _serve([alone])
+        _serve([alone], mode=mode)
         m = mixed[i]
         assert alone.status == m.status == 0
         assert abs(alone.iterations - m.iterations) <= 1, (p, alone.iterations, m.iterations)
@@ -201,3 +204,38 @@ def test_graph_replay_matches_direct_launches():
         assert abs(d[1] - g[1]) <= 1, (kind, d[1], g[1])
         assert d[2] <= 1e-10 and g[2] <= 1e-10
         assert (d[3] - g[3]).abs().max().item() <= 1e-8 * d[3].abs().max().item()
+
+
+def test_async_step_protocol():
+    """mfq_solve_step_async / _poll: a second submit before the poll completes is refused, the
+    poll reports done exactly when the solve has finished, and the result is certified."""
+    mfq = _mfq()
+    torch = _torch()
+    _lib = mfq._lib
+    m = mfq.Mesh(6, 0.1)
+    s = mfq.Space(m, 2, mfq.MFQ_BC_DIRICHLET0)
+    op = mfq.Operator(s, 0.3, mfq.MFQ_FP64)
+    b = s.random(9)
+    x = op.new_vector()
+    st = torch.cuda.Stream()
+    sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, coarse_mode=1)
+    with pytest.raises(_lib.MfqError):
+        _lib.mfq_solve_step_poll(sv.handle)          # nothing begun
+    sv.begin(b, x, stream=st)
+    _lib.mfq_solve_step_async(sv.handle, 2)
+    with pytest.raises(_lib.MfqError) as e:
+        _lib.mfq_solve_step_async(sv.handle, 2)      # previous step not yet polled complete
+    assert e.value.status == mfq.MFQ_EBUSY
+    polls = 0
+    while True:
+        ready, done = _lib.mfq_solve_step_poll(sv.handle)
+        polls += 1
+        assert polls < 10**7
+        if not ready:
+            continue
+        if done:
+            break
+        _lib.mfq_solve_step_async(sv.handle, 2)
+    status, info = sv.end()
+    torch.cuda.synchronize()
+    assert status == mfq.MFQ_OK and info.rel_residual <= 1e-10

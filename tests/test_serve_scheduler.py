@@ -45,6 +45,19 @@ class FakeExecutor:
             out.append(h["left"] <= 0)
         return out
 
+    # asynchronous protocol: a submitted step is ready after `lag` polls
+    def submit(self, h, iters):
+        assert not h.get("pending"), "submit while a step is in flight"
+        h["pending"] = h["req"].seed % 3 + 1
+
+    def poll(self, h):
+        self.clock.t += 1e-4
+        h["pending"] -= 1
+        if h["pending"] > 0:
+            return False, False
+        h["left"] -= 1
+        return True, h["left"] <= 0
+
     def finish(self, req, h):
         req.status = _lib.MFQ_OK
         req.iterations = req.n * 2
@@ -133,3 +146,34 @@ def test_percentile_nearest_rank():
     v = list(range(1, 101))
     assert percentile(v, 50) == 50 and percentile(v, 99) == 99 and percentile(v, 100) == 100
     assert percentile([7.0], 99) == 7.0
+
+
+@pytest.mark.parametrize("budget", [500, 10**6])
+def test_async_mode_completes_everything_within_budget(budget):
+    """Asynchronous stepping: every request finishes, the budget is never exceeded, each request's
+    steps are submitted only after the previous one was polled complete (asserted by the fake)."""
+    srv, ex, clock = make(budget=budget, mode="async", idle_sleep=0)
+    reqs = [Request(degree=1 + i % 4, n=1 + i % 5, alpha=0.0, seed=i) for i in range(30)]
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    assert all(r.status == _lib.MFQ_OK for r in reqs) and len(srv.done) == 30
+    assert ex.max_live_bytes <= budget and srv.peak_used <= budget and srv.used == 0
+    assert all(r.finished >= r.admitted >= r.arrival for r in reqs)
+
+
+def test_async_mode_short_request_overtakes_long_one():
+    srv, ex, clock = make(budget=10**6, mode="async", idle_sleep=0)
+    long = Request(degree=1, n=60, alpha=0.0, seed=0)
+    short = Request(degree=1, n=2, alpha=0.0, seed=3)
+    srv.submit(long)
+    srv.submit(short)
+    order = []
+    while not srv.idle:
+        order += [r.id for r in srv.step()]
+    assert order == [short.id, long.id]
+
+
+def test_mode_is_validated():
+    with pytest.raises(ValueError):
+        make(budget=1, mode="parallel")
