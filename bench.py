@@ -5,10 +5,12 @@ Step = one matrix-free application y = A x of the variable-coefficient Q4 Laplac
 curved 64^3-cell mesh (257^3 = 16,974,593 DoFs; deformation amplitude 0.1, coefficient
 a = 1 + 0.5 sin sin sin), FP64, with the input resident in HBM.  Prints one JSON line:
 DoFs/s of the step, the roofline of the dominant kernel (the cell loop, timed with HIP events
-on its stream), an FP32 figure of the same operator, and the CPU oracle on a bounded sample of
-the same workload.
+on its stream), an FP32 figure of the same operator, the same operator assembled as a sparse
+matrix and applied by the library's CSR product, and the CPU oracle on a bounded sample of the
+same workload.
 
-    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--solves] [--serve N] [--copy-probe]
+    python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--solves] [--serve N] [--no-csr]
+                    [--csr-sweep] [--copy-probe]
 """
 import argparse
 import json
@@ -156,6 +158,82 @@ def high_degree_comparison(steps, warmup):
     return out
 
 
+def time_events(fn, steps, warmup):
+    """Average seconds per call of fn() between two events on torch's current stream."""
+    import torch
+    for _ in range(warmup):
+        fn()
+    e0 = torch.cuda.Event(enable_timing=True)
+    e1 = torch.cuda.Event(enable_timing=True)
+    torch.cuda.synchronize()
+    e0.record()
+    for _ in range(steps):
+        fn()
+    e1.record()
+    torch.cuda.synchronize()
+    return e0.elapsed_time(e1) / 1e3 / steps
+
+
+def csr_bytes(n_rows, nnz):
+    """Algorithmic bytes of one CSR product: values (8 B) and columns (4 B) per entry, row pointers
+    (8 B per row + 1), the source and destination vectors (8 B per row each)."""
+    return 12 * nnz + 8 * (n_rows + 1) + 16 * n_rows
+
+
+def assembled_comparison(op, x, y_mf, mf_s, steps, warmup):
+    """The same operator assembled as a CSR matrix on the device and applied by the library's
+    sparse product: assembly time, product time, its HBM roofline fraction, and the matrix-free
+    application's speed-up over it (matrix-free time = the cell loop of one application)."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    A = mfq.SparseMatrix(op)
+    torch.cuda.synchronize()
+    t_asm = time.perf_counter() - t0
+    y = torch.empty_like(x)
+    s = time_events(lambda: A.spmv(x, y), steps, warmup)
+    rb = csr_bytes(A.n_rows, A.nnz)
+    out = {"nnz": A.nnz, "device_bytes": A.device_bytes, "assemble_s": t_asm, "ms": s * 1e3,
+           "algorithmic_bytes": rb, "achieved_GBs": rb / s / 1e9, "frac": rb / s / 1e9 / HBM_PEAK_GBS,
+           "kernel": "csr_spmv_rows_kernel" if A.nnz / A.n_rows >= 384 else "csr_spmv_kernel (row blocks)",
+           "matrix_free_ms": mf_s * 1e3, "speedup_matrix_free": s / mf_s,
+           "bytes_ratio": rb / algorithmic_bytes(op.space.degree, op.space.mesh.n, 8),
+           "normwise_rel_diff_vs_matrix_free": ((y - y_mf).abs().max() / y_mf.abs().max()).item()}
+    del A, y
+    torch.cuda.synchronize()
+    torch.cuda.empty_cache()
+    return out
+
+
+# degree sweep of the assembled-matrix comparison: (p, n) with about 16M DoFs (7.5M at p = 7, 8,
+# whose matrices would otherwise exceed 100 GB)
+CSR_SWEEP = [(1, 256), (2, 128), (3, 85), (4, 64), (5, 50), (6, 42), (7, 28), (8, 24)]
+
+
+def csr_sweep(steps, warmup):
+    import torch
+    import paper_1910_13247_amd as mfq
+    from synthetic import uniform_vector
+    out = []
+    for p, n in CSR_SWEEP:
+        print(f"# csr sweep p={p} n={n}", file=sys.stderr, flush=True)
+        op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.1), p, mfq.MFQ_BC_DIRICHLET0), 0.5, mfq.MFQ_FP64)
+        x = torch.from_numpy(uniform_vector(op.n_dofs, seed=0)).cuda()
+        y = op.new_vector()
+        mf = time_events(lambda: op.vmult(x, y), steps, warmup)
+        rec = assembled_comparison(op, x, y, mf, steps, warmup)
+        rec.update({"degree": p, "cells_1d": n, "dofs": op.n_dofs,
+                    "csr_bytes_per_dof": rec["algorithmic_bytes"] / op.n_dofs,
+                    "matrix_free_bytes_per_dof": algorithmic_bytes(p, n, 8) / op.n_dofs,
+                    "matrix_free_GBs": algorithmic_bytes(p, n, 8) / mf / 1e9})
+        out.append(rec)
+        del op, x, y
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def solve_benchmarks(steps):
     """Time-to-1e-10 of the multigrid and CG solvers on the Q3 128^3 curved problem."""
     import torch
@@ -215,6 +293,9 @@ def main():
     ap.add_argument("--serve-mode", choices=["sync", "async"], default="async",
                     help="serving steps: all solves together (sync) or each at its own pace (async)")
     ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--no-csr", action="store_true", help="skip the assembled-matrix (CSR) comparison")
+    ap.add_argument("--csr-sweep", action="store_true",
+                    help="add the assembled-matrix comparison for degrees 1..8 at about 16M DoFs")
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run 3 plain device copies of 1 GiB (reference reading for HBM byte counters)")
     args = ap.parse_args()
@@ -291,6 +372,11 @@ def main():
         torch.cuda.synchronize()
         rec["copy_probe_bytes"] = {"read": a.numel() * 8, "write": b.numel() * 8}
         del a, b
+    if not args.no_csr:
+        print("# assembled matrix (CSR) of the same operator", file=sys.stderr, flush=True)
+        rec["assembled_csr"] = assembled_comparison(op64, x64, y64, kern64, min(args.steps, 20), args.warmup)
+    if args.csr_sweep:
+        rec["csr_sweep"] = csr_sweep(min(args.steps, 20), args.warmup)
     print("# Q8 24^3: FP64 / FP32 / FP32 matrix cores", file=sys.stderr, flush=True)
     rec["high_degree_q8_24"] = high_degree_comparison(min(args.steps, 20), args.warmup)
     if args.solves:

@@ -68,6 +68,7 @@ typedef struct mfq_mesh mfq_mesh;
 typedef struct mfq_space mfq_space;
 typedef struct mfq_op mfq_op;
 typedef struct mfq_transfer mfq_transfer;
+typedef struct mfq_csr mfq_csr;
 typedef struct mfq_solver mfq_solver;
 
 /* Library version string and the message of the last failed call on this thread. */
@@ -146,6 +147,34 @@ int mfq_op_geometry(const mfq_op* op, double* out_device, void* hip_stream);
  * solution u* = sin(pi x1) sin(pi x2) sin(pi x3), f = -div(a grad u*); zero on Dirichlet rows.
  * b is a double device vector; computed in FP64 for either operator precision. */
 int mfq_rhs_manufactured(const mfq_op* op, double* b, void* hip_stream);
+
+/* ---------------------------------------------------------------- assembled matrix (Sec. 3.6)
+ * The same operator stored as a global sparse matrix, the representation that the matrix-free
+ * action replaces (Sec. 3.6 weighs the memory transfer of a matrix that couples every unknown
+ * to its neighbours against computing the integrals on the fly).  For measuring the two side
+ * by side on one device; the solvers never use it.
+ * Layout (CSR, in the caller's buffer): rowptr int64 [n_rows+1], cols int32 [nnz] increasing
+ * within each row, vals double [nnz]; n_rows = n_dofs.  Row (I,J,K) holds every node that
+ * shares a cell with it (the tensor product of the 1D neighbour ranges), so
+ * nnz = (n(p+1)^2 - n + 1)^3.  Entries are sum_K A^K_ij over the cells holding both nodes,
+ * computed in FP64 from the operator's stored G.  With MFQ_BC_DIRICHLET0 the couplings of
+ * Dirichlet nodes are stored as zeros and their diagonal as 1, so the matrix applies
+ * m*A(m*x) + (1-m)*x exactly as mfq_vmult does. */
+/* op: an MFQ_FP64 operator (MFQ_EINVAL otherwise).  Host only; nothing is read from the device. */
+int mfq_csr_create(const mfq_op* op, mfq_csr** out);
+void mfq_csr_destroy(mfq_csr* a);
+/* Rows, stored entries and the device bytes mfq_csr_bind needs (any output may be NULL). */
+int mfq_csr_size(const mfq_csr* a, int64_t* n_rows, int64_t* nnz, size_t* device_bytes);
+/* Binds the buffer (256-byte aligned, at least the reported bytes) and assembles the matrix on
+ * the stream (asynchronous).  The operator must be bound, its G complete before the work on
+ * this stream runs, and unchanged until this work has finished; after that the matrix no
+ * longer reads the operator. */
+int mfq_csr_bind(mfq_csr* a, void* dev_buf, size_t bytes, void* hip_stream);
+/* Device addresses of the three arrays inside the bound buffer (MFQ_EINVAL when unbound). */
+int mfq_csr_arrays(const mfq_csr* a, void** rowptr, void** cols, void** vals);
+/* dst = A src for double device vectors of n_rows elements that must not overlap.  Asynchronous,
+ * no host synchronisation, deterministic (fixed summation order per row). */
+int mfq_csr_spmv(const mfq_csr* a, const void* src, void* dst, void* hip_stream);
 
 /* ---------------------------------------------------------------- transfer (Sec. 3.5, 3.1)
  * Interpolation between nested spaces on the same domain: either the fine mesh halves the

@@ -17,7 +17,7 @@ from ._lib import (MfqError, MFQ_FP64, MFQ_FP32, MFQ_FP32_MFMA, MFQ_BC_NONE, MFQ
 __all__ = ["Mesh", "Space", "Operator", "Transfer", "Solver", "MfqError", "MFQ_FP64", "MFQ_FP32", "MFQ_FP32_MFMA",
            "MFQ_BC_NONE", "MFQ_BC_DIRICHLET0", "MFQ_SOLVER_CG", "MFQ_SOLVER_GMG_FP64",
            "MFQ_SOLVER_GMG_MIXED", "MFQ_SOLVER_GMG_MIXED_IR", "MFQ_OK", "MFQ_EINVAL", "MFQ_ENOMEM",
-           "MFQ_EHIP", "MFQ_ENOCONV", "MFQ_ENONFINITE", "MFQ_EBUSY", "batch_step"]
+           "MFQ_EHIP", "MFQ_ENOCONV", "MFQ_ENONFINITE", "MFQ_EBUSY", "batch_step", "SparseMatrix"]
 
 
 def _torch():
@@ -157,6 +157,48 @@ class Operator:
     def __del__(self):
         if getattr(self, "handle", None):
             _lib.mfq_op_destroy(self.handle)
+            self.handle = None
+
+
+class SparseMatrix:
+    """The operator assembled as a CSR matrix on the device (for comparison with the matrix-free
+    action); device data in a torch buffer.  rowptr int64, cols int32, vals float64."""
+
+    def __init__(self, op, stream=None):
+        torch = _torch()
+        if op.precision != MFQ_FP64:
+            raise ValueError("the assembled matrix needs an FP64 operator")
+        self.op = op
+        self.handle = _lib.mfq_csr_create(op.handle)
+        self.n_rows, self.nnz, self.device_bytes = _lib.mfq_csr_size(self.handle)
+        self.buffer = torch.empty(self.device_bytes, dtype=torch.uint8, device=op.buffer.device)
+        _lib.mfq_csr_bind(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream(stream))
+
+    def arrays(self):
+        """(rowptr, cols, vals) as torch views of the bound buffer."""
+        torch = _torch()
+        r, c, v = _lib.mfq_csr_arrays(self.handle)
+        base = self.buffer.data_ptr()
+
+        def view(addr, count, dtype, size):
+            off = addr - base
+            return self.buffer[off:off + count * size].view(dtype)
+
+        return (view(r, self.n_rows + 1, torch.int64, 8), view(c, self.nnz, torch.int32, 4),
+                view(v, self.nnz, torch.float64, 8))
+
+    def spmv(self, src, dst=None, stream=None):
+        torch = _torch()
+        if dst is None:
+            dst = torch.empty(self.n_rows, dtype=torch.float64, device=self.buffer.device)
+        _lib.mfq_csr_spmv(self.handle, _check_vec(src, self.n_rows, MFQ_FP64, "src"),
+                          _check_vec(dst, self.n_rows, MFQ_FP64, "dst"), _stream(stream))
+        return dst
+
+    def __del__(self):
+        h = getattr(self, "handle", None)
+        if h:
+            _lib.mfq_csr_destroy(h)
             self.handle = None
 
 

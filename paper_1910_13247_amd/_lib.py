@@ -73,6 +73,12 @@ _SIGS = {
     "mfq_op_diagonal": ([P, P, P], I),
     "mfq_op_geometry": ([P, P, P], I),
     "mfq_rhs_manufactured": ([P, P, P], I),
+    "mfq_csr_create": ([P, PP], I),
+    "mfq_csr_destroy": ([P], None),
+    "mfq_csr_size": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(SZ)], I),
+    "mfq_csr_bind": ([P, P, SZ, P], I),
+    "mfq_csr_arrays": ([P, PP, PP, PP], I),
+    "mfq_csr_spmv": ([P, P, P, P], I),
     "mfq_transfer_create": ([P, P, PP], I),
     "mfq_transfer_destroy": ([P], None),
     "mfq_prolongate": ([P, I, P, P, P], I),
@@ -218,6 +224,36 @@ def mfq_op_geometry(op, out, stream):
 
 def mfq_rhs_manufactured(op, b, stream):
     _check(lib().mfq_rhs_manufactured(op, b, stream))
+
+
+def mfq_csr_create(op):
+    return _handle(lib().mfq_csr_create, op)
+
+
+def mfq_csr_destroy(a):
+    lib().mfq_csr_destroy(a)
+
+
+def mfq_csr_size(a):
+    """(n_rows, nnz, device_bytes)."""
+    r, z, b = I64(), I64(), SZ()
+    _check(lib().mfq_csr_size(a, C.byref(r), C.byref(z), C.byref(b)))
+    return r.value, z.value, b.value
+
+
+def mfq_csr_bind(a, dev_buf, nbytes, stream):
+    _check(lib().mfq_csr_bind(a, dev_buf, nbytes, stream))
+
+
+def mfq_csr_arrays(a):
+    """Device addresses (rowptr, cols, vals) inside the bound buffer."""
+    r, c, v = C.c_void_p(), C.c_void_p(), C.c_void_p()
+    _check(lib().mfq_csr_arrays(a, C.byref(r), C.byref(c), C.byref(v)))
+    return r.value, c.value, v.value
+
+
+def mfq_csr_spmv(a, src, dst, stream):
+    _check(lib().mfq_csr_spmv(a, src, dst, stream))
 
 
 def mfq_transfer_create(coarse, fine):

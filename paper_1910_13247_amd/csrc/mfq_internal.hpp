@@ -160,6 +160,23 @@ struct mfq_op {
   void* geo = nullptr;        // [n_bricks][p+1][3][lanes][2] of the precision's type
 };
 
+struct mfq_csr {
+  const mfq_op* op;           // FP64 operator whose stored geometry the values are assembled from
+  int p, n, bc;
+  int64_t n_rows, nnz;
+  bool long_rows;             // product by lane groups per row (long rows) instead of row blocks
+  int lanes_per_row;          // lanes that share one row in the product
+  int64_t window;             // entries per row block of the product
+  int64_t n_blocks;           // row blocks: ceil(nnz / window)
+  int64_t max_row;            // longest row
+  size_t rowptr_bytes, cols_bytes, vals_bytes, blk_bytes;
+  void* buf = nullptr;        // caller-owned device memory
+  int64_t* rowptr = nullptr;  // [n_rows + 1]
+  int* cols = nullptr;        // [nnz], increasing within a row
+  double* vals = nullptr;     // [nnz]
+  int64_t* blk = nullptr;     // [n_blocks + 1]: first row of each row block
+};
+
 struct mfq_transfer {
   const mfq_space* coarse;
   const mfq_space* fine;
@@ -205,6 +222,14 @@ hipError_t launch_rhs_cells(const OpView& v, double* b, hipStream_t st);
 hipError_t launch_assemble_dense(const OpView& v, double* mat, int64_t ld, hipStream_t st);
 hipError_t launch_transfer(const mfq_transfer* t, int precision, bool prolongate, const void* in,
                            void* out, hipStream_t st);
+
+// assembled sparse matrix (kernels_csr.hip)
+hipError_t launch_csr_pattern(int p, int n, int64_t* rowptr, int* cols, hipStream_t st);
+hipError_t launch_csr_values(const OpView& v, const int64_t* rowptr, double* vals, hipStream_t st);
+hipError_t launch_csr_blocks(const int64_t* rowptr, int64_t* blk, int64_t n_rows, int64_t n_blocks, int64_t window,
+                             hipStream_t st);
+hipError_t launch_csr_spmv(const mfq_csr* a, const double* x, double* y, hipStream_t st);
+int64_t csr_row_start_host(int64_t I, int64_t J, int64_t K, int p, int n);
 
 // vector kernels (kernels_vector.hip)
 hipError_t launch_fill(int precision, void* x, int64_t n, double value, hipStream_t st);

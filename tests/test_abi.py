@@ -123,3 +123,38 @@ def test_operator_layout(p, n, brick, launches, groups):
     lib.mfq_op_destroy(op)
     lib.mfq_space_destroy(s)
     lib.mfq_mesh_destroy(m)
+
+
+@pytest.mark.parametrize("p,n", [(1, 1), (1, 4), (2, 3), (3, 2), (4, 3), (8, 1)])
+def test_csr_size_matches_assembled_pattern(p, n):
+    """Rows, stored entries and buffer size of the assembled matrix, host only: the entry count is
+    that of the oracle's assembled matrix, (n(p+1)^2 - n + 1)^3."""
+    from oracle import assemble
+    lib = _lib()
+    m = lib.mfq_mesh_create(n, 0.0)
+    s = lib.mfq_space_create(m, p, 1)
+    op = lib.mfq_op_create(s, 0.0, lib.MFQ_FP64)
+    a = lib.mfq_csr_create(op)
+    rows, nnz, nbytes = lib.mfq_csr_size(a)
+    Ao = assemble.assemble_csr(p, n, 0.0, 0.0)
+    assert rows == Ao.shape[0] == (p * n + 1) ** 3
+    assert nnz == Ao.nnz == (n * (p + 1) ** 2 - n + 1) ** 3
+    rnd = lambda b: -(-b // 256) * 256
+    len1 = 2 * p + 1 if n >= 2 else p + 1
+    window = min(2048, (8192 - len1 ** 3) // 256 * 256)
+    nblk = -(-nnz // window)
+    assert nbytes == rnd((rows + 1) * 8) + rnd(nnz * 4) + rnd(nnz * 8) + rnd((nblk + 1) * 8)
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_csr_arrays(a)                      # not bound
+    assert e.value.status == lib.MFQ_EINVAL
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_csr_bind(a, 256, nbytes, None)     # operator not bound: refused before any launch
+    assert e.value.status == lib.MFQ_EINVAL
+    lib.mfq_csr_destroy(a)
+    op32 = lib.mfq_op_create(s, 0.0, lib.MFQ_FP32)
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_csr_create(op32)
+    assert e.value.status == lib.MFQ_EINVAL
+    for h, f in ((op32, lib.mfq_op_destroy), (op, lib.mfq_op_destroy), (s, lib.mfq_space_destroy),
+                 (m, lib.mfq_mesh_destroy)):
+        f(h)

@@ -1,0 +1,179 @@
+"""GPU parity of the assembled sparse matrix (mfq_csr_*) against the oracle's assembled matrix.
+
+The pattern (row pointers, column indices) is integer data and must be bit-exact; the values are
+FP64 sums of at most eight element-matrix entries in another order than the oracle's, held to
+1e-12 of the largest entry; the product to the FP64 operator bar ||y - y_o||_inf <= 1e-12 ||y_o||_inf.
+"""
+import numpy as np
+import pytest
+import scipy.sparse as sp
+
+from oracle import assemble, ebe, mesh
+from synthetic import uniform_vector
+
+pytestmark = pytest.mark.gpu
+
+# (p, n): several cell colours, odd and even n
+SIZES = {1: 5, 2: 4, 3: 3, 4: 3, 5: 2, 6: 2, 7: 3, 8: 2}
+
+
+def _mfq():
+    import paper_1910_13247_amd as mfq
+    return mfq
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _build(p, n, amp, alpha, bc):
+    mfq = _mfq()
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, amp), p, bc), alpha, mfq.MFQ_FP64)
+    A = mfq.SparseMatrix(op)
+    _torch().cuda.synchronize()
+    rowptr, cols, vals = (t.cpu().numpy() for t in A.arrays())
+    return op, A, rowptr, cols, vals
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_pattern_and_values_equal_assembled_matrix(p):
+    n = SIZES[p]
+    print(f"csr unconstrained p={p} n={n}", flush=True)
+    op, A, rowptr, cols, vals = _build(p, n, 0.1, 0.5, 0)
+    Ao = assemble.assemble_csr(p, n, 0.1, 0.5)
+    Ao.sort_indices()
+    np.testing.assert_array_equal(rowptr, Ao.indptr)
+    np.testing.assert_array_equal(cols, Ao.indices)
+    assert A.nnz == Ao.nnz == (n * (p + 1) ** 2 - n + 1) ** 3
+    assert np.abs(vals - Ao.data).max() <= 1e-12 * np.abs(Ao.data).max()
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+@pytest.mark.parametrize("amp,alpha", [(0.0, 0.0), (0.1, 0.5)])
+def test_dirichlet_values_equal_constrained_matrix(p, amp, alpha):
+    n = SIZES[p]
+    print(f"csr dirichlet p={p} n={n} amp={amp}", flush=True)
+    op, A, rowptr, cols, vals = _build(p, n, amp, alpha, 1)
+    N = op.n_dofs
+    G = sp.csr_matrix((vals, cols, rowptr), shape=(N, N))
+    Ao = assemble.operator_csr(p, n, amp, alpha, 1)
+    assert abs(G - Ao).max() <= 1e-12 * abs(Ao).max()
+    # the stored zeros are exactly the couplings of a Dirichlet node with another node
+    m = mesh.boundary_mask(p, n)
+    rows = np.repeat(np.arange(N), np.diff(rowptr))
+    coupled = (m[rows] == 0) | (m[cols] == 0)
+    off = rows != cols
+    assert np.all(vals[coupled & off] == 0.0)
+    assert np.all(vals[coupled & ~off] == 1.0)
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+@pytest.mark.parametrize("amp,alpha,bc", [(0.0, 0.0, 1), (0.1, 0.5, 1), (0.1, 0.5, 0)])
+def test_spmv_matches_oracle(p, amp, alpha, bc):
+    n = SIZES[p]
+    print(f"csr spmv p={p} n={n} amp={amp} bc={bc}", flush=True)
+    torch = _torch()
+    op, A, *_ = _build(p, n, amp, alpha, bc)
+    x_np = uniform_vector(op.n_dofs, seed=20 + p)
+    x = torch.from_numpy(x_np).cuda()
+    y = A.spmv(x)
+    ymf = op.vmult(x)
+    torch.cuda.synchronize()
+    yo = assemble.operator_csr(p, n, amp, alpha, bc) @ x_np
+    yc = y.cpu().numpy()
+    assert np.abs(yc - yo).max() <= 1e-12 * np.abs(yo).max()
+    # the matrix-free action of the same operator agrees to the same bar
+    assert np.abs(yc - ymf.cpu().numpy()).max() <= 2e-12 * np.abs(yo).max()
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 8])
+def test_single_cell(p):
+    """n = 1: with Dirichlet rows the boundary rows and columns are those of the identity (for
+    p = 1 every node is on the boundary: the identity matrix); without, the matrix is the one
+    element matrix, dense."""
+    torch = _torch()
+    op, A, rowptr, cols, vals = _build(p, 1, 0.0, 0.3, 1)
+    N = (p + 1) ** 3
+    G = sp.csr_matrix((vals, cols, rowptr), shape=(N, N)).toarray()
+    b = mesh.boundary_mask(p, 1) == 0
+    np.testing.assert_array_equal(G[b], np.eye(N)[b])
+    np.testing.assert_array_equal(G[:, b], np.eye(N)[:, b])
+    Ao = assemble.operator_csr(p, 1, 0.0, 0.3, 1).toarray()
+    assert np.abs(G - Ao).max() <= 1e-12 * np.abs(Ao).max()
+    if p == 1:
+        np.testing.assert_array_equal(G, np.eye(N))
+    op, A, rowptr, cols, vals = _build(p, 1, 0.0, 0.3, 0)
+    assert A.nnz == N * N
+    Ao = assemble.assemble_csr(p, 1, 0.0, 0.3).toarray()
+    G = sp.csr_matrix((vals, cols, rowptr), shape=(N, N)).toarray()
+    assert np.abs(G - Ao).max() <= 1e-12 * np.abs(Ao).max()
+    x = torch.from_numpy(uniform_vector(N, seed=3)).cuda()
+    y = A.spmv(x)
+    torch.cuda.synchronize()
+    yo = Ao @ x.cpu().numpy()
+    assert np.abs(y.cpu().numpy() - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+def test_spmv_deterministic_and_argument_errors():
+    mfq = _mfq()
+    torch = _torch()
+    op, A, *_ = _build(3, 4, 0.1, 0.5, 1)
+    x = torch.from_numpy(uniform_vector(op.n_dofs, seed=5)).cuda()
+    y1 = A.spmv(x)
+    y2 = A.spmv(x)
+    torch.cuda.synchronize()
+    assert torch.equal(y1, y2)
+    buf = torch.empty(2 * op.n_dofs, dtype=torch.float64, device="cuda")
+    with pytest.raises(mfq.MfqError) as e:
+        mfq._lib.mfq_csr_spmv(A.handle, buf.data_ptr(), buf.data_ptr() + 8 * 16, None)
+    assert e.value.status == mfq.MFQ_EINVAL
+    op32 = mfq.Operator(mfq.Space(mfq.Mesh(2, 0.0), 2, 1), 0.0, mfq.MFQ_FP32)
+    with pytest.raises(mfq.MfqError):
+        mfq._lib.mfq_csr_create(op32.handle)
+    h = mfq._lib.mfq_csr_create(op.handle)
+    with pytest.raises(mfq.MfqError) as e:
+        mfq._lib.mfq_csr_spmv(h, x.data_ptr(), y1.data_ptr(), None)   # unbound
+    assert e.value.status == mfq.MFQ_EINVAL
+    mfq._lib.mfq_csr_destroy(h)
+
+
+def test_full_size_q4_64_sampled():
+    """The 64^3-cell Q4 curved variable-coefficient operator (16,974,593 rows, 3,630,961,153
+    stored entries) assembled in full: sampled rows of the pattern against the cells that hold
+    each row's node, sampled rows of the product against the oracle, and the whole product
+    against the matrix-free action."""
+    torch = _torch()
+    p, n = 4, 64
+    print("csr full-size Q4 64^3", flush=True)
+    mfq = _mfq()
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.1), p, 1), 0.5, mfq.MFQ_FP64)
+    A = mfq.SparseMatrix(op)
+    assert A.nnz == (n * 25 - n + 1) ** 3
+    x_np = uniform_vector(op.n_dofs, seed=0)
+    x = torch.from_numpy(x_np).cuda()
+    y = A.spmv(x)
+    ymf = op.vmult(x)
+    torch.cuda.synchronize()
+    N1 = p * n + 1
+    rng = np.random.default_rng(2)
+    rows = np.concatenate([rng.integers(0, op.n_dofs, 400),
+                           [0, N1 ** 3 - 1, 1 + N1 + N1 * N1, N1 ** 3 // 2, 4 + 4 * N1 + 4 * N1 * N1]])
+    rowptr, cols, _ = A.arrays()
+    rp = rowptr.cpu().numpy()
+    assert rp[-1] == A.nnz and np.all(np.diff(rp) > 0)
+    for g in rows[:60]:
+        I, J, K = g % N1, (g // N1) % N1, g // (N1 * N1)
+        cells = [ci + n * (cj + n * ck)
+                 for ck in ebe._cells_of_index_1d(p, n, K)
+                 for cj in ebe._cells_of_index_1d(p, n, J)
+                 for ci in ebe._cells_of_index_1d(p, n, I)]
+        expect = np.unique(mesh.cell_dofs(p, n, np.array(cells)).reshape(-1))
+        got = cols[int(rp[g]):int(rp[g + 1])].cpu().numpy()
+        np.testing.assert_array_equal(got, expect)
+    yo = ebe.ebe_rows(p, n, 0.1, 0.5, x_np, 1, rows)
+    yg = y[torch.from_numpy(rows).cuda()].cpu().numpy()
+    assert np.abs(yg - yo).max() <= 1e-12 * np.abs(yo).max()
+    assert (y - ymf).abs().max().item() <= 2e-12 * ymf.abs().max().item()
+    del A, y, ymf
+    torch.cuda.empty_cache()
