@@ -256,18 +256,17 @@ __device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, co
 #define MFQ_G_STAGE 0
 #endif
 
-// One launch per colour, one workgroup per brick; ACC adds A src into dst instead of overwriting
-// it.  Lanes beyond the brick's pencils work on a spare LDS slot so no branch is needed around
-// LDS stores or loads (their results are never read).
+// One launch per colour, one workgroup per brick of exactly NT threads (one per pencil; the
+// hardware masks the lanes of a partial last wave, so no lane is idle and no LDS is set aside for
+// idle lanes); ACC adds A src into dst instead of overwriting it.
 template <int P, typename Real, bool ACC>
-__global__ __launch_bounds__(Cell<P>::BLOCK) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
-                                                       const Real* __restrict__ src, Real* __restrict__ dst, Bricks bk,
-                                                       int colour, ShapeEO<P, Real> sh) {
+__global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo, const Real* __restrict__ src,
+                  Real* __restrict__ dst, Bricks bk, int colour, ShapeEO<P, Real> sh) {
   using C = Cell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NCELL = C::NCELL, NT = C::NT, LX = C::LX, LY = C::LY, NL = C::NL;
-  constexpr int BLOCK = C::BLOCK;
+  constexpr int BLOCK = NT;                        // threads of the workgroup
   constexpr int KPT = (NL + BLOCK - 1) / BLOCK;    // lattice nodes per thread
-  constexpr int SLOT = (NCELL + 1) * NQ;           // one array per cell plus the spare slot
+  constexpr int SLOT = NCELL * NQ;                 // one array per cell
   constexpr int L2SZ = SLOT > KPT * BLOCK ? SLOT : KPT * BLOCK;
   // cell arrays stored array-major: [L0 of every cell][L1 ...][L2 ...]; the node lattice is only
   // read before the first write of an L2 array, so it shares the L2 block
@@ -275,12 +274,10 @@ __global__ __launch_bounds__(Cell<P>::BLOCK) void vmult_kernel(const int* __rest
   Real* const lat = lds + 2 * SLOT;
 
   const int tid = threadIdx.x;
-  const bool lane_ok = tid < NT;
-  const int lc = lane_ok ? tid / T : NCELL;  // spare slot for the idle lanes
-  const int e = lane_ok ? tid - lc * T : (tid - NT) % T;
+  const int lc = tid / T;
+  const int e = tid - lc * T;
   const int e0 = e % N1, e1 = e / N1;
-  const int cl = lc < NCELL ? lc : 0;
-  const int cx = cl % C::BX, cy = (cl / C::BX) % C::BY, cz = cl / (C::BX * C::BY);
+  const int cx = lc % C::BX, cy = (lc / C::BX) % C::BY, cz = lc / (C::BX * C::BY);
   const int64_t ord = bk.offset[colour] + blockIdx.x;
   int bi, bj, bz;
   brick_of(bk, colour, blockIdx.x, bi, bj, bz);
@@ -293,7 +290,7 @@ __global__ __launch_bounds__(Cell<P>::BLOCK) void vmult_kernel(const int* __rest
   // start, 1: after the x contraction, 2: after the y contraction): earlier hides more latency,
   // later holds the 6(p+1) values in registers for a shorter time.
   Real2<Real> g[N1][3];
-  const bool cell_in = lane_ok && bi * C::BX + cx < bk.n && bj * C::BY + cy < bk.n && bz * C::BZ + cz < bk.n;
+  const bool cell_in = bi * C::BX + cx < bk.n && bj * C::BY + cy < bk.n && bz * C::BZ + cz < bk.n;
   // Branch-free: lanes without a cell in the mesh read lane 0's entries (inside the brick, a line
   // the wave fetches anyway) and zero them.  A branch around the loads would make the compiler wait
   // for all outstanding loads at the join, G included, before the dependent source gather.
@@ -949,10 +946,10 @@ hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipSt
     const int64_t nb = v.bricks.count[c];
     if (nb == 0) continue;
     if (acc)
-      vmult_kernel<P, Real, true><<<(unsigned)nb, Cell<P>::BLOCK, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
+      vmult_kernel<P, Real, true><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
                                                                    (Real*)dst, v.bricks, c, sh);
     else
-      vmult_kernel<P, Real, false><<<(unsigned)nb, Cell<P>::BLOCK, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
+      vmult_kernel<P, Real, false><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
                                                                     (Real*)dst, v.bricks, c, sh);
   }
   return hipGetLastError();
