@@ -254,7 +254,7 @@ def solve_benchmarks(steps):
     return out
 
 
-def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=4, mode="async"):
+def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=4, mode="async", setup_threads=1):
     """The serving stream: Poisson arrivals at `rate`/s, degree U{1..6}, n U{4..48}, alpha
     U[0,0.9], right-hand side from the request's seed; each solved to relative residual 1e-10."""
     import torch
@@ -265,15 +265,18 @@ def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=
     arrivals = [d["arrival"] for d in stream]
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(0.75 * free, 160e9))
-    srv = Server(DeviceExecutor(n_streams=n_streams), budget, iters_per_step=iters_per_step, mode=mode)
+    srv = Server(DeviceExecutor(n_streams=n_streams), budget, iters_per_step=iters_per_step, mode=mode,
+                 setup_threads=setup_threads)
     t0 = time.perf_counter()
     st = run_stream(srv, reqs, arrivals)
+    srv.close()
     torch.cuda.synchronize()
     st["wall_s"] = time.perf_counter() - t0
     st["budget_bytes"] = budget
     st["iters_per_step"] = iters_per_step
     st["streams"] = n_streams
     st["mode"] = mode
+    st["setup_threads"] = setup_threads
     st["rate_per_s"] = rate
     st["dofs_total"] = sum((r.degree * r.n + 1) ** 3 for r in reqs)
     st["iterations_mean"] = sum(r.iterations for r in srv.done) / max(len(srv.done), 1)
@@ -292,7 +295,9 @@ def main():
                     help="also replay N requests of the serving stream (200 requests/s) and report solves/s, p50/p99")
     ap.add_argument("--serve-mode", choices=["sync", "async"], default="async",
                     help="serving steps: all solves together (sync) or each at its own pace (async)")
-    ap.add_argument("--serve-streams", type=int, default=4)
+    ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-setup-threads", type=int, default=1,
+                    help="worker threads that set up admitted requests (0: on the scheduler thread)")
     ap.add_argument("--no-csr", action="store_true", help="skip the assembled-matrix (CSR) comparison")
     ap.add_argument("--csr-sweep", action="store_true",
                     help="add the assembled-matrix comparison for degrees 1..8 at about 16M DoFs")
@@ -383,7 +388,8 @@ def main():
         rec["solves_q3_128"] = solve_benchmarks(args.steps)
     if args.serve:
         print(f"# serving {args.serve} requests", file=sys.stderr, flush=True)
-        rec["serving"] = serve_benchmark(args.serve, mode=args.serve_mode, n_streams=args.serve_streams)
+        rec["serving"] = serve_benchmark(args.serve, mode=args.serve_mode, n_streams=args.serve_streams,
+                                         setup_threads=args.serve_setup_threads)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, n, pr.amplitude, pr.alpha, x_np)

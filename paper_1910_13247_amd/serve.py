@@ -14,8 +14,10 @@ at most ``rtol``; its coarsest level uses the Chebyshev mode, so no solve ever w
 between steps.  This batching of independent requests is a serving pattern, not part of the
 paper's method.
 """
+import concurrent.futures as cf
 import dataclasses
 import math
+import threading
 import time
 from typing import List, Optional
 
@@ -83,12 +85,13 @@ class DeviceExecutor:
         h["bytes"] = h["op_bytes"] + h["solver_bytes"] + 2 * vec
         return h
 
-    def start(self, req, h):
-        """Allocate, set up (geometry, hierarchy, eigenvalue estimates) and begin the solve."""
+    def setup(self, req, h):
+        """Allocate and set up (geometry, hierarchy, eigenvalue estimates) on the set-up stream.  May
+        run on a set-up thread while the scheduler steps other requests (the library's calls release
+        the interpreter lock; each request has its own handles).  It enqueues nothing on the solve
+        streams: the scheduler captures CG iterations into HIP graphs on those, and a capture
+        records every launch into the stream, whichever thread issues it."""
         torch = self.torch
-        st = self.streams[self._next_stream % len(self.streams)]
-        self._next_stream += 1
-        h["stream"] = st
         su = self.setup_stream
         with torch.cuda.stream(su):
             h["op_buf"] = torch.empty(max(h["op_bytes"], 256), dtype=torch.uint8, device="cuda")
@@ -100,8 +103,18 @@ class DeviceExecutor:
         _lib.mfq_space_random(h["space"], MFQ_FP64, h["b"].data_ptr(), req.seed, sp)
         # synchronises the set-up stream: everything above is complete before the solve starts
         _lib.mfq_solver_bind(h["solver"], h["solver_buf"].data_ptr(), h["solver_bytes"], sp)
+
+    def begin(self, req, h):
+        """Begin the solve on the next solve stream (scheduler thread only)."""
+        st = self.streams[self._next_stream % len(self.streams)]
+        self._next_stream += 1
+        h["stream"] = st
         _lib.mfq_solve_begin(h["solver"], h["b"].data_ptr(), h["x"].data_ptr(), req.rtol, req.max_iter,
                              st.cuda_stream)
+
+    def start(self, req, h):
+        self.setup(req, h)
+        self.begin(req, h)
 
     def step(self, handles, iters):
         return _lib.mfq_batch_step([h["solver"] for h in handles], iters)
@@ -138,13 +151,24 @@ class Server:
     mode "sync": every step advances all running solves together and waits for all of them
     (mfq_batch_step).  mode "async": each solve's next few iterations are enqueued as soon as its
     previous ones have been polled complete (mfq_solve_step_async / _poll), so a long request does
-    not hold back the others; a step is one pass over the running solves and never waits."""
+    not hold back the others; a step is one pass over the running solves and never waits.
+
+    setup_threads > 0: an admitted request is set up (executor.setup) on a worker thread while
+    the scheduler keeps stepping the running solves; at the first step after its set-up has
+    finished the scheduler begins its solve (executor.begin) and it joins the others.  Its memory
+    counts against the budget from admission on.  Only the scheduler thread issues work to the
+    solve streams."""
 
     def __init__(self, executor, budget_bytes, iters_per_step=2, max_active=256, clock=time.perf_counter,
-                 mode="sync", idle_sleep=2e-5):
+                 mode="sync", idle_sleep=2e-5, setup_threads=0):
         if mode not in ("sync", "async"):
             raise ValueError("mode must be 'sync' or 'async'")
+        if setup_threads < 0:
+            raise ValueError("setup_threads must be >= 0")
         self.mode = mode
+        self._pool = cf.ThreadPoolExecutor(setup_threads) if setup_threads else None
+        self._setup_lock = threading.Lock()
+        self.starting = []                  # (request, handles, future): set-up running on a worker
         self.idle_sleep = idle_sleep
         self.ex = executor
         self.budget = int(budget_bytes)
@@ -172,7 +196,7 @@ class Server:
         return req.id
 
     def _admit(self):
-        while self.queue and len(self.active) < self.max_active:
+        while self.queue and len(self.active) + len(self.starting) < self.max_active:
             req = self.queue[0]
             if self._head is None:
                 self._head = self.ex.prepare(req)
@@ -193,18 +217,44 @@ class Server:
             req.footprint = h["bytes"]
             self.used += h["bytes"]
             req.admitted = self.clock()
-            t = time.perf_counter()
-            self.ex.start(req, h)
-            self.setup_s += time.perf_counter() - t
-            self.active.append((req, h))
+            if self._pool is not None:
+                self.starting.append((req, h, self._pool.submit(self._setup, req, h)))
+            else:
+                self._setup(req, h)
+                self.ex.begin(req, h)
+                self.active.append((req, h))
         self.peak_used = max(self.peak_used, self.used)
-        self.peak_active = max(self.peak_active, len(self.active))
+        self.peak_active = max(self.peak_active, len(self.active) + len(self.starting))
+
+    def _setup(self, req, h):
+        t = time.perf_counter()
+        self.ex.setup(req, h)
+        with self._setup_lock:
+            self.setup_s += time.perf_counter() - t
+
+    def _collect_started(self):
+        """Move requests whose set-up has finished into the running set (set-up errors re-raise)."""
+        if not self.starting:
+            return
+        still = []
+        for req, h, fut in self.starting:
+            if fut.done():
+                fut.result()
+                self.ex.begin(req, h)
+                self.active.append((req, h))
+            else:
+                still.append((req, h, fut))
+        self.starting = still
 
     def step(self):
         """Admit what fits, advance the running solves, retire the finished ones.
         Returns the requests finished in this step."""
         self._admit()
+        self._collect_started()
         if not self.active:
+            if self.starting:
+                # nothing to step yet: wait for the first set-up to finish
+                cf.wait([f for _, _, f in self.starting], return_when=cf.FIRST_COMPLETED)
             return []
         if self.mode == "async":
             return self._step_async()
@@ -262,7 +312,13 @@ class Server:
 
     @property
     def idle(self):
-        return not self.queue and not self.active
+        return not self.queue and not self.active and not self.starting
+
+    def close(self):
+        """Stop the set-up workers (after draining)."""
+        if self._pool is not None:
+            self._pool.shutdown(wait=True)
+            self._pool = None
 
     def drain(self):
         while not self.idle:

@@ -34,6 +34,7 @@ def _serve(reqs, budget=8 << 30, **kw):
     for r in reqs:
         srv.submit(r)
     srv.drain()
+    srv.close()
     _torch().cuda.synchronize()
     return srv
 
@@ -116,13 +117,14 @@ def test_cg_true_residual_certified():
     assert solve.rel_residual(lambda v: At @ v, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10
 
 
-@pytest.mark.parametrize("mode", ["sync", "async"])
-def test_served_results_match_oracle(mode):
+@pytest.mark.parametrize("mode,threads", [("sync", 0), ("async", 0), ("async", 1), ("sync", 2)])
+def test_served_results_match_oracle(mode, threads):
     """Each served request solves its own system: the solution agrees with a sparse direct solve
-    of the oracle's assembled operator for the same counter-based right-hand side."""
-    print(f"serve vs oracle ({mode})", flush=True)
+    of the oracle's assembled operator for the same counter-based right-hand side (set-up on the
+    scheduler thread or on worker threads)."""
+    print(f"serve vs oracle ({mode}, {threads} set-up threads)", flush=True)
     reqs = _requests()
-    srv = _serve(reqs, mode=mode)
+    srv = _serve(reqs, mode=mode, setup_threads=threads)
     assert len(srv.done) == len(reqs)
     for r in reqs:
         assert r.status == 0 and r.rel_residual <= 1e-10, (r.degree, r.n, r.rel_residual)
@@ -136,13 +138,13 @@ def test_served_results_match_oracle(mode):
         assert np.abs(x - xd).max() <= 1e-6 * np.abs(xd).max(), (r.degree, r.n)
 
 
-@pytest.mark.parametrize("mode", ["sync", "async"])
-def test_alone_and_in_mix_agree(mode):
+@pytest.mark.parametrize("mode,threads", [("sync", 0), ("async", 0), ("async", 1)])
+def test_alone_and_in_mix_agree(mode, threads):
     """The same request alone and among others: equal iteration counts and solutions equal
     within what the 1e-10 residual tolerance allows (both are certified)."""
-    print(f"alone vs mix ({mode})", flush=True)
+    print(f"alone vs mix ({mode}, {threads} set-up threads)", flush=True)
     mixed = _requests()
-    _serve(mixed, mode=mode)
+    _serve(mixed, mode=mode, setup_threads=threads)
     for i, p in enumerate(MIX):
         alone = _requests()[i]
         _serve([alone], mode=mode)

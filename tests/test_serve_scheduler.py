@@ -1,5 +1,7 @@
 """Scheduler logic of the serving loop on the host: a fake executor stands in for the device
 (tests only), so admission, continuous batching and latency accounting run without a GPU."""
+import threading
+
 import pytest
 
 from paper_1910_13247_amd import _lib
@@ -26,16 +28,28 @@ class FakeExecutor:
         self.live = {}
         self.max_live_bytes = 0
         self.prepared = 0
+        self.gates = {}            # request id -> threading.Event its set-up waits for
+        self.lock = threading.Lock()
+        self.scheduler_thread = threading.get_ident()
 
     def prepare(self, req):
         self.prepared += 1
         return {"bytes": 100 * req.degree, "req": req}
 
-    def start(self, req, h):
-        self.started.append(req.id)
+    def setup(self, req, h):
+        gate = self.gates.get(req.id)
+        if gate is not None:
+            assert gate.wait(10.0), "set-up gate never opened"
+        with self.lock:
+            self.started.append(req.id)
+            self.live[req.id] = h["bytes"]
+            self.max_live_bytes = max(self.max_live_bytes, sum(self.live.values()))
+        h["setup_thread"] = threading.get_ident()
+
+    def begin(self, req, h):
+        # the solve itself starts on the scheduler thread
+        assert threading.get_ident() == self.scheduler_thread
         h["left"] = req.n
-        self.live[req.id] = h["bytes"]
-        self.max_live_bytes = max(self.max_live_bytes, sum(self.live.values()))
 
     def step(self, handles, iters):
         self.clock.t += 1e-3
@@ -65,7 +79,8 @@ class FakeExecutor:
 
     def release(self, h):
         if "req" in h:
-            self.live.pop(h["req"].id, None)
+            with self.lock:
+                self.live.pop(h["req"].id, None)
 
 
 def make(budget, **kw):
@@ -177,3 +192,48 @@ def test_async_mode_short_request_overtakes_long_one():
 def test_mode_is_validated():
     with pytest.raises(ValueError):
         make(budget=1, mode="parallel")
+
+
+@pytest.mark.parametrize("mode", ["sync", "async"])
+def test_setup_thread_overlaps_stepping(mode):
+    """With a set-up worker, a running request keeps stepping (and finishes) while a later
+    request's set-up is still blocked; the later one joins once its set-up is done."""
+    srv, ex, clock = make(budget=10**6, mode=mode, idle_sleep=0, setup_threads=1)
+    a = Request(degree=1, n=4, alpha=0.0, seed=0)
+    b = Request(degree=1, n=2, alpha=0.0, seed=1)
+    gate = threading.Event()
+    ex.gates[1] = gate
+    srv.submit(a)
+    finished = []
+    for _ in range(3):
+        finished += srv.step()
+    srv.submit(b)
+    for _ in range(200):
+        finished += srv.step()
+        if a in finished:
+            break
+    assert a in finished and a.status == _lib.MFQ_OK
+    assert b.status is None and len(srv.starting) == 1 and not srv.idle
+    assert srv.used == 100          # b's memory is held from admission on
+    gate.set()
+    while not srv.idle:
+        finished += srv.step()
+    srv.close()
+    assert finished == [a, b] and b.status == _lib.MFQ_OK and srv.used == 0
+    assert srv.peak_active == 2
+    # set-up ran on the worker, the solves began on the scheduler thread (asserted in begin)
+    assert all(r.id in ex.started for r in (a, b))
+
+
+def test_setup_errors_reach_the_scheduler():
+    srv, ex, clock = make(budget=10**6, setup_threads=1)
+
+    def broken(req, h):
+        raise RuntimeError("set-up failed")
+
+    ex.setup = broken
+    srv.submit(Request(degree=1, n=1, alpha=0.0, seed=0))
+    with pytest.raises(RuntimeError, match="set-up failed"):
+        for _ in range(10):
+            srv.step()
+    srv.close()
