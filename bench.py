@@ -10,7 +10,7 @@ matrix and applied by the library's CSR product, and the CPU oracle on a bounded
 same workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--solves] [--serve N] [--no-csr]
-                    [--csr-sweep] [--copy-probe]
+                    [--csr-sweep] [--vcycle] [--copy-probe]
 """
 import argparse
 import json
@@ -98,10 +98,12 @@ def time_vmult(op, x, steps, warmup):
     return wall, kern, y
 
 
-def cpu_baseline(p, n, amp, alpha, x_np, budget_s=12.0):
-    """Oracle element-by-element application on a bounded sample of cells, scaled to DoFs/s."""
+def cpu_baseline(p, n, amp, alpha, x_np, budget_s=12.0, check_rows=None, y64_rows=None, y32_rows=None):
+    """Oracle element-by-element application on a bounded sample of cells, scaled to DoFs/s; and
+    the FP64 and FP32 benchmark results on `check_rows` against the oracle's rows (the FP32 path
+    against the oracle applied to the input rounded to FP32, the input that path sees)."""
     import numpy as np
-    from oracle.ebe import ebe_vmult
+    from oracle.ebe import ebe_rows, ebe_vmult
     try:
         from threadpoolctl import threadpool_limits
     except ImportError:  # pragma: no cover
@@ -123,9 +125,19 @@ def cpu_baseline(p, n, amp, alpha, x_np, budget_s=12.0):
         if ctx is not None:
             ctx.__exit__(None, None, None)
     dofs_per_s = (done / C) * N / elapsed
-    return {"value": dofs_per_s, "unit": "DoFs/s", "cores": cores, "kind": "oracle",
-            "sample": f"{done} of {C} cells (element-by-element, dense cell matrices), {elapsed:.1f} s, "
-                      f"scaled by cells/total to a full application"}
+    out = {"value": dofs_per_s, "unit": "DoFs/s", "cores": cores, "kind": "oracle",
+           "sample": f"{done} of {C} cells (element-by-element, dense cell matrices), {elapsed:.1f} s, "
+                     f"scaled by cells/total to a full application"}
+    if check_rows is not None:
+        yo = ebe_rows(p, n, amp, alpha, x_np, 1, check_rows)
+        x32 = x_np.astype(np.float32).astype(np.float64)
+        yo32 = ebe_rows(p, n, amp, alpha, x32, 1, check_rows)
+        out["oracle_check"] = {
+            "rows": int(len(check_rows)),
+            "fp64_normwise_rel_err": float(np.abs(y64_rows - yo).max() / np.abs(yo).max()),
+            "fp32_normwise_rel_err": float(np.abs(y32_rows - yo32).max() / np.abs(yo32).max()),
+            "bars": "FP64 1e-12 normwise; FP32 componentwise 2k u32 (sum of |terms|), k = 8(p+1)+16"}
+    return out
 
 
 def high_degree_comparison(steps, warmup):
@@ -254,6 +266,35 @@ def solve_benchmarks(steps):
     return out
 
 
+# Q4 V-cycles beside the paper's only measurements (an FP32 V-cycle of DG Q4, Chebyshev degree 6,
+# matrix-free, on one 48-core node: 31.7 ms for 65,536 cells, 264 ms for 524,288 cells)
+VCYCLE_MESHES = [40, 80]
+
+
+def vcycle_benchmark(steps, warmup):
+    """One FP32 V-cycle (the GMG_MIXED preconditioner: Chebyshev degree 6 on every level, coarse
+    Chebyshev) of the constant-coefficient Q4 Laplacian on the undeformed cube, timed with HIP
+    events; the geometry is still read per quadrature point (no affine shortcut)."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    from synthetic import uniform_vector
+    out = []
+    for n in VCYCLE_MESHES:
+        print(f"# V-cycle Q4 {n}^3", file=sys.stderr, flush=True)
+        space = mfq.Space(mfq.Mesh(n, 0.0), 4, mfq.MFQ_BC_DIRICHLET0)
+        op = mfq.Operator(space, 0.0, mfq.MFQ_FP64)
+        sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, smoother_degree=6, coarse_mode=1)
+        r = torch.from_numpy(uniform_vector(space.n_dofs, seed=3)).cuda()
+        z = torch.empty_like(r)
+        sec = time_events(lambda: sv.precondition(r, z), steps, warmup)
+        out.append({"degree": 4, "cells": space.n_cells, "dofs": space.n_dofs,
+                    "ms": sec * 1e3, "DoFs_per_s": space.n_dofs / sec, "cells_per_s": space.n_cells / sec})
+        del sv, op, r, z
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=4, mode="async", setup_threads=1):
     """The serving stream: Poisson arrivals at `rate`/s, degree U{1..6}, n U{4..48}, alpha
     U[0,0.9], right-hand side from the request's seed; each solved to relative residual 1e-10."""
@@ -299,6 +340,8 @@ def main():
     ap.add_argument("--serve-setup-threads", type=int, default=1,
                     help="worker threads that set up admitted requests (0: on the scheduler thread)")
     ap.add_argument("--no-csr", action="store_true", help="skip the assembled-matrix (CSR) comparison")
+    ap.add_argument("--vcycle", action="store_true",
+                    help="add FP32 V-cycle times of the Q4 Laplacian (40^3 and 80^3 cells)")
     ap.add_argument("--csr-sweep", action="store_true",
                     help="add the assembled-matrix comparison for degrees 1..8 at about 16M DoFs")
     ap.add_argument("--copy-probe", action="store_true",
@@ -330,6 +373,13 @@ def main():
     x32 = x64.float()
     wall32, kern32, y32 = time_vmult(op32, x32, args.steps, args.warmup)
     rel32 = ((y32.double() - y64).abs().max() / y64.abs().max()).item()
+    N1 = p * n + 1
+    rng = np.random.default_rng(1)
+    check_rows = np.unique(np.concatenate([rng.integers(0, space.n_dofs, 200),
+                                           [0, N1 ** 3 - 1, 1 + N1 + N1 * N1, N1 ** 3 // 2]]))
+    rows_t = torch.from_numpy(check_rows).cuda()
+    y64_rows = y64[rows_t].cpu().numpy()
+    y32_rows = y32[rows_t].double().cpu().numpy()
     print(f"# fp32: {wall32 * 1e3:.3f} ms/step, cell kernel {kern32 * 1e3:.3f} ms", file=sys.stderr, flush=True)
     del op32, x32, y32
     torch.cuda.synchronize()
@@ -386,13 +436,16 @@ def main():
     rec["high_degree_q8_24"] = high_degree_comparison(min(args.steps, 20), args.warmup)
     if args.solves:
         rec["solves_q3_128"] = solve_benchmarks(args.steps)
+    if args.vcycle:
+        rec["vcycle_q4"] = vcycle_benchmark(min(args.steps, 20), args.warmup)
     if args.serve:
         print(f"# serving {args.serve} requests", file=sys.stderr, flush=True)
         rec["serving"] = serve_benchmark(args.serve, mode=args.serve_mode, n_streams=args.serve_streams,
                                          setup_threads=args.serve_setup_threads)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
-        rec["cpu_baseline"] = cpu_baseline(p, n, pr.amplitude, pr.alpha, x_np)
+        rec["cpu_baseline"] = cpu_baseline(p, n, pr.amplitude, pr.alpha, x_np, check_rows=check_rows,
+                                           y64_rows=y64_rows, y32_rows=y32_rows)
     print(json.dumps(rec), flush=True)
 
 
