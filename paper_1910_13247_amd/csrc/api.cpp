@@ -36,9 +36,7 @@ int op_vmult(const mfq_op* op, const void* src, void* dst, hipStream_t st) {
 }
 
 int op_diagonal(const mfq_op* op, void* diag, hipStream_t st) {
-  const OpView v = view(op);
-  MFQ_HIP(launch_fill(op->precision, diag, v.n_dofs, 0.0, st));
-  MFQ_HIP(launch_diagonal_cells(v, op->precision, diag, st));
+  MFQ_HIP(launch_diagonal_cells(view(op), op->precision, diag, st));
   return MFQ_OK;
 }
 

@@ -216,10 +216,26 @@ __device__ __forceinline__ void lattice_values(const Real* __restrict__ src, con
   }
 }
 
+// Result values this launch adds to (nodes whose `first` bit is clear), for kernels that only
+// write the result (no source lattice).
+template <typename Real, int BLOCK, int KPT, int NL>
+__device__ __forceinline__ void lattice_dst(const Real* __restrict__ dst, int (&gk)[KPT], unsigned first,
+                                            Real (&dv)[KPT]) {
+  const int tid = threadIdx.x;
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    const int g0 = tid + j * BLOCK < NL ? gk[j] : kAbsent;
+    gk[j] = g0;
+    const bool live = g0 >= 0;
+    const Real d = dst[live ? g0 : 0];
+    dv[j] = (live && !(first >> j & 1u)) ? d : (Real)0;
+  }
+}
+
 // Sum the cells' results per lattice node in a fixed order (cell c's result at res + c * cstride,
 // local lexicographic order) and write the brick's nodes: store or add per the `first` bit,
 // Dirichlet nodes get src (added to dst when accumulating) from the brick that stores.
-template <int P, typename Real, bool ACC, int BLOCK, int KPT>
+template <int P, typename Real, bool ACC, int BLOCK, int KPT, bool UNIT_DIRICHLET = false>
 __device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, const Real* __restrict__ src,
                                                 Real* __restrict__ dst, const int (&gk)[KPT], unsigned first,
                                                 const Real (&dv)[KPT]) {
@@ -247,7 +263,10 @@ __device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, co
       dst[g0] = (ACC || !fj) ? dv[j] + sum : sum;
     } else if (fj) {
       const int gg = ~g0;
-      dst[gg] = ACC ? dst[gg] + src[gg] : src[gg];
+      if constexpr (UNIT_DIRICHLET)
+        dst[gg] = (Real)1;
+      else
+        dst[gg] = ACC ? dst[gg] + src[gg] : src[gg];
     }
   }
 }
@@ -756,38 +775,153 @@ __global__ __launch_bounds__(MCell<P>::BLOCK) void vmult_mfma_kernel(MfmaTables<
 }
 
 // ---------------------------------------------------------------- diagonal
-// diag_i = sum_K sum_q grad phi_i(q)^T G_q grad phi_i(q); one thread per (cell, i), atomics.
+// diag_i = sum_K sum_q grad phi_i(q)^T G_q grad phi_i(q), 1 on Dirichlet rows.  With
+// i = (a,b,c), q = (r,s,t) the sum separates per component pair (d,e) of G into 1D factors:
+// grad_d phi_i(q) grad_e phi_i(q) = X(r,a) Y(s,b) Z(t,c) with X one of S^2, D S, D^2 (D where d or
+// e is x, S otherwise) and likewise Y, Z.  So each cell's diagonal is three 1D contractions per
+// pair, done with the operator's brick/lane/colour layout: a lane holds the z-pencil of G at
+// (r,s) and contracts t; through LDS the y-lanes contract s and group the pairs by their x table;
+// the x-lanes contract r.  Results are summed per lattice node and written like the operator's
+// (colour order, store then add): deterministic, no atomics, no clearing pass.
 template <int P, typename Real>
-__global__ __launch_bounds__(kBlock) void diagonal_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
-                                                          Real* __restrict__ diag, Bricks bk, Shape<P, Real> sh) {
-  using C = Cell<P>;
-  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NT = C::NT;
-  const int64_t ord = blockIdx.x;
-  for (int k = threadIdx.x; k < C::NCELL * NQ; k += kBlock) {
-    const int lc = k / NQ;
-    const int i = k - lc * NQ;
-    const int a = i % N1, b = (i / N1) % N1, c = i / T;
-    const int g = idx[ord * (int64_t)C::NL + lattice_of<P>(lc, a, b, c)];
-    if (g == kAbsent) continue;
-    if (g < 0) {
-      diag[~g] = (Real)1;
-      continue;
-    }
-    const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + lc * T;
-    Real sum = 0;
-    for (int t = 0; t < N1; ++t)
-      for (int s = 0; s < N1; ++s)
-        for (int r = 0; r < N1; ++r) {
-          const Real bx = sh.D[r * N1 + a] * sh.S[s * N1 + b] * sh.S[t * N1 + c];
-          const Real by = sh.S[r * N1 + a] * sh.D[s * N1 + b] * sh.S[t * N1 + c];
-          const Real bz = sh.S[r * N1 + a] * sh.S[s * N1 + b] * sh.D[t * N1 + c];
-          const Real2<Real> G0 = gp[(t * 3 + 0) * NT + r + N1 * s];
-          const Real2<Real> G1 = gp[(t * 3 + 1) * NT + r + N1 * s];
-          const Real2<Real> G2 = gp[(t * 3 + 2) * NT + r + N1 * s];
-          sum += bx * (G0.x * bx + 2 * (G0.y * by + G1.x * bz)) + by * (G1.y * by + 2 * G2.x * bz) + G2.y * bz * bz;
-        }
-    atomic_add(diag + g, sum);
+struct DiagTables {
+  Real SS[(P + 1) * (P + 1)];  // [q*(P+1)+a]: S^2
+  Real DS[(P + 1) * (P + 1)];  // D S
+  Real DD[(P + 1) * (P + 1)];  // D^2
+};
+
+template <int P, typename Real>
+DiagTables<P, Real> make_diag_tables() {
+  DiagTables<P, Real> t{};
+  for (int k = 0; k < (P + 1) * (P + 1); ++k) {
+    const double sv = ct::kTab<P>.S[k], dv = ct::kTab<P>.D[k];
+    t.SS[k] = (Real)(sv * sv);
+    t.DS[k] = (Real)(dv * sv);
+    t.DD[k] = (Real)(dv * dv);
   }
+  return t;
+}
+
+template <int P, typename Real>
+__global__ __launch_bounds__(Cell<P>::NT) void diagonal_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
+                                                               Real* __restrict__ diag, Bricks bk, int colour,
+                                                               DiagTables<P, Real> tb) {
+  using C = Cell<P>;
+  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NCELL = C::NCELL, NT = C::NT, NL = C::NL;
+  constexpr int BLOCK = NT;
+  constexpr int KPT = (NL + BLOCK - 1) / BLOCK;
+  constexpr int SLOT = NCELL * NQ;
+  __shared__ Real lds[3 * SLOT];
+  const int tid = threadIdx.x;
+  const int lc = tid / T;
+  const int e = tid - lc * T;
+  const int e0 = e % N1, e1 = e / N1;
+  const int cx = lc % C::BX, cy = (lc / C::BX) % C::BY, cz = lc / (C::BX * C::BY);
+  const int64_t ord = bk.offset[colour] + blockIdx.x;
+  int bi, bj, bz;
+  brick_of(bk, colour, blockIdx.x, bi, bj, bz);
+  Real* L0 = lds + lc * NQ;
+  Real* L1 = L0 + SLOT;
+  Real* L2 = L1 + SLOT;
+  const bool cell_in = bi * C::BX + cx < bk.n && bj * C::BY + cy < bk.n && bz * C::BZ + cz < bk.n;
+
+  int gk[KPT];
+  unsigned first;
+  Real dv[KPT];
+  lattice_index<P, BLOCK, KPT>(idx + ord * (int64_t)NL, bk, bi, bj, bz, gk, first);
+  // G of this lane's z-pencil; lanes without a cell in the mesh read lane 0's entries and zero them
+  Real gz[6][N1];
+  {
+    const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + (cell_in ? tid : 0);
+#pragma unroll
+    for (int t = 0; t < N1; ++t)
+#pragma unroll
+      for (int m = 0; m < 3; ++m) {
+        const Real2<Real> v = gp[(t * 3 + m) * NT];
+        gz[2 * m][t] = cell_in ? v.x : (Real)0;      // G00, G02, G12
+        gz[2 * m + 1][t] = cell_in ? v.y : (Real)0;  // G01, G11, G22
+      }
+  }
+  lattice_dst<Real, BLOCK, KPT, NL>(diag, gk, first, dv);
+  // z: H(r,s,c) = sum_t Z[t][c] G(r,s,t) per pair; pair order xx, xy, xz, yy, yz, zz with
+  // (X, Y, Z) = (DD,SS,SS), (DS,DS,SS), (DS,SS,DS), (SS,DD,SS), (SS,DS,DS), (SS,SS,DD)
+  Real hxx[N1], hxy[N1], hxz[N1], hyy[N1], hyz[N1], hzz[N1];
+  apply_t<N1>(tb.SS, gz[0], hxx);
+  apply_t<N1>(tb.SS, gz[1], hxy);
+  apply_t<N1>(tb.DS, gz[2], hxz);
+  apply_t<N1>(tb.SS, gz[3], hyy);
+  apply_t<N1>(tb.DS, gz[4], hyz);
+  apply_t<N1>(tb.DD, gz[5], hzz);
+#pragma unroll
+  for (int c = 0; c < N1; ++c) {
+    L0[e + T * c] = hxx[c];
+    L1[e + T * c] = hxy[c];
+    L2[e + T * c] = hxz[c];
+  }
+  lds_barrier();
+  // y, first round: lane (r=e0, c=e1) contracts s; K grouped by the x table
+  Real kdd[N1], kds[N1], kss[N1];
+  {
+    Real a[N1], b[N1], c2[N1], t1[N1], t2[N1];
+#pragma unroll
+    for (int s2 = 0; s2 < N1; ++s2) {
+      a[s2] = L0[e0 + N1 * s2 + T * e1];
+      b[s2] = L1[e0 + N1 * s2 + T * e1];
+      c2[s2] = L2[e0 + N1 * s2 + T * e1];
+    }
+    apply_t<N1>(tb.SS, a, kdd);
+    apply_t<N1>(tb.DS, b, t1);
+    apply_t<N1>(tb.SS, c2, t2);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) kds[k] = 2 * (t1[k] + t2[k]);
+  }
+  lds_barrier();
+#pragma unroll
+  for (int c = 0; c < N1; ++c) {
+    L0[e + T * c] = hyy[c];
+    L1[e + T * c] = hyz[c];
+    L2[e + T * c] = hzz[c];
+  }
+  lds_barrier();
+  {
+    Real a[N1], b[N1], c2[N1], t0[N1], t1[N1], t2[N1];
+#pragma unroll
+    for (int s2 = 0; s2 < N1; ++s2) {
+      a[s2] = L0[e0 + N1 * s2 + T * e1];
+      b[s2] = L1[e0 + N1 * s2 + T * e1];
+      c2[s2] = L2[e0 + N1 * s2 + T * e1];
+    }
+    apply_t<N1>(tb.DD, a, t0);
+    apply_t<N1>(tb.DS, b, t1);
+    apply_t<N1>(tb.SS, c2, t2);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) kss[k] = t0[k] + 2 * t1[k] + t2[k];
+  }
+  lds_barrier();
+#pragma unroll
+  for (int b = 0; b < N1; ++b) {
+    L0[e0 + N1 * b + T * e1] = kdd[b];
+    L1[e0 + N1 * b + T * e1] = kds[b];
+    L2[e0 + N1 * b + T * e1] = kss[b];
+  }
+  lds_barrier();
+  // x: lane (b=e0, c=e1) contracts r; the cell's diagonal in local lexicographic order in L0
+  {
+    Real a[N1], b[N1], c2[N1], t0[N1], t1[N1], t2[N1];
+#pragma unroll
+    for (int r = 0; r < N1; ++r) {
+      a[r] = L0[r + N1 * e];
+      b[r] = L1[r + N1 * e];
+      c2[r] = L2[r + N1 * e];
+    }
+    apply_t<N1>(tb.DD, a, t0);
+    apply_t<N1>(tb.DS, b, t1);
+    apply_t<N1>(tb.SS, c2, t2);
+#pragma unroll
+    for (int k = 0; k < N1; ++k) L0[k + N1 * e] = t0[k] + t1[k] + t2[k];
+  }
+  lds_barrier();
+  scatter_lattice<P, Real, false, BLOCK, KPT, true>(lds, NQ, nullptr, diag, gk, first, dv);
 }
 
 // ---------------------------------------------------------------- right-hand side
@@ -980,13 +1114,16 @@ hipError_t vmult_p(const OpView& v, int precision, const void* src, void* dst, b
 
 template <int P>
 hipError_t diagonal_p(const OpView& v, int precision, void* diag, hipStream_t st) {
-  const unsigned g = (unsigned)v.bricks.n_bricks;
-  if (precision == MFQ_FP64)
-    diagonal_kernel<P, double><<<g, kBlock, 0, st>>>(v.idx, (const double*)v.geo, (double*)diag, v.bricks,
-                                                     make_shape<P, double>());
-  else
-    diagonal_kernel<P, float><<<g, kBlock, 0, st>>>(v.idx, (const float*)v.geo, (float*)diag, v.bricks,
-                                                    make_shape<P, float>());
+  for (int c = 0; c < kColours; ++c) {
+    const int64_t nb = v.bricks.count[c];
+    if (nb == 0) continue;
+    if (precision == MFQ_FP64)
+      diagonal_kernel<P, double><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(v.idx, (const double*)v.geo, (double*)diag,
+                                                                     v.bricks, c, make_diag_tables<P, double>());
+    else
+      diagonal_kernel<P, float><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(v.idx, (const float*)v.geo, (float*)diag,
+                                                                    v.bricks, c, make_diag_tables<P, float>());
+  }
   return hipGetLastError();
 }
 

@@ -216,8 +216,9 @@ hipError_t launch_geometry_export(const OpView& v, int precision, double* out, h
 // dst = A src (accumulate = false: every node written, no clearing needed) or dst += A src.
 hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, void* dst, bool accumulate,
                               hipStream_t st);
-// Setup-time cell loops (they add into diag/b/mat, which the callers zero first).
+// diag = diagonal of A (1 on Dirichlet rows); every node written, no clearing needed.
 hipError_t launch_diagonal_cells(const OpView& v, int precision, void* diag, hipStream_t st);
+// Setup-time cell loops (they add into b/mat, which the callers zero first).
 hipError_t launch_rhs_cells(const OpView& v, double* b, hipStream_t st);
 hipError_t launch_assemble_dense(const OpView& v, double* mat, int64_t ld, hipStream_t st);
 hipError_t launch_transfer(const mfq_transfer* t, int precision, bool prolongate, const void* in,

@@ -186,13 +186,35 @@ def test_geometry_matches_oracle(p, n, prec):
     assert np.abs(g - ref).max() <= tol * np.abs(ref).max()
 
 
-@pytest.mark.parametrize("p,n", [(1, 4), (3, 3), (5, 2)])
-def test_diagonal_matches_assembled(p, n):
+@pytest.mark.parametrize("p", range(1, 9))
+@pytest.mark.parametrize("amp,alpha,bc", [(0.1, 0.5, 1), (0.0, 0.0, 1), (0.1, 0.5, 0)])
+def test_diagonal_matches_assembled(p, amp, alpha, bc):
+    """The operator's diagonal (sum-factorised per cell, colour-ordered node sums) against the
+    diagonal of the oracle's assembled matrix, FP64, all degrees, ragged bricks."""
     mfq = _mfq()
-    op = _op(p, n, 0.1, 0.5, 1, mfq.MFQ_FP64)
+    n = SIZES[p]
+    op = _op(p, n, amp, alpha, bc, mfq.MFQ_FP64)
     d = op.diagonal().cpu().numpy()
-    do = assemble.operator_csr(p, n, 0.1, 0.5, 1).diagonal()
+    do = assemble.operator_csr(p, n, amp, alpha, bc).diagonal()
     assert np.abs(d - do).max() <= 1e-13 * np.abs(do).max()
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_diagonal_fp32_within_rounding_bound(p):
+    """FP32 diagonal within k u32 of the summed magnitudes: the regrouped 1D contractions mix
+    signs, so the bound is taken on sum_q |B_q|^T |G_q| |B_q| (its row sums bound each diagonal
+    entry's terms); k = 4(p+1) + 16 (stored G, three contractions of p+1 terms, up to 8 cell
+    contributions).  Dirichlet rows are exactly 1."""
+    mfq = _mfq()
+    n = SIZES[p]
+    op = _op(p, n, 0.1, 0.5, 1, mfq.MFQ_FP32)
+    d = op.diagonal().double().cpu().numpy()
+    do = assemble.operator_csr(p, n, 0.1, 0.5, 1).diagonal()
+    mag = ebe.magnitude_bound(p, n, 0.1, 0.5, np.ones(op.n_dofs), 1)
+    k = 4 * (p + 1) + 16
+    assert np.all(np.abs(d - do) <= k * U32 * mag + 1e-30)
+    m = mesh.boundary_mask(p, n) == 0
+    assert np.all(d[m] == 1.0)
 
 
 @pytest.mark.parametrize("p,n", [(1, 4), (3, 3), (4, 2)])
