@@ -289,3 +289,25 @@ def test_sampled_parity_full_size_q4_64_curved():
     yo = ebe.ebe_rows(p, n, 0.1, 0.5, x_np, 1, rows)
     yg = y[torch.from_numpy(rows).cuda()].cpu().numpy()
     assert np.abs(yg - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+def test_sampled_parity_full_size_q4_64_fp32():
+    """The FP32 operator at the benchmark's full size (Q4 curved 64^3): 400 sampled rows against
+    the oracle applied to the FP32-rounded input, to the componentwise FP32 bound."""
+    mfq = _mfq()
+    torch = _torch()
+    p, n = 4, 64
+    print("full-size sampled parity Q4 64^3 FP32", flush=True)
+    op = _op(p, n, 0.1, 0.5, 1, mfq.MFQ_FP32)
+    x_np = uniform_vector(op.n_dofs, seed=0)
+    x32 = x_np.astype(np.float32).astype(np.float64)
+    y = op.vmult(torch.from_numpy(x_np).float().cuda())
+    torch.cuda.synchronize()
+    rng = np.random.default_rng(4)
+    N1 = p * n + 1
+    rows = np.concatenate([rng.integers(0, op.n_dofs, 400), [1 + N1 + N1 * N1, N1 ** 3 // 2]])
+    yo = ebe.ebe_rows(p, n, 0.1, 0.5, x32, 1, rows)
+    mag = ebe.ebe_rows(p, n, 0.1, 0.5, np.abs(x32), 1, rows, magnitude=True)
+    yg = y[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    k = 8 * (p + 1) + 16
+    assert np.all(np.abs(yg - yo) <= 2 * k * U32 * mag + 1e-30)
