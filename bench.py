@@ -266,6 +266,62 @@ def solve_benchmarks(steps):
     return out
 
 
+def small_poisson(steps, warmup):
+    """The small Poisson workload (Q2, affine 8^3 cells, 4,913 DoFs, Dirichlet, b = masked seeded
+    uniform f): operator application time (cache and launch bound, reported in microseconds) and
+    unpreconditioned FP64 CG to relative residual 1e-10."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    from synthetic import POISSON_Q2_8, uniform_vector
+    pr = POISSON_Q2_8
+    space = mfq.Space(mfq.Mesh(pr.cells_1d, pr.amplitude), pr.degree, mfq.MFQ_BC_DIRICHLET0)
+    op = mfq.Operator(space, pr.alpha, mfq.MFQ_FP64)
+    f = torch.from_numpy(uniform_vector(space.n_dofs, seed=0)).cuda()
+    y = op.new_vector()
+    us = time_events(lambda: op.vmult(f, y), steps, warmup) * 1e6
+    b = space.apply_mask(f.clone())
+    sv = mfq.Solver(op, mfq.MFQ_SOLVER_CG)
+    sv.solve(b, rtol=1e-10, max_iter=10000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    x, info, st = sv.solve(b, rtol=1e-10, max_iter=10000)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    return {"workload": pr.name, "dofs": space.n_dofs, "vmult_us": us, "cg_s": wall, "cg_iterations": info.iterations,
+            "cg_rel_residual": info.rel_residual, "status": st}
+
+
+def cpu_small_poisson():
+    """Oracle side of the small Poisson workload: SciPy CSR product of the assembled matrix on one
+    thread, and the oracle's CG to 1e-10 on it."""
+    import numpy as np
+    from oracle import assemble, mesh, solve
+    from synthetic import POISSON_Q2_8, uniform_vector
+    try:
+        from threadpoolctl import threadpool_limits
+    except ImportError:  # pragma: no cover
+        threadpool_limits = None
+    pr = POISSON_Q2_8
+    A = assemble.operator_csr(pr.degree, pr.cells_1d, pr.amplitude, pr.alpha, 1)
+    f = uniform_vector(A.shape[0], seed=0)
+    b = f * mesh.boundary_mask(pr.degree, pr.cells_1d)
+    ctx = threadpool_limits(limits=1) if threadpool_limits else None
+    try:
+        reps = 200
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            A @ f
+        spmv = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        x, it, rr = solve.cg(lambda v: A @ v, b, rtol=1e-10)
+        cg = time.perf_counter() - t0
+    finally:
+        if ctx is not None:
+            ctx.__exit__(None, None, None)
+    return {"workload": pr.name, "cores": 1, "csr_spmv_us": spmv * 1e6, "cg_s": cg, "cg_iterations": it,
+            "cg_rel_residual": rr}
+
+
 # Q4 V-cycles beside the paper's only measurements (an FP32 V-cycle of DG Q4, Chebyshev degree 6,
 # matrix-free, on one 48-core node: 31.7 ms for 65,536 cells, 264 ms for 524,288 cells)
 VCYCLE_MESHES = [40, 80]
@@ -295,7 +351,8 @@ def vcycle_benchmark(steps, warmup):
     return out
 
 
-def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=4, mode="async", setup_threads=1):
+def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=4, mode="async", setup_threads=1,
+                    solver_params=None):
     """The serving stream: Poisson arrivals at `rate`/s, degree U{1..6}, n U{4..48}, alpha
     U[0,0.9], right-hand side from the request's seed; each solved to relative residual 1e-10."""
     import torch
@@ -306,8 +363,8 @@ def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=
     arrivals = [d["arrival"] for d in stream]
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(0.75 * free, 160e9))
-    srv = Server(DeviceExecutor(n_streams=n_streams), budget, iters_per_step=iters_per_step, mode=mode,
-                 setup_threads=setup_threads)
+    srv = Server(DeviceExecutor(n_streams=n_streams, **(solver_params or {})), budget, iters_per_step=iters_per_step,
+                 mode=mode, setup_threads=setup_threads)
     t0 = time.perf_counter()
     st = run_stream(srv, reqs, arrivals)
     srv.close()
@@ -318,6 +375,7 @@ def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=
     st["streams"] = n_streams
     st["mode"] = mode
     st["setup_threads"] = setup_threads
+    st["solver_params"] = solver_params or {}
     st["rate_per_s"] = rate
     st["dofs_total"] = sum((r.degree * r.n + 1) ** 3 for r in reqs)
     st["iterations_mean"] = sum(r.iterations for r in srv.done) / max(len(srv.done), 1)
@@ -337,6 +395,8 @@ def main():
     ap.add_argument("--serve-mode", choices=["sync", "async"], default="async",
                     help="serving steps: all solves together (sync) or each at its own pace (async)")
     ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-params", default="",
+                    help="solver parameters of the served requests, e.g. coarse_degree=8,smoother_degree=3")
     ap.add_argument("--serve-setup-threads", type=int, default=1,
                     help="worker threads that set up admitted requests (0: on the scheduler thread)")
     ap.add_argument("--no-csr", action="store_true", help="skip the assembled-matrix (CSR) comparison")
@@ -432,6 +492,7 @@ def main():
         rec["assembled_csr"] = assembled_comparison(op64, x64, y64, kern64, min(args.steps, 20), args.warmup)
     if args.csr_sweep:
         rec["csr_sweep"] = csr_sweep(min(args.steps, 20), args.warmup)
+    rec["small_poisson"] = small_poisson(min(args.steps, 50), args.warmup)
     print("# Q8 24^3: FP64 / FP32 / FP32 matrix cores", file=sys.stderr, flush=True)
     rec["high_degree_q8_24"] = high_degree_comparison(min(args.steps, 20), args.warmup)
     if args.solves:
@@ -440,12 +501,17 @@ def main():
         rec["vcycle_q4"] = vcycle_benchmark(min(args.steps, 20), args.warmup)
     if args.serve:
         print(f"# serving {args.serve} requests", file=sys.stderr, flush=True)
+        prm = {}
+        for kv in filter(None, args.serve_params.split(",")):
+            k, v = kv.split("=")
+            prm[k.strip()] = float(v) if "." in v else int(v)
         rec["serving"] = serve_benchmark(args.serve, mode=args.serve_mode, n_streams=args.serve_streams,
-                                         setup_threads=args.serve_setup_threads)
+                                         setup_threads=args.serve_setup_threads, solver_params=prm)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
         rec["cpu_baseline"] = cpu_baseline(p, n, pr.amplitude, pr.alpha, x_np, check_rows=check_rows,
                                            y64_rows=y64_rows, y32_rows=y32_rows)
+        rec["cpu_baseline"]["small_poisson"] = cpu_small_poisson()
     print(json.dumps(rec), flush=True)
 
 
