@@ -186,32 +186,36 @@ def time_events(fn, steps, warmup):
     return e0.elapsed_time(e1) / 1e3 / steps
 
 
-def csr_bytes(n_rows, nnz):
-    """Algorithmic bytes of one CSR product: values (8 B) and columns (4 B) per entry, row pointers
-    (8 B per row + 1), the source and destination vectors (8 B per row each)."""
-    return 12 * nnz + 8 * (n_rows + 1) + 16 * n_rows
+def csr_bytes(n_rows, nnz, value_bytes=8):
+    """Algorithmic bytes of one CSR product: values (8 or 4 B) and columns (4 B) per entry, row
+    pointers (8 B per row + 1), the source and destination vectors (one value per row each)."""
+    return (value_bytes + 4) * nnz + 8 * (n_rows + 1) + 2 * value_bytes * n_rows
 
 
-def assembled_comparison(op, x, y_mf, mf_s, steps, warmup):
+def assembled_comparison(op, x, y_mf, mf_s, steps, warmup, precision=None):
     """The same operator assembled as a CSR matrix on the device and applied by the library's
     sparse product: assembly time, product time, its HBM roofline fraction, and the matrix-free
-    application's speed-up over it (matrix-free time = the cell loop of one application)."""
+    application's speed-up over it (matrix-free time = the cell loop of one application in the
+    same precision; `y_mf` the FP64 matrix-free result)."""
     import torch
     import paper_1910_13247_amd as mfq
+    precision = mfq.MFQ_FP64 if precision is None else precision
+    vb = 8 if precision == mfq.MFQ_FP64 else 4
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    A = mfq.SparseMatrix(op)
+    A = mfq.SparseMatrix(op, precision)
     torch.cuda.synchronize()
     t_asm = time.perf_counter() - t0
+    x = x.to(A.dtype)
     y = torch.empty_like(x)
     s = time_events(lambda: A.spmv(x, y), steps, warmup)
-    rb = csr_bytes(A.n_rows, A.nnz)
+    rb = csr_bytes(A.n_rows, A.nnz, vb)
     out = {"nnz": A.nnz, "device_bytes": A.device_bytes, "assemble_s": t_asm, "ms": s * 1e3,
            "algorithmic_bytes": rb, "achieved_GBs": rb / s / 1e9, "frac": rb / s / 1e9 / HBM_PEAK_GBS,
            "kernel": "csr_spmv_rows_kernel" if A.nnz / A.n_rows >= 384 else "csr_spmv_kernel (row blocks)",
            "matrix_free_ms": mf_s * 1e3, "speedup_matrix_free": s / mf_s,
-           "bytes_ratio": rb / algorithmic_bytes(op.space.degree, op.space.mesh.n, 8),
-           "normwise_rel_diff_vs_matrix_free": ((y - y_mf).abs().max() / y_mf.abs().max()).item()}
+           "bytes_ratio": rb / algorithmic_bytes(op.space.degree, op.space.mesh.n, vb),
+           "normwise_rel_diff_vs_matrix_free_fp64": ((y.double() - y_mf).abs().max() / y_mf.abs().max()).item()}
     del A, y
     torch.cuda.synchronize()
     torch.cuda.empty_cache()
@@ -490,6 +494,8 @@ def main():
     if not args.no_csr:
         print("# assembled matrix (CSR) of the same operator", file=sys.stderr, flush=True)
         rec["assembled_csr"] = assembled_comparison(op64, x64, y64, kern64, min(args.steps, 20), args.warmup)
+        rec["assembled_csr_fp32"] = assembled_comparison(op64, x64, y64, kern32, min(args.steps, 20), args.warmup,
+                                                         precision=mfq.MFQ_FP32)
     if args.csr_sweep:
         rec["csr_sweep"] = csr_sweep(min(args.steps, 20), args.warmup)
     rec["small_poisson"] = small_poisson(min(args.steps, 50), args.warmup)

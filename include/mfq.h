@@ -154,14 +154,17 @@ int mfq_rhs_manufactured(const mfq_op* op, double* b, void* hip_stream);
  * to its neighbours against computing the integrals on the fly).  For measuring the two side
  * by side on one device; the solvers never use it.
  * Layout (CSR, in the caller's buffer): rowptr int64 [n_rows+1], cols int32 [nnz] increasing
- * within each row, vals double [nnz]; n_rows = n_dofs.  Row (I,J,K) holds every node that
+ * within each row, vals [nnz] of the value precision (double or float); n_rows = n_dofs.  Row (I,J,K) holds every node that
  * shares a cell with it (the tensor product of the 1D neighbour ranges), so
  * nnz = (n(p+1)^2 - n + 1)^3.  Entries are sum_K A^K_ij over the cells holding both nodes,
- * computed in FP64 from the operator's stored G.  With MFQ_BC_DIRICHLET0 the couplings of
+ * computed in FP64 from the operator's stored G (FP32 values: each cell colour's FP64 sum is
+ * added into the stored value with one rounding, at most 8 per entry).  With MFQ_BC_DIRICHLET0
+ * the couplings of
  * Dirichlet nodes are stored as zeros and their diagonal as 1, so the matrix applies
  * m*A(m*x) + (1-m)*x exactly as mfq_vmult does. */
-/* op: an MFQ_FP64 operator (MFQ_EINVAL otherwise).  Host only; nothing is read from the device. */
-int mfq_csr_create(const mfq_op* op, mfq_csr** out);
+/* op: an MFQ_FP64 operator; precision: of the stored values and of the product's vectors,
+ * MFQ_FP64 or MFQ_FP32 (MFQ_EINVAL otherwise).  Host only; nothing is read from the device. */
+int mfq_csr_create(const mfq_op* op, int precision, mfq_csr** out);
 void mfq_csr_destroy(mfq_csr* a);
 /* Rows, stored entries and the device bytes mfq_csr_bind needs (any output may be NULL). */
 int mfq_csr_size(const mfq_csr* a, int64_t* n_rows, int64_t* nnz, size_t* device_bytes);
@@ -172,8 +175,9 @@ int mfq_csr_size(const mfq_csr* a, int64_t* n_rows, int64_t* nnz, size_t* device
 int mfq_csr_bind(mfq_csr* a, void* dev_buf, size_t bytes, void* hip_stream);
 /* Device addresses of the three arrays inside the bound buffer (MFQ_EINVAL when unbound). */
 int mfq_csr_arrays(const mfq_csr* a, void** rowptr, void** cols, void** vals);
-/* dst = A src for double device vectors of n_rows elements that must not overlap.  Asynchronous,
- * no host synchronisation, deterministic (fixed summation order per row). */
+/* dst = A src for device vectors of n_rows elements of the value precision (double or float,
+ * accumulated in that precision) that must not overlap.  Asynchronous, no host synchronisation,
+ * deterministic (fixed summation order per row). */
 int mfq_csr_spmv(const mfq_csr* a, const void* src, void* dst, void* hip_stream);
 
 /* ---------------------------------------------------------------- transfer (Sec. 3.5, 3.1)

@@ -162,14 +162,17 @@ class Operator:
 
 class SparseMatrix:
     """The operator assembled as a CSR matrix on the device (for comparison with the matrix-free
-    action); device data in a torch buffer.  rowptr int64, cols int32, vals float64."""
+    action); device data in a torch buffer.  rowptr int64, cols int32, vals float64 or float32
+    (`precision`, also the precision of the product's vectors)."""
 
-    def __init__(self, op, stream=None):
+    def __init__(self, op, precision=MFQ_FP64, stream=None):
         torch = _torch()
         if op.precision != MFQ_FP64:
             raise ValueError("the assembled matrix needs an FP64 operator")
         self.op = op
-        self.handle = _lib.mfq_csr_create(op.handle)
+        self.precision = int(precision)
+        self.dtype = _dtype(self.precision)
+        self.handle = _lib.mfq_csr_create(op.handle, self.precision)
         self.n_rows, self.nnz, self.device_bytes = _lib.mfq_csr_size(self.handle)
         self.buffer = torch.empty(self.device_bytes, dtype=torch.uint8, device=op.buffer.device)
         _lib.mfq_csr_bind(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream(stream))
@@ -184,15 +187,16 @@ class SparseMatrix:
             off = addr - base
             return self.buffer[off:off + count * size].view(dtype)
 
+        vs = 8 if self.precision == MFQ_FP64 else 4
         return (view(r, self.n_rows + 1, torch.int64, 8), view(c, self.nnz, torch.int32, 4),
-                view(v, self.nnz, torch.float64, 8))
+                view(v, self.nnz, self.dtype, vs))
 
     def spmv(self, src, dst=None, stream=None):
         torch = _torch()
         if dst is None:
-            dst = torch.empty(self.n_rows, dtype=torch.float64, device=self.buffer.device)
-        _lib.mfq_csr_spmv(self.handle, _check_vec(src, self.n_rows, MFQ_FP64, "src"),
-                          _check_vec(dst, self.n_rows, MFQ_FP64, "dst"), _stream(stream))
+            dst = torch.empty(self.n_rows, dtype=self.dtype, device=self.buffer.device)
+        _lib.mfq_csr_spmv(self.handle, _check_vec(src, self.n_rows, self.precision, "src"),
+                          _check_vec(dst, self.n_rows, self.precision, "dst"), _stream(stream))
         return dst
 
     def __del__(self):

@@ -73,7 +73,7 @@ _SIGS = {
     "mfq_op_diagonal": ([P, P, P], I),
     "mfq_op_geometry": ([P, P, P], I),
     "mfq_rhs_manufactured": ([P, P, P], I),
-    "mfq_csr_create": ([P, PP], I),
+    "mfq_csr_create": ([P, I, PP], I),
     "mfq_csr_destroy": ([P], None),
     "mfq_csr_size": ([P, C.POINTER(I64), C.POINTER(I64), C.POINTER(SZ)], I),
     "mfq_csr_bind": ([P, P, SZ, P], I),
@@ -226,8 +226,8 @@ def mfq_rhs_manufactured(op, b, stream):
     _check(lib().mfq_rhs_manufactured(op, b, stream))
 
 
-def mfq_csr_create(op):
-    return _handle(lib().mfq_csr_create, op)
+def mfq_csr_create(op, precision=MFQ_FP64):
+    return _handle(lib().mfq_csr_create, op, precision)
 
 
 def mfq_csr_destroy(a):

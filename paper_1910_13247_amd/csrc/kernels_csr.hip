@@ -89,10 +89,10 @@ __global__ __launch_bounds__(kCsrBlock) void csr_cols_kernel(const int64_t* __re
 // parities of `colour` share no node, so no two workgroups of a launch touch the same entry);
 // G and the 1D tables are staged in LDS and every lane of a wave reads the same quadrature point
 // at the same time.  Entries of a row are contiguous in j, and j runs fastest over the lanes.
-template <int P>
+template <int P, typename V>
 __global__ __launch_bounds__(kCsrBlock) void csr_values_kernel(const double* __restrict__ geo,
                                                                const int64_t* __restrict__ rowptr,
-                                                               double* __restrict__ vals, Bricks bk, int n, int bc,
+                                                               V* __restrict__ vals, Bricks bk, int n, int bc,
                                                                int colour, Shape<P, double> sh) {
   using C = Cell<P>;
   constexpr int N1 = P + 1, T = N1 * N1, NQ = N1 * T, NT = C::NT;
@@ -166,20 +166,22 @@ __global__ __launch_bounds__(kCsrBlock) void csr_values_kernel(const double* __r
     }
     const Range1D rx = range_1d(Ii, P, pn), ry = range_1d(Ji, P, pn), rz = range_1d(Ki, P, pn);
     const int64_t pos = (Ij - rx.lo) + rx.len * ((Jj - ry.lo) + (int64_t)ry.len * (Kj - rz.lo));
-    vals[rowptr[Ii + N1g * (Ji + N1g * Ki)] + pos] += sum;
+    V* const entry = vals + rowptr[Ii + N1g * (Ji + N1g * Ki)] + pos;
+    *entry = (V)((double)*entry + sum);  // one rounding per colour for FP32 storage
   }
 }
 
 // Identity rows of the Dirichlet nodes: the diagonal entry is one (all others stay zero).
+template <typename V>
 __global__ __launch_bounds__(kCsrBlock) void csr_dirichlet_kernel(const int64_t* __restrict__ rowptr,
-                                                                  double* __restrict__ vals, int p, int n) {
+                                                                  V* __restrict__ vals, int p, int n) {
   const int64_t N1 = (int64_t)p * n + 1, pn = N1 - 1;
   const int64_t N = N1 * N1 * N1;
   for (int64_t g = blockIdx.x * (int64_t)kCsrBlock + threadIdx.x; g < N; g += (int64_t)gridDim.x * kCsrBlock) {
     const int64_t I = g % N1, J = (g / N1) % N1, K = g / (N1 * N1);
     if (!(I == 0 || I == pn || J == 0 || J == pn || K == 0 || K == pn)) continue;
     const Range1D rx = range_1d(I, p, pn), ry = range_1d(J, p, pn), rz = range_1d(K, p, pn);
-    vals[rowptr[g] + (I - rx.lo) + rx.len * ((J - ry.lo) + (int64_t)ry.len * (K - rz.lo))] = 1.0;
+    vals[rowptr[g] + (I - rx.lo) + rx.len * ((J - ry.lo) + (int64_t)ry.len * (K - rz.lo))] = (V)1;
   }
 }
 
@@ -212,12 +214,12 @@ __global__ __launch_bounds__(kCsrBlock) void csr_blocks_kernel(const int64_t* __
 // entries.  The grid is a multiple of 8 and block b runs on XCD b % 8, so block b works on the
 // b % 8-th contiguous eighth of the rows (each XCD's L2 serves the source entries that
 // neighbouring rows share).
-template <int LPR, int UNROLL>
+template <int LPR, int UNROLL, typename V>
 __global__ __launch_bounds__(kCsrBlock) void csr_spmv_rows_kernel(const int64_t* __restrict__ rowptr,
                                                                   const int* __restrict__ cols,
-                                                                  const double* __restrict__ vals,
-                                                                  const double* __restrict__ x,
-                                                                  double* __restrict__ y, int64_t n_rows) {
+                                                                  const V* __restrict__ vals,
+                                                                  const V* __restrict__ x,
+                                                                  V* __restrict__ y, int64_t n_rows) {
   constexpr int GPB = kCsrBlock / LPR;
   const int xcd = blockIdx.x & 7;
   const int64_t slot = blockIdx.x >> 3, per_xcd = gridDim.x >> 3;
@@ -240,17 +242,17 @@ __global__ __launch_bounds__(kCsrBlock) void csr_spmv_rows_kernel(const int64_t*
       nbeg = rowptr[next];
       nend = rowptr[next + 1];
     }
-    double acc = 0.0;
+    V acc = 0;
     for (int64_t base = beg + lane; base < end; base += UNROLL * LPR) {
       int c[UNROLL];
-      double v[UNROLL];
+      V v[UNROLL];
       bool ok[UNROLL];
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u) {
         const int64_t k = base + u * LPR;
         ok[u] = k < end;
         c[u] = ok[u] ? cols[k] : 0;
-        v[u] = ok[u] ? vals[k] : 0.0;
+        v[u] = ok[u] ? vals[k] : (V)0;
       }
 #pragma unroll
       for (int u = 0; u < UNROLL; ++u)
@@ -272,14 +274,15 @@ __global__ __launch_bounds__(kCsrBlock) void csr_spmv_rows_kernel(const int64_t*
 // reproducible.  Block b of the grid (a multiple of 8) runs on XCD b % 8; it takes block
 // (b % 8) * ceil(nb / 8) + b / 8, so each XCD's L2 serves a contiguous eighth of the rows and
 // the source entries their columns share.
-template <int LPR, int UNROLL>
+template <int LPR, int UNROLL, typename V>
 __global__ __launch_bounds__(kCsrBlock) void csr_spmv_kernel(const int64_t* __restrict__ rowptr,
                                                              const int* __restrict__ cols,
-                                                             const double* __restrict__ vals,
+                                                             const V* __restrict__ vals,
                                                              const int64_t* __restrict__ blk,
-                                                             const double* __restrict__ x, double* __restrict__ y,
+                                                             const V* __restrict__ x, V* __restrict__ y,
                                                              int64_t n_blocks) {
-  extern __shared__ double prod[];
+  extern __shared__ unsigned char smem[];
+  V* const prod = reinterpret_cast<V*>(smem);
   const int64_t per_xcd = (n_blocks + 7) / 8;
   const int64_t b = (int64_t)(blockIdx.x & 7) * per_xcd + (blockIdx.x >> 3);
   if (b >= n_blocks || (blockIdx.x >> 3) >= per_xcd) return;
@@ -290,16 +293,16 @@ __global__ __launch_bounds__(kCsrBlock) void csr_spmv_kernel(const int64_t* __re
   const int t = threadIdx.x;
   for (int base = t; base < cnt; base += UNROLL * kCsrBlock) {
     int c[UNROLL];
-    double v[UNROLL];
+    V v[UNROLL];
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       const int k = base + u * kCsrBlock;
       c[u] = k < cnt ? cols[beg + k] : 0;
-      v[u] = k < cnt ? vals[beg + k] : 0.0;
+      v[u] = k < cnt ? vals[beg + k] : (V)0;
     }
-    double xv[UNROLL];
+    V xv[UNROLL];
 #pragma unroll
-    for (int u = 0; u < UNROLL; ++u) xv[u] = base + u * kCsrBlock < cnt ? x[c[u]] : 0.0;
+    for (int u = 0; u < UNROLL; ++u) xv[u] = base + u * kCsrBlock < cnt ? x[c[u]] : (V)0;
 #pragma unroll
     for (int u = 0; u < UNROLL; ++u) {
       const int k = base + u * kCsrBlock;
@@ -311,7 +314,7 @@ __global__ __launch_bounds__(kCsrBlock) void csr_spmv_kernel(const int64_t* __re
   const int lane = t % LPR, grp = t / LPR;
   for (int64_t r = row0 + grp; r < row1; r += GPB) {
     const int a = (int)(rowptr[r] - beg), e = (int)(rowptr[r + 1] - beg);
-    double s = 0.0;
+    V s = 0;
     for (int k = a + lane; k < e; k += LPR) s += prod[k];
 #pragma unroll
     for (int off = LPR / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, LPR);
@@ -326,16 +329,16 @@ int csr_grid(int64_t work, int per_block) {
   return (int)g;
 }
 
-template <int P>
-hipError_t csr_values_p(const OpView& v, const int64_t* rowptr, double* vals, hipStream_t st) {
+template <int P, typename V>
+hipError_t csr_values_pv(const OpView& v, const int64_t* rowptr, V* vals, hipStream_t st) {
   const int n = v.n;
   for (int c = 0; c < kColours; ++c) {
     const int px = c & 1, py = (c >> 1) & 1, pz = c >> 2;
     const int64_t cells = (int64_t)((n + 1 - px) / 2) * ((n + 1 - py) / 2) * ((n + 1 - pz) / 2);
     if (cells == 0) continue;
     if (cells > 0x7fffffff) return hipErrorInvalidValue;
-    csr_values_kernel<P><<<(unsigned)cells, kCsrBlock, 0, st>>>((const double*)v.geo, rowptr, vals, v.bricks, n, v.bc,
-                                                                c, make_shape<P, double>());
+    csr_values_kernel<P, V><<<(unsigned)cells, kCsrBlock, 0, st>>>((const double*)v.geo, rowptr, vals, v.bricks, n,
+                                                                   v.bc, c, make_shape<P, double>());
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
@@ -355,20 +358,58 @@ hipError_t csr_values_p(const OpView& v, const int64_t* rowptr, double* vals, hi
 #define MFQ_CSR_WG_PER_CU 8
 #endif
 
-template <int LPR>
-hipError_t spmv_blocks(const mfq_csr* a, const double* x, double* y, hipStream_t st) {
+template <int LPR, typename V>
+hipError_t spmv_blocks(const mfq_csr* a, const V* x, V* y, hipStream_t st) {
   const int64_t grid = 8 * ((a->n_blocks + 7) / 8);
   if (grid > 0x7fffffff) return hipErrorInvalidValue;
-  const size_t lds = (size_t)(a->window + a->max_row) * sizeof(double);
-  csr_spmv_kernel<LPR, MFQ_CSR_UNROLL><<<(unsigned)grid, kCsrBlock, lds, st>>>(a->rowptr, a->cols, a->vals, a->blk, x, y,
-                                                                            a->n_blocks);
+  const size_t lds = (size_t)(a->window + a->max_row) * sizeof(V);
+  csr_spmv_kernel<LPR, MFQ_CSR_UNROLL, V><<<(unsigned)grid, kCsrBlock, lds, st>>>(a->rowptr, a->cols, (const V*)a->vals,
+                                                                               a->blk, x, y, a->n_blocks);
   return hipGetLastError();
 }
 
-template <int LPR>
-hipError_t spmv_rows(const mfq_csr* a, const double* x, double* y, hipStream_t st) {
-  csr_spmv_rows_kernel<LPR, MFQ_CSR_ROW_UNROLL><<<MFQ_CSR_WG_PER_CU * 256, kCsrBlock, 0, st>>>(a->rowptr, a->cols, a->vals,
-                                                                                           x, y, a->n_rows);
+template <int LPR, typename V>
+hipError_t spmv_rows(const mfq_csr* a, const V* x, V* y, hipStream_t st) {
+  csr_spmv_rows_kernel<LPR, MFQ_CSR_ROW_UNROLL, V><<<MFQ_CSR_WG_PER_CU * 256, kCsrBlock, 0, st>>>(
+      a->rowptr, a->cols, (const V*)a->vals, x, y, a->n_rows);
+  return hipGetLastError();
+}
+
+template <typename V>
+hipError_t spmv_typed(const mfq_csr* a, const V* x, V* y, hipStream_t st) {
+  if (a->long_rows) {
+    switch (a->lanes_per_row) {
+      case 32: return spmv_rows<32, V>(a, x, y, st);
+      case 64: return spmv_rows<64, V>(a, x, y, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+  switch (a->lanes_per_row) {
+    case 8: return spmv_blocks<8, V>(a, x, y, st);
+    case 16: return spmv_blocks<16, V>(a, x, y, st);
+    case 32: return spmv_blocks<32, V>(a, x, y, st);
+    case 64: return spmv_blocks<64, V>(a, x, y, st);
+    default: return hipErrorInvalidValue;
+  }
+}
+
+template <typename V>
+hipError_t csr_values_typed(const OpView& v, const int64_t* rowptr, V* vals, hipStream_t st) {
+  hipError_t e;
+  switch (v.p) {
+    case 1: e = csr_values_pv<1, V>(v, rowptr, vals, st); break;
+    case 2: e = csr_values_pv<2, V>(v, rowptr, vals, st); break;
+    case 3: e = csr_values_pv<3, V>(v, rowptr, vals, st); break;
+    case 4: e = csr_values_pv<4, V>(v, rowptr, vals, st); break;
+    case 5: e = csr_values_pv<5, V>(v, rowptr, vals, st); break;
+    case 6: e = csr_values_pv<6, V>(v, rowptr, vals, st); break;
+    case 7: e = csr_values_pv<7, V>(v, rowptr, vals, st); break;
+    case 8: e = csr_values_pv<8, V>(v, rowptr, vals, st); break;
+    default: return hipErrorInvalidValue;
+  }
+  if (e != hipSuccess || v.bc != MFQ_BC_DIRICHLET0) return e;
+  const int64_t N1 = (int64_t)v.p * v.n + 1;
+  csr_dirichlet_kernel<V><<<csr_grid(N1 * N1 * N1, kCsrBlock), kCsrBlock, 0, st>>>(rowptr, vals, v.p, v.n);
   return hipGetLastError();
 }
 
@@ -386,23 +427,9 @@ hipError_t launch_csr_pattern(int p, int n, int64_t* rowptr, int* cols, hipStrea
   return hipGetLastError();
 }
 
-hipError_t launch_csr_values(const OpView& v, const int64_t* rowptr, double* vals, hipStream_t st) {
-  hipError_t e;
-  switch (v.p) {
-    case 1: e = csr_values_p<1>(v, rowptr, vals, st); break;
-    case 2: e = csr_values_p<2>(v, rowptr, vals, st); break;
-    case 3: e = csr_values_p<3>(v, rowptr, vals, st); break;
-    case 4: e = csr_values_p<4>(v, rowptr, vals, st); break;
-    case 5: e = csr_values_p<5>(v, rowptr, vals, st); break;
-    case 6: e = csr_values_p<6>(v, rowptr, vals, st); break;
-    case 7: e = csr_values_p<7>(v, rowptr, vals, st); break;
-    case 8: e = csr_values_p<8>(v, rowptr, vals, st); break;
-    default: return hipErrorInvalidValue;
-  }
-  if (e != hipSuccess || v.bc != MFQ_BC_DIRICHLET0) return e;
-  const int64_t N1 = (int64_t)v.p * v.n + 1;
-  csr_dirichlet_kernel<<<csr_grid(N1 * N1 * N1, kCsrBlock), kCsrBlock, 0, st>>>(rowptr, vals, v.p, v.n);
-  return hipGetLastError();
+hipError_t launch_csr_values(const OpView& v, int precision, const int64_t* rowptr, void* vals, hipStream_t st) {
+  if (precision == MFQ_FP64) return csr_values_typed<double>(v, rowptr, (double*)vals, st);
+  return csr_values_typed<float>(v, rowptr, (float*)vals, st);
 }
 
 hipError_t launch_csr_blocks(const int64_t* rowptr, int64_t* blk, int64_t n_rows, int64_t n_blocks, int64_t window,
@@ -411,21 +438,9 @@ hipError_t launch_csr_blocks(const int64_t* rowptr, int64_t* blk, int64_t n_rows
   return hipGetLastError();
 }
 
-hipError_t launch_csr_spmv(const mfq_csr* a, const double* x, double* y, hipStream_t st) {
-  if (a->long_rows) {
-    switch (a->lanes_per_row) {
-      case 32: return spmv_rows<32>(a, x, y, st);
-      case 64: return spmv_rows<64>(a, x, y, st);
-      default: return hipErrorInvalidValue;
-    }
-  }
-  switch (a->lanes_per_row) {
-    case 8: return spmv_blocks<8>(a, x, y, st);
-    case 16: return spmv_blocks<16>(a, x, y, st);
-    case 32: return spmv_blocks<32>(a, x, y, st);
-    case 64: return spmv_blocks<64>(a, x, y, st);
-    default: return hipErrorInvalidValue;
-  }
+hipError_t launch_csr_spmv(const mfq_csr* a, const void* x, void* y, hipStream_t st) {
+  if (a->precision == MFQ_FP64) return spmv_typed<double>(a, (const double*)x, (double*)y, st);
+  return spmv_typed<float>(a, (const float*)x, (float*)y, st);
 }
 
 }  // namespace mfq

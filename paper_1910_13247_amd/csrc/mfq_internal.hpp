@@ -162,6 +162,7 @@ struct mfq_op {
 
 struct mfq_csr {
   const mfq_op* op;           // FP64 operator whose stored geometry the values are assembled from
+  int precision;              // of the stored values and the product's vectors (MFQ_FP64 or MFQ_FP32)
   int p, n, bc;
   int64_t n_rows, nnz;
   bool long_rows;             // product by lane groups per row (long rows) instead of row blocks
@@ -173,7 +174,7 @@ struct mfq_csr {
   void* buf = nullptr;        // caller-owned device memory
   int64_t* rowptr = nullptr;  // [n_rows + 1]
   int* cols = nullptr;        // [nnz], increasing within a row
-  double* vals = nullptr;     // [nnz]
+  void* vals = nullptr;       // [nnz] of the value precision
   int64_t* blk = nullptr;     // [n_blocks + 1]: first row of each row block
 };
 
@@ -226,10 +227,10 @@ hipError_t launch_transfer(const mfq_transfer* t, int precision, bool prolongate
 
 // assembled sparse matrix (kernels_csr.hip)
 hipError_t launch_csr_pattern(int p, int n, int64_t* rowptr, int* cols, hipStream_t st);
-hipError_t launch_csr_values(const OpView& v, const int64_t* rowptr, double* vals, hipStream_t st);
+hipError_t launch_csr_values(const OpView& v, int precision, const int64_t* rowptr, void* vals, hipStream_t st);
 hipError_t launch_csr_blocks(const int64_t* rowptr, int64_t* blk, int64_t n_rows, int64_t n_blocks, int64_t window,
                              hipStream_t st);
-hipError_t launch_csr_spmv(const mfq_csr* a, const double* x, double* y, hipStream_t st);
+hipError_t launch_csr_spmv(const mfq_csr* a, const void* x, void* y, hipStream_t st);
 int64_t csr_row_start_host(int64_t I, int64_t J, int64_t K, int p, int n);
 
 // vector kernels (kernels_vector.hip)

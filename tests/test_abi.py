@@ -144,6 +144,14 @@ def test_csr_size_matches_assembled_pattern(p, n):
     window = min(2048, (8192 - len1 ** 3) // 256 * 256)
     nblk = -(-nnz // window)
     assert nbytes == rnd((rows + 1) * 8) + rnd(nnz * 4) + rnd(nnz * 8) + rnd((nblk + 1) * 8)
+    a32 = lib.mfq_csr_create(op, lib.MFQ_FP32)     # float values: 4 bytes per entry, same pattern
+    r32, z32, b32 = lib.mfq_csr_size(a32)
+    assert (r32, z32) == (rows, nnz)
+    assert b32 == rnd((rows + 1) * 8) + rnd(nnz * 4) + rnd(nnz * 4) + rnd((-(-nnz // 4096) + 1) * 8)
+    lib.mfq_csr_destroy(a32)
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_csr_create(op, 7)                  # unknown value precision
+    assert e.value.status == lib.MFQ_EINVAL
     with pytest.raises(lib.MfqError) as e:
         lib.mfq_csr_arrays(a)                      # not bound
     assert e.value.status == lib.MFQ_EINVAL

@@ -8,7 +8,7 @@ import numpy as np
 import pytest
 import scipy.sparse as sp
 
-from oracle import assemble, ebe, mesh
+from oracle import assemble, ebe, element, mesh
 from synthetic import uniform_vector
 
 pytestmark = pytest.mark.gpu
@@ -27,10 +27,30 @@ def _torch():
     return torch
 
 
-def _build(p, n, amp, alpha, bc):
+U32 = 2.0 ** -24
+
+
+def _abs_assembled(p, n, amp, alpha, bc):
+    """sum_K |A^K| assembled (the magnitudes the FP32 entries are summed from); Dirichlet
+    couplings dropped like the constrained matrix's."""
+    C = n ** 3
+    cells = np.arange(C)
+    Ak = np.abs(element.element_matrices(p, n, amp, alpha, cells, element.reference_tabulation(p)))
+    g = mesh.cell_dofs(p, n, cells)
+    rows = np.repeat(g[:, :, None], g.shape[1], axis=2).reshape(-1)
+    cols = np.repeat(g[:, None, :], g.shape[1], axis=1).reshape(-1)
+    N = (p * n + 1) ** 3
+    M = sp.coo_matrix((Ak.reshape(-1), (rows, cols)), shape=(N, N)).tocsr()
+    if bc:
+        m = mesh.boundary_mask(p, n)
+        M = (sp.diags(m) @ M @ sp.diags(m) + sp.diags(1.0 - m)).tocsr()
+    return M
+
+
+def _build(p, n, amp, alpha, bc, precision=None):
     mfq = _mfq()
     op = mfq.Operator(mfq.Space(mfq.Mesh(n, amp), p, bc), alpha, mfq.MFQ_FP64)
-    A = mfq.SparseMatrix(op)
+    A = mfq.SparseMatrix(op, mfq.MFQ_FP64 if precision is None else precision)
     _torch().cuda.synchronize()
     rowptr, cols, vals = (t.cpu().numpy() for t in A.arrays())
     return op, A, rowptr, cols, vals
@@ -136,6 +156,42 @@ def test_spmv_deterministic_and_argument_errors():
         mfq._lib.mfq_csr_spmv(h, x.data_ptr(), y1.data_ptr(), None)   # unbound
     assert e.value.status == mfq.MFQ_EINVAL
     mfq._lib.mfq_csr_destroy(h)
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_fp32_matrix_and_product_within_bounds(p):
+    """FP32 values: the same pattern, Dirichlet rows and columns exact, every entry within 8 u32
+    of the summed cell magnitudes (at most eight FP32 roundings); the FP32 product within
+    k u32 (M |x|), M = sum_K |A^K|, k = 8 (values) + 1 (product) + ceil(L/8) + 6 (lane sums and
+    the reduction over at most 64 lanes) for rows of at most L entries."""
+    mfq = _mfq()
+    torch = _torch()
+    n = SIZES[p]
+    print(f"csr fp32 p={p} n={n}", flush=True)
+    op, A, rowptr, cols, vals = _build(p, n, 0.1, 0.5, 1, mfq.MFQ_FP32)
+    assert vals.dtype == np.float32
+    N = op.n_dofs
+    Ao = assemble.assemble_csr(p, n, 0.1, 0.5)
+    Ao.sort_indices()
+    np.testing.assert_array_equal(rowptr, Ao.indptr)
+    np.testing.assert_array_equal(cols, Ao.indices)
+    G = sp.csr_matrix((vals.astype(np.float64), cols, rowptr), shape=(N, N))
+    Ac = assemble.operator_csr(p, n, 0.1, 0.5, 1)
+    M = _abs_assembled(p, n, 0.1, 0.5, 1)
+    excess = (abs(G - Ac) - 8 * U32 * M).tocsr()   # positive where an entry exceeds its bound
+    assert excess.nnz == 0 or excess.data.max() <= 1e-30
+    m = mesh.boundary_mask(p, n)
+    rows = np.repeat(np.arange(N), np.diff(rowptr))
+    coupled = (m[rows] == 0) | (m[cols] == 0)
+    assert np.all(vals[coupled & (rows != cols)] == 0) and np.all(vals[coupled & (rows == cols)] == 1)
+    x = uniform_vector(N, seed=40 + p)
+    x32 = x.astype(np.float32).astype(np.float64)
+    y = A.spmv(torch.from_numpy(x).float().cuda())
+    torch.cuda.synchronize()
+    yo = Ac @ x32
+    L = int(np.diff(rowptr).max())
+    k = 8 + 1 + -(-L // 8) + 6
+    assert np.all(np.abs(y.double().cpu().numpy() - yo) <= k * U32 * (M @ np.abs(x32)) + 1e-30)
 
 
 def test_full_size_q4_64_sampled():
