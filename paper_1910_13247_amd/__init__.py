@@ -36,6 +36,15 @@ def _dtype(precision):
     return torch.float64 if precision == MFQ_FP64 else torch.float32
 
 
+def _release(obj, destroy):
+    """Destroy obj's library handle once.  At interpreter shutdown the binding module may already
+    be torn down; the process is ending, so the handle is left to it then."""
+    h = getattr(obj, "handle", None)
+    obj.handle = None
+    if h and _lib is not None and getattr(_lib, "_lib", None) is not None:
+        getattr(_lib, destroy)(h)
+
+
 def _check_vec(t, n, precision, name):
     torch = _torch()
     if not t.is_cuda or t.dtype != _dtype(precision) or not t.is_contiguous() or t.numel() != n:
@@ -52,9 +61,7 @@ class Mesh:
         self.handle = _lib.mfq_mesh_create(self.n, self.amplitude)
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.mfq_mesh_destroy(self.handle)
-            self.handle = None
+        _release(self, "mfq_mesh_destroy")
 
 
 class Space:
@@ -83,9 +90,7 @@ class Space:
         return x
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.mfq_space_destroy(self.handle)
-            self.handle = None
+        _release(self, "mfq_space_destroy")
 
 
 class Operator:
@@ -155,9 +160,7 @@ class Operator:
         return x
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.mfq_op_destroy(self.handle)
-            self.handle = None
+        _release(self, "mfq_op_destroy")
 
 
 class SparseMatrix:
@@ -200,10 +203,7 @@ class SparseMatrix:
         return dst
 
     def __del__(self):
-        h = getattr(self, "handle", None)
-        if h:
-            _lib.mfq_csr_destroy(h)
-            self.handle = None
+        _release(self, "mfq_csr_destroy")
 
 
 class Transfer:
@@ -224,9 +224,7 @@ class Transfer:
         return coarse_vec
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.mfq_transfer_destroy(self.handle)
-            self.handle = None
+        _release(self, "mfq_transfer_destroy")
 
 
 def batch_step(solvers, iters=2):
@@ -284,6 +282,4 @@ class Solver:
         return _lib.mfq_solver_lambdas(self.handle, max(n_levels - 1, 0))
 
     def __del__(self):
-        if getattr(self, "handle", None):
-            _lib.mfq_solver_destroy(self.handle)
-            self.handle = None
+        _release(self, "mfq_solver_destroy")
