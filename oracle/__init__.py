@@ -21,7 +21,10 @@ What it computes (section numbers refer to the deal.II paper, arXiv 1910.13247):
 * conjugate gradients and direct solves (``solve.py``);
 * the pieces of the geometric multigrid of Sec. 3.5 / Sec. 6.1: level
   transfer by interpolation between nested meshes, Jacobi diagonal, Chebyshev
-  smoothing, V-cycle (``gmg.py``).
+  smoothing, V-cycle (``gmg.py``);
+* the symmetric interior penalty DG discretisation of the Laplacian used in the
+  paper's multigrid experiment (Sec. 6.1): cell and face matrices, assembly, the
+  action on sampled rows (``dg.py``).
 
 Readings of points the paper leaves open (node family, quadrature rule,
 geometry, Dirichlet treatment, numbering, Chebyshev constants) are fixed in
