@@ -69,6 +69,7 @@ typedef struct mfq_space mfq_space;
 typedef struct mfq_op mfq_op;
 typedef struct mfq_transfer mfq_transfer;
 typedef struct mfq_csr mfq_csr;
+typedef struct mfq_dg mfq_dg;
 typedef struct mfq_solver mfq_solver;
 
 /* Library version string and the message of the last failed call on this thread. */
@@ -179,6 +180,27 @@ int mfq_csr_arrays(const mfq_csr* a, void** rowptr, void** cols, void** vals);
  * accumulated in that precision) that must not overlap.  Asynchronous, no host synchronisation,
  * deterministic (fixed summation order per row). */
 int mfq_csr_spmv(const mfq_csr* a, const void* src, void* dst, void* hip_stream);
+
+/* ---------------------------------------------------------------- discontinuous Galerkin operator (Sec. 6.1)
+ * The symmetric interior penalty DG discretisation of the Laplacian of the paper's multigrid
+ * experiment (Laplace equation, DG of degree p on a hyper-rectangle), applied matrix-free.
+ * Readings (the paper gives none of them): the undeformed n^3 mesh of the unit cube, coefficient
+ * 1; per cell the discontinuous Q_p basis on the GLL nodes, DoF (a,b,c) of cell K = i + n j +
+ * n^2 k at index K (p+1)^3 + a + (p+1) b + (p+1)^2 c; (p+1)-point Gauss rules on cells and
+ * faces;
+ *   a(u,v) = sum_K int_K grad u . grad v + sum_F int_F ( -{d_n u}[v] - {d_n v}[u] + sigma [u][v] )
+ * with [u] = u_L - u_R and {.} the mean across an interior face (n from the lower to the upper
+ * cell), the outside values zero and the inside value for the mean on boundary faces
+ * (homogeneous Dirichlet data imposed weakly), sigma = 2 (p+1)^2 / h.  No device storage: the
+ * affine cells need no stored geometry. */
+/* mesh: amplitude 0 (MFQ_EINVAL otherwise); degree 1..8.  Host only. */
+int mfq_dg_create(const mfq_mesh* mesh, int degree, mfq_dg** out);
+void mfq_dg_destroy(mfq_dg* op);
+int64_t mfq_dg_n_dofs(const mfq_dg* op);  /* n^3 (p+1)^3; -1 for NULL */
+/* dst = A src for double device vectors of n_dofs elements that must not overlap: one launch
+ * for the cell terms (stores every entry) and six for the faces (one per normal direction and
+ * face parity; each adds into the two cells of its faces).  Asynchronous, deterministic. */
+int mfq_dg_vmult(const mfq_dg* op, const double* src, double* dst, void* hip_stream);
 
 /* ---------------------------------------------------------------- transfer (Sec. 3.5, 3.1)
  * Interpolation between nested spaces on the same domain: either the fine mesh halves the

@@ -17,7 +17,7 @@ from ._lib import (MfqError, MFQ_FP64, MFQ_FP32, MFQ_FP32_MFMA, MFQ_BC_NONE, MFQ
 __all__ = ["Mesh", "Space", "Operator", "Transfer", "Solver", "MfqError", "MFQ_FP64", "MFQ_FP32", "MFQ_FP32_MFMA",
            "MFQ_BC_NONE", "MFQ_BC_DIRICHLET0", "MFQ_SOLVER_CG", "MFQ_SOLVER_GMG_FP64",
            "MFQ_SOLVER_GMG_MIXED", "MFQ_SOLVER_GMG_MIXED_IR", "MFQ_OK", "MFQ_EINVAL", "MFQ_ENOMEM",
-           "MFQ_EHIP", "MFQ_ENOCONV", "MFQ_ENONFINITE", "MFQ_EBUSY", "batch_step", "SparseMatrix"]
+           "MFQ_EHIP", "MFQ_ENOCONV", "MFQ_ENONFINITE", "MFQ_EBUSY", "batch_step", "SparseMatrix", "DGOperator"]
 
 
 def _torch():
@@ -161,6 +161,28 @@ class Operator:
 
     def __del__(self):
         _release(self, "mfq_op_destroy")
+
+
+class DGOperator:
+    """Symmetric interior penalty DG Laplacian of degree p on the undeformed n^3 mesh (no device
+    storage); vectors are float64, cell-major."""
+
+    def __init__(self, mesh, degree):
+        self.mesh = mesh
+        self.degree = int(degree)
+        self.handle = _lib.mfq_dg_create(mesh.handle, self.degree)
+        self.n_dofs = _lib.mfq_dg_n_dofs(self.handle)
+
+    def vmult(self, src, dst=None, stream=None):
+        torch = _torch()
+        if dst is None:
+            dst = torch.empty(self.n_dofs, dtype=torch.float64, device=src.device)
+        _lib.mfq_dg_vmult(self.handle, _check_vec(src, self.n_dofs, MFQ_FP64, "src"),
+                          _check_vec(dst, self.n_dofs, MFQ_FP64, "dst"), _stream(stream))
+        return dst
+
+    def __del__(self):
+        _release(self, "mfq_dg_destroy")
 
 
 class SparseMatrix:

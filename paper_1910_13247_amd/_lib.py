@@ -79,6 +79,10 @@ _SIGS = {
     "mfq_csr_bind": ([P, P, SZ, P], I),
     "mfq_csr_arrays": ([P, PP, PP, PP], I),
     "mfq_csr_spmv": ([P, P, P, P], I),
+    "mfq_dg_create": ([P, I, PP], I),
+    "mfq_dg_destroy": ([P], None),
+    "mfq_dg_n_dofs": ([P], I64),
+    "mfq_dg_vmult": ([P, P, P, P], I),
     "mfq_transfer_create": ([P, P, PP], I),
     "mfq_transfer_destroy": ([P], None),
     "mfq_prolongate": ([P, I, P, P, P], I),
@@ -254,6 +258,22 @@ def mfq_csr_arrays(a):
 
 def mfq_csr_spmv(a, src, dst, stream):
     _check(lib().mfq_csr_spmv(a, src, dst, stream))
+
+
+def mfq_dg_create(mesh, degree):
+    return _handle(lib().mfq_dg_create, mesh, degree)
+
+
+def mfq_dg_destroy(op):
+    lib().mfq_dg_destroy(op)
+
+
+def mfq_dg_n_dofs(op):
+    return lib().mfq_dg_n_dofs(op)
+
+
+def mfq_dg_vmult(op, src, dst, stream):
+    _check(lib().mfq_dg_vmult(op, src, dst, stream))
 
 
 def mfq_transfer_create(coarse, fine):

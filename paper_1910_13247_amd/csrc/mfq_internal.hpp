@@ -233,6 +233,9 @@ hipError_t launch_csr_blocks(const int64_t* rowptr, int64_t* blk, int64_t n_rows
 hipError_t launch_csr_spmv(const mfq_csr* a, const void* x, void* y, hipStream_t st);
 int64_t csr_row_start_host(int64_t I, int64_t J, int64_t K, int p, int n);
 
+// DG-SIPG operator (kernels_dg.hip): dst = A src (cell term stored, face terms added)
+hipError_t launch_dg_vmult(int p, int n, const double* src, double* dst, hipStream_t st);
+
 // vector kernels (kernels_vector.hip)
 hipError_t launch_fill(int precision, void* x, int64_t n, double value, hipStream_t st);
 hipError_t launch_mask(int precision, int p, int n, void* x, hipStream_t st);

@@ -166,3 +166,23 @@ def test_csr_size_matches_assembled_pattern(p, n):
     for h, f in ((op32, lib.mfq_op_destroy), (op, lib.mfq_op_destroy), (s, lib.mfq_space_destroy),
                  (m, lib.mfq_mesh_destroy)):
         f(h)
+
+
+def test_dg_host_validation():
+    """DG operator: undeformed meshes only, degree 1..8, n^3 (p+1)^3 DoFs; no device needed."""
+    lib = _lib()
+    m = lib.mfq_mesh_create(3, 0.0)
+    g = lib.mfq_dg_create(m, 4)
+    assert lib.mfq_dg_n_dofs(g) == 27 * 125
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_dg_vmult(g, 256, 256, None)          # src and dst overlap
+    assert e.value.status == lib.MFQ_EINVAL
+    lib.mfq_dg_destroy(g)
+    with pytest.raises(lib.MfqError):
+        lib.mfq_dg_create(m, 9)
+    md = lib.mfq_mesh_create(3, 0.1)
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_dg_create(md, 2)                     # deformed mesh refused
+    assert e.value.status == lib.MFQ_EINVAL
+    lib.mfq_mesh_destroy(md)
+    lib.mfq_mesh_destroy(m)
