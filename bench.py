@@ -6,7 +6,8 @@ curved 64^3-cell mesh (257^3 = 16,974,593 DoFs; deformation amplitude 0.1, coeff
 a = 1 + 0.5 sin sin sin), FP64, with the input resident in HBM.  Prints one JSON line:
 DoFs/s of the step, the roofline of the dominant kernel (the cell loop, timed with HIP events
 on its stream), an FP32 figure of the same operator, the same operator assembled as a sparse
-matrix and applied by the library's CSR product, time to 1e-10 of the Q3 128^3 multigrid and CG
+matrix and applied by the library's CSR product, the DG-SIPG Q4 operator of the paper's
+multigrid experiment, time to 1e-10 of the Q3 128^3 multigrid and CG
 solvers, a 400-request serving stream (solves/s, p50/p99 latency), and the CPU oracle on a
 bounded sample of the same workload.
 
@@ -306,6 +307,28 @@ def small_poisson(steps, warmup):
             "cg_rel_residual": info.rel_residual, "status": st}
 
 
+def dg_benchmark(steps, warmup, degree=4, cells_1d=64):
+    """The symmetric interior penalty DG Laplacian of the paper's multigrid experiment (degree 4,
+    undeformed 64^3 mesh, 32,768,000 DoFs), one matrix-free application: one cell-term launch and
+    six face launches.  Algorithmic bytes: read the source and write the result once (16 B per
+    DoF; the affine cells store no geometry); the face launches re-read both cells of each face
+    and update their results, which the HBM traffic pays on top."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    from synthetic import uniform_vector
+    op = mfq.DGOperator(mfq.Mesh(cells_1d, 0.0), degree)
+    x = torch.from_numpy(uniform_vector(op.n_dofs, seed=0)).cuda()
+    y = torch.empty_like(x)
+    s = time_events(lambda: op.vmult(x, y), steps, warmup)
+    rb = 16 * op.n_dofs
+    out = {"workload": f"dg_sipg_q{degree}_{cells_1d}^3_affine", "dofs": op.n_dofs, "ms": s * 1e3,
+           "DoFs_per_s": op.n_dofs / s, "algorithmic_bytes": rb, "achieved_GBs": rb / s / 1e9,
+           "frac": rb / s / 1e9 / HBM_PEAK_GBS}
+    del op, x, y
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_small_poisson():
     """Oracle side of the small Poisson workload: SciPy CSR product of the assembled matrix on one
     thread, and the oracle's CG to 1e-10 on it."""
@@ -514,6 +537,7 @@ def main():
     if args.csr_sweep:
         rec["csr_sweep"] = csr_sweep(min(args.steps, 20), args.warmup)
     rec["small_poisson"] = small_poisson(min(args.steps, 50), args.warmup)
+    rec["dg_sipg_q4_64"] = dg_benchmark(min(args.steps, 20), args.warmup)
     print("# Q8 24^3: FP64 / FP32 / FP32 matrix cores", file=sys.stderr, flush=True)
     rec["high_degree_q8_24"] = high_degree_comparison(min(args.steps, 20), args.warmup)
     if not args.no_solves:
