@@ -7,12 +7,12 @@ a = 1 + 0.5 sin sin sin), FP64, with the input resident in HBM.  Prints one JSON
 DoFs/s of the step, the roofline of the dominant kernel (the cell loop, timed with HIP events
 on its stream), an FP32 figure of the same operator, the same operator assembled as a sparse
 matrix and applied by the library's CSR product, the DG-SIPG Q4 operator of the paper's
-multigrid experiment, time to 1e-10 of the Q3 128^3 multigrid and CG
+multigrid experiment and its V-cycle and solve, time to 1e-10 of the Q3 128^3 multigrid and CG
 solvers, a 400-request serving stream (solves/s, p50/p99 latency), and the CPU oracle on a
 bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-solves] [--serve N] [--no-csr]
-                    [--csr-sweep] [--vcycle] [--copy-probe]
+                    [--no-dg-mg] [--csr-sweep] [--vcycle] [--copy-probe]
 """
 import argparse
 import json
@@ -389,6 +389,43 @@ def vcycle_benchmark(steps, warmup):
     return out
 
 
+def dg_multigrid_benchmark(steps, warmup, solve_rtol=1e-10):
+    """The paper's multigrid experiment on one GPU: the DG-SIPG Q4 operator on the undeformed n^3
+    mesh, one FP32 V-cycle (Chebyshev degree 6 on the DG level, switch to the continuous Q4 space
+    on the same mesh, its h- and p-hierarchy, dense coarse inverse) timed with HIP events, and on
+    the smaller mesh a full FP64 CG solve to `solve_rtol` from a seeded right-hand side, with the
+    mean residual reduction per iteration."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    from synthetic import uniform_vector
+    out = []
+    for n in VCYCLE_MESHES:
+        print(f"# DG V-cycle Q4 {n}^3", file=sys.stderr, flush=True)
+        op = mfq.DGOperator(mfq.Mesh(n, 0.0), 4)
+        t0 = time.perf_counter()
+        sv = mfq.DGSolver(op)
+        torch.cuda.synchronize()
+        setup = time.perf_counter() - t0
+        r = torch.from_numpy(uniform_vector(op.n_dofs, seed=3)).cuda()
+        z = torch.empty_like(r)
+        sec = time_events(lambda: sv.precondition(r, z), steps, warmup)
+        rec = {"degree": 4, "cells": n ** 3, "dofs": op.n_dofs, "vcycle_ms": sec * 1e3,
+               "DoFs_per_s": op.n_dofs / sec, "setup_s": setup}
+        if n == VCYCLE_MESHES[0]:
+            x, info, st = sv.solve(r, rtol=solve_rtol, max_iter=200)
+            x, info, st = sv.solve(r, rtol=solve_rtol, max_iter=200)     # warm
+            rec.update({"solve_s": info.seconds, "iterations": info.iterations, "passes": info.outer_iterations,
+                        "rel_residual": info.rel_residual, "levels": info.n_levels,
+                        "rate_per_iteration": info.rel_residual ** (1.0 / max(info.iterations, 1)),
+                        "status": int(st)})
+            del x
+        out.append(rec)
+        del sv, op, r, z
+        torch.cuda.synchronize()
+        torch.cuda.empty_cache()
+    return out
+
+
 def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=4, mode="async", setup_threads=1,
                     solver_params=None):
     """The serving stream: Poisson arrivals at `rate`/s, degree U{1..6}, n U{4..48}, alpha
@@ -444,6 +481,8 @@ def main():
     ap.add_argument("--no-csr", action="store_true", help="skip the assembled-matrix (CSR) comparison")
     ap.add_argument("--vcycle", action="store_true",
                     help="add FP32 V-cycle times of the Q4 Laplacian (40^3 and 80^3 cells)")
+    ap.add_argument("--no-dg-mg", action="store_true",
+                    help="skip the DG-SIPG Q4 multigrid (V-cycle at 40^3 and 80^3 cells, solve at 40^3)")
     ap.add_argument("--csr-sweep", action="store_true",
                     help="add the assembled-matrix comparison for degrees 1..8 at about 16M DoFs")
     ap.add_argument("--copy-probe", action="store_true",
@@ -545,6 +584,8 @@ def main():
         rec["solves_q3_128"] = solve_benchmarks(args.steps, [k for k in args.solve_kinds.split(",") if k])
     if args.vcycle:
         rec["vcycle_q4"] = vcycle_benchmark(min(args.steps, 20), args.warmup)
+    if not args.no_dg_mg:
+        rec["dg_multigrid_q4"] = dg_multigrid_benchmark(min(args.steps, 20), args.warmup)
     if args.serve:
         print(f"# serving {args.serve} requests", file=sys.stderr, flush=True)
         prm = {}

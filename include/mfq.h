@@ -71,6 +71,7 @@ typedef struct mfq_transfer mfq_transfer;
 typedef struct mfq_csr mfq_csr;
 typedef struct mfq_dg mfq_dg;
 typedef struct mfq_solver mfq_solver;
+typedef struct mfq_dg_solver mfq_dg_solver;
 
 /* Library version string and the message of the last failed call on this thread. */
 const char* mfq_version(void);
@@ -201,6 +202,23 @@ int64_t mfq_dg_n_dofs(const mfq_dg* op);  /* n^3 (p+1)^3; -1 for NULL */
  * for the cell terms (stores every entry) and six for the faces (one per normal direction and
  * face parity; each adds into the two cells of its faces).  Asynchronous, deterministic. */
 int mfq_dg_vmult(const mfq_dg* op, const double* src, double* dst, void* hip_stream);
+/* The same product in MFQ_FP64 or MFQ_FP32 (vectors and arithmetic of that precision; the FP32
+ * form is the smoother operator of the multigrid below). */
+int mfq_dg_vmult_prec(const mfq_dg* op, int precision, const void* src, void* dst, void* hip_stream);
+/* diag[i] = A_ii of the DG-SIPG matrix (n_dofs device values of `precision`), evaluated in closed
+ * form per cell: the cell term is separable in the three directions and each face adds its
+ * penalty, consistency and symmetry terms of the node's trace.  Overwrites diag. */
+int mfq_dg_diagonal(const mfq_dg* op, int precision, void* diag, void* hip_stream);
+/* Number of nodes (n p + 1)^3 of the continuous Q_p space with Dirichlet nodes on the same mesh
+ * (lattice order, as mfq_space_create with MFQ_BC_DIRICHLET0); -1 for NULL. */
+int64_t mfq_dg_cg_n_dofs(const mfq_dg* op);
+/* Transfer between the continuous space (cg, mfq_dg_cg_n_dofs values) and the DG space (dg,
+ * n_dofs values), the change of space inside the multigrid hierarchy (Sec. 6.1).  to_dg = 1:
+ * dg = E cg, every cell takes the values of its lattice nodes (the continuous function is also a
+ * discontinuous one).  to_dg = 0: cg = E^T dg, each node sums its copies in the cells holding it
+ * in a fixed cell order (deterministic), zero on boundary nodes.  Overwrites out; in and out must
+ * not overlap.  Device vectors of `precision`. */
+int mfq_dg_transfer(const mfq_dg* op, int precision, int to_dg, const void* in, void* out, void* hip_stream);
 
 /* ---------------------------------------------------------------- transfer (Sec. 3.5, 3.1)
  * Interpolation between nested spaces on the same domain: either the fine mesh halves the
@@ -310,6 +328,30 @@ int mfq_solve_end(mfq_solver* s, mfq_solve_info* info);
 int mfq_solver_precondition(mfq_solver* s, const double* r, double* z, void* hip_stream);
 /* Largest-eigenvalue estimates of D^{-1}A per level (finest last); n_out >= n_levels - 1. */
 int mfq_solver_lambdas(const mfq_solver* s, double* out, int n_out);
+
+/* ---------------------------------------------------------------- DG multigrid solver (Sec. 6.1)
+ * FP64 CG on the DG-SIPG operator preconditioned by an FP32 V-cycle whose finest level is the DG
+ * space and whose next level is the continuous Q_p space on the same mesh: Chebyshev smoothing
+ * (smoother_degree, Jacobi with the exact DG diagonal, largest eigenvalue from lanczos_iters
+ * Jacobi-PCG steps on the DG level), the residual moved to the continuous space by
+ * mfq_dg_transfer(to_dg = 0), one V-cycle of a GMG_MIXED solver of the continuous Q_p Laplacian
+ * (Dirichlet nodes, coefficient 1) with the same parameters, the correction moved back by
+ * mfq_dg_transfer(to_dg = 1), post-smoothing.  params NULL: mfq_solver_default_params with
+ * smoother_degree 6, the Chebyshev degree of the paper's experiment.  The DG operator must
+ * outlive the solver. */
+int mfq_dg_solver_create(const mfq_dg* op, const mfq_solver_params* params, mfq_dg_solver** out);
+void mfq_dg_solver_destroy(mfq_dg_solver* s);
+int mfq_dg_solver_device_bytes(const mfq_dg_solver* s, size_t* bytes);
+/* Binds a 256-byte aligned device buffer of at least device_bytes; builds the continuous
+ * hierarchy, the DG diagonal and the eigenvalue bound.  Synchronises the stream. */
+int mfq_dg_solver_bind(mfq_dg_solver* s, void* dev_buf, size_t bytes, void* hip_stream);
+/* z = M r: one V-cycle on the double device vector r (n_dofs).  Asynchronous. */
+int mfq_dg_precondition(mfq_dg_solver* s, const double* r, double* z, void* hip_stream);
+/* Solves A x = b to ||b - A x||_2 <= rtol ||b||_2 from x = 0, with FP64 correction passes on the
+ * residual equation while the FP64 true residual exceeds rtol (as mfq_solve).  Blocks until done;
+ * MFQ_ENOCONV when max_iter is reached (info valid).  info->n_levels counts the DG level. */
+int mfq_dg_solve(mfq_dg_solver* s, const double* b, double* x, double rtol, int max_iter, void* hip_stream,
+                 mfq_solve_info* info);
 
 #ifdef __cplusplus
 }

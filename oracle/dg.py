@@ -22,7 +22,8 @@ both cells' basis functions at the face quadrature points; nothing is sum-factor
 import numpy as np
 import scipy.sparse as sp
 
-from .element import element_matrices
+from .element import element_matrices, reference_tabulation
+from .mesh import boundary_mask, cell_dofs
 from .tables import gauss, gll_nodes, lagrange_derivs, lagrange_values
 
 
@@ -80,16 +81,36 @@ def face_matrix(jump, avg, W, sigma):
     return -JW.T @ avg - AW.T @ jump + sigma * JW.T @ jump
 
 
+def face_magnitude(jump, avg, W, sigma):
+    """Entrywise bound of the terms face_matrix sums: |J|^T W |A| + |A|^T W |J| + sigma |J|^T W |J|."""
+    J, A = np.abs(jump), np.abs(avg)
+    JW = J * W[:, None]
+    return JW.T @ A + (A * W[:, None]).T @ J + sigma * JW.T @ J
+
+
+def cell_magnitude(p, n):
+    """Entrywise bound of the terms of the cell matrix of an affine cube of side h = 1/n:
+    h sum_q w_q sum_d |d_d phi_i(q)| |d_d phi_j(q)| over the reference Gauss points."""
+    _, B = reference_tabulation(p)
+    _, omega = gauss(p + 1)
+    w3 = np.einsum('t,s,r->tsr', omega, omega, omega).reshape(-1)
+    Bd = np.abs(B)
+    return (1.0 / n) * sum(Bd[:, d, :].T @ (w3[:, None] * Bd[:, d, :]) for d in range(3))
+
+
 def _cell(n, i, j, k):
     return i + n * (j + n * k)
 
 
-def assemble(p, n):
-    """The DG-SIPG matrix (scipy CSR, float64)."""
+def assemble(p, n, magnitude=False):
+    """The DG-SIPG matrix (scipy CSR, float64).  magnitude=True: the same assembly with every cell
+    and face matrix replaced by the entrywise bound of its terms (cell_magnitude, face_magnitude),
+    the magnitude that rounding errors of an evaluation in lower precision scale with."""
     N1 = p + 1
     nloc = N1 ** 3
     sig = penalty(p, n)
     tr, dn, W = _face_tables(p, n)
+    fmat = face_magnitude if magnitude else face_matrix
     rows, cols, vals = [], [], []
 
     def add(dofs, M):
@@ -98,16 +119,21 @@ def assemble(p, n):
         vals.append(M.reshape(-1))
 
     C = n ** 3
-    Ak = element_matrices(p, n, 0.0, 0.0, np.arange(C))
-    for K in range(C):
-        add(K * nloc + np.arange(nloc), Ak[K])
+    if magnitude:
+        Am = cell_magnitude(p, n)
+        for K in range(C):
+            add(K * nloc + np.arange(nloc), Am)
+    else:
+        Ak = element_matrices(p, n, 0.0, 0.0, np.arange(C))
+        for K in range(C):
+            add(K * nloc + np.arange(nloc), Ak[K])
     # interior faces: L at its xi_d = 1 end, R at its xi_d = 0 end
-    Mint = [face_matrix(np.hstack([tr[d][1], -tr[d][0]]), 0.5 * np.hstack([dn[d][1], dn[d][0]]), W, sig)
+    Mint = [fmat(np.hstack([tr[d][1], -tr[d][0]]), 0.5 * np.hstack([dn[d][1], dn[d][0]]), W, sig)
             for d in range(3)]
     # boundary faces: only the inside cell; low boundary: inside cell at its xi_d = 0 end, outside
     # on the L side ([u] = -u_R); high boundary: inside at xi_d = 1 ([u] = u_L)
-    Mlo = [face_matrix(-tr[d][0], dn[d][0], W, sig) for d in range(3)]
-    Mhi = [face_matrix(tr[d][1], dn[d][1], W, sig) for d in range(3)]
+    Mlo = [fmat(-tr[d][0], dn[d][0], W, sig) for d in range(3)]
+    Mhi = [fmat(tr[d][1], dn[d][1], W, sig) for d in range(3)]
     for d in range(3):
         for a in range(n):
             for b in range(n):
@@ -209,3 +235,17 @@ def dg_rows(p, n, x, rows):
                 val += Mhi[d][il] @ xs
         out[r] = val
     return out
+
+
+def cg_embedding(p, n):
+    """E [DG DoFs x lattice nodes] (scipy CSR): row K (p+1)^3 + local has a single 1 in the column
+    of the lattice node that local DoF of cell K sits on, and the columns of boundary nodes are
+    zero (the continuous space with Dirichlet nodes carries no value there).  E c is the
+    continuous function c written in the DG basis (the two spaces share the GLL nodes); E^T moves
+    a DG residual to the continuous space.  This is the change of space in the multigrid
+    hierarchy of the paper's DG experiment (Sec. 6.1)."""
+    nloc = (p + 1) ** 3
+    cols = cell_dofs(p, n).reshape(-1)
+    vals = boundary_mask(p, n)[cols]
+    N = n_dofs(p, n)
+    return sp.csr_matrix((vals, (np.arange(N), cols)), shape=(N, (p * n + 1) ** 3))

@@ -17,7 +17,8 @@ from ._lib import (MfqError, MFQ_FP64, MFQ_FP32, MFQ_FP32_MFMA, MFQ_BC_NONE, MFQ
 __all__ = ["Mesh", "Space", "Operator", "Transfer", "Solver", "MfqError", "MFQ_FP64", "MFQ_FP32", "MFQ_FP32_MFMA",
            "MFQ_BC_NONE", "MFQ_BC_DIRICHLET0", "MFQ_SOLVER_CG", "MFQ_SOLVER_GMG_FP64",
            "MFQ_SOLVER_GMG_MIXED", "MFQ_SOLVER_GMG_MIXED_IR", "MFQ_OK", "MFQ_EINVAL", "MFQ_ENOMEM",
-           "MFQ_EHIP", "MFQ_ENOCONV", "MFQ_ENONFINITE", "MFQ_EBUSY", "batch_step", "SparseMatrix", "DGOperator"]
+           "MFQ_EHIP", "MFQ_ENOCONV", "MFQ_ENONFINITE", "MFQ_EBUSY", "batch_step", "SparseMatrix", "DGOperator",
+           "DGSolver"]
 
 
 def _torch():
@@ -173,16 +174,88 @@ class DGOperator:
         self.handle = _lib.mfq_dg_create(mesh.handle, self.degree)
         self.n_dofs = _lib.mfq_dg_n_dofs(self.handle)
 
+        self.cg_n_dofs = _lib.mfq_dg_cg_n_dofs(self.handle)
+
     def vmult(self, src, dst=None, stream=None):
+        """dst = A src; float64 vectors use mfq_dg_vmult, float32 ones the FP32 product."""
         torch = _torch()
         if dst is None:
-            dst = torch.empty(self.n_dofs, dtype=torch.float64, device=src.device)
-        _lib.mfq_dg_vmult(self.handle, _check_vec(src, self.n_dofs, MFQ_FP64, "src"),
-                          _check_vec(dst, self.n_dofs, MFQ_FP64, "dst"), _stream(stream))
+            dst = torch.empty(self.n_dofs, dtype=src.dtype, device=src.device)
+        if src.dtype == torch.float64:
+            _lib.mfq_dg_vmult(self.handle, _check_vec(src, self.n_dofs, MFQ_FP64, "src"),
+                              _check_vec(dst, self.n_dofs, MFQ_FP64, "dst"), _stream(stream))
+        else:
+            _lib.mfq_dg_vmult_prec(self.handle, MFQ_FP32, _check_vec(src, self.n_dofs, MFQ_FP32, "src"),
+                                   _check_vec(dst, self.n_dofs, MFQ_FP32, "dst"), _stream(stream))
         return dst
+
+    def diagonal(self, precision=MFQ_FP64, device="cuda", stream=None):
+        torch = _torch()
+        d = torch.empty(self.n_dofs, dtype=_dtype(precision), device=device)
+        _lib.mfq_dg_diagonal(self.handle, int(precision), _check_vec(d, self.n_dofs, precision, "diag"),
+                             _stream(stream))
+        return d
+
+    def from_cg(self, cg, stream=None):
+        """DG vector of the continuous lattice vector cg (every cell takes its nodes' values)."""
+        torch = _torch()
+        prec = MFQ_FP64 if cg.dtype == torch.float64 else MFQ_FP32
+        out = torch.empty(self.n_dofs, dtype=cg.dtype, device=cg.device)
+        _lib.mfq_dg_transfer(self.handle, prec, 1, _check_vec(cg, self.cg_n_dofs, prec, "cg"),
+                             _check_vec(out, self.n_dofs, prec, "out"), _stream(stream))
+        return out
+
+    def to_cg(self, dg, stream=None):
+        """Transpose of from_cg: each lattice node sums its cell copies; zero on the boundary."""
+        torch = _torch()
+        prec = MFQ_FP64 if dg.dtype == torch.float64 else MFQ_FP32
+        out = torch.empty(self.cg_n_dofs, dtype=dg.dtype, device=dg.device)
+        _lib.mfq_dg_transfer(self.handle, prec, 0, _check_vec(dg, self.n_dofs, prec, "dg"),
+                             _check_vec(out, self.cg_n_dofs, prec, "out"), _stream(stream))
+        return out
 
     def __del__(self):
         _release(self, "mfq_dg_destroy")
+
+
+class DGSolver:
+    """FP64 CG on a DGOperator preconditioned by the FP32 V-cycle DG -> continuous Q_p -> the
+    continuous hierarchy (see mfq_dg_solver_create)."""
+
+    def __init__(self, dg, stream=None, device="cuda", **params):
+        torch = _torch()
+        self.op = dg
+        prm = _lib.mfq_solver_default_params()
+        params.setdefault("smoother_degree", 6)     # the Chebyshev degree of the paper's DG runs
+        for k, v in params.items():
+            setattr(prm, k, v)
+        self.params = prm
+        self.handle = _lib.mfq_dg_solver_create(dg.handle, prm)
+        self.device_bytes = _lib.mfq_dg_solver_device_bytes(self.handle)
+        self.buffer = torch.empty(max(self.device_bytes, 256), dtype=torch.uint8, device=device)
+        _lib.mfq_dg_solver_bind(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream(stream))
+
+    def new_vector(self):
+        torch = _torch()
+        return torch.zeros(self.op.n_dofs, dtype=torch.float64, device=self.buffer.device)
+
+    def solve(self, b, x=None, rtol=1e-10, max_iter=1000, stream=None, check=True):
+        if x is None:
+            x = self.new_vector()
+        st, info = _lib.mfq_dg_solve(self.handle, _check_vec(b, self.op.n_dofs, MFQ_FP64, "b"),
+                                     _check_vec(x, self.op.n_dofs, MFQ_FP64, "x"), rtol, max_iter,
+                                     _stream(stream), check=check)
+        return x, info, st
+
+    def precondition(self, r, z=None, stream=None):
+        if z is None:
+            z = self.new_vector()
+        _lib.mfq_dg_precondition(self.handle, _check_vec(r, self.op.n_dofs, MFQ_FP64, "r"),
+                                 _check_vec(z, self.op.n_dofs, MFQ_FP64, "z"), _stream(stream))
+        return z
+
+    def __del__(self):
+        _release(self, "mfq_dg_solver_destroy")
 
 
 class SparseMatrix:

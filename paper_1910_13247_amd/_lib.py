@@ -83,6 +83,16 @@ _SIGS = {
     "mfq_dg_destroy": ([P], None),
     "mfq_dg_n_dofs": ([P], I64),
     "mfq_dg_vmult": ([P, P, P, P], I),
+    "mfq_dg_vmult_prec": ([P, I, P, P, P], I),
+    "mfq_dg_diagonal": ([P, I, P, P], I),
+    "mfq_dg_cg_n_dofs": ([P], I64),
+    "mfq_dg_transfer": ([P, I, I, P, P, P], I),
+    "mfq_dg_solver_create": ([P, C.POINTER(SolverParams), PP], I),
+    "mfq_dg_solver_destroy": ([P], None),
+    "mfq_dg_solver_device_bytes": ([P, C.POINTER(SZ)], I),
+    "mfq_dg_solver_bind": ([P, P, SZ, P], I),
+    "mfq_dg_precondition": ([P, P, P, P], I),
+    "mfq_dg_solve": ([P, P, P, D, I, P, C.POINTER(SolveInfo)], I),
     "mfq_transfer_create": ([P, P, PP], I),
     "mfq_transfer_destroy": ([P], None),
     "mfq_prolongate": ([P, I, P, P, P], I),
@@ -274,6 +284,53 @@ def mfq_dg_n_dofs(op):
 
 def mfq_dg_vmult(op, src, dst, stream):
     _check(lib().mfq_dg_vmult(op, src, dst, stream))
+
+
+def mfq_dg_vmult_prec(op, precision, src, dst, stream):
+    _check(lib().mfq_dg_vmult_prec(op, precision, src, dst, stream))
+
+
+def mfq_dg_diagonal(op, precision, diag, stream):
+    _check(lib().mfq_dg_diagonal(op, precision, diag, stream))
+
+
+def mfq_dg_cg_n_dofs(op):
+    return lib().mfq_dg_cg_n_dofs(op)
+
+
+def mfq_dg_transfer(op, precision, to_dg, src, dst, stream):
+    _check(lib().mfq_dg_transfer(op, precision, int(bool(to_dg)), src, dst, stream))
+
+
+def mfq_dg_solver_create(op, params=None):
+    return _handle(lib().mfq_dg_solver_create, op, C.byref(params) if params is not None else None)
+
+
+def mfq_dg_solver_destroy(s):
+    lib().mfq_dg_solver_destroy(s)
+
+
+def mfq_dg_solver_device_bytes(s):
+    n = SZ()
+    _check(lib().mfq_dg_solver_device_bytes(s, C.byref(n)))
+    return n.value
+
+
+def mfq_dg_solver_bind(s, dev_buf, nbytes, stream):
+    _check(lib().mfq_dg_solver_bind(s, dev_buf, nbytes, stream))
+
+
+def mfq_dg_precondition(s, r, z, stream):
+    _check(lib().mfq_dg_precondition(s, r, z, stream))
+
+
+def mfq_dg_solve(s, b, x, rtol, max_iter, stream, check=True):
+    """Returns (status, SolveInfo).  With check=True a status other than MFQ_OK raises."""
+    info = SolveInfo()
+    st = lib().mfq_dg_solve(s, b, x, rtol, max_iter, stream, C.byref(info))
+    if check:
+        _check(st)
+    return st, info
 
 
 def mfq_transfer_create(coarse, fine):

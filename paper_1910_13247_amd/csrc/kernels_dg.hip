@@ -24,34 +24,34 @@
 namespace mfq {
 namespace {
 
-template <int P>
+template <int P, typename Real>
 struct DgTables {
-  double S[(P + 1) * (P + 1)];  // [q*(P+1)+a]: l_a(zeta_q)
-  double D[(P + 1) * (P + 1)];  // l_a'(zeta_q)
-  double w[P + 1];              // Gauss weights on [0,1]
-  double d0[P + 1];             // l_a'(0)
-  double d1[P + 1];             // l_a'(1)
+  Real S[(P + 1) * (P + 1)];  // [q*(P+1)+a]: l_a(zeta_q)
+  Real D[(P + 1) * (P + 1)];  // l_a'(zeta_q)
+  Real w[P + 1];              // Gauss weights on [0,1]
+  Real d0[P + 1];             // l_a'(0)
+  Real d1[P + 1];             // l_a'(1)
 };
 
-template <int P>
-DgTables<P> make_dg_tables() {
-  DgTables<P> t{};
+template <int P, typename Real>
+DgTables<P, Real> make_dg_tables() {
+  DgTables<P, Real> t{};
   const Tables1D& tb = tables(P);
   for (int k = 0; k < (P + 1) * (P + 1); ++k) {
-    t.S[k] = tb.S[k];
-    t.D[k] = tb.D[k];
+    t.S[k] = (Real)tb.S[k];
+    t.D[k] = (Real)tb.D[k];
   }
   for (int a = 0; a <= P; ++a) {
-    t.w[a] = tb.omega[a];
-    t.d0[a] = lagrange_derivative(tb.xi, a, 0.0);
-    t.d1[a] = lagrange_derivative(tb.xi, a, 1.0);
+    t.w[a] = (Real)tb.omega[a];
+    t.d0[a] = (Real)lagrange_derivative(tb.xi, a, 0.0);
+    t.d1[a] = (Real)lagrange_derivative(tb.xi, a, 1.0);
   }
   return t;
 }
 
-template <int P>
+template <int P, typename Real>
 struct DgWeights {
-  double w[P + 1];  // Gauss weights on [0,1]
+  Real w[P + 1];  // Gauss weights on [0,1]
 };
 
 template <int P>
@@ -63,27 +63,27 @@ struct DgCell {
   static constexpr int THREADS = CPW * T;
 };
 
-template <int P>
-__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const double* __restrict__ src,
-                                                                     double* __restrict__ dst, int64_t n_cells,
-                                                                     double h, ShapeEO<P, double> sh,
-                                                                     DgWeights<P> tb) {
+template <int P, typename Real>
+__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const Real* __restrict__ src,
+                                                                     Real* __restrict__ dst, int64_t n_cells,
+                                                                     Real h, ShapeEO<P, Real> sh,
+                                                                     DgWeights<P, Real> tb) {
   using C = DgCell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, CPW = C::CPW;
-  __shared__ double lds[3 * CPW * NQ];
+  __shared__ Real lds[3 * CPW * NQ];
   const int tid = threadIdx.x;
   const int lc = tid / T, e = tid - lc * T;
   const int e0 = e % N1, e1 = e / N1;
   const int64_t cell = (int64_t)blockIdx.x * CPW + lc;
   const bool live = cell < n_cells;
   const int64_t base = (live ? cell : 0) * NQ;
-  double* L0 = lds + lc * NQ;
-  double* L1 = L0 + CPW * NQ;
-  double* L2 = L1 + CPW * NQ;
+  Real* L0 = lds + lc * NQ;
+  Real* L1 = L0 + CPW * NQ;
+  Real* L2 = L1 + CPW * NQ;
   {  // x: values and x-derivatives at (q, e0, e1)
-    double u[N1], A[N1], B[N1];
+    Real u[N1], A[N1], B[N1];
 #pragma unroll
-    for (int a = 0; a < N1; ++a) u[a] = live ? src[base + a + N1 * e] : 0.0;
+    for (int a = 0; a < N1; ++a) u[a] = live ? src[base + a + N1 * e] : (Real)0;
     eo_apply<N1, 1, false>(sh.S, u, A);
     eo_apply<N1, -1, false>(sh.D, u, B);
 #pragma unroll
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const doubl
   }
   __syncthreads();
   {  // y: lane (r = e0, c = e1)
-    double a1[N1], b1[N1], A2[N1], B2[N1], C2[N1];
+    Real a1[N1], b1[N1], A2[N1], B2[N1], C2[N1];
 #pragma unroll
     for (int b = 0; b < N1; ++b) {
       a1[b] = L0[e0 + N1 * b + T * e1];
@@ -113,7 +113,7 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const doubl
   }
   __syncthreads();
   {  // z: lane (r = e0, s = e1): gradient, weight, transposed z contraction
-    double a2[N1], b2[N1], c2[N1], gx[N1], gy[N1], gz[N1];
+    Real a2[N1], b2[N1], c2[N1], gx[N1], gy[N1], gz[N1];
 #pragma unroll
     for (int c = 0; c < N1; ++c) {
       a2[c] = L0[e + T * c];
@@ -123,21 +123,21 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const doubl
     eo_apply<N1, 1, false>(sh.S, b2, gx);
     eo_apply<N1, 1, false>(sh.S, c2, gy);
     eo_apply<N1, -1, false>(sh.D, a2, gz);
-    double w0 = 0, w1 = 0;  // weights of this lane's (r, s), selected with compile-time indices
+    Real w0 = 0, w1 = 0;  // weights of this lane's (r, s), selected with compile-time indices
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
       w0 = e0 == k ? tb.w[k] : w0;
       w1 = e1 == k ? tb.w[k] : w1;
     }
-    const double wrs = h * w0 * w1;
+    const Real wrs = h * w0 * w1;
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
-      const double w = wrs * tb.w[t];
+      const Real w = wrs * tb.w[t];
       gx[t] *= w;
       gy[t] *= w;
       gz[t] *= w;
     }
-    double Az[N1], Bz[N1], Cz[N1];
+    Real Az[N1], Bz[N1], Cz[N1];
     eo_apply<N1, -1, true>(sh.D, gz, Az);
     eo_apply<N1, 1, true>(sh.S, gx, Bz);
     eo_apply<N1, 1, true>(sh.S, gy, Cz);
@@ -151,7 +151,7 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const doubl
   }
   __syncthreads();
   {  // transposed y: lane (r = e0, c = e1)
-    double az[N1], bz[N1], cz[N1], Ap[N1], Bp[N1];
+    Real az[N1], bz[N1], cz[N1], Ap[N1], Bp[N1];
 #pragma unroll
     for (int s = 0; s < N1; ++s) {
       az[s] = L0[e0 + N1 * s + T * e1];
@@ -169,7 +169,7 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const doubl
   }
   __syncthreads();
   {  // transposed x: lane (b = e0, c = e1) writes its x-pencil of the cell result
-    double ap[N1], bp[N1], y[N1];
+    Real ap[N1], bp[N1], y[N1];
 #pragma unroll
     for (int r = 0; r < N1; ++r) {
       ap[r] = L0[r + N1 * e];
@@ -188,14 +188,14 @@ __device__ __forceinline__ int face_local(int d, int ad, int a1, int a2) {
   return d == 0 ? ad + N1 * a1 + N1 * N1 * a2 : d == 1 ? a1 + N1 * ad + N1 * N1 * a2 : a1 + N1 * a2 + N1 * N1 * ad;
 }
 
-template <int P>
-__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_face_kernel(const double* __restrict__ src,
-                                                                     double* __restrict__ dst, int n, int d, int parity,
-                                                                     int64_t n_faces, double h, double sigma,
-                                                                     DgTables<P> tb) {
+template <int P, typename Real>
+__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_face_kernel(const Real* __restrict__ src,
+                                                                     Real* __restrict__ dst, int n, int d, int parity,
+                                                                     int64_t n_faces, Real h, Real sigma,
+                                                                     DgTables<P, Real> tb) {
   using C = DgCell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, FPW = C::CPW;
-  __shared__ double lds[4 * FPW * T];
+  __shared__ Real lds[4 * FPW * T];
   const int tid = threadIdx.x;
   const int lf = tid / T, e = tid - lf * T;
   const int e0 = e % N1, e1 = e / N1;
@@ -218,14 +218,14 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_face_kernel(const doubl
     if (f > 0) cL = ijk[0] + n * (ijk[1] + (int64_t)n * ijk[2]);
   }
   const bool hasL = live && cL >= 0, hasR = live && cR >= 0;
-  const double ih = 1.0 / h;
-  double uL[N1], uR[N1];
+  const Real ih = (Real)1 / h;
+  Real uL[N1], uR[N1];
 #pragma unroll
   for (int a = 0; a < N1; ++a) {
-    uL[a] = hasL ? src[cL * NQ + face_local<N1>(d, a, e0, e1)] : 0.0;
-    uR[a] = hasR ? src[cR * NQ + face_local<N1>(d, a, e0, e1)] : 0.0;
+    uL[a] = hasL ? src[cL * NQ + face_local<N1>(d, a, e0, e1)] : (Real)0;
+    uR[a] = hasR ? src[cR * NQ + face_local<N1>(d, a, e0, e1)] : (Real)0;
   }
-  double dnL = 0, dnR = 0;
+  Real dnL = 0, dnR = 0;
 #pragma unroll
   for (int a = 0; a < N1; ++a) {
     dnL = fmad(tb.d1[a], uL[a], dnL);
@@ -234,19 +234,19 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_face_kernel(const doubl
   dnL *= ih;
   dnR *= ih;
   const bool interior = hasL && hasR;
-  const double jump = uL[N1 - 1] - uR[0];
-  const double mean = interior ? 0.5 * (dnL + dnR) : dnL + dnR;  // one of them is zero on a boundary face
-  const double dfac = interior ? 0.5 : 1.0;
-  double* F0 = lds + lf * T;
-  double* F1 = F0 + FPW * T;
-  double* G0 = F1 + FPW * T;
-  double* G1 = G0 + FPW * T;
+  const Real jump = uL[N1 - 1] - uR[0];
+  const Real mean = interior ? (Real)0.5 * (dnL + dnR) : dnL + dnR;  // one of them is zero on a boundary face
+  const Real dfac = interior ? (Real)0.5 : (Real)1;
+  Real* F0 = lds + lf * T;
+  Real* F1 = F0 + FPW * T;
+  Real* G0 = F1 + FPW * T;
+  Real* G1 = G0 + FPW * T;
   // nodes -> Gauss points, first tangential direction: lane (q1 = e0, a2 = e1)
   F0[e] = jump;
   F1[e] = mean;
   __syncthreads();
   {
-    double sj = 0, sm = 0;
+    Real sj = 0, sm = 0;
 #pragma unroll
     for (int a1 = 0; a1 < N1; ++a1) {
       sj = fmad(tb.S[e0 * N1 + a1], F0[a1 + N1 * e1], sj);
@@ -257,28 +257,28 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_face_kernel(const doubl
   }
   __syncthreads();
   // second tangential direction: lane (q1 = e0, q2 = e1) at its Gauss point
-  double jq = 0, mq = 0;
+  Real jq = 0, mq = 0;
 #pragma unroll
   for (int a2 = 0; a2 < N1; ++a2) {
     jq = fmad(tb.S[e1 * N1 + a2], G0[e0 + N1 * a2], jq);
     mq = fmad(tb.S[e1 * N1 + a2], G1[e0 + N1 * a2], mq);
   }
-  double w0 = 0, w1 = 0;
+  Real w0 = 0, w1 = 0;
 #pragma unroll
   for (int k = 0; k < N1; ++k) {
     w0 = e0 == k ? tb.w[k] : w0;
     w1 = e1 == k ? tb.w[k] : w1;
   }
-  const double W = h * h * w0 * w1;
-  const double cval = W * (sigma * jq - mq);
-  const double cder = -dfac * W * jq;
+  const Real W = h * h * w0 * w1;
+  const Real cval = W * (sigma * jq - mq);
+  const Real cder = -dfac * W * jq;
   __syncthreads();
   // Gauss points -> nodes (transposed), second direction first: lane (q1 = e0, a2 = e1)
   F0[e] = cval;
   F1[e] = cder;
   __syncthreads();
   {
-    double sv = 0, sd = 0;
+    Real sv = 0, sd = 0;
 #pragma unroll
     for (int q2 = 0; q2 < N1; ++q2) {
       sv = fmad(tb.S[q2 * N1 + e1], F0[e0 + N1 * q2], sv);
@@ -289,7 +289,7 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_face_kernel(const doubl
   }
   __syncthreads();
   // first direction: lane (a1 = e0, a2 = e1) gets its face node's coefficients
-  double V = 0, Dd = 0;
+  Real V = 0, Dd = 0;
 #pragma unroll
   for (int q1 = 0; q1 < N1; ++q1) {
     V = fmad(tb.S[q1 * N1 + e0], G0[q1 + N1 * e1], V);
@@ -300,30 +300,30 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_face_kernel(const doubl
   if (hasL)
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
-      double* p = dst + cL * NQ + face_local<N1>(d, a, e0, e1);
-      *p += (a == N1 - 1 ? V : 0.0) + Dd * tb.d1[a];
+      Real* p = dst + cL * NQ + face_local<N1>(d, a, e0, e1);
+      *p += (a == N1 - 1 ? V : (Real)0) + Dd * tb.d1[a];
     }
   if (hasR)
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
-      double* p = dst + cR * NQ + face_local<N1>(d, a, e0, e1);
-      *p += (a == 0 ? -V : 0.0) + Dd * tb.d0[a];
+      Real* p = dst + cR * NQ + face_local<N1>(d, a, e0, e1);
+      *p += (a == 0 ? -V : (Real)0) + Dd * tb.d0[a];
     }
 }
 
-template <int P>
-hipError_t dg_vmult_p(int n, const double* src, double* dst, hipStream_t st) {
+template <int P, typename Real>
+hipError_t dg_vmult_pr(int n, const Real* src, Real* dst, hipStream_t st) {
   using C = DgCell<P>;
-  static const DgTables<P> tb = make_dg_tables<P>();
-  static const ShapeEO<P, double> sh = make_shape_eo<P, double>();
-  DgWeights<P> wt;
+  static const DgTables<P, Real> tb = make_dg_tables<P, Real>();
+  static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
+  DgWeights<P, Real> wt;
   for (int a = 0; a <= P; ++a) wt.w[a] = tb.w[a];
-  const double h = 1.0 / n;
-  const double sigma = 2.0 * (P + 1) * (P + 1) / h;
+  const Real h = (Real)(1.0 / n);
+  const Real sigma = (Real)(2.0 * (P + 1) * (P + 1) * n);
   const int64_t cells = (int64_t)n * n * n;
   const int64_t g = (cells + C::CPW - 1) / C::CPW;
   if (g > 0x7fffffff) return hipErrorInvalidValue;
-  dg_cell_kernel<P><<<(unsigned)g, C::THREADS, 0, st>>>(src, dst, cells, h, sh, wt);
+  dg_cell_kernel<P, Real><<<(unsigned)g, C::THREADS, 0, st>>>(src, dst, cells, h, sh, wt);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   for (int d = 0; d < 3; ++d)
@@ -331,27 +331,170 @@ hipError_t dg_vmult_p(int n, const double* src, double* dst, hipStream_t st) {
       if (parity > n) continue;
       const int64_t nf = (int64_t)((n - parity) / 2 + 1) * n * n;
       const int64_t gf = (nf + C::CPW - 1) / C::CPW;
-      dg_face_kernel<P><<<(unsigned)gf, C::THREADS, 0, st>>>(src, dst, n, d, parity, nf, h, sigma, tb);
+      dg_face_kernel<P, Real><<<(unsigned)gf, C::THREADS, 0, st>>>(src, dst, n, d, parity, nf, h, sigma, tb);
       e = hipGetLastError();
       if (e != hipSuccess) return e;
     }
   return hipSuccess;
 }
 
+template <int P>
+hipError_t dg_vmult_p(int n, int precision, const void* src, void* dst, hipStream_t st) {
+  if (precision == MFQ_FP64) return dg_vmult_pr<P, double>(n, (const double*)src, (double*)dst, st);
+  return dg_vmult_pr<P, float>(n, (const float*)src, (float*)dst, st);
+}
+
+// Jacobi diagonal of the DG-SIPG matrix in closed form.  With m_a = sum_q w_q S_qa^2 and
+// k_a = sum_q w_q D_qa^2 (1D Gauss sums), the cell part of DoF (a,b,c) is
+// h (k_a m_b m_c + m_a k_b m_c + m_a m_b k_c); a face of normal d adds, at the cell's face-layer
+// nodes only (the trace of every other basis function vanishes on the GLL end points),
+// h^2 m_a1 m_a2 (sigma + c l'_end(end) / h) with c = -1 for the upper face and +1 for the lower one
+// of an interior face (the mean halves the two cross terms), doubled on boundary faces.
+struct DgDiag1D {
+  double m[kMaxDegree + 1];
+  double k[kMaxDegree + 1];
+  double dp1;  // l_p'(1)
+  double d00;  // l_0'(0)
+};
+
+template <typename Real>
+__global__ __launch_bounds__(256) void dg_diag_kernel(Real* __restrict__ diag, int p, int n, DgDiag1D t) {
+  const int N1 = p + 1;
+  const int64_t nloc = (int64_t)N1 * N1 * N1;
+  const int64_t N = (int64_t)n * n * n * nloc;
+  const double h = 1.0 / n, sigma = 2.0 * N1 * N1 * n;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < N; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t K = g / nloc;
+    const int i = (int)(g - K * nloc);
+    const int ai[3] = {i % N1, (i / N1) % N1, i / (N1 * N1)};
+    const int64_t ck[3] = {K % n, (K / n) % n, K / ((int64_t)n * n)};
+    double v = h * (t.k[ai[0]] * t.m[ai[1]] * t.m[ai[2]] + t.m[ai[0]] * t.k[ai[1]] * t.m[ai[2]] +
+                    t.m[ai[0]] * t.m[ai[1]] * t.k[ai[2]]);
+    for (int d = 0; d < 3; ++d) {
+      const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+      const double mm = h * h * t.m[ai[t1]] * t.m[ai[t2]];
+      if (ai[d] == 0) v += mm * (sigma + (ck[d] == 0 ? 2.0 : 1.0) * t.d00 / h);
+      if (ai[d] == p) v += mm * (sigma - (ck[d] == n - 1 ? 2.0 : 1.0) * t.dp1 / h);
+    }
+    diag[g] = (Real)v;
+  }
+}
+
+// Continuous Q_p (lattice of (pn+1)^3 nodes, Dirichlet nodes zero) <-> DG on the same mesh and
+// nodes.  Prolongation copies each lattice node into every cell that holds it; restriction (its
+// transpose) sums, per free lattice node, the entries of the cells that hold it in a fixed order.
+template <typename Real>
+__global__ __launch_bounds__(256) void dg_from_cg_kernel(const Real* __restrict__ cg, Real* __restrict__ dg, int p,
+                                                         int n) {
+  const int N1 = p + 1;
+  const int64_t nloc = (int64_t)N1 * N1 * N1, L1 = (int64_t)p * n + 1;
+  const int64_t N = (int64_t)n * n * n * nloc;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < N; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t K = g / nloc;
+    const int i = (int)(g - K * nloc);
+    const int64_t I = p * (K % n) + i % N1, J = p * ((K / n) % n) + (i / N1) % N1,
+                  Kz = p * (K / ((int64_t)n * n)) + i / (N1 * N1);
+    dg[g] = cg[I + L1 * (J + L1 * Kz)];
+  }
+}
+
+template <typename Real>
+__global__ __launch_bounds__(256) void cg_from_dg_kernel(const Real* __restrict__ dg, Real* __restrict__ cg, int p,
+                                                         int n) {
+  const int N1 = p + 1;
+  const int64_t nloc = (int64_t)N1 * N1 * N1, L1 = (int64_t)p * n + 1, pn = L1 - 1;
+  const int64_t M = L1 * L1 * L1;
+  for (int64_t g = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; g < M; g += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t X[3] = {g % L1, (g / L1) % L1, g / (L1 * L1)};
+    if (X[0] == 0 || X[0] == pn || X[1] == 0 || X[1] == pn || X[2] == 0 || X[2] == pn) {
+      cg[g] = (Real)0;
+      continue;
+    }
+    // per direction the cells holding the node: one, or two when it is a cell vertex
+    int64_t c0[3], c1[3];
+    int cnt[3];
+    for (int d = 0; d < 3; ++d) {
+      const int64_t c = X[d] / p;
+      if (X[d] % p == 0) {
+        c0[d] = c - 1;
+        c1[d] = c;
+        cnt[d] = 2;
+      } else {
+        c0[d] = c;
+        cnt[d] = 1;
+      }
+    }
+    Real s = 0;
+    for (int kz = 0; kz < cnt[2]; ++kz)
+      for (int ky = 0; ky < cnt[1]; ++ky)
+        for (int kx = 0; kx < cnt[0]; ++kx) {
+          const int64_t ci = kx ? c1[0] : c0[0], cj = ky ? c1[1] : c0[1], ck = kz ? c1[2] : c0[2];
+          const int64_t K = ci + n * (cj + (int64_t)n * ck);
+          const int li = (int)(X[0] - p * ci) + N1 * ((int)(X[1] - p * cj) + N1 * (int)(X[2] - p * ck));
+          s += dg[K * nloc + li];
+        }
+    cg[g] = s;
+  }
+}
+
+int dg_grid(int64_t work) {
+  int64_t g = (work + 255) / 256;
+  return (int)(g > 65536 ? 65536 : g < 1 ? 1 : g);
+}
+
 }  // namespace
 
-hipError_t launch_dg_vmult(int p, int n, const double* src, double* dst, hipStream_t st) {
+hipError_t launch_dg_vmult(int p, int n, int precision, const void* src, void* dst, hipStream_t st) {
   switch (p) {
-    case 1: return dg_vmult_p<1>(n, src, dst, st);
-    case 2: return dg_vmult_p<2>(n, src, dst, st);
-    case 3: return dg_vmult_p<3>(n, src, dst, st);
-    case 4: return dg_vmult_p<4>(n, src, dst, st);
-    case 5: return dg_vmult_p<5>(n, src, dst, st);
-    case 6: return dg_vmult_p<6>(n, src, dst, st);
-    case 7: return dg_vmult_p<7>(n, src, dst, st);
-    case 8: return dg_vmult_p<8>(n, src, dst, st);
+    case 1: return dg_vmult_p<1>(n, precision, src, dst, st);
+    case 2: return dg_vmult_p<2>(n, precision, src, dst, st);
+    case 3: return dg_vmult_p<3>(n, precision, src, dst, st);
+    case 4: return dg_vmult_p<4>(n, precision, src, dst, st);
+    case 5: return dg_vmult_p<5>(n, precision, src, dst, st);
+    case 6: return dg_vmult_p<6>(n, precision, src, dst, st);
+    case 7: return dg_vmult_p<7>(n, precision, src, dst, st);
+    case 8: return dg_vmult_p<8>(n, precision, src, dst, st);
     default: return hipErrorInvalidValue;
   }
+}
+
+hipError_t launch_dg_diagonal(int p, int n, int precision, void* diag, hipStream_t st) {
+  const Tables1D& tb = tables(p);
+  DgDiag1D t{};
+  for (int a = 0; a <= p; ++a) {
+    double m = 0, k = 0;
+    for (int q = 0; q <= p; ++q) {
+      m += tb.omega[q] * tb.S[q * (p + 1) + a] * tb.S[q * (p + 1) + a];
+      k += tb.omega[q] * tb.D[q * (p + 1) + a] * tb.D[q * (p + 1) + a];
+    }
+    t.m[a] = m;
+    t.k[a] = k;
+  }
+  t.dp1 = lagrange_derivative(tb.xi, p, 1.0);
+  t.d00 = lagrange_derivative(tb.xi, 0, 0.0);
+  const int64_t N = (int64_t)n * n * n * (p + 1) * (p + 1) * (p + 1);
+  if (precision == MFQ_FP64)
+    dg_diag_kernel<double><<<dg_grid(N), 256, 0, st>>>((double*)diag, p, n, t);
+  else
+    dg_diag_kernel<float><<<dg_grid(N), 256, 0, st>>>((float*)diag, p, n, t);
+  return hipGetLastError();
+}
+
+hipError_t launch_dg_transfer(int p, int n, int precision, bool to_dg, const void* in, void* out, hipStream_t st) {
+  const int64_t N = (int64_t)n * n * n * (p + 1) * (p + 1) * (p + 1);
+  const int64_t L1 = (int64_t)p * n + 1;
+  if (to_dg) {
+    if (precision == MFQ_FP64)
+      dg_from_cg_kernel<double><<<dg_grid(N), 256, 0, st>>>((const double*)in, (double*)out, p, n);
+    else
+      dg_from_cg_kernel<float><<<dg_grid(N), 256, 0, st>>>((const float*)in, (float*)out, p, n);
+  } else {
+    if (precision == MFQ_FP64)
+      cg_from_dg_kernel<double><<<dg_grid(L1 * L1 * L1), 256, 0, st>>>((const double*)in, (double*)out, p, n);
+    else
+      cg_from_dg_kernel<float><<<dg_grid(L1 * L1 * L1), 256, 0, st>>>((const float*)in, (float*)out, p, n);
+  }
+  return hipGetLastError();
 }
 
 }  // namespace mfq

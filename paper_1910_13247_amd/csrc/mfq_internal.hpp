@@ -178,6 +178,11 @@ struct mfq_csr {
   int64_t* blk = nullptr;     // [n_blocks + 1]: first row of each row block
 };
 
+struct mfq_dg {
+  int p, n;
+  int64_t n_dofs;
+};
+
 struct mfq_transfer {
   const mfq_space* coarse;
   const mfq_space* fine;
@@ -233,8 +238,11 @@ hipError_t launch_csr_blocks(const int64_t* rowptr, int64_t* blk, int64_t n_rows
 hipError_t launch_csr_spmv(const mfq_csr* a, const void* x, void* y, hipStream_t st);
 int64_t csr_row_start_host(int64_t I, int64_t J, int64_t K, int p, int n);
 
-// DG-SIPG operator (kernels_dg.hip): dst = A src (cell term stored, face terms added)
-hipError_t launch_dg_vmult(int p, int n, const double* src, double* dst, hipStream_t st);
+// DG-SIPG operator (kernels_dg.hip): dst = A src (cell term stored, face terms added), its
+// Jacobi diagonal, and the transfer between the continuous Q_p lattice and DG on the same mesh
+hipError_t launch_dg_vmult(int p, int n, int precision, const void* src, void* dst, hipStream_t st);
+hipError_t launch_dg_diagonal(int p, int n, int precision, void* diag, hipStream_t st);
+hipError_t launch_dg_transfer(int p, int n, int precision, bool to_dg, const void* in, void* out, hipStream_t st);
 
 // vector kernels (kernels_vector.hip)
 hipError_t launch_fill(int precision, void* x, int64_t n, double value, hipStream_t st);

@@ -946,3 +946,266 @@ int mfq_solve_end(mfq_solver* s, mfq_solve_info* info) {
 }
 
 }  // extern "C"
+
+// ---------------------------------------------------------------- DG-SIPG multigrid solver
+// FP64 CG on the DG operator, preconditioned by an FP32 V-cycle whose finest level is the DG space
+// and whose coarser levels are the continuous Q_p space on the same mesh and its hierarchy (the
+// switch from the discontinuous to the continuous space inside the hierarchy of the paper's
+// experiment, Sec. 6.1): Chebyshev smoothing on the DG level, the residual restricted to the
+// continuous lattice (sum over the cells holding each node), the continuous GMG_MIXED V-cycle as
+// the coarse correction, prolongation by copying lattice values into every cell.
+struct mfq_dg_solver {
+  const mfq_dg* op = nullptr;
+  mfq_solver_params prm{};
+  int64_t N = 0, Ncg = 0;
+  mfq_mesh* mesh = nullptr;    // owned: the continuous levels' mesh (same cells)
+  mfq_space* space = nullptr;  // owned: continuous Q_p with Dirichlet nodes
+  mfq_op* cg_op = nullptr;     // owned FP64 continuous operator
+  mfq_solver* cg = nullptr;    // owned GMG_MIXED solver on cg_op: its V-cycle is the coarse correction
+  size_t off_cgop = 0, off_cgsol = 0, off_vec = 0, off_state = 0, off_trace = 0, bytes = 0;
+  void* buf = nullptr;
+  float *b = nullptr, *x = nullptr, *r = nullptr, *d = nullptr, *t = nullptr, *dinv = nullptr;
+  double *kr = nullptr, *kp = nullptr, *kAp = nullptr, *kz = nullptr, *kc = nullptr, *kres = nullptr;
+  SolverState* state = nullptr;
+  SolverState* aux = nullptr;
+  double* scal = nullptr;
+  double* trace = nullptr;
+  double* trace_host = nullptr;
+  double lmin = 0, lmax = 0;
+  ~mfq_dg_solver() {
+    if (trace_host) (void)hipHostFree(trace_host);
+    mfq_solver_destroy(cg);
+    mfq_op_destroy(cg_op);
+    mfq_space_destroy(space);
+    mfq_mesh_destroy(mesh);
+  }
+};
+
+namespace {
+
+int dg_apply(const mfq_dg_solver* s, int prec, const void* in, void* out, hipStream_t st) {
+  MFQ_HIP(launch_dg_vmult(s->op->p, s->op->n, prec, in, out, st));
+  return MFQ_OK;
+}
+
+// `degree` Chebyshev updates of x for A x = b on [lmin, lmax] of D^{-1}A (FP32 DG level)
+int dg_chebyshev(mfq_dg_solver* s, bool x_is_zero, hipStream_t st) {
+  const int64_t n = s->N;
+  const double theta = 0.5 * (s->lmax + s->lmin), delta = 0.5 * (s->lmax - s->lmin);
+  const double sigma = theta / delta;
+  double rho = 1.0 / sigma;
+  if (!x_is_zero)
+    if (int rc = dg_apply(s, MFQ_FP32, s->x, s->t, st)) return rc;
+  MFQ_HIP(launch_cheb_first(MFQ_FP32, s->b, s->t, s->dinv, s->x, s->r, s->d, n, 1.0 / theta, x_is_zero, st));
+  for (int k = 1; k < s->prm.smoother_degree; ++k) {
+    if (int rc = dg_apply(s, MFQ_FP32, s->d, s->t, st)) return rc;
+    const double rho_new = 1.0 / (2.0 * sigma - rho);
+    MFQ_HIP(launch_cheb_step(MFQ_FP32, s->t, s->dinv, s->x, s->r, s->d, n, rho_new * rho, 2.0 * rho_new / delta, st));
+    rho = rho_new;
+  }
+  return MFQ_OK;
+}
+
+int dg_vcycle(mfq_dg_solver* s, hipStream_t st) {
+  const int p = s->op->p, n = s->op->n;
+  if (int rc = dg_chebyshev(s, true, st)) return rc;
+  if (int rc = dg_apply(s, MFQ_FP32, s->x, s->t, st)) return rc;
+  MFQ_HIP(launch_sub(MFQ_FP32, s->b, s->t, s->r, s->N, st));
+  // the continuous hierarchy's finest level holds FP32 vectors of the same mesh and degree
+  Level& F = s->cg->lv.back();
+  MFQ_HIP(launch_dg_transfer(p, n, MFQ_FP32, false, s->r, F.b, st));
+  if (int rc = vcycle(s->cg, (int)s->cg->lv.size() - 1, st)) return rc;
+  MFQ_HIP(launch_dg_transfer(p, n, MFQ_FP32, true, F.x, s->t, st));
+  MFQ_HIP(launch_add(MFQ_FP32, s->x, MFQ_FP32, s->t, s->N, st));
+  return dg_chebyshev(s, false, st);
+}
+
+int dg_precondition(mfq_dg_solver* s, const double* r, double* z, hipStream_t st) {
+  MFQ_HIP(launch_cast(MFQ_FP64, r, MFQ_FP32, s->b, s->N, st));
+  if (int rc = dg_vcycle(s, st)) return rc;
+  MFQ_HIP(launch_cast(MFQ_FP32, s->x, MFQ_FP64, z, s->N, st));
+  return MFQ_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int mfq_dg_solver_create(const mfq_dg* op, const mfq_solver_params* params, mfq_dg_solver** out) {
+  if (!op || !out) return fail(MFQ_EINVAL, "op or out is NULL");
+  mfq_dg_solver* s = new (std::nothrow) mfq_dg_solver();
+  if (!s) return fail(MFQ_ENOMEM, "host allocation failed");
+  s->op = op;
+  if (params) {
+    s->prm = *params;
+  } else {
+    mfq_solver_default_params(&s->prm);
+    s->prm.smoother_degree = 6;
+  }
+  if (s->prm.smoother_degree < 1 || s->prm.lanczos_iters < 2) {
+    delete s;
+    return fail(MFQ_EINVAL, "smoother_degree must be >= 1 and lanczos_iters >= 2");
+  }
+  s->N = op->n_dofs;
+  int rc = mfq_mesh_create(op->n, 0.0, &s->mesh);
+  if (rc == MFQ_OK) rc = mfq_space_create(s->mesh, op->p, MFQ_BC_DIRICHLET0, &s->space);
+  if (rc == MFQ_OK) rc = mfq_op_create(s->space, 0.0, MFQ_FP64, &s->cg_op);
+  if (rc == MFQ_OK) rc = mfq_solver_create(s->cg_op, MFQ_SOLVER_GMG_MIXED, &s->prm, &s->cg);
+  if (rc == MFQ_OK && s->cg->prec_v != MFQ_FP32) rc = fail(MFQ_EINVAL, "continuous hierarchy is not FP32");
+  if (rc != MFQ_OK) {
+    delete s;
+    return rc;
+  }
+  s->Ncg = s->space->n_dofs;
+  size_t ob = 0, sb = 0;
+  mfq_op_device_bytes(s->cg_op, &ob);
+  mfq_solver_device_bytes(s->cg, &sb);
+  size_t off = 0;
+  s->off_cgop = off;
+  off += round_up(ob, 256);
+  s->off_cgsol = off;
+  off += round_up(sb, 256);
+  s->off_vec = off;
+  off += 6 * round_up(s->N * 4, 256) + 6 * round_up(s->N * 8, 256);
+  s->off_state = off;
+  off += round_up(2 * sizeof(SolverState) + 64, 256);
+  s->off_trace = off;
+  off += round_up((2 * s->prm.lanczos_iters + 1) * sizeof(double), 256);
+  s->bytes = off;
+  *out = s;
+  return MFQ_OK;
+}
+
+void mfq_dg_solver_destroy(mfq_dg_solver* s) { delete s; }
+
+int mfq_dg_solver_device_bytes(const mfq_dg_solver* s, size_t* bytes) {
+  if (!s || !bytes) return fail(MFQ_EINVAL, "solver or bytes is NULL");
+  *bytes = s->bytes;
+  return MFQ_OK;
+}
+
+int mfq_dg_solver_bind(mfq_dg_solver* s, void* dev_buf, size_t bytes, void* hip_stream) {
+  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) % 256)) return fail(MFQ_EINVAL, "buffer NULL or misaligned");
+  if (bytes < s->bytes) return fail(MFQ_ENOMEM, "buffer of %zu bytes, solver needs %zu", bytes, s->bytes);
+  hipStream_t st = (hipStream_t)hip_stream;
+  char* base = (char*)dev_buf;
+  size_t ob = 0, sb = 0;
+  mfq_op_device_bytes(s->cg_op, &ob);
+  mfq_solver_device_bytes(s->cg, &sb);
+  if (int rc = mfq_op_bind(s->cg_op, base + s->off_cgop, ob, st)) return rc;
+  if (int rc = mfq_solver_bind(s->cg, base + s->off_cgsol, sb, st)) return rc;
+  char* v = base + s->off_vec;
+  const size_t f4 = round_up(s->N * 4, 256), f8 = round_up(s->N * 8, 256);
+  float** fv[6] = {&s->b, &s->x, &s->r, &s->d, &s->t, &s->dinv};
+  for (int i = 0; i < 6; ++i) {
+    *fv[i] = (float*)v;
+    v += f4;
+  }
+  double** dv[6] = {&s->kr, &s->kp, &s->kAp, &s->kz, &s->kc, &s->kres};
+  for (int i = 0; i < 6; ++i) {
+    *dv[i] = (double*)v;
+    v += f8;
+  }
+  s->state = (SolverState*)(base + s->off_state);
+  s->aux = s->state + 1;
+  s->scal = (double*)(s->aux + 1);
+  s->trace = (double*)(base + s->off_trace);
+  s->buf = dev_buf;
+  MFQ_HIP(launch_fill(MFQ_FP64, s->state, (2 * sizeof(SolverState) + 64) / 8, 0.0, st));
+  // Jacobi diagonal and the largest eigenvalue of D^{-1}A on the DG level (FP32 Lanczos)
+  MFQ_HIP(launch_dg_diagonal(s->op->p, s->op->n, MFQ_FP32, s->dinv, st));
+  MFQ_HIP(launch_reciprocal(MFQ_FP32, s->dinv, s->N, st));
+  const int k = s->prm.lanczos_iters;
+  MFQ_HIP(launch_splitmix(MFQ_FP32, s->r, (int64_t)s->op->n * (s->op->p + 1), 0, false, st));
+  MFQ_HIP(launch_lz_init(MFQ_FP32, s->r, s->dinv, s->d, s->t, s->N, s->aux, s->trace, 2 * k, st));
+  for (int it = 0; it < k; ++it) {
+    if (int rc = dg_apply(s, MFQ_FP32, s->t, s->x, st)) return rc;
+    MFQ_HIP(launch_lz_alpha(MFQ_FP32, s->t, s->x, s->N, s->aux, s->trace, st));
+    MFQ_HIP(launch_lz_update(MFQ_FP32, s->r, s->d, s->x, s->dinv, s->N, s->aux, s->trace, 2 * k, st));
+    MFQ_HIP(launch_lz_direction(MFQ_FP32, s->d, s->t, s->N, s->aux, st));
+  }
+  if (!s->trace_host) MFQ_HIP(hipHostMalloc((void**)&s->trace_host, (2 * k + 1) * sizeof(double), hipHostMallocDefault));
+  MFQ_HIP(hipMemcpyAsync(s->trace_host, s->trace, (2 * k + 1) * sizeof(double), hipMemcpyDeviceToHost, st));
+  MFQ_HIP(hipStreamSynchronize(st));
+  const double* tr = s->trace_host;
+  const int m = std::min(k, std::max(0, (int)tr[2 * k]));
+  if (m == 0) return fail(MFQ_ENONFINITE, "eigenvalue estimate failed on the DG level");
+  std::vector<double> T((size_t)m * m, 0.0);
+  for (int i = 0; i < m; ++i) {
+    const double ai = tr[2 * i], bi = tr[2 * i + 1];
+    T[i * m + i] = 1.0 / ai + (i > 0 ? tr[2 * i - 1] / tr[2 * i - 2] : 0.0);
+    if (i + 1 < m) T[i * m + i + 1] = T[(i + 1) * m + i] = std::sqrt(bi) / ai;
+  }
+  s->lmax = s->prm.lambda_factor * sym_max_eig(T, m);
+  s->lmin = s->lmax / s->prm.lambda_ratio;
+  return MFQ_OK;
+}
+
+int mfq_dg_precondition(mfq_dg_solver* s, const double* r, double* z, void* hip_stream) {
+  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
+  if (!s->buf) return fail(MFQ_EINVAL, "solver is not bound");
+  if (!r || !z) return fail(MFQ_EINVAL, "r or z is NULL");
+  return dg_precondition(s, r, z, (hipStream_t)hip_stream);
+}
+
+int mfq_dg_solve(mfq_dg_solver* s, const double* b, double* x, double rtol, int max_iter, void* hip_stream,
+                 mfq_solve_info* info) {
+  if (!s) return fail(MFQ_EINVAL, "solver is NULL");
+  if (!s->buf) return fail(MFQ_EINVAL, "solver is not bound");
+  if (!b || !x || (reinterpret_cast<uintptr_t>(b) % 16) || (reinterpret_cast<uintptr_t>(x) % 16))
+    return fail(MFQ_EINVAL, "b or x NULL or misaligned");
+  if (!(rtol > 0 && rtol < 1)) return fail(MFQ_EINVAL, "rtol must be in (0,1)");
+  if (max_iter < 1) return fail(MFQ_EINVAL, "max_iter must be >= 1");
+  hipStream_t st = (hipStream_t)hip_stream;
+  const auto t0 = std::chrono::steady_clock::now();
+  Apply A = [s, st](const double* in, double* out) { return dg_apply(s, MFQ_FP64, in, out, st); };
+  Apply M = [s, st](const double* in, double* out) { return dg_precondition(s, in, out, st); };
+  PcgResult res;
+  MFQ_HIP(launch_fill(MFQ_FP64, s->state, sizeof(SolverState) / 8, 0.0, st));
+  if (int rc = pcg(A, &M, b, x, s->kr, s->kp, s->kAp, s->kz, s->N, s->state, rtol, max_iter, s->prm.check_every, st, res))
+    return rc;
+  const double bb = res.bb;
+  int iters = res.iters, passes = 1;
+  double rr = 0;
+  int status = MFQ_OK;
+  // FP64 true residual; correction passes on A c = b - A x while it is above rtol ||b||
+  for (;;) {
+    if (int rc = A(x, s->kAp)) return rc;
+    MFQ_HIP(launch_residual_norm(b, s->kAp, s->kres, s->N, s->aux, s->scal, st));
+    MFQ_HIP(hipMemcpyAsync(&rr, s->scal, sizeof(double), hipMemcpyDeviceToHost, st));
+    MFQ_HIP(hipStreamSynchronize(st));
+    if (!std::isfinite(rr)) {
+      status = MFQ_ENONFINITE;
+      break;
+    }
+    if (bb == 0 || rr <= rtol * rtol * bb) break;
+    if (iters >= max_iter || passes >= 8) {
+      status = MFQ_ENOCONV;
+      break;
+    }
+    const double tol = std::sqrt(std::min(0.25, 0.25 * rtol * rtol * bb / rr));
+    MFQ_HIP(launch_fill(MFQ_FP64, s->state, sizeof(SolverState) / 8, 0.0, st));
+    PcgResult rc2;
+    if (int rc = pcg(A, &M, s->kres, s->kc, s->kr, s->kp, s->kAp, s->kz, s->N, s->state, tol, max_iter - iters,
+                     s->prm.check_every, st, rc2))
+      return rc;
+    MFQ_HIP(launch_add(MFQ_FP64, x, MFQ_FP64, s->kc, s->N, st));
+    iters += rc2.iters;
+    ++passes;
+  }
+  if (info) {
+    mfq_solve_info inf{};
+    inf.iterations = iters;
+    inf.outer_iterations = passes;
+    inf.rel_residual = bb > 0 ? std::sqrt(rr / bb) : 0.0;
+    inf.seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    inf.n_levels = (int)s->cg->lv.size() + 1;
+    *info = inf;
+  }
+  if (status == MFQ_ENOCONV) return fail(MFQ_ENOCONV, "no convergence to %g within %d iterations", rtol, max_iter);
+  if (status == MFQ_ENONFINITE) return fail(MFQ_ENONFINITE, "non-finite residual");
+  return MFQ_OK;
+}
+
+}  // extern "C"

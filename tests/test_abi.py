@@ -177,6 +177,32 @@ def test_dg_host_validation():
     with pytest.raises(lib.MfqError) as e:
         lib.mfq_dg_vmult(g, 256, 256, None)          # src and dst overlap
     assert e.value.status == lib.MFQ_EINVAL
+    assert lib.mfq_dg_cg_n_dofs(g) == 13 ** 3
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_dg_vmult_prec(g, lib.MFQ_FP32_MFMA, 256, 1 << 20, None)   # precision not offered
+    assert e.value.status == lib.MFQ_EINVAL
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_dg_transfer(g, lib.MFQ_FP64, 1, 256, 512, None)           # in and out overlap
+    assert e.value.status == lib.MFQ_EINVAL
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_dg_diagonal(g, lib.MFQ_FP64, None, None)
+    assert e.value.status == lib.MFQ_EINVAL
+    # the multigrid solver: host-side set-up and sizing, the continuous hierarchy under it
+    sv = lib.mfq_dg_solver_create(g)
+    nbytes = lib.mfq_dg_solver_device_bytes(sv)
+    assert nbytes >= 6 * 4 * 27 * 125 + 6 * 8 * 27 * 125
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_dg_solve(sv, 256, 512, 1e-10, 10, None)                   # not bound
+    assert e.value.status == lib.MFQ_EINVAL
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_dg_solver_bind(sv, 256, nbytes - 1, None)                 # too small
+    assert e.value.status == lib.MFQ_ENOMEM
+    lib.mfq_dg_solver_destroy(sv)
+    prm = lib.mfq_solver_default_params()
+    prm.smoother_degree = 0
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_dg_solver_create(g, prm)
+    assert e.value.status == lib.MFQ_EINVAL
     lib.mfq_dg_destroy(g)
     with pytest.raises(lib.MfqError):
         lib.mfq_dg_create(m, 9)

@@ -4,7 +4,7 @@ interior faces of both parities; the full Q4 64^3 size on rows the oracle recomp
 import numpy as np
 import pytest
 
-from oracle import dg
+from oracle import dg, mesh, solve
 from synthetic import uniform_vector
 
 pytestmark = pytest.mark.gpu
@@ -87,3 +87,145 @@ def test_dg_full_size_q4_64_sampled():
                            [0, nloc - 1, len(x) - 1, (n ** 3 // 2) * nloc + 62, 63 * nloc + 124]])
     yo = dg.dg_rows(p, n, x, rows)
     assert np.abs(y[rows] - yo).max() <= 1e-12 * np.abs(yo).max()
+
+
+U32 = 2.0 ** -24
+
+
+def _torch_vec(x, dtype):
+    torch = _torch()
+    return torch.from_numpy(x).to(dtype).cuda()
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 6, 8])
+def test_dg_vmult_fp32_within_rounding_bound(p):
+    """FP32 product: |y32 - A x32| <= 2 k u32 (M |x32|) componentwise, M the oracle's magnitude
+    matrix (every table, weight and term by its absolute value) and k = 8(p+1) + 16 the longest
+    rounding chain (six 1D passes per cell term, the face interpolation passes, the sums of the
+    cell and six face contributions)."""
+    mfq = _mfq()
+    torch = _torch()
+    n = SIZES[p]
+    print(f"dg vmult fp32 p={p} n={n}", flush=True)
+    op = mfq.DGOperator(mfq.Mesh(n, 0.0), p)
+    x = uniform_vector(op.n_dofs, seed=90 + p)
+    x32 = x.astype(np.float32).astype(np.float64)
+    y = op.vmult(_torch_vec(x, torch.float32))
+    torch.cuda.synchronize()
+    y = y.double().cpu().numpy()
+    yo = dg.assemble(p, n) @ x32
+    mag = dg.assemble(p, n, magnitude=True) @ np.abs(x32)
+    k = 8 * (p + 1) + 16
+    assert np.all(np.abs(y - yo) <= 2 * k * U32 * mag + 1e-30)
+    print(f"p={p} dg fp32 normwise rel err {np.abs(y - yo).max() / np.abs(yo).max():.2e}")
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_dg_diagonal_matches_assembled(p):
+    """Closed-form diagonal against the diagonal of the oracle's assembled matrix (FP64), and the
+    FP32 diagonal within a few roundings of it."""
+    mfq = _mfq()
+    torch = _torch()
+    n = SIZES[p]
+    print(f"dg diagonal p={p} n={n}", flush=True)
+    op = mfq.DGOperator(mfq.Mesh(n, 0.0), p)
+    d64 = op.diagonal(mfq.MFQ_FP64)
+    d32 = op.diagonal(mfq.MFQ_FP32)
+    torch.cuda.synchronize()
+    do = dg.assemble(p, n).diagonal()
+    assert np.abs(d64.cpu().numpy() - do).max() <= 1e-13 * np.abs(do).max()
+    assert np.all(np.abs(d32.double().cpu().numpy() - do) <= 64 * U32 * np.abs(do))
+
+
+@pytest.mark.parametrize("p,n", [(1, 4), (2, 3), (4, 3), (5, 2), (8, 2)])
+def test_dg_transfer_matches_embedding(p, n):
+    """from_cg = E c bit for bit (a copy); to_cg = E^T r within one rounding per summed copy
+    (at most 8 cells share a node); FP32 forms likewise in FP32."""
+    mfq = _mfq()
+    torch = _torch()
+    print(f"dg transfer p={p} n={n}", flush=True)
+    op = mfq.DGOperator(mfq.Mesh(n, 0.0), p)
+    E = dg.cg_embedding(p, n)
+    assert op.cg_n_dofs == E.shape[1]
+    c = uniform_vector(E.shape[1], seed=7) * mesh.boundary_mask(p, n)
+    r = uniform_vector(E.shape[0], seed=8)
+    for dtype, tol in ((torch.float64, 8 * 2.0 ** -53), (torch.float32, 8 * U32)):
+        cv = _torch_vec(c, dtype)
+        rv = _torch_vec(r, dtype)
+        fd = op.from_cg(cv).double().cpu().numpy()
+        tc = op.to_cg(rv).double().cpu().numpy()
+        c_in = cv.double().cpu().numpy()
+        r_in = rv.double().cpu().numpy()
+        np.testing.assert_array_equal(fd, E @ c_in)
+        ref = E.T @ r_in
+        assert np.all(np.abs(tc - ref) <= tol * (abs(E.T) @ np.abs(r_in)) + 1e-300)
+    # adjointness on the GPU path: (E^T r) . c == r . (E c)
+    cv, rv = _torch_vec(c, torch.float64), _torch_vec(r, torch.float64)
+    lhs = torch.dot(op.to_cg(rv), cv).item()
+    rhs = torch.dot(rv, op.from_cg(cv)).item()
+    assert abs(lhs - rhs) <= 1e-12 * np.abs(r).sum()
+
+
+def _dg_system(p, n, seed):
+    mfq = _mfq()
+    op = mfq.DGOperator(mfq.Mesh(n, 0.0), p)
+    b = uniform_vector(op.n_dofs, seed=seed)
+    return mfq, op, b
+
+
+@pytest.mark.parametrize("p,n", [(1, 8), (2, 6), (3, 4), (4, 4), (4, 5), (6, 2)])
+def test_dg_solver_matches_direct_solve(p, n):
+    """FP64 CG with the FP32 DG -> continuous V-cycle: certified FP64 residual, and the solution
+    equal to a sparse direct solve of the oracle's assembled DG matrix within what the 1e-10
+    residual allows (cond(A) < 1e5 on these meshes)."""
+    torch = _torch()
+    print(f"dg solve p={p} n={n}", flush=True)
+    mfq, op, b_np = _dg_system(p, n, seed=40 + p)
+    sv = mfq.DGSolver(op)
+    b = torch.from_numpy(b_np).cuda()
+    x, info, st = sv.solve(b, rtol=1e-10, max_iter=200)
+    torch.cuda.synchronize()
+    assert st == mfq.MFQ_OK and info.rel_residual <= 1e-10
+    A = dg.assemble(p, n)
+    xn = x.cpu().numpy()
+    assert np.linalg.norm(b_np - A @ xn) <= 1e-10 * np.linalg.norm(b_np) * (1 + 1e-6)
+    xd = solve.direct_solve(A, b_np)
+    assert np.abs(xn - xd).max() <= 1e-5 * np.abs(xd).max()
+    print(f"p={p} n={n}: {info.iterations} iterations, {info.outer_iterations} passes, {info.n_levels} levels")
+    # a V-cycle with a Chebyshev(6) smoother and the continuous hierarchy: a few iterations
+    assert info.iterations <= 25, info.iterations
+
+
+def test_dg_preconditioner_is_symmetric_and_deterministic():
+    """The V-cycle (same smoother before and after, symmetric continuous cycle, E and E^T) is a
+    symmetric operator up to FP32 rounding; two applications to the same input are identical."""
+    torch = _torch()
+    mfq, op, b_np = _dg_system(3, 4, seed=3)
+    sv = mfq.DGSolver(op)
+    r1 = torch.from_numpy(b_np).cuda()
+    r2 = torch.from_numpy(uniform_vector(op.n_dofs, seed=4)).cuda()
+    z1 = sv.precondition(r1)
+    z1b = sv.precondition(r1)
+    z2 = sv.precondition(r2)
+    torch.cuda.synchronize()
+    assert torch.equal(z1, z1b)
+    a, c = torch.dot(z1, r2).item(), torch.dot(r1, z2).item()
+    assert abs(a - c) <= 1e-4 * (z1.abs() @ r2.abs()).item()
+    assert torch.dot(z1, r1).item() > 0
+
+
+def test_dg_solver_errors():
+    mfq = _mfq()
+    torch = _torch()
+    _, op, b_np = _dg_system(2, 4, seed=1)
+    sv = mfq.DGSolver(op)
+    b = torch.from_numpy(b_np).cuda()
+    with pytest.raises(mfq.MfqError):
+        sv.solve(b, rtol=0.0)
+    with pytest.raises(mfq.MfqError):
+        sv.solve(b, rtol=1e-10, max_iter=0)
+    # too few iterations: ENOCONV, the info still filled
+    x, info, st = sv.solve(b, rtol=1e-14, max_iter=1, check=False)
+    assert st == mfq.MFQ_ENOCONV and info.iterations >= 1
+    with pytest.raises(mfq.MfqError):
+        mfq.DGSolver(op, smoother_degree=0)

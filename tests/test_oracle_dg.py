@@ -6,7 +6,7 @@ by parts cancel against the consistency terms only with the right signs, normals
 import numpy as np
 import pytest
 
-from oracle import dg
+from oracle import assemble, dg, mesh
 
 
 def _u(x, y, z):
@@ -53,3 +53,45 @@ def test_sampled_rows_match_assembly():
     rows = np.random.default_rng(1).integers(0, dg.n_dofs(p, n), 60)
     y = A @ x
     assert np.abs(dg.dg_rows(p, n, x, rows) - y[rows]).max() <= 1e-12 * np.abs(y).max()
+
+
+def _v(x, y, z):
+    # vanishes on the boundary, different along each axis (a transposed index changes it)
+    return x * (1 - x) * (1 + 2 * x) * y * (1 - y) * z * (1 - z) * (2 - z) ** 2
+
+
+@pytest.mark.parametrize("p,n", [(1, 3), (2, 2), (3, 2), (4, 2)])
+def test_embedding_maps_nodal_values(p, n):
+    """E applied to the continuous nodal interpolant is the DG nodal interpolant of the same
+    function (both spaces interpolate at the GLL nodes of every cell)."""
+    E = dg.cg_embedding(p, n)
+    X = mesh.node_coords(p, n)
+    c = _v(X[:, 0], X[:, 1], X[:, 2])
+    assert np.abs(E @ c - dg.nodal_interpolant(p, n, _v)).max() <= 1e-15
+    # every DG DoF on an interior lattice node gets exactly one value; boundary rows are empty
+    assert set(np.unique(E.sum(axis=1).A.ravel())) <= {0.0, 1.0}
+
+
+@pytest.mark.parametrize("p,n", [(1, 3), (2, 2), (3, 2), (4, 1), (4, 2)])
+def test_galerkin_product_is_the_continuous_operator(p, n):
+    """For continuous functions vanishing on the boundary every jump is zero, so all face terms
+    of the SIPG form vanish and E^T A_DG E is the continuous stiffness matrix on the free nodes
+    (a face term that survives on continuous functions, such as a jump with the wrong sign or a
+    trace taken at the wrong end, or a wrong index in E breaks this)."""
+    E = dg.cg_embedding(p, n)
+    G = (E.T @ dg.assemble(p, n) @ E).toarray()
+    m = mesh.boundary_mask(p, n)
+    Acg = assemble.assemble_csr(p, n, 0.0, 0.0).toarray() * np.outer(m, m)
+    assert np.abs(G - Acg).max() <= 1e-11 * np.abs(Acg).max()
+
+
+@pytest.mark.parametrize("p,n", [(1, 2), (3, 2), (4, 1)])
+def test_magnitude_bounds_the_matrix(p, n):
+    """The magnitude matrix bounds |A| entrywise, and its cell part has the cell matrix's
+    diagonal (a sum of squares has no cancellation)."""
+    A = dg.assemble(p, n).toarray()
+    M = dg.assemble(p, n, magnitude=True).toarray()
+    assert np.all(np.abs(A) <= M * (1 + 1e-13) + 1e-15)
+    # diagonal of the cell term: a sum of squares, so no cancellation
+    Ac = dg.element_matrices(p, n, 0.0, 0.0, np.array([0]))[0]
+    assert np.allclose(np.diag(dg.cell_magnitude(p, n)), np.diag(Ac), rtol=1e-13)
