@@ -408,12 +408,16 @@ def dg_multigrid_benchmark(steps, warmup, solve_rtol=1e-10):
         setup = time.perf_counter() - t0
         r = torch.from_numpy(uniform_vector(op.n_dofs, seed=3)).cuda()
         z = torch.empty_like(r)
-        sec = time_events(lambda: sv.precondition(r, z), steps, warmup)
+        side = torch.cuda.Stream()          # a non-default stream: the V-cycle replays as a graph
+        torch.cuda.synchronize()
+        with torch.cuda.stream(side):
+            sec = time_events(lambda: sv.precondition(r, z, stream=side), steps, warmup)
         rec = {"degree": 4, "cells": n ** 3, "dofs": op.n_dofs, "vcycle_ms": sec * 1e3,
                "DoFs_per_s": op.n_dofs / sec, "setup_s": setup}
         if n == VCYCLE_MESHES[0]:
-            x, info, st = sv.solve(r, rtol=solve_rtol, max_iter=200)
-            x, info, st = sv.solve(r, rtol=solve_rtol, max_iter=200)     # warm
+            with torch.cuda.stream(side):
+                x, info, st = sv.solve(r, rtol=solve_rtol, max_iter=200, stream=side)
+                x, info, st = sv.solve(r, rtol=solve_rtol, max_iter=200, stream=side)     # warm
             rec.update({"solve_s": info.seconds, "iterations": info.iterations, "passes": info.outer_iterations,
                         "rel_residual": info.rel_residual, "levels": info.n_levels,
                         "rate_per_iteration": info.rel_residual ** (1.0 / max(info.iterations, 1)),

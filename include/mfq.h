@@ -345,7 +345,9 @@ int mfq_dg_solver_device_bytes(const mfq_dg_solver* s, size_t* bytes);
 /* Binds a 256-byte aligned device buffer of at least device_bytes; builds the continuous
  * hierarchy, the DG diagonal and the eigenvalue bound.  Synchronises the stream. */
 int mfq_dg_solver_bind(mfq_dg_solver* s, void* dev_buf, size_t bytes, void* hip_stream);
-/* z = M r: one V-cycle on the double device vector r (n_dofs).  Asynchronous. */
+/* z = M r: one V-cycle on the double device vector r (n_dofs).  Asynchronous.  With use_graphs
+ * (default) on a non-default stream, the V-cycle is captured once per (stream, r, z) as a HIP
+ * graph and replayed (the last two captures are kept); mfq_dg_solve uses this too. */
 int mfq_dg_precondition(mfq_dg_solver* s, const double* r, double* z, void* hip_stream);
 /* Solves A x = b to ||b - A x||_2 <= rtol ||b||_2 from x = 0, with FP64 correction passes on the
  * residual equation while the FP64 true residual exceeds rtol (as mfq_solve).  Blocks until done;

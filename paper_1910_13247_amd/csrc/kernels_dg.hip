@@ -9,16 +9,16 @@
 // boundary faces with the outside values zero and the inside value instead of the mean
 // (homogeneous Dirichlet data imposed weakly).
 //
-// Cell term: one lane per 1D pencil of a cell, the sum factorisation of the continuous operator
-// (even-odd forms of the 1D tables) with the quadrature tensor h w_r w_s w_t I of the affine cube; a cell's DoFs are contiguous, so
-// loads and stores are plain coalesced reads and writes (no lattice, no colours).
-// Face terms: one launch per normal direction d and parity of the face position along d (faces of
-// one parity touch disjoint cells, so their adds need no atomics), one lane per tangential node
-// of a face.  The lane reads the normal lines of both cells (the trace is the end node on the GLL
-// nodes, the normal derivative a dot product with l'_a at the end point), forms the jump and the
-// mean normal derivative, interpolates both to the face Gauss points through LDS (two 1D passes),
-// applies weight and penalty there, interpolates back and adds the value part to the face node and
-// the derivative part along the whole normal line of each cell.
+// One kernel computes everything, cell by cell: CPW consecutive cells per workgroup, one lane per
+// 1D pencil of a cell.  Cell term: the sum factorisation of the continuous operator (even-odd forms
+// of the 1D tables) with the quadrature tensor h w_r w_s w_t I of the affine cube.  Face terms: the
+// cell evaluates all six of its faces itself (an interior face is evaluated by both its cells, each
+// keeping its own half), one lane per tangential node: it reads its own and the neighbour's normal
+// line (the trace is the end node of the GLL line, the normal derivative a dot product with l'_a
+// at the end point), forms jump and mean normal derivative at the face nodes, applies the face
+// rule's tensor-product mass matrix in two 1D passes through LDS, and adds the value part at the
+// face node and the derivative part along the normal line.  A cell's DoFs are contiguous, so the
+// result is written once with coalesced stores; the neighbours' lines come from the caches.
 #include "kernels_common.hpp"
 
 namespace mfq {
@@ -31,6 +31,7 @@ struct DgTables {
   Real w[P + 1];              // Gauss weights on [0,1]
   Real d0[P + 1];             // l_a'(0)
   Real d1[P + 1];             // l_a'(1)
+  Real M[(P + 1) * (P + 1)];  // 1D mass matrix of the face rule: M[a*(P+1)+b] = sum_q w_q l_a(zeta_q) l_b(zeta_q)
 };
 
 template <int P, typename Real>
@@ -46,13 +47,14 @@ DgTables<P, Real> make_dg_tables() {
     t.d0[a] = (Real)lagrange_derivative(tb.xi, a, 0.0);
     t.d1[a] = (Real)lagrange_derivative(tb.xi, a, 1.0);
   }
+  for (int a = 0; a <= P; ++a)
+    for (int b = 0; b <= P; ++b) {
+      double m = 0;
+      for (int q = 0; q <= P; ++q) m += tb.omega[q] * tb.S[q * (P + 1) + a] * tb.S[q * (P + 1) + b];
+      t.M[a * (P + 1) + b] = (Real)m;
+    }
   return t;
 }
-
-template <int P, typename Real>
-struct DgWeights {
-  Real w[P + 1];  // Gauss weights on [0,1]
-};
 
 template <int P>
 struct DgCell {
@@ -63,20 +65,16 @@ struct DgCell {
   static constexpr int THREADS = CPW * T;
 };
 
+// Cell term of one cell per T lanes: on return, lane e = b + N1 c holds the x-pencil (b, c) of the
+// cell's result in y.  lds holds 3 CPW NQ values (three arrays of CPW cells); ends after its last
+// read of the first two arrays (the caller synchronises before reusing them).
 template <int P, typename Real>
-__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const Real* __restrict__ src,
-                                                                     Real* __restrict__ dst, int64_t n_cells,
-                                                                     Real h, ShapeEO<P, Real> sh,
-                                                                     DgWeights<P, Real> tb) {
+__device__ __forceinline__ void dg_cell_term(const Real* __restrict__ src, int64_t base, bool live, Real* lds,
+                                             int lc, int e, Real h, const ShapeEO<P, Real>& sh,
+                                             const Real (&wq)[P + 1], Real (&y)[P + 1]) {
   using C = DgCell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, CPW = C::CPW;
-  __shared__ Real lds[3 * CPW * NQ];
-  const int tid = threadIdx.x;
-  const int lc = tid / T, e = tid - lc * T;
   const int e0 = e % N1, e1 = e / N1;
-  const int64_t cell = (int64_t)blockIdx.x * CPW + lc;
-  const bool live = cell < n_cells;
-  const int64_t base = (live ? cell : 0) * NQ;
   Real* L0 = lds + lc * NQ;
   Real* L1 = L0 + CPW * NQ;
   Real* L2 = L1 + CPW * NQ;
@@ -126,13 +124,13 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const Real*
     Real w0 = 0, w1 = 0;  // weights of this lane's (r, s), selected with compile-time indices
 #pragma unroll
     for (int k = 0; k < N1; ++k) {
-      w0 = e0 == k ? tb.w[k] : w0;
-      w1 = e1 == k ? tb.w[k] : w1;
+      w0 = e0 == k ? wq[k] : w0;
+      w1 = e1 == k ? wq[k] : w1;
     }
     const Real wrs = h * w0 * w1;
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
-      const Real w = wrs * tb.w[t];
+      const Real w = wrs * wq[t];
       gx[t] *= w;
       gy[t] *= w;
       gz[t] *= w;
@@ -168,17 +166,14 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_cell_kernel(const Real*
     }
   }
   __syncthreads();
-  {  // transposed x: lane (b = e0, c = e1) writes its x-pencil of the cell result
-    Real ap[N1], bp[N1], y[N1];
+  {  // transposed x: lane (b = e0, c = e1) forms its x-pencil of the cell result
+    Real ap[N1], bp[N1];
 #pragma unroll
     for (int r = 0; r < N1; ++r) {
       ap[r] = L0[r + N1 * e];
       bp[r] = L1[r + N1 * e];
     }
     eo_apply_t2<N1>(sh.S, ap, sh.D, bp, y);
-    if (live)
-#pragma unroll
-      for (int a = 0; a < N1; ++a) dst[base + a + N1 * e] = y[a];
   }
 }
 
@@ -188,127 +183,117 @@ __device__ __forceinline__ int face_local(int d, int ad, int a1, int a2) {
   return d == 0 ? ad + N1 * a1 + N1 * N1 * a2 : d == 1 ? a1 + N1 * ad + N1 * N1 * a2 : a1 + N1 * a2 + N1 * N1 * ad;
 }
 
+// Cell-centric form of the whole operator: one workgroup per CPW consecutive cells computes each
+// cell's volume term and all six of its face terms (every interior face is evaluated by both of its
+// cells, each keeping its own half), then writes each cell's result once with coalesced stores.
+// The neighbours' normal lines are read from the caches (they are the same workgroup's or a
+// nearby one's cells); the result is never re-read.  Workgroups are mapped so that each XCD runs
+// a contiguous range of cells, keeping the y and z neighbours in that XCD's L2 more often.
+template <int P>
+struct DgFused {
+  static constexpr int N1 = P + 1, T = N1 * N1, NQ = N1 * T, CPW = DgCell<P>::CPW;
+  // per cell: the cell term's three arrays, or the result plus 8 face arrays (the 4 inputs of one
+  // direction's two faces and the 4 outputs of the first 1D pass)
+  static constexpr int PER_CELL = 3 * NQ > NQ + 8 * T ? 3 * NQ : NQ + 8 * T;
+};
+
 template <int P, typename Real>
-__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_face_kernel(const Real* __restrict__ src,
-                                                                     Real* __restrict__ dst, int n, int d, int parity,
-                                                                     int64_t n_faces, Real h, Real sigma,
-                                                                     DgTables<P, Real> tb) {
-  using C = DgCell<P>;
-  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, FPW = C::CPW;
-  __shared__ Real lds[4 * FPW * T];
+__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_fused_kernel(const Real* __restrict__ src,
+                                                                      Real* __restrict__ dst, int n,
+                                                                      int64_t n_cells, Real h, Real sigma,
+                                                                      ShapeEO<P, Real> sh, DgTables<P, Real> tb) {
+  using F = DgFused<P>;
+  constexpr int N1 = F::N1, T = F::T, NQ = F::NQ, CPW = F::CPW;
+  __shared__ Real lds[CPW * F::PER_CELL];
   const int tid = threadIdx.x;
-  const int lf = tid / T, e = tid - lf * T;
+  const int lc = tid / T, e = tid - lc * T;
   const int e0 = e % N1, e1 = e / N1;
-  const int64_t face = (int64_t)blockIdx.x * FPW + lf;
-  const bool live = face < n_faces;
-  const int64_t fc = live ? face : 0;
-  // face = (f index along d) * n^2 + tangential cell (ta + n tb), f = parity + 2 * (face / n^2)
+  // XCD-contiguous block order: block b runs on XCD b % 8 and takes the (b / 8)-th block of that
+  // XCD's contiguous share (a bijection for any grid size)
+  const int64_t G = gridDim.x, q8 = G / 8, r8 = G % 8;
+  const int64_t x8 = blockIdx.x % 8, i8 = blockIdx.x / 8;
+  const int64_t blk = (x8 < r8 ? x8 * (q8 + 1) : r8 * (q8 + 1) + (x8 - r8) * q8) + i8;
+  const int64_t cell0 = blk * CPW;
+  const int64_t cell = cell0 + lc;
+  const bool live = cell < n_cells;
+  const int64_t K = live ? cell : 0;
+  const int64_t base = K * NQ;
+  Real y[N1];
+  dg_cell_term<P, Real>(src, base, live, lds, lc, e, h, sh, tb.w, y);
+  __syncthreads();
+  Real* R = lds + lc * NQ;  // this cell's result, node order (contiguous over the workgroup's cells)
+#pragma unroll
+  for (int a = 0; a < N1; ++a) R[a + N1 * e] = y[a];
+  Real* Fa = lds + CPW * NQ + lc * 4 * T;  // four face arrays of this cell
+  Real* Ga = lds + CPW * NQ + CPW * 4 * T + lc * 4 * T;
+  const int64_t ijk[3] = {K % n, (K / n) % n, K / ((int64_t)n * n)};
   const int64_t nn = (int64_t)n * n;
-  const int f = parity + 2 * (int)(fc / nn);
-  const int ta = (int)(fc % nn) % n, tb2 = (int)(fc % nn) / n;
-  int64_t cL = -1, cR = -1;
-  {
-    int64_t ijk[3];
-    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-    ijk[t1] = ta;
-    ijk[t2] = tb2;
-    ijk[d] = f;
-    if (f < n) cR = ijk[0] + n * (ijk[1] + (int64_t)n * ijk[2]);
-    ijk[d] = f - 1;
-    if (f > 0) cL = ijk[0] + n * (ijk[1] + (int64_t)n * ijk[2]);
-  }
-  const bool hasL = live && cL >= 0, hasR = live && cR >= 0;
   const Real ih = (Real)1 / h;
-  Real uL[N1], uR[N1];
-#pragma unroll
-  for (int a = 0; a < N1; ++a) {
-    uL[a] = hasL ? src[cL * NQ + face_local<N1>(d, a, e0, e1)] : (Real)0;
-    uR[a] = hasR ? src[cR * NQ + face_local<N1>(d, a, e0, e1)] : (Real)0;
-  }
-  Real dnL = 0, dnR = 0;
-#pragma unroll
-  for (int a = 0; a < N1; ++a) {
-    dnL = fmad(tb.d1[a], uL[a], dnL);
-    dnR = fmad(tb.d0[a], uR[a], dnR);
-  }
-  dnL *= ih;
-  dnR *= ih;
-  const bool interior = hasL && hasR;
-  const Real jump = uL[N1 - 1] - uR[0];
-  const Real mean = interior ? (Real)0.5 * (dnL + dnR) : dnL + dnR;  // one of them is zero on a boundary face
-  const Real dfac = interior ? (Real)0.5 : (Real)1;
-  Real* F0 = lds + lf * T;
-  Real* F1 = F0 + FPW * T;
-  Real* G0 = F1 + FPW * T;
-  Real* G1 = G0 + FPW * T;
-  // nodes -> Gauss points, first tangential direction: lane (q1 = e0, a2 = e1)
-  F0[e] = jump;
-  F1[e] = mean;
-  __syncthreads();
-  {
-    Real sj = 0, sm = 0;
-#pragma unroll
-    for (int a1 = 0; a1 < N1; ++a1) {
-      sj = fmad(tb.S[e0 * N1 + a1], F0[a1 + N1 * e1], sj);
-      sm = fmad(tb.S[e0 * N1 + a1], F1[a1 + N1 * e1], sm);
-    }
-    G0[e] = sj;
-    G1[e] = sm;
-  }
-  __syncthreads();
-  // second tangential direction: lane (q1 = e0, q2 = e1) at its Gauss point
-  Real jq = 0, mq = 0;
-#pragma unroll
-  for (int a2 = 0; a2 < N1; ++a2) {
-    jq = fmad(tb.S[e1 * N1 + a2], G0[e0 + N1 * a2], jq);
-    mq = fmad(tb.S[e1 * N1 + a2], G1[e0 + N1 * a2], mq);
-  }
-  Real w0 = 0, w1 = 0;
-#pragma unroll
-  for (int k = 0; k < N1; ++k) {
-    w0 = e0 == k ? tb.w[k] : w0;
-    w1 = e1 == k ? tb.w[k] : w1;
-  }
-  const Real W = h * h * w0 * w1;
-  const Real cval = W * (sigma * jq - mq);
-  const Real cder = -dfac * W * jq;
-  __syncthreads();
-  // Gauss points -> nodes (transposed), second direction first: lane (q1 = e0, a2 = e1)
-  F0[e] = cval;
-  F1[e] = cder;
-  __syncthreads();
-  {
-    Real sv = 0, sd = 0;
-#pragma unroll
-    for (int q2 = 0; q2 < N1; ++q2) {
-      sv = fmad(tb.S[q2 * N1 + e1], F0[e0 + N1 * q2], sv);
-      sd = fmad(tb.S[q2 * N1 + e1], F1[e0 + N1 * q2], sd);
-    }
-    G0[e] = sv;
-    G1[e] = sd;
-  }
-  __syncthreads();
-  // first direction: lane (a1 = e0, a2 = e1) gets its face node's coefficients
-  Real V = 0, Dd = 0;
-#pragma unroll
-  for (int q1 = 0; q1 < N1; ++q1) {
-    V = fmad(tb.S[q1 * N1 + e0], G0[q1 + N1 * e1], V);
-    Dd = fmad(tb.S[q1 * N1 + e0], G1[q1 + N1 * e1], Dd);
-  }
-  Dd *= ih;
-  // add: value part on the face node, derivative part along the normal line
-  if (hasL)
+#pragma unroll 1
+  for (int d = 0; d < 3; ++d) {
+    const int64_t stride = d == 0 ? 1 : d == 1 ? n : nn;
+    const bool hasLo = live && ijk[d] > 0, hasHi = live && ijk[d] < n - 1;
+    Real uK[N1], uLo[N1], uHi[N1];
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
-      Real* p = dst + cL * NQ + face_local<N1>(d, a, e0, e1);
-      *p += (a == N1 - 1 ? V : (Real)0) + Dd * tb.d1[a];
+      const int loc = face_local<N1>(d, a, e0, e1);
+      uK[a] = live ? src[base + loc] : (Real)0;
+      uLo[a] = hasLo ? src[base - stride * NQ + loc] : (Real)0;
+      uHi[a] = hasHi ? src[base + stride * NQ + loc] : (Real)0;
     }
-  if (hasR)
+    Real dK0 = 0, dK1 = 0, dLo = 0, dHi = 0;
 #pragma unroll
     for (int a = 0; a < N1; ++a) {
-      Real* p = dst + cR * NQ + face_local<N1>(d, a, e0, e1);
-      *p += (a == 0 ? -V : (Real)0) + Dd * tb.d0[a];
+      dK0 = fmad(tb.d0[a], uK[a], dK0);
+      dK1 = fmad(tb.d1[a], uK[a], dK1);
+      dLo = fmad(tb.d1[a], uLo[a], dLo);
+      dHi = fmad(tb.d0[a], uHi[a], dHi);
     }
+    // lower face (this cell on its upper side) and upper face (this cell on its lower side): jump
+    // and mean normal derivative at the face nodes
+    Fa[e] = uLo[N1 - 1] - uK[0];
+    Fa[T + e] = hasLo ? (Real)0.5 * ih * (dLo + dK0) : ih * dK0;
+    Fa[2 * T + e] = uK[N1 - 1] - uHi[0];
+    Fa[3 * T + e] = hasHi ? (Real)0.5 * ih * (dK1 + dHi) : ih * dK1;
+    __syncthreads();
+    // The face terms are the face mass matrix h^2 (M x M) applied to sigma [u] - {d_n u} (value
+    // part) and to [u] (derivative part); M = S^T diag(w) S is the Gauss rule's 1D mass matrix,
+    // so the interpolation to the face points and back collapses into one 1D pass per direction.
+    // First tangential direction: lane (a1 = e0, a2 = e1)
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Real acc = 0;
+#pragma unroll
+      for (int b1 = 0; b1 < N1; ++b1) acc = fmad(tb.M[e0 * N1 + b1], Fa[k * T + b1 + N1 * e1], acc);
+      Ga[k * T + e] = acc;
+    }
+    __syncthreads();
+    Real g[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      Real acc = 0;
+#pragma unroll
+      for (int b2 = 0; b2 < N1; ++b2) acc = fmad(tb.M[e1 * N1 + b2], Ga[k * T + e0 + N1 * b2], acc);
+      g[k] = acc;
+    }
+    const Real fLo = hasLo ? (Real)0.5 : (Real)1, fHi = hasHi ? (Real)0.5 : (Real)1;
+    const Real h2 = h * h;
+    const Real VLo = h2 * (sigma * g[0] - g[1]), DLo = -fLo * h * g[0];
+    const Real VHi = h2 * (sigma * g[2] - g[3]), DHi = -fHi * h * g[2];
+    // value part on the face layer, derivative part along the normal line (this lane's own line:
+    // no other lane touches it in this direction)
+#pragma unroll
+    for (int a = 0; a < N1; ++a) {
+      const int loc = face_local<N1>(d, a, e0, e1);
+      R[loc] += (a == 0 ? -VLo : (Real)0) + (a == N1 - 1 ? VHi : (Real)0) + DLo * tb.d0[a] + DHi * tb.d1[a];
+    }
+  }
+  __syncthreads();
+  // coalesced store of the workgroup's cells
+  const int64_t limit = (n_cells - cell0) * NQ;
+  Real* out = dst + cell0 * NQ;
+  for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
+    if (i < limit) out[i] = lds[i];
 }
 
 template <int P, typename Real>
@@ -316,26 +301,13 @@ hipError_t dg_vmult_pr(int n, const Real* src, Real* dst, hipStream_t st) {
   using C = DgCell<P>;
   static const DgTables<P, Real> tb = make_dg_tables<P, Real>();
   static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
-  DgWeights<P, Real> wt;
-  for (int a = 0; a <= P; ++a) wt.w[a] = tb.w[a];
   const Real h = (Real)(1.0 / n);
   const Real sigma = (Real)(2.0 * (P + 1) * (P + 1) * n);
   const int64_t cells = (int64_t)n * n * n;
   const int64_t g = (cells + C::CPW - 1) / C::CPW;
   if (g > 0x7fffffff) return hipErrorInvalidValue;
-  dg_cell_kernel<P, Real><<<(unsigned)g, C::THREADS, 0, st>>>(src, dst, cells, h, sh, wt);
-  hipError_t e = hipGetLastError();
-  if (e != hipSuccess) return e;
-  for (int d = 0; d < 3; ++d)
-    for (int parity = 0; parity < 2; ++parity) {
-      if (parity > n) continue;
-      const int64_t nf = (int64_t)((n - parity) / 2 + 1) * n * n;
-      const int64_t gf = (nf + C::CPW - 1) / C::CPW;
-      dg_face_kernel<P, Real><<<(unsigned)gf, C::THREADS, 0, st>>>(src, dst, n, d, parity, nf, h, sigma, tb);
-      e = hipGetLastError();
-      if (e != hipSuccess) return e;
-    }
-  return hipSuccess;
+  dg_fused_kernel<P, Real><<<(unsigned)g, C::THREADS, 0, st>>>(src, dst, n, cells, h, sigma, sh, tb);
+  return hipGetLastError();
 }
 
 template <int P>

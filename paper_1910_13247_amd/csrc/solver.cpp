@@ -972,7 +972,19 @@ struct mfq_dg_solver {
   double* trace = nullptr;
   double* trace_host = nullptr;
   double lmin = 0, lmax = 0;
+  // the V-cycle captured as a HIP graph per (stream, r, z); replayed instead of its several
+  // hundred launches
+  struct VcycleGraph {
+    hipStream_t st = nullptr;
+    const double* r = nullptr;
+    double* z = nullptr;
+    hipGraphExec_t exec = nullptr;
+  };
+  VcycleGraph graphs[2];
+  int next_graph = 0;
   ~mfq_dg_solver() {
+    for (VcycleGraph& g : graphs)
+      if (g.exec) (void)hipGraphExecDestroy(g.exec);
     if (trace_host) (void)hipHostFree(trace_host);
     mfq_solver_destroy(cg);
     mfq_op_destroy(cg_op);
@@ -1020,10 +1032,43 @@ int dg_vcycle(mfq_dg_solver* s, hipStream_t st) {
   return dg_chebyshev(s, false, st);
 }
 
-int dg_precondition(mfq_dg_solver* s, const double* r, double* z, hipStream_t st) {
+int dg_precondition_direct(mfq_dg_solver* s, const double* r, double* z, hipStream_t st) {
   MFQ_HIP(launch_cast(MFQ_FP64, r, MFQ_FP32, s->b, s->N, st));
   if (int rc = dg_vcycle(s, st)) return rc;
   MFQ_HIP(launch_cast(MFQ_FP32, s->x, MFQ_FP64, z, s->N, st));
+  return MFQ_OK;
+}
+
+// Graph replay on a non-default stream when no step of the V-cycle waits on the host (dense or
+// Chebyshev coarse solve of the continuous hierarchy).
+int dg_precondition(mfq_dg_solver* s, const double* r, double* z, hipStream_t st) {
+  if (!s->prm.use_graphs || st == nullptr || !(s->cg->dense || s->cg->prm.coarse_mode == 1))
+    return dg_precondition_direct(s, r, z, st);
+  hipGraphExec_t exec = nullptr;
+  for (auto& g : s->graphs)
+    if (g.exec && g.st == st && g.r == r && g.z == z) exec = g.exec;
+  if (!exec) {
+    hipGraph_t graph = nullptr;
+    MFQ_HIP(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+    const int rc = dg_precondition_direct(s, r, z, st);
+    const hipError_t e = hipStreamEndCapture(st, &graph);
+    if (rc) {
+      if (graph) (void)hipGraphDestroy(graph);
+      return rc;
+    }
+    if (e != hipSuccess) return fail(MFQ_EHIP, "capture of the V-cycle failed: %s", hipGetErrorString(e));
+    const hipError_t e2 = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+    (void)hipGraphDestroy(graph);
+    if (e2 != hipSuccess) return fail(MFQ_EHIP, "graph instantiation failed: %s", hipGetErrorString(e2));
+    auto& slot = s->graphs[s->next_graph];
+    s->next_graph = (s->next_graph + 1) % 2;
+    if (slot.exec) (void)hipGraphExecDestroy(slot.exec);
+    slot.st = st;
+    slot.r = r;
+    slot.z = z;
+    slot.exec = exec;
+  }
+  MFQ_HIP(hipGraphLaunch(exec, st));
   return MFQ_OK;
 }
 
