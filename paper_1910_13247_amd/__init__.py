@@ -39,7 +39,8 @@ def _dtype(precision):
 
 def _release(obj, destroy):
     """Destroy obj's library handle once.  At interpreter shutdown the binding module may already
-    be torn down; the process is ending, so the handle is left to it then."""
+    be torn down; the process is ending, so the handle is left to it then.  (Each __del__ binds
+    this function as a default argument, which outlives the module's globals.)"""
     h = getattr(obj, "handle", None)
     obj.handle = None
     if h and _lib is not None and getattr(_lib, "_lib", None) is not None:
@@ -61,7 +62,7 @@ class Mesh:
         self.amplitude = float(amplitude)
         self.handle = _lib.mfq_mesh_create(self.n, self.amplitude)
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self, "mfq_mesh_destroy")
 
 
@@ -90,7 +91,7 @@ class Space:
         _lib.mfq_space_apply_mask(self.handle, precision, _check_vec(x, self.n_dofs, precision, "x"), _stream(stream))
         return x
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self, "mfq_space_destroy")
 
 
@@ -160,7 +161,7 @@ class Operator:
                            work.data_ptr(), _stream(stream))
         return x
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self, "mfq_op_destroy")
 
 
@@ -214,7 +215,7 @@ class DGOperator:
                              _check_vec(out, self.cg_n_dofs, prec, "out"), _stream(stream))
         return out
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self, "mfq_dg_destroy")
 
 
@@ -254,7 +255,7 @@ class DGSolver:
                                  _check_vec(z, self.op.n_dofs, MFQ_FP64, "z"), _stream(stream))
         return z
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self, "mfq_dg_solver_destroy")
 
 
@@ -297,7 +298,7 @@ class SparseMatrix:
                           _check_vec(dst, self.n_rows, self.precision, "dst"), _stream(stream))
         return dst
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self, "mfq_csr_destroy")
 
 
@@ -318,7 +319,7 @@ class Transfer:
                           _check_vec(coarse_vec, self.coarse.n_dofs, precision, "coarse"), _stream(stream))
         return coarse_vec
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self, "mfq_transfer_destroy")
 
 
@@ -376,5 +377,5 @@ class Solver:
     def lambdas(self, n_levels):
         return _lib.mfq_solver_lambdas(self.handle, max(n_levels - 1, 0))
 
-    def __del__(self):
+    def __del__(self, _release=_release):
         _release(self, "mfq_solver_destroy")

@@ -278,9 +278,18 @@ __device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, co
 // One launch per colour, one workgroup per brick of exactly NT threads (one per pencil; the
 // hardware masks the lanes of a partial last wave, so no lane is idle and no LDS is set aside for
 // idle lanes); ACC adds A src into dst instead of overwriting it.
-template <int P, typename Real, bool ACC>
+// Gauss weights and cell size for the operator of undeformed (axis-parallel cube) cells with
+// coefficient 1, whose quadrature tensors are G_q = h w_r w_s w_t I and need not be read.
+template <int P, typename Real>
+struct CartQuad {
+  Real w[P + 1];
+  Real h;
+};
+
+template <int P, typename Real, bool ACC, bool CART = false>
 __global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo, const Real* __restrict__ src,
-                  Real* __restrict__ dst, Bricks bk, int colour, ShapeEO<P, Real> sh) {
+                  Real* __restrict__ dst, Bricks bk, int colour, ShapeEO<P, Real> sh,
+                  CartQuad<P, Real> cq = {}) {
   using C = Cell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NCELL = C::NCELL, NT = C::NT, LX = C::LX, LY = C::LY, NL = C::NL;
   constexpr int BLOCK = NT;                        // threads of the workgroup
@@ -314,14 +323,27 @@ __global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restric
   // the wave fetches anyway) and zero them.  A branch around the loads would make the compiler wait
   // for all outstanding loads at the join, G included, before the dependent source gather.
   auto load_g = [&]() {
-    const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + (cell_in ? tid : 0);
+    if constexpr (CART) {
+      // G = h w_r w_s w_t I: kept in g[t][0].x (the diagonal), weights selected with compile-time indices
+      Real w0 = 0, w1 = 0;
 #pragma unroll
-    for (int t = 0; t < N1; ++t)
-#pragma unroll
-      for (int m = 0; m < 3; ++m) {
-        const Real2<Real> v = __builtin_nontemporal_load(gp + (t * 3 + m) * NT);
-        g[t][m] = cell_in ? v : Real2<Real>{0, 0};
+      for (int k = 0; k < N1; ++k) {
+        w0 = e0 == k ? cq.w[k] : w0;
+        w1 = e1 == k ? cq.w[k] : w1;
       }
+      const Real c = cell_in ? cq.h * w0 * w1 : (Real)0;
+#pragma unroll
+      for (int t = 0; t < N1; ++t) g[t][0] = Real2<Real>{c * cq.w[t], 0};
+    } else {
+      const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + (cell_in ? tid : 0);
+#pragma unroll
+      for (int t = 0; t < N1; ++t)
+#pragma unroll
+        for (int m = 0; m < 3; ++m) {
+          const Real2<Real> v = __builtin_nontemporal_load(gp + (t * 3 + m) * NT);
+          g[t][m] = cell_in ? v : Real2<Real>{0, 0};
+        }
+    }
   };
 
   // this thread's lattice nodes: index lattice first, then G (not needed before the z
@@ -388,11 +410,18 @@ __global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restric
     Real vx[N1], vy[N1], vz[N1];
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
-      // (G00 G01 G02; G01 G11 G12; G02 G12 G22) = (G0.x G0.y G1.x; . G1.y G2.x; . . G2.y)
-      const Real2<Real> G0 = g[t][0], G1 = g[t][1], G2 = g[t][2];
-      vx[t] = G0.x * gx[t] + G0.y * gy[t] + G1.x * gz[t];
-      vy[t] = G0.y * gx[t] + G1.y * gy[t] + G2.x * gz[t];
-      vz[t] = G1.x * gx[t] + G2.x * gy[t] + G2.y * gz[t];
+      if constexpr (CART) {
+        const Real c = g[t][0].x;
+        vx[t] = c * gx[t];
+        vy[t] = c * gy[t];
+        vz[t] = c * gz[t];
+      } else {
+        // (G00 G01 G02; G01 G11 G12; G02 G12 G22) = (G0.x G0.y G1.x; . G1.y G2.x; . . G2.y)
+        const Real2<Real> G0 = g[t][0], G1 = g[t][1], G2 = g[t][2];
+        vx[t] = G0.x * gx[t] + G0.y * gy[t] + G1.x * gz[t];
+        vy[t] = G0.y * gx[t] + G1.y * gy[t] + G2.x * gz[t];
+        vz[t] = G1.x * gx[t] + G2.x * gy[t] + G2.y * gz[t];
+      }
     }
     Real Az[N1], Bz[N1], Cz[N1];
     eo_apply<N1, 1, true>(sh.S, vx, Bz);
@@ -1076,10 +1105,25 @@ hipError_t geometry_export_p(const OpView& v, int precision, double* out, hipStr
 template <int P, typename Real>
 hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipStream_t st) {
   static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
+  // undeformed cells and coefficient 1: the quadrature tensors are h w_r w_s w_t I (the
+  // specialised mapping of axis-parallel box cells), formed in registers instead of read
+  const bool cart = v.amplitude == 0.0 && v.alpha == 0.0;
+  CartQuad<P, Real> cq{};
+  if (cart) {
+    const Tables1D& tb = tables(P);
+    for (int a = 0; a <= P; ++a) cq.w[a] = (Real)tb.omega[a];
+    cq.h = (Real)(1.0 / v.n);
+  }
   for (int c = 0; c < kColours; ++c) {
     const int64_t nb = v.bricks.count[c];
     if (nb == 0) continue;
-    if (acc)
+    if (cart && acc)
+      vmult_kernel<P, Real, true, true><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(
+          v.idx, (const Real*)v.geo, (const Real*)src, (Real*)dst, v.bricks, c, sh, cq);
+    else if (cart)
+      vmult_kernel<P, Real, false, true><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(
+          v.idx, (const Real*)v.geo, (const Real*)src, (Real*)dst, v.bricks, c, sh, cq);
+    else if (acc)
       vmult_kernel<P, Real, true><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
                                                                    (Real*)dst, v.bricks, c, sh);
     else

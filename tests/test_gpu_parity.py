@@ -58,15 +58,17 @@ def test_vmult_fp64_matches_assembled_matrix(p, amp, alpha, bc):
 
 
 @pytest.mark.parametrize("p", range(1, 9))
-def test_vmult_fp32_within_rounding_bound(p):
+@pytest.mark.parametrize("amp,alpha", [(0.1, 0.5), (0.0, 0.0)])
+def test_vmult_fp32_within_rounding_bound(p, amp, alpha):
+    """(0, 0): undeformed cells, coefficient 1, the path that forms G_q = h w I in registers."""
     n = SIZES[p]
     mfq = _mfq()
-    op = _op(p, n, 0.1, 0.5, 1, mfq.MFQ_FP32)
+    op = _op(p, n, amp, alpha, 1, mfq.MFQ_FP32)
     x = uniform_vector(op.n_dofs, seed=10 + p)
     x32 = x.astype(np.float32).astype(np.float64)     # the input the FP32 path sees
     y = _run(op, x)
-    yo = assemble.operator_csr(p, n, 0.1, 0.5, 1) @ x32
-    mag = ebe.magnitude_bound(p, n, 0.1, 0.5, x32, 1)
+    yo = assemble.operator_csr(p, n, amp, alpha, 1) @ x32
+    mag = ebe.magnitude_bound(p, n, amp, alpha, x32, 1)
     k = 8 * (p + 1) + 16
     assert np.all(np.abs(y - yo) <= 2 * k * U32 * mag + 1e-30)
     print(f"p={p} fp32 normwise rel err {np.abs(y - yo).max() / np.abs(yo).max():.2e}")
