@@ -197,11 +197,30 @@ struct DgFused {
   static constexpr int PER_CELL = 3 * NQ > NQ + 8 * T ? 3 * NQ : NQ + 8 * T;
 };
 
+// What the kernel does with its result v = (A src)_i before storing (one pass over the vectors,
+// fused with the operator):
+//   kStore:    dst = v
+//   kChebStep: r -= v; dnew = c1 src + c2 dinv r; x += dnew   (a Chebyshev step, src = d; dnew
+//              must be another buffer since other cells still read src)
+//   kResidual: r = b - v
+enum DgEpilogueMode { kStore = 0, kChebStep = 1, kResidual = 2 };
+template <typename Real>
+struct DgEpilogue {
+  int mode;
+  Real* dst;
+  const Real* b;
+  const Real* dinv;
+  Real* x;
+  Real* r;
+  Real* dnew;
+  Real c1, c2;
+};
+
 template <int P, typename Real>
-__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_fused_kernel(const Real* __restrict__ src,
-                                                                      Real* __restrict__ dst, int n,
+__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_fused_kernel(const Real* __restrict__ src, int n,
                                                                       int64_t n_cells, Real h, Real sigma,
-                                                                      ShapeEO<P, Real> sh, DgTables<P, Real> tb) {
+                                                                      ShapeEO<P, Real> sh, DgTables<P, Real> tb,
+                                                                      DgEpilogue<Real> ep) {
   using F = DgFused<P>;
   constexpr int N1 = F::N1, T = F::T, NQ = F::NQ, CPW = F::CPW;
   __shared__ Real lds[CPW * F::PER_CELL];
@@ -289,15 +308,41 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) void dg_fused_kernel(const Real
     }
   }
   __syncthreads();
-  // coalesced store of the workgroup's cells
+  // coalesced pass over the workgroup's cells
   const int64_t limit = (n_cells - cell0) * NQ;
-  Real* out = dst + cell0 * NQ;
-  for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
-    if (i < limit) out[i] = lds[i];
+  const int64_t g0 = cell0 * NQ;
+  if (ep.mode == kStore) {
+    for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
+      if (i < limit) ep.dst[g0 + i] = lds[i];
+  } else if (ep.mode == kChebStep) {
+    for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
+      if (i < limit) {
+        const int64_t gi = g0 + i;
+        const Real rv = ep.r[gi] - lds[i];
+        const Real dv = ep.c1 * src[gi] + ep.c2 * ep.dinv[gi] * rv;
+        ep.r[gi] = rv;
+        ep.dnew[gi] = dv;
+        ep.x[gi] += dv;
+      }
+  } else {
+    for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
+      if (i < limit) ep.r[g0 + i] = ep.b[g0 + i] - lds[i];
+  }
 }
 
+struct DgApplyArgs {
+  int mode;
+  void* dst;
+  const void* b;
+  const void* dinv;
+  void* x;
+  void* r;
+  void* dnew;
+  double c1, c2;
+};
+
 template <int P, typename Real>
-hipError_t dg_vmult_pr(int n, const Real* src, Real* dst, hipStream_t st) {
+hipError_t dg_apply_pr(int n, const Real* src, const DgEpilogue<Real>& ep, hipStream_t st) {
   using C = DgCell<P>;
   static const DgTables<P, Real> tb = make_dg_tables<P, Real>();
   static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
@@ -306,14 +351,34 @@ hipError_t dg_vmult_pr(int n, const Real* src, Real* dst, hipStream_t st) {
   const int64_t cells = (int64_t)n * n * n;
   const int64_t g = (cells + C::CPW - 1) / C::CPW;
   if (g > 0x7fffffff) return hipErrorInvalidValue;
-  dg_fused_kernel<P, Real><<<(unsigned)g, C::THREADS, 0, st>>>(src, dst, n, cells, h, sigma, sh, tb);
+  dg_fused_kernel<P, Real><<<(unsigned)g, C::THREADS, 0, st>>>(src, n, cells, h, sigma, sh, tb, ep);
   return hipGetLastError();
 }
 
 template <int P>
-hipError_t dg_vmult_p(int n, int precision, const void* src, void* dst, hipStream_t st) {
-  if (precision == MFQ_FP64) return dg_vmult_pr<P, double>(n, (const double*)src, (double*)dst, st);
-  return dg_vmult_pr<P, float>(n, (const float*)src, (float*)dst, st);
+hipError_t dg_apply_p(int n, int precision, const void* src, const DgApplyArgs& a, hipStream_t st) {
+  if (precision == MFQ_FP64) {
+    const DgEpilogue<double> ep{a.mode, (double*)a.dst, (const double*)a.b, (const double*)a.dinv, (double*)a.x,
+                                (double*)a.r, (double*)a.dnew, a.c1, a.c2};
+    return dg_apply_pr<P, double>(n, (const double*)src, ep, st);
+  }
+  const DgEpilogue<float> ep{a.mode, (float*)a.dst, (const float*)a.b, (const float*)a.dinv, (float*)a.x,
+                             (float*)a.r, (float*)a.dnew, (float)a.c1, (float)a.c2};
+  return dg_apply_pr<P, float>(n, (const float*)src, ep, st);
+}
+
+hipError_t dg_apply(int p, int n, int precision, const void* src, const DgApplyArgs& a, hipStream_t st) {
+  switch (p) {
+    case 1: return dg_apply_p<1>(n, precision, src, a, st);
+    case 2: return dg_apply_p<2>(n, precision, src, a, st);
+    case 3: return dg_apply_p<3>(n, precision, src, a, st);
+    case 4: return dg_apply_p<4>(n, precision, src, a, st);
+    case 5: return dg_apply_p<5>(n, precision, src, a, st);
+    case 6: return dg_apply_p<6>(n, precision, src, a, st);
+    case 7: return dg_apply_p<7>(n, precision, src, a, st);
+    case 8: return dg_apply_p<8>(n, precision, src, a, st);
+    default: return hipErrorInvalidValue;
+  }
 }
 
 // Jacobi diagonal of the DG-SIPG matrix in closed form.  With m_a = sum_q w_q S_qa^2 and
@@ -417,17 +482,31 @@ int dg_grid(int64_t work) {
 }  // namespace
 
 hipError_t launch_dg_vmult(int p, int n, int precision, const void* src, void* dst, hipStream_t st) {
-  switch (p) {
-    case 1: return dg_vmult_p<1>(n, precision, src, dst, st);
-    case 2: return dg_vmult_p<2>(n, precision, src, dst, st);
-    case 3: return dg_vmult_p<3>(n, precision, src, dst, st);
-    case 4: return dg_vmult_p<4>(n, precision, src, dst, st);
-    case 5: return dg_vmult_p<5>(n, precision, src, dst, st);
-    case 6: return dg_vmult_p<6>(n, precision, src, dst, st);
-    case 7: return dg_vmult_p<7>(n, precision, src, dst, st);
-    case 8: return dg_vmult_p<8>(n, precision, src, dst, st);
-    default: return hipErrorInvalidValue;
-  }
+  DgApplyArgs a{};
+  a.mode = kStore;
+  a.dst = dst;
+  return dg_apply(p, n, precision, src, a, st);
+}
+
+hipError_t launch_dg_cheb_step(int p, int n, int precision, const void* d, const void* dinv, void* x, void* r,
+                               void* dnew, double c1, double c2, hipStream_t st) {
+  DgApplyArgs a{};
+  a.mode = kChebStep;
+  a.dinv = dinv;
+  a.x = x;
+  a.r = r;
+  a.dnew = dnew;
+  a.c1 = c1;
+  a.c2 = c2;
+  return dg_apply(p, n, precision, d, a, st);
+}
+
+hipError_t launch_dg_residual(int p, int n, int precision, const void* b, const void* x, void* r, hipStream_t st) {
+  DgApplyArgs a{};
+  a.mode = kResidual;
+  a.b = b;
+  a.r = r;
+  return dg_apply(p, n, precision, x, a, st);
 }
 
 hipError_t launch_dg_diagonal(int p, int n, int precision, void* diag, hipStream_t st) {

@@ -241,6 +241,12 @@ int64_t csr_row_start_host(int64_t I, int64_t J, int64_t K, int p, int n);
 // DG-SIPG operator (kernels_dg.hip): dst = A src (cell term stored, face terms added), its
 // Jacobi diagonal, and the transfer between the continuous Q_p lattice and DG on the same mesh
 hipError_t launch_dg_vmult(int p, int n, int precision, const void* src, void* dst, hipStream_t st);
+// Chebyshev step fused with the DG product (vectors of `precision`, n_dofs each): r -= A d;
+// dnew = c1 d + c2 dinv r; x += dnew.  dnew must not alias d, x or r.
+hipError_t launch_dg_cheb_step(int p, int n, int precision, const void* d, const void* dinv, void* x, void* r,
+                               void* dnew, double c1, double c2, hipStream_t st);
+// r = b - A x with the DG product
+hipError_t launch_dg_residual(int p, int n, int precision, const void* b, const void* x, void* r, hipStream_t st);
 hipError_t launch_dg_diagonal(int p, int n, int precision, void* diag, hipStream_t st);
 hipError_t launch_dg_transfer(int p, int n, int precision, bool to_dg, const void* in, void* out, hipStream_t st);
 

@@ -1009,10 +1009,15 @@ int dg_chebyshev(mfq_dg_solver* s, bool x_is_zero, hipStream_t st) {
   if (!x_is_zero)
     if (int rc = dg_apply(s, MFQ_FP32, s->x, s->t, st)) return rc;
   MFQ_HIP(launch_cheb_first(MFQ_FP32, s->b, s->t, s->dinv, s->x, s->r, s->d, n, 1.0 / theta, x_is_zero, st));
+  // each further step is one launch: the DG product of d with the vector update in its epilogue;
+  // d alternates between the d and t buffers (other cells still read the old d)
+  float* dc = s->d;
+  float* dn = s->t;
   for (int k = 1; k < s->prm.smoother_degree; ++k) {
-    if (int rc = dg_apply(s, MFQ_FP32, s->d, s->t, st)) return rc;
     const double rho_new = 1.0 / (2.0 * sigma - rho);
-    MFQ_HIP(launch_cheb_step(MFQ_FP32, s->t, s->dinv, s->x, s->r, s->d, n, rho_new * rho, 2.0 * rho_new / delta, st));
+    MFQ_HIP(launch_dg_cheb_step(s->op->p, s->op->n, MFQ_FP32, dc, s->dinv, s->x, s->r, dn, rho_new * rho,
+                                2.0 * rho_new / delta, st));
+    std::swap(dc, dn);
     rho = rho_new;
   }
   return MFQ_OK;
@@ -1021,8 +1026,7 @@ int dg_chebyshev(mfq_dg_solver* s, bool x_is_zero, hipStream_t st) {
 int dg_vcycle(mfq_dg_solver* s, hipStream_t st) {
   const int p = s->op->p, n = s->op->n;
   if (int rc = dg_chebyshev(s, true, st)) return rc;
-  if (int rc = dg_apply(s, MFQ_FP32, s->x, s->t, st)) return rc;
-  MFQ_HIP(launch_sub(MFQ_FP32, s->b, s->t, s->r, s->N, st));
+  MFQ_HIP(launch_dg_residual(p, n, MFQ_FP32, s->b, s->x, s->r, st));
   // the continuous hierarchy's finest level holds FP32 vectors of the same mesh and degree
   Level& F = s->cg->lv.back();
   MFQ_HIP(launch_dg_transfer(p, n, MFQ_FP32, false, s->r, F.b, st));
