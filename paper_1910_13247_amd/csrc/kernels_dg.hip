@@ -21,6 +21,12 @@
 // result is written once with coalesced stores; the neighbours' lines come from the caches.
 #include "kernels_common.hpp"
 
+// Ask for at least 5 waves per SIMD: the register allocation then fits 5 workgroups per CU at
+// p = 4 FP64 (96 instead of 126 VGPRs, no spills at any degree), which the LDS use also allows.
+#ifndef MFQ_DG_WAVES
+#define MFQ_DG_WAVES __attribute__((amdgpu_waves_per_eu(5, 8)))
+#endif
+
 namespace mfq {
 namespace {
 
@@ -217,7 +223,7 @@ struct DgEpilogue {
 };
 
 template <int P, typename Real>
-__global__ __launch_bounds__(DgCell<P>::THREADS) void dg_fused_kernel(const Real* __restrict__ src, int n,
+__global__ __launch_bounds__(DgCell<P>::THREADS) MFQ_DG_WAVES void dg_fused_kernel(const Real* __restrict__ src, int n,
                                                                       int64_t n_cells, Real h, Real sigma,
                                                                       ShapeEO<P, Real> sh, DgTables<P, Real> tb,
                                                                       DgEpilogue<Real> ep) {
