@@ -260,3 +260,19 @@ def test_dg_vcycle_graph_matches_direct_launches():
     assert abs(infod.iterations - infog.iterations) <= 1
     assert infod.rel_residual <= 1e-10 and infog.rel_residual <= 1e-10
     assert (xd - xg).abs().max().item() <= 1e-8 * xd.abs().max().item()
+
+
+def test_dg_solver_zero_and_nonfinite_rhs():
+    """b = 0 returns x = 0 at once; a NaN in b ends with MFQ_ENONFINITE (no hang, info filled)."""
+    torch = _torch()
+    mfq, op, b_np = _dg_system(2, 3, seed=5)
+    sv = mfq.DGSolver(op)
+    z = torch.zeros(op.n_dofs, dtype=torch.float64, device="cuda")
+    x, info, st = sv.solve(z, rtol=1e-10)
+    torch.cuda.synchronize()
+    assert st == mfq.MFQ_OK and info.iterations == 0 and x.abs().max().item() == 0.0
+    b = torch.from_numpy(b_np).cuda()
+    b[17] = float("nan")
+    x, info, st = sv.solve(b, rtol=1e-10, max_iter=50, check=False)
+    torch.cuda.synchronize()
+    assert st == mfq.MFQ_ENONFINITE
