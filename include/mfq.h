@@ -336,7 +336,9 @@ int mfq_solver_lambdas(const mfq_solver* s, double* out, int n_out);
  * Jacobi-PCG steps on the DG level), the residual moved to the continuous space by
  * mfq_dg_transfer(to_dg = 0), one V-cycle of a GMG_MIXED solver of the continuous Q_p Laplacian
  * (Dirichlet nodes, coefficient 1) with the same parameters, the correction moved back by
- * mfq_dg_transfer(to_dg = 1), post-smoothing.  params NULL: mfq_solver_default_params with
+ * mfq_dg_transfer(to_dg = 1), post-smoothing.  lambda_override, if given, lists lmax of the
+ * continuous levels 1.. (finest last, as for mfq_solver_create) followed by the DG level's.
+ * params NULL: mfq_solver_default_params with
  * smoother_degree 6, the Chebyshev degree of the paper's experiment.  The DG operator must
  * outlive the solver. */
 int mfq_dg_solver_create(const mfq_dg* op, const mfq_solver_params* params, mfq_dg_solver** out);

@@ -23,6 +23,7 @@ import numpy as np
 import scipy.sparse as sp
 
 from .element import element_matrices, reference_tabulation
+from .gmg import chebyshev, vcycle as cg_vcycle
 from .mesh import boundary_mask, cell_dofs
 from .tables import gauss, gll_nodes, lagrange_derivs, lagrange_values
 
@@ -249,3 +250,17 @@ def cg_embedding(p, n):
     vals = boundary_mask(p, n)[cols]
     N = n_dofs(p, n)
     return sp.csr_matrix((vals, (np.arange(N), cols)), shape=(N, (p * n + 1) ** 3))
+
+
+def vcycle(A, dinv, E, b, lmin, lmax, cg_levels, cg_prolong, degree=6):
+    """One V-cycle of the multigrid of the paper's DG experiment (Sec. 6.1) applied to b: Chebyshev
+    smoothing of the DG system (Jacobi, interval [lmin, lmax] of D^{-1}A, from zero), the residual
+    moved to the continuous space on the same mesh by E^T, one V-cycle of the continuous hierarchy
+    (same smoother degree, exact coarse solve), the correction moved back by E, and the same
+    smoothing again from the corrected iterate."""
+    apply = lambda v: A @ v
+    x = chebyshev(apply, dinv, b, None, degree, lmin, lmax)
+    r = b - apply(x)
+    ec = cg_vcycle(cg_levels, cg_prolong, len(cg_levels) - 1, E.T @ r, degree)
+    x = x + E @ ec
+    return chebyshev(apply, dinv, b, x, degree, lmin, lmax)

@@ -223,13 +223,19 @@ class DGSolver:
     """FP64 CG on a DGOperator preconditioned by the FP32 V-cycle DG -> continuous Q_p -> the
     continuous hierarchy (see mfq_dg_solver_create)."""
 
-    def __init__(self, dg, stream=None, device="cuda", **params):
+    def __init__(self, dg, stream=None, device="cuda", lambda_override=None, **params):
         torch = _torch()
+        import ctypes
         self.op = dg
         prm = _lib.mfq_solver_default_params()
         params.setdefault("smoother_degree", 6)     # the Chebyshev degree of the paper's DG runs
         for k, v in params.items():
             setattr(prm, k, v)
+        if lambda_override is not None:
+            # lmax of the continuous levels 1.. (finest last), then of the DG level
+            self._lam = (ctypes.c_double * len(lambda_override))(*lambda_override)
+            prm.n_lambda_override = len(lambda_override)
+            prm.lambda_override = ctypes.cast(self._lam, ctypes.POINTER(ctypes.c_double))
         self.params = prm
         self.handle = _lib.mfq_dg_solver_create(dg.handle, prm)
         self.device_bytes = _lib.mfq_dg_solver_device_bytes(self.handle)

@@ -1165,6 +1165,15 @@ int mfq_dg_solver_bind(mfq_dg_solver* s, void* dev_buf, size_t bytes, void* hip_
   // Jacobi diagonal and the largest eigenvalue of D^{-1}A on the DG level (FP32 Lanczos)
   MFQ_HIP(launch_dg_diagonal(s->op->p, s->op->n, MFQ_FP32, s->dinv, st));
   MFQ_HIP(launch_reciprocal(MFQ_FP32, s->dinv, s->N, st));
+  // lambda_override: the continuous levels' entries (levels 1.. of that hierarchy), then the DG
+  // level's
+  const int dg_idx = (int)s->cg->lv.size() - 1;
+  if (s->prm.lambda_override && s->prm.n_lambda_override > dg_idx) {
+    s->lmax = s->prm.lambda_override[dg_idx];
+    s->lmin = s->lmax / s->prm.lambda_ratio;
+    MFQ_HIP(hipStreamSynchronize(st));
+    return MFQ_OK;
+  }
   const int k = s->prm.lanczos_iters;
   MFQ_HIP(launch_splitmix(MFQ_FP32, s->r, (int64_t)s->op->n * (s->op->p + 1), 0, false, st));
   MFQ_HIP(launch_lz_init(MFQ_FP32, s->r, s->dinv, s->d, s->t, s->N, s->aux, s->trace, 2 * k, st));

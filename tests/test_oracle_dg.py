@@ -95,3 +95,31 @@ def test_magnitude_bounds_the_matrix(p, n):
     # diagonal of the cell term: a sum of squares, so no cancellation
     Ac = dg.element_matrices(p, n, 0.0, 0.0, np.array([0]))[0]
     assert np.allclose(np.diag(dg.cell_magnitude(p, n)), np.diag(Ac), rtol=1e-13)
+
+
+def _dg_multigrid(p, n):
+    from oracle import gmg
+    A = dg.assemble(p, n)
+    dinv = 1.0 / A.diagonal()
+    E = dg.cg_embedding(p, n)
+    levels, prolong = gmg.build_hierarchy(p, n, 0.0, 0.0, bc=1)
+    for L in levels[1:]:
+        L.estimate()
+    v0 = gmg.splitmix64_uniform(A.shape[0], 0)
+    lmax = 1.2 * gmg.lanczos_lambda_max(lambda v: A @ v, dinv, v0, 12)
+    return A, dinv, E, levels, prolong, lmax
+
+
+@pytest.mark.parametrize("p,n", [(1, 2), (2, 2)])
+def test_dg_vcycle_is_a_convergent_symmetric_preconditioner(p, n):
+    """The V-cycle as a matrix M (columns from unit vectors): symmetric (the same smoother before
+    and after, E^T and E, an exact symmetric coarse solve), positive definite, and I - M A
+    contracts (spectral radius well below 1)."""
+    A, dinv, E, levels, prolong, lmax = _dg_multigrid(p, n)
+    N = A.shape[0]
+    M = np.column_stack([dg.vcycle(A, dinv, E, np.eye(N)[:, j], lmax / 15, lmax, levels, prolong)
+                         for j in range(N)])
+    assert np.abs(M - M.T).max() <= 1e-10 * np.abs(M).max()
+    assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
+    rho = np.abs(np.linalg.eigvals(np.eye(N) - M @ A.toarray())).max()
+    assert rho < 0.3, rho
