@@ -494,8 +494,8 @@ def main():
                     help="also run 3 plain device copies of 1 GiB (reference reading for HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: this build has no multi-GPU path (see DESIGN.md for how it "
-              "would shard); run with --gpus 1", file=sys.stderr)
+        print("bench.py measures one GPU: the library has no multi-GPU path (the operator, CG and "
+              "multigrid run on one device); run with --gpus 1", file=sys.stderr)
         sys.exit(2)
 
     import numpy as np
