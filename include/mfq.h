@@ -287,7 +287,8 @@ int mfq_solver_create(const mfq_op* op_fp64, int kind, const mfq_solver_params* 
 void mfq_solver_destroy(mfq_solver* s);
 int mfq_solver_device_bytes(const mfq_solver* s, size_t* bytes);
 /* Binds the buffer; builds the level operators, diagonals, eigenvalue bounds and the coarse
- * inverse.  Synchronises the stream. */
+ * inverse.  Synchronises the stream.  May be called again (another buffer, or after the operator
+ * was re-bound): captured HIP graphs are dropped. */
 int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream);
 /* Solves A x = b to ||b - A x||_2 <= rtol ||b||_2 from x = 0 (x overwritten).  b, x: double
  * device vectors.  Blocks until done.  MFQ_ENOCONV when max_iter is reached (info valid).

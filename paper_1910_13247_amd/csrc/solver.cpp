@@ -723,6 +723,11 @@ int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream
   if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) % 256)) return fail(MFQ_EINVAL, "buffer NULL or misaligned");
   if (bytes < s->bytes) return fail(MFQ_ENOMEM, "buffer of %zu bytes, solver needs %zu", bytes, s->bytes);
   hipStream_t st = (hipStream_t)hip_stream;
+  // captured iterations refer to the previous buffer's vectors and the operators' current data
+  for (auto& g : s->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = mfq_solver::IterGraph{};
+  }
   if (!s->hstat) {
     MFQ_HIP(hipHostMalloc((void**)&s->hstat, sizeof(mfq_solver::HostStatus), hipHostMallocDefault));
     std::memset(s->hstat, 0, sizeof(mfq_solver::HostStatus));
@@ -1138,6 +1143,11 @@ int mfq_dg_solver_bind(mfq_dg_solver* s, void* dev_buf, size_t bytes, void* hip_
   if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) % 256)) return fail(MFQ_EINVAL, "buffer NULL or misaligned");
   if (bytes < s->bytes) return fail(MFQ_ENOMEM, "buffer of %zu bytes, solver needs %zu", bytes, s->bytes);
   hipStream_t st = (hipStream_t)hip_stream;
+  // captured V-cycles refer to the previous buffer's vectors
+  for (auto& g : s->graphs) {
+    if (g.exec) (void)hipGraphExecDestroy(g.exec);
+    g = mfq_dg_solver::VcycleGraph{};
+  }
   char* base = (char*)dev_buf;
   size_t ob = 0, sb = 0;
   mfq_op_device_bytes(s->cg_op, &ob);

@@ -330,3 +330,32 @@ def test_dg_solve_bench_size_certified_by_oracle_rows():
     rows = np.concatenate([rng.integers(0, op.n_dofs, 195), [0, nloc - 1, op.n_dofs - 1, 31 * nloc + 62, 20 * nloc]])
     r = b_np[rows] - dg.dg_rows(p, n, xn, rows)
     assert np.abs(r).max() <= 1e-10 * np.linalg.norm(b_np) * (1 + 1e-3)
+
+
+def test_dg_solver_rebind_drops_captured_graphs():
+    """Binding the solver to another buffer drops the captured V-cycle: with the old buffer filled
+    with NaN (and kept allocated), the next V-cycle on the same stream still equals the first."""
+    torch = _torch()
+    mfq, op, b_np = _dg_system(3, 4, seed=12)
+    sv = mfq.DGSolver(op)
+    side = torch.cuda.Stream()
+    r = torch.from_numpy(b_np).cuda()
+    torch.cuda.synchronize()
+    z = torch.empty_like(r)                              # one output vector: one graph key
+    with torch.cuda.stream(side):
+        z1 = sv.precondition(r, z, stream=side).clone()  # captured
+        z1b = sv.precondition(r, z, stream=side).clone()  # replayed
+    torch.cuda.synchronize()
+    old = sv.buffer
+    new = torch.empty_like(old)
+    mfq._lib.mfq_dg_solver_bind(sv.handle, new.data_ptr(), sv.device_bytes, side.cuda_stream)
+    sv.buffer = new
+    old.fill_(255)                                       # every float in it is now a NaN
+    torch.cuda.synchronize()
+    with torch.cuda.stream(side):
+        z2 = sv.precondition(r, z, stream=side).clone()  # same key: must not replay the old graph
+    torch.cuda.synchronize()
+    assert torch.isfinite(z2).all()
+    assert (z2 - z1).abs().max().item() <= 1e-5 * z1.abs().max().item()
+    assert (z1b - z1).abs().max().item() <= 1e-5 * z1.abs().max().item()
+    del old

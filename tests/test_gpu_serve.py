@@ -241,3 +241,37 @@ def test_async_step_protocol():
     status, info = sv.end()
     torch.cuda.synchronize()
     assert status == mfq.MFQ_OK and info.rel_residual <= 1e-10
+
+
+def test_solver_rebind_drops_captured_graphs():
+    """A solver bound to another buffer does not replay iterations captured on the old one: with
+    the old buffer filled with NaN (and kept allocated) the next solve on the same stream still
+    converges to the same solution."""
+    mfq = _mfq()
+    torch = _torch()
+    m = mfq.Mesh(6, 0.1)
+    s = mfq.Space(m, 2, mfq.MFQ_BC_DIRICHLET0)
+    op = mfq.Operator(s, 0.3, mfq.MFQ_FP64)
+    b = s.random(5)
+    st = torch.cuda.Stream()
+    torch.cuda.synchronize()
+    sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, coarse_mode=1)
+    xs = []
+    x = op.new_vector()                  # one solution vector: the graphs' key stays the same
+    for k in range(2):
+        if k == 1:
+            old = sv.buffer
+            new = torch.empty_like(old)
+            mfq._lib.mfq_solver_bind(sv.handle, new.data_ptr(), sv.device_bytes, st.cuda_stream)
+            sv.buffer = new
+            old.fill_(255)
+            torch.cuda.synchronize()
+        sv.begin(b, x, rtol=1e-10, max_iter=200, stream=st)
+        while not mfq.batch_step([sv], iters=3)[0]:
+            pass
+        status, info = sv.end()
+        torch.cuda.synchronize()
+        assert status == mfq.MFQ_OK and info.rel_residual <= 1e-10
+        xs.append(x.clone())
+    assert (xs[0] - xs[1]).abs().max().item() <= 1e-8 * xs[0].abs().max().item()
+    del old
