@@ -309,10 +309,10 @@ def small_poisson(steps, warmup):
 
 def dg_benchmark(steps, warmup, degree=4, cells_1d=64):
     """The symmetric interior penalty DG Laplacian of the paper's multigrid experiment (degree 4,
-    undeformed 64^3 mesh, 32,768,000 DoFs), one matrix-free application: one cell-term launch and
-    six face launches.  Algorithmic bytes: read the source and write the result once (16 B per
-    DoF; the affine cells store no geometry); the face launches re-read both cells of each face
-    and update their results, which the HBM traffic pays on top."""
+    undeformed 64^3 mesh, 32,768,000 DoFs), one matrix-free application: one launch, each cell's
+    volume term and six faces.  Algorithmic bytes: read the source and write the result once (16 B
+    per DoF; the affine cells store no geometry); the neighbours' normal lines that miss in the
+    caches are fetched again on top."""
     import torch
     import paper_1910_13247_amd as mfq
     from synthetic import uniform_vector
