@@ -341,7 +341,8 @@ int mfq_solver_lambdas(const mfq_solver* s, double* out, int n_out);
  * mfq_dg_transfer(to_dg = 1), post-smoothing.  lambda_override, if given, lists lmax of the
  * continuous levels 1.. (finest last, as for mfq_solver_create) followed by the DG level's.
  * params NULL: mfq_solver_default_params with
- * smoother_degree 6, the Chebyshev degree of the paper's experiment.  The DG operator must
+ * smoother_degree 6, the Chebyshev degree of the paper's experiment.  Needs p n >= 2 (the
+ * continuous level must have an interior node; MFQ_EINVAL otherwise).  The DG operator must
  * outlive the solver. */
 int mfq_dg_solver_create(const mfq_dg* op, const mfq_solver_params* params, mfq_dg_solver** out);
 void mfq_dg_solver_destroy(mfq_dg_solver* s);

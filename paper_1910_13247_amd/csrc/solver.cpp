@@ -1100,6 +1100,10 @@ int mfq_dg_solver_create(const mfq_dg* op, const mfq_solver_params* params, mfq_
     delete s;
     return fail(MFQ_EINVAL, "smoother_degree must be >= 1 and lanczos_iters >= 2");
   }
+  if (op->p * op->n < 2) {
+    delete s;
+    return fail(MFQ_EINVAL, "the continuous level has no interior node (p n = %d); need p n >= 2", op->p * op->n);
+  }
   s->N = op->n_dofs;
   int rc = mfq_mesh_create(op->n, 0.0, &s->mesh);
   if (rc == MFQ_OK) rc = mfq_space_create(s->mesh, op->p, MFQ_BC_DIRICHLET0, &s->space);

@@ -203,6 +203,13 @@ def test_dg_host_validation():
     with pytest.raises(lib.MfqError) as e:
         lib.mfq_dg_solver_create(g, prm)
     assert e.value.status == lib.MFQ_EINVAL
+    m1 = lib.mfq_mesh_create(1, 0.0)
+    g1 = lib.mfq_dg_create(m1, 1)                     # Q1 on one cell: no interior lattice node
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_dg_solver_create(g1)
+    assert e.value.status == lib.MFQ_EINVAL
+    lib.mfq_dg_destroy(g1)
+    lib.mfq_mesh_destroy(m1)
     lib.mfq_dg_destroy(g)
     with pytest.raises(lib.MfqError):
         lib.mfq_dg_create(m, 9)

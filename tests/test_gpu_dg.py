@@ -173,7 +173,7 @@ def _dg_system(p, n, seed):
     return mfq, op, b
 
 
-@pytest.mark.parametrize("p,n", [(1, 8), (2, 6), (3, 4), (4, 4), (4, 5), (6, 2)])
+@pytest.mark.parametrize("p,n", [(1, 2), (2, 1), (1, 8), (2, 6), (3, 4), (4, 4), (4, 5), (6, 2)])
 def test_dg_solver_matches_direct_solve(p, n):
     """FP64 CG with the FP32 DG -> continuous V-cycle: certified FP64 residual, and the solution
     equal to a sparse direct solve of the oracle's assembled DG matrix within what the 1e-10
