@@ -195,19 +195,21 @@ def load_vector(p, n, f):
     return out
 
 
-def dg_rows(p, n, x, rows):
+def dg_rows(p, n, x, rows, magnitude=False):
     """Entries `rows` of A x for the DG-SIPG matrix, each from its cell's matrix and that cell's
-    six faces: the sampled form of ``assemble`` for meshes too large to assemble."""
+    six faces: the sampled form of ``assemble`` for meshes too large to assemble.  magnitude=True:
+    the same rows of the magnitude matrix of ``assemble(p, n, magnitude=True)``."""
     N1 = p + 1
     nloc = N1 ** 3
     sig = penalty(p, n)
     tr, dn, W = _face_tables(p, n)
-    Ak = {}
-    Mint = [face_matrix(np.hstack([tr[d][1], -tr[d][0]]), 0.5 * np.hstack([dn[d][1], dn[d][0]]), W, sig)
+    fmat = face_magnitude if magnitude else face_matrix
+    Mint = [fmat(np.hstack([tr[d][1], -tr[d][0]]), 0.5 * np.hstack([dn[d][1], dn[d][0]]), W, sig)
             for d in range(3)]
-    Mlo = [face_matrix(-tr[d][0], dn[d][0], W, sig) for d in range(3)]
-    Mhi = [face_matrix(tr[d][1], dn[d][1], W, sig) for d in range(3)]
-    Acell = element_matrices(p, n, 0.0, 0.0, np.array([0]))[0]   # affine, coefficient 1: same for every cell
+    Mlo = [fmat(-tr[d][0], dn[d][0], W, sig) for d in range(3)]
+    Mhi = [fmat(tr[d][1], dn[d][1], W, sig) for d in range(3)]
+    # affine cells, coefficient 1: the same cell matrix for every cell
+    Acell = cell_magnitude(p, n) if magnitude else element_matrices(p, n, 0.0, 0.0, np.array([0]))[0]
     out = np.empty(len(rows))
     for r, g in enumerate(rows):
         K, il = divmod(int(g), nloc)

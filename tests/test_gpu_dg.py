@@ -359,3 +359,26 @@ def test_dg_solver_rebind_drops_captured_graphs():
     assert (z2 - z1).abs().max().item() <= 1e-5 * z1.abs().max().item()
     assert (z1b - z1).abs().max().item() <= 1e-5 * z1.abs().max().item()
     del old
+
+
+def test_dg_full_size_q4_64_fp32_sampled():
+    """FP32 DG product at Q4 64^3 (32,768,000 DoFs): 300 sampled rows within the componentwise FP32
+    bound 2 k u32 (M |x32|)_i, rows of the oracle's product and magnitude matrix recomputed one by
+    one from the cell and its six faces."""
+    torch = _torch()
+    mfq = _mfq()
+    p, n = 4, 64
+    print("dg full-size Q4 64^3 fp32", flush=True)
+    op = mfq.DGOperator(mfq.Mesh(n, 0.0), p)
+    x = uniform_vector(op.n_dofs, seed=6)
+    x32 = x.astype(np.float32).astype(np.float64)
+    y = op.vmult(_torch_vec(x, torch.float32))
+    torch.cuda.synchronize()
+    y = y.double().cpu().numpy()
+    nloc = (p + 1) ** 3
+    rng = np.random.default_rng(8)
+    rows = np.concatenate([rng.integers(0, op.n_dofs, 295), [0, nloc - 1, op.n_dofs - 1, 63 * nloc + 124, 4096 * nloc]])
+    yo = dg.dg_rows(p, n, x32, rows)
+    mag = dg.dg_rows(p, n, np.abs(x32), rows, magnitude=True)
+    k = 8 * (p + 1) + 16
+    assert np.all(np.abs(y[rows] - yo) <= 2 * k * U32 * mag + 1e-30)

@@ -123,3 +123,12 @@ def test_dg_vcycle_is_a_convergent_symmetric_preconditioner(p, n):
     assert np.linalg.eigvalsh(0.5 * (M + M.T)).min() > 0
     rho = np.abs(np.linalg.eigvals(np.eye(N) - M @ A.toarray())).max()
     assert rho < 0.3, rho
+
+
+def test_sampled_magnitude_rows_match_assembly():
+    p, n = 2, 3
+    M = dg.assemble(p, n, magnitude=True)
+    x = np.abs(np.random.default_rng(2).uniform(-1, 1, dg.n_dofs(p, n)))
+    rows = np.random.default_rng(3).integers(0, dg.n_dofs(p, n), 40)
+    y = M @ x
+    assert np.abs(dg.dg_rows(p, n, x, rows, magnitude=True) - y[rows]).max() <= 1e-12 * np.abs(y).max()
