@@ -23,6 +23,13 @@
 
 // Ask for at least 5 waves per SIMD: the register allocation then fits 5 workgroups per CU at
 // p = 4 FP64 (96 instead of 126 VGPRs, no spills at any degree), which the LDS use also allows.
+// Lanes per workgroup that the cells fill (one lane per 1D pencil): 128 up to degree 4 (5 cells of
+// 25 lanes at p = 4; fewer waves wait at each of the kernel's barriers), 256 above (at p >= 6 a
+// 128-lane workgroup holds a single cell).
+#ifndef MFQ_DG_LANES
+#define MFQ_DG_LANES(P) ((P) <= 4 ? 128 : 256)
+#endif
+
 #ifndef MFQ_DG_WAVES
 #define MFQ_DG_WAVES __attribute__((amdgpu_waves_per_eu(5, 8)))
 #endif
@@ -67,7 +74,7 @@ struct DgCell {
   static constexpr int N1 = P + 1;
   static constexpr int T = N1 * N1;
   static constexpr int NQ = N1 * T;
-  static constexpr int CPW = 256 / T > 0 ? 256 / T : 1;  // cells (or faces) per workgroup
+  static constexpr int CPW = MFQ_DG_LANES(P) / T > 0 ? MFQ_DG_LANES(P) / T : 1;  // cells per workgroup
   static constexpr int THREADS = CPW * T;
 };
 
