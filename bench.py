@@ -8,7 +8,7 @@ DoFs/s of the step, the roofline of the dominant kernel (the cell loop, timed wi
 on its stream), an FP32 figure of the same operator, the same operator assembled as a sparse
 matrix and applied by the library's CSR product, the DG-SIPG Q4 operator of the paper's
 multigrid experiment and its V-cycle and solve, time to 1e-10 of the Q3 128^3 multigrid and CG
-solvers, a 400-request serving stream (solves/s, p50/p99 latency), and the CPU oracle on a
+solvers, the 2,000-request serving stream (solves/s, p50/p99 latency), and the CPU oracle on a
 bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--no-cpu-baseline] [--no-solves] [--serve N] [--no-csr]
@@ -70,6 +70,105 @@ def algorithmic_bytes(p, n, real_bytes):
 def algorithmic_flops(p, n):
     C = n ** 3
     return C * (24 * (p + 1) ** 4 + 15 * (p + 1) ** 3)
+
+
+# ---------------------------------------------------------------- algorithmic bytes of solves
+# Byte counts of the solvers' algorithmic traffic, from the operators' algorithmic bytes (above)
+# and the vector streams each step reads or writes once (b bytes per value):
+#   FP64 CG iteration: p.Ap (2 streams), x += a p, r -= a Ap (6), r.z (2), p = z + beta p (3);
+#     unpreconditioned: z = r, no r.z pass (11);
+#   V-cycle level l >= 1 (Chebyshev degree k, V(1,1)): pre-smoothing from zero = first step (read
+#     b, dinv; write r, d, x: 5) + (k-1) x (operator + step: read Ad, dinv, x, r, d; write r, d, x:
+#     8); residual = operator + (read b, t; write r: 3); restriction (read the fine residual, write
+#     the coarse right-hand side: N_l + N_{l-1}); prolongation (read coarse, write fine: N_{l-1} +
+#     N_l); x += t (3); post-smoothing = operator + first step (read b, t, dinv, x; write r, d, x:
+#     7) + (k-1) x (operator + 8): 2k operator applications and 5 + 8(k-1) + 3 + 3 + 7 + 8(k-1)
+#     vector streams, plus the two transfers;
+#   coarsest level: dense inverse (nf^2 FP64 values read, b and x) or Chebyshev of the coarse
+#     degree from zero (5 + (deg-1) x (operator + 8));
+#   FP32 V-cycle under FP64 CG: casts of r in and z out (8 + 4 bytes per DoF each way);
+#   each correction pass: the FP64 residual check (operator + read b, t, write r: 3 x 8 N).
+def hierarchy(p, n, limit=4096):
+    """(p, n) per multigrid level, coarsest first: halve n while even and > limit free DoFs, then p ->
+    ceil(p/2) (the library's rule)."""
+    free = lambda p_, n_: max(p_ * n_ - 1, 0) ** 3
+    lv = [(p, n)]
+    while n % 2 == 0 and free(p, n) > limit:
+        n //= 2
+        lv.append((p, n))
+    while p > 1 and free(p, n) > limit:
+        p = (p + 1) // 2
+        lv.append((p, n))
+    return lv[::-1]
+
+
+def vcycle_bytes(levels, b, smoother_degree=3, coarse_mode=0, coarse_degree=16, cart=False):
+    """Algorithmic bytes of one V-cycle over `levels` (coarsest first) in value size b."""
+    N = [(p_ * n_ + 1) ** 3 for p_, n_ in levels]
+    k = smoother_degree
+    op = lambda l: algorithmic_bytes(levels[l][0], levels[l][1], b) - (6 * b * levels[l][1] ** 3 *
+                                                                        (levels[l][0] + 1) ** 3 if cart else 0)
+    tot = 0
+    for l in range(1, len(levels)):
+        streams = 5 + 8 * (k - 1) + 3 + 3 + 7 + 8 * (k - 1)
+        tot += 2 * k * op(l) + streams * b * N[l] + 2 * b * (N[l] + N[l - 1])
+    p0, n0 = levels[0]
+    if coarse_mode == 1:
+        tot += (coarse_degree - 1) * op(0) + (5 + 8 * (coarse_degree - 1)) * b * N[0]
+    else:
+        nf = max(p0 * n0 - 1, 0) ** 3
+        tot += 8 * nf * nf + 2 * b * N[0]
+    return tot
+
+
+def solve_bytes(kind, p, n, iterations, passes, smoother_degree=3, coarse_mode=0, coarse_degree=16, cart=False):
+    """Algorithmic bytes of a whole solve (iterations summed over passes, `passes` residual checks)."""
+    N = (p * n + 1) ** 3
+    op64 = algorithmic_bytes(p, n, 8) - (48 * n ** 3 * (p + 1) ** 3 if cart else 0)
+    check = op64 + 3 * 8 * N
+    if kind == "cg_fp64":
+        return iterations * (op64 + 11 * 8 * N) + passes * check
+    lv = hierarchy(p, n)
+    if kind == "gmg_fp64":
+        vc = vcycle_bytes(lv, 8, smoother_degree, coarse_mode, coarse_degree, cart)
+        return iterations * (op64 + 13 * 8 * N + vc) + passes * check
+    vc = vcycle_bytes(lv, 4, smoother_degree, coarse_mode, coarse_degree, cart) + 24 * N
+    if kind == "gmg_mixed":
+        return iterations * (op64 + 13 * 8 * N + vc) + passes * check
+    # gmg_mixed_ir: inner CG on the FP32 operator (casts p in and Ap out: 24 B per DoF) with FP64
+    # vectors; each pass also adds its correction into x (3 x 8 N)
+    op32 = algorithmic_bytes(p, n, 4) - (24 * n ** 3 * (p + 1) ** 3 if cart else 0)
+    return iterations * (op32 + 24 * N + 13 * 8 * N + vc) + passes * (check + 3 * 8 * N)
+
+
+def setup_bytes(p, n, smoother_degree=3, coarse_mode=1, lanczos=12):
+    """Algorithmic bytes of a solver's set-up on the device: index maps and geometry written for the
+    FP64 operator and every FP32 level, each level's diagonal (operator data read, diagonal
+    written), and the Lanczos steps (operator + about 10 vector streams each)."""
+    lv = hierarchy(p, n)
+    tot = 0
+    for l, (pl, nl) in enumerate(lv):
+        Nl = (pl * nl + 1) ** 3
+        geo4 = algorithmic_bytes(pl, nl, 4) - 8 * Nl           # idx + G in FP32
+        tot += geo4 + geo4 + 4 * Nl                             # written, read back by the diagonal
+        if l > 0 or coarse_mode == 1:
+            tot += lanczos * (algorithmic_bytes(pl, nl, 4) + 10 * 4 * Nl)
+    N = (p * n + 1) ** 3
+    tot += algorithmic_bytes(p, n, 8) - 16 * N                 # FP64 operator's idx + G written
+    return tot
+
+
+def copy_bandwidth(gib=1, reps=5):
+    """HBM bandwidth of a plain device copy (torch, 1 GiB): bytes read + written per second."""
+    import torch
+    a = torch.empty(gib << 27, dtype=torch.float64, device="cuda").uniform_()
+    b = torch.empty_like(a)
+    s = time_events(lambda: b.copy_(a), reps, 2)
+    nbytes = 2 * a.numel() * 8
+    del a, b
+    torch.cuda.synchronize()
+    return {"bytes_per_copy": nbytes, "ms": s * 1e3, "GB_per_s": nbytes / s / 1e9,
+            "frac_of_peak": nbytes / s / 1e9 / HBM_PEAK_GBS}
 
 
 def time_vmult(op, x, steps, warmup):
@@ -169,6 +268,24 @@ def high_degree_comparison(steps, warmup):
         out[name] = rec
         del op, y
         torch.cuda.synchronize()
+    # the workload's solve: FP64 iterative refinement around the FP32 inner CG and V-cycle
+    # (levels 3^3 .. 24^3), manufactured right-hand side, to 1e-10; timed on its second solve
+    op = mfq.Operator(space, pr.alpha, mfq.MFQ_FP64)
+    b = op.rhs_manufactured()
+    sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED_IR)
+    sv.solve(b, rtol=1e-10, max_iter=300, check=False)
+    torch.cuda.synchronize()
+    x, info, st = sv.solve(b, rtol=1e-10, max_iter=300, check=False)
+    torch.cuda.synchronize()
+    lb = solve_bytes("gmg_mixed_ir", pr.degree, pr.cells_1d, info.iterations, info.outer_iterations)
+    out["solve_gmg_mixed_ir"] = {"seconds": info.seconds, "iterations": info.iterations,
+                                 "outer": info.outer_iterations, "rel_residual": info.rel_residual,
+                                 "status": st, "levels": info.n_levels, "algorithmic_bytes": lb,
+                                 "roofline_lower_bound_s": lb / (HBM_PEAK_GBS * 1e9),
+                                 "roofline_frac": lb / (HBM_PEAK_GBS * 1e9) / info.seconds}
+    out["_solution"] = (b.cpu().numpy(), x.cpu().numpy())
+    del sv, op, b, x
+    torch.cuda.synchronize()
     return out
 
 
@@ -275,8 +392,11 @@ def solve_benchmarks(steps, kinds=None):
             s.solve(b, rtol=1e-10, max_iter=20000, check=False)
             torch.cuda.synchronize()
         x, info, st = s.solve(b, rtol=1e-10, max_iter=20000, check=False)
+        lb = solve_bytes(name, 3, 128, info.iterations, info.outer_iterations)
         out[name] = {"seconds": info.seconds, "iterations": info.iterations, "outer": info.outer_iterations,
-                     "rel_residual": info.rel_residual, "status": st, "levels": info.n_levels}
+                     "rel_residual": info.rel_residual, "status": st, "levels": info.n_levels,
+                     "algorithmic_bytes": lb, "roofline_lower_bound_s": lb / (HBM_PEAK_GBS * 1e9),
+                     "roofline_frac": lb / (HBM_PEAK_GBS * 1e9) / info.seconds}
         del s
         torch.cuda.synchronize()
     return out
@@ -358,6 +478,26 @@ def cpu_small_poisson():
             ctx.__exit__(None, None, None)
     return {"workload": pr.name, "cores": 1, "csr_spmv_us": spmv * 1e6, "cg_s": cg, "cg_iterations": it,
             "cg_rel_residual": rr}
+
+
+def q8_solve_check(b, x, n_rows=24):
+    """The Q8 24^3 solve's residual b - A x on sampled rows, the load vector and the operator rows
+    recomputed by the oracle from each row's cells, relative to ||b||_2 (every row of a solution
+    certified to 1e-10 lies within 1e-10)."""
+    import numpy as np
+    from oracle import ebe, rhs
+    from synthetic import VARCOEF_Q8_24 as pr
+    p, n = pr.degree, pr.cells_1d
+    N1 = p * n + 1
+    rng = np.random.default_rng(17)
+    rows = np.concatenate([rng.integers(0, len(b), n_rows - 2), [N1 ** 3 // 2, 24 + 7 * N1 + 9 * N1 * N1]])
+    t0 = time.perf_counter()
+    bo = rhs.rhs_rows(p, n, pr.amplitude, pr.alpha, lambda xx: rhs.manufactured_f(xx, pr.alpha), rows, 1)
+    r = bo - ebe.ebe_rows(p, n, pr.amplitude, pr.alpha, x, 1, rows)
+    nb = float(np.linalg.norm(b))
+    return {"rows": int(len(rows)), "max_abs_residual_over_norm_b": float(np.abs(r).max() / nb),
+            "load_vector_max_rel_diff": float(np.abs(b[rows] - bo).max() / np.abs(b).max()),
+            "bar": "each |r_i| <= 1e-10 ||b||_2", "seconds": time.perf_counter() - t0}
 
 
 # Q4 V-cycles beside the paper's only measurements (an FP32 V-cycle of DG Q4, Chebyshev degree 6,
@@ -459,6 +599,16 @@ def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=
     st["dofs_total"] = sum((r.degree * r.n + 1) ** 3 for r in reqs)
     st["iterations_mean"] = sum(r.iterations for r in srv.done) / max(len(srv.done), 1)
     st["not_converged"] = sum(1 for r in srv.done if r.status != 0)
+    # aggregate algorithmic traffic: every request's set-up and solve (Cartesian cell loop: the
+    # requests' meshes are undeformed; FP64 operator with its coefficient reads G)
+    prm = solver_params or {}
+    kw = dict(smoother_degree=prm.get("smoother_degree", 3), coarse_mode=prm.get("coarse_mode", 1),
+              coarse_degree=prm.get("coarse_degree", 16))
+    tot = sum(solve_bytes("gmg_mixed", r.degree, r.n, r.iterations, 1, **kw) +
+              setup_bytes(r.degree, r.n, kw["smoother_degree"], kw["coarse_mode"]) for r in srv.done)
+    st["algorithmic_bytes"] = tot
+    st["aggregate_algorithmic_GBs"] = tot / st["wall_s"] / 1e9
+    st["aggregate_frac_of_peak"] = tot / st["wall_s"] / 1e9 / HBM_PEAK_GBS
     return st
 
 
@@ -472,9 +622,9 @@ def main():
                     help="skip the time-to-1e-10 of the Q3 128^3 solvers (multigrid forms and plain FP64 CG)")
     ap.add_argument("--solve-kinds", default=",".join(SOLVE_KINDS),
                     help="which Q3 128^3 solvers to time (comma-separated subset of the default)")
-    ap.add_argument("--serve", type=int, default=400, metavar="N",
+    ap.add_argument("--serve", type=int, default=2000, metavar="N",
                     help="replay N requests of the serving stream (200 requests/s) and report solves/s, p50/p99 "
-                         "(default 400; 0 skips)")
+                         "(default 2000, the full stream; 0 skips)")
     ap.add_argument("--serve-mode", choices=["sync", "async"], default="async",
                     help="serving steps: all solves together (sync) or each at its own pace (async)")
     ap.add_argument("--serve-streams", type=int, default=8)
@@ -564,6 +714,7 @@ def main():
                  "achieved_GBs": bytes32 / kern32 / 1e9, "frac": bytes32 / kern32 / 1e9 / HBM_PEAK_GBS,
                  "normwise_rel_err_vs_fp64": rel32},
     }
+    rec["copy_kernel"] = copy_bandwidth()
     if args.copy_probe:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda").uniform_()
         b = torch.empty_like(a)
@@ -583,6 +734,7 @@ def main():
     rec["dg_sipg_q4_64"] = dg_benchmark(min(args.steps, 20), args.warmup)
     print("# Q8 24^3: FP64 / FP32 / FP32 matrix cores", file=sys.stderr, flush=True)
     rec["high_degree_q8_24"] = high_degree_comparison(min(args.steps, 20), args.warmup)
+    q8_solution = rec["high_degree_q8_24"].pop("_solution")
     if not args.no_solves:
         print("# Q3 128^3 solves to 1e-10", file=sys.stderr, flush=True)
         rec["solves_q3_128"] = solve_benchmarks(args.steps, [k for k in args.solve_kinds.split(",") if k])
@@ -603,6 +755,7 @@ def main():
         rec["cpu_baseline"] = cpu_baseline(p, n, pr.amplitude, pr.alpha, x_np, check_rows=check_rows,
                                            y64_rows=y64_rows, y32_rows=y32_rows)
         rec["cpu_baseline"]["small_poisson"] = cpu_small_poisson()
+        rec["cpu_baseline"]["q8_24_solve_check"] = q8_solve_check(*q8_solution)
     print(json.dumps(rec), flush=True)
 
 

@@ -118,20 +118,29 @@ def magnitude_bound(p, n, A, alpha, x, bc, chunk=2048):
     return y
 
 
-def abs_operator_times_abs(p, n, A, alpha, x, bc, chunk=2048):
-    """(|A_tilde| |x|): the componentwise magnitude bound used by rounding-error tolerances."""
-    x = np.abs(np.asarray(x, dtype=np.float64))
+
+def magnitude_csr(p, n, A, alpha, bc, chunk=2048):
+    """The magnitude matrix itself (scipy CSR): sum_K P_K^T (sum_q |B_q|^T |G_q| |B_q|) P_K, with
+    Dirichlet rows and columns replaced by identity rows when bc=1, so that
+    magnitude_csr(...) @ |x| == magnitude_bound(..., x, bc)."""
+    import scipy.sparse as sp
+    from .geometry import qpoint_data
+    N = n_dofs(p, n)
     C = n ** 3
-    m = boundary_mask(p, n) if bc else np.ones(n_dofs(p, n))
-    y = np.zeros_like(x)
-    tab = reference_tabulation(p)
+    _, B = reference_tabulation(p)
+    Ba = np.abs(B)
+    Q = B.shape[0]
+    rows, cols, vals = [], [], []
     for c0 in range(0, C, chunk):
         cc = np.arange(c0, min(C, c0 + chunk))
-        Ak = np.abs(element_matrices(p, n, A, alpha, cc, tab))
+        G = np.abs(qpoint_data(p, n, A, alpha, cc)["G"])
+        Ak = Ba.reshape(Q * 3, -1).T[None] @ (G @ Ba[None]).reshape(len(cc), Q * 3, -1)
         g = cell_dofs(p, n, cc)
-        yk = (Ak @ (m * x)[g][:, :, None])[:, :, 0]
-        np.add.at(y, g.reshape(-1), yk.reshape(-1))
-    y = m * y
+        rows.append(np.repeat(g[:, :, None], g.shape[1], axis=2).reshape(-1))
+        cols.append(np.repeat(g[:, None, :], g.shape[1], axis=1).reshape(-1))
+        vals.append(Ak.reshape(-1))
+    M = sp.coo_matrix((np.concatenate(vals), (np.concatenate(rows), np.concatenate(cols))), shape=(N, N)).tocsr()
     if bc:
-        y += (1.0 - m) * x
-    return y
+        m = boundary_mask(p, n)
+        M = (sp.diags(m) @ M @ sp.diags(m) + sp.diags(1.0 - m)).tocsr()
+    return M

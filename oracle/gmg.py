@@ -42,13 +42,14 @@ def n_free(p, n):
     return (p * n - 1) ** 3
 
 
-def hierarchy(p, n):
-    """List of (p, n) from coarsest to finest, by the rule in the module docstring."""
+def hierarchy(p, n, coarse_dofs=FREE_DOF_COARSE_LIMIT):
+    """List of (p, n) from coarsest to finest, by the rule in the module docstring (with the free-DoF
+    limit `coarse_dofs` in place of 4096 when given)."""
     levels = [(p, n)]
-    while n % 2 == 0 and n_free(p, n) > FREE_DOF_COARSE_LIMIT:
+    while n % 2 == 0 and n_free(p, n) > coarse_dofs:
         n //= 2
         levels.append((p, n))
-    while p > 1 and n_free(p, n) > FREE_DOF_COARSE_LIMIT:
+    while p > 1 and n_free(p, n) > coarse_dofs:
         p = (p + 1) // 2
         levels.append((p, n))
     return levels[::-1]
@@ -186,11 +187,11 @@ class Level:
         return lhat
 
 
-def build_hierarchy(p, n, A, alpha, bc=1, operator=None):
+def build_hierarchy(p, n, A, alpha, bc=1, operator=None, coarse_dofs=FREE_DOF_COARSE_LIMIT):
     """Levels (coarsest first) and prolongations P_l: level l-1 -> level l (index l)."""
     from .assemble import operator_csr
     op = operator or operator_csr
-    spec = hierarchy(p, n)
+    spec = hierarchy(p, n, coarse_dofs)
     levels = [Level(pl, nl, op(pl, nl, A, alpha, bc), bc) for (pl, nl) in spec]
     prolong = [None] + [prolongation(spec[l - 1][0], spec[l - 1][1], spec[l][0], spec[l][1], bc)
                         for l in range(1, len(spec))]

@@ -55,6 +55,34 @@ def rhs_from_function(p, n, A, alpha, f, bc=1, chunk=4096):
     return b
 
 
+def rhs_rows(p, n, A, alpha, f, rows, bc=1):
+    """Entries `rows` of ``rhs_from_function``, each summed over the cells whose closure holds the
+    row's node (the sampled form for meshes too large to assemble the whole vector)."""
+    N1 = p * n + 1
+    rows = np.asarray(rows, dtype=np.int64)
+    Phi, _ = reference_tabulation(p)
+
+    def cells_1d(I):
+        if I % p == 0:
+            return [c for c in (I // p - 1, I // p) if 0 <= c < n]
+        return [I // p]
+
+    out = np.zeros(len(rows))
+    for r, g in enumerate(rows):
+        I, J, K = g % N1, (g // N1) % N1, g // (N1 * N1)
+        if bc and (min(I, J, K) == 0 or max(I, J, K) == N1 - 1):
+            continue
+        for ck in cells_1d(K):
+            for cj in cells_1d(J):
+                for ci in cells_1d(I):
+                    cell = ci + n * cj + n * n * ck
+                    qd = qpoint_data(p, n, A, alpha, [cell])
+                    fq = f(qd["x"][0]) * qd["JxW"][0]
+                    loc = (I - p * ci) + (p + 1) * (J - p * cj) + (p + 1) ** 2 * (K - p * ck)
+                    out[r] += fq @ Phi[:, loc]
+    return out
+
+
 def rhs_manufactured(p, n, A, alpha, bc=1):
     return rhs_from_function(p, n, A, alpha, lambda x: manufactured_f(x, alpha), bc)
 

@@ -232,10 +232,14 @@ __device__ __forceinline__ void lattice_dst(const Real* __restrict__ dst, int (&
   }
 }
 
+// What scatter_lattice writes on Dirichlet rows: the source value (operator: identity rows), 1
+// (diagonal) or 0 (load vector).
+enum DirichletRow { kDirSource = 0, kDirUnit = 1, kDirZero = 2 };
+
 // Sum the cells' results per lattice node in a fixed order (cell c's result at res + c * cstride,
 // local lexicographic order) and write the brick's nodes: store or add per the `first` bit,
-// Dirichlet nodes get src (added to dst when accumulating) from the brick that stores.
-template <int P, typename Real, bool ACC, int BLOCK, int KPT, bool UNIT_DIRICHLET = false>
+// Dirichlet nodes get the DIR value (src added to dst when accumulating) from the brick that stores.
+template <int P, typename Real, bool ACC, int BLOCK, int KPT, int DIR = kDirSource>
 __device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, const Real* __restrict__ src,
                                                 Real* __restrict__ dst, const int (&gk)[KPT], unsigned first,
                                                 const Real (&dv)[KPT]) {
@@ -263,8 +267,10 @@ __device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, co
       dst[g0] = (ACC || !fj) ? dv[j] + sum : sum;
     } else if (fj) {
       const int gg = ~g0;
-      if constexpr (UNIT_DIRICHLET)
+      if constexpr (DIR == kDirUnit)
         dst[gg] = (Real)1;
+      else if constexpr (DIR == kDirZero)
+        dst[gg] = (Real)0;
       else
         dst[gg] = ACC ? dst[gg] + src[gg] : src[gg];
     }
@@ -950,28 +956,37 @@ __global__ __launch_bounds__(Cell<P>::NT) void diagonal_kernel(const int* __rest
     for (int k = 0; k < N1; ++k) L0[k + N1 * e] = t0[k] + t1[k] + t2[k];
   }
   lds_barrier();
-  scatter_lattice<P, Real, false, BLOCK, KPT, true>(lds, NQ, nullptr, diag, gk, first, dv);
+  scatter_lattice<P, Real, false, BLOCK, KPT, kDirUnit>(lds, NQ, nullptr, diag, gk, first, dv);
 }
 
 // ---------------------------------------------------------------- right-hand side
-// b_i += sum_q f(x_q) JxW_q phi_i(q) for u* = sin(pi x) sin(pi y) sin(pi z), f = -div(a grad u*).
+// b_i = sum_K sum_q f(x_q) JxW_q phi_i(q) for u* = sin(pi x) sin(pi y) sin(pi z), f = -div(a grad u*):
+// per cell the z-pencil of f JxW is tested with S^T in z, y and x (sum factorisation), the cells'
+// results are summed per node of the brick lattice and written in colour order like the
+// operator's (store, then add; 0 on Dirichlet rows): deterministic, no atomics, no clearing.
 template <int P>
-__global__ __launch_bounds__(Cell<P>::BLOCK) void rhs_kernel(const int* __restrict__ idx, double* __restrict__ b, Bricks bk,
-                                                     int n, double amp, double alpha, Shape<P, double> sh,
-                                                     QuadRule<P> qr) {
+__global__ __launch_bounds__(Cell<P>::NT) void rhs_kernel(const int* __restrict__ idx, double* __restrict__ b,
+                                                          Bricks bk, int colour, int n, double amp, double alpha,
+                                                          Shape<P, double> sh, QuadRule<P> qr) {
   using C = Cell<P>;
-  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NT = C::NT;
+  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NT = C::NT, NL = C::NL;
+  constexpr int BLOCK = NT;
+  constexpr int KPT = (NL + BLOCK - 1) / BLOCK;
   __shared__ double lds[C::NCELL * NQ];
   const int tid = threadIdx.x;
-  const bool lane_ok = tid < NT;
-  const int lc = lane_ok ? tid / T : 0;
-  const int e = lane_ok ? tid - lc * T : 0;
+  const int lc = tid / T;
+  const int e = tid - lc * T;
   const int e0 = e % N1, e1 = e / N1;
-  const int64_t ord = blockIdx.x;
+  const int64_t ord = bk.offset[colour] + blockIdx.x;
   int bi, bj, bz;
-  brick_of_ordinal(bk, ord, bi, bj, bz);
+  brick_of(bk, colour, blockIdx.x, bi, bj, bz);
   int64_t ci, cj, ck;
-  const bool active = lane_ok && cell_of<P>(bi, bj, bz, lc, n, ci, cj, ck);
+  const bool active = cell_of<P>(bi, bj, bz, lc, n, ci, cj, ck);
+  int gk[KPT];
+  unsigned first;
+  double dv[KPT];
+  lattice_index<P, BLOCK, KPT>(idx + ord * (int64_t)NL, bk, bi, bj, bz, gk, first);
+  lattice_dst<double, BLOCK, KPT, NL>(b, gk, first, dv);
   double* L0 = lds + lc * NQ;
   // z-pencil of f*JxW at points (e0, e1, t), tested with S^T in z
   double fz[N1];
@@ -998,44 +1013,46 @@ __global__ __launch_bounds__(Cell<P>::BLOCK) void rhs_kernel(const int* __restri
   }
   double bzv[N1];
   apply_t<N1>(sh.S, fz, bzv);
-  if (lane_ok)
-    for (int c = 0; c < N1; ++c) L0[e + T * c] = bzv[c];
+  for (int c = 0; c < N1; ++c) L0[e + T * c] = bzv[c];
   lds_barrier();
   double by[N1], tmp[N1];
   for (int s = 0; s < N1; ++s) tmp[s] = L0[e0 + N1 * s + T * e1];
   apply_t<N1>(sh.S, tmp, by);
   lds_barrier();
-  if (lane_ok)
-    for (int bb = 0; bb < N1; ++bb) L0[e0 + N1 * bb + T * e1] = by[bb];
+  for (int bb = 0; bb < N1; ++bb) L0[e0 + N1 * bb + T * e1] = by[bb];
   lds_barrier();
+  // x: lane (b=e0, c=e1) reads and rewrites its own row; the cell's vector in local lexicographic order
   double bx[N1];
   for (int r = 0; r < N1; ++r) tmp[r] = L0[r + N1 * e];
   apply_t<N1>(sh.S, tmp, bx);
-  if (active) {
-    for (int a = 0; a < N1; ++a) {
-      const int g = idx[ord * (int64_t)C::NL + lattice_of<P>(lc, a, e0, e1)];
-      if (g >= 0) atomic_add(b + g, bx[a]);
-    }
-  }
+  for (int a = 0; a < N1; ++a) L0[a + N1 * e] = bx[a];
+  lds_barrier();
+  scatter_lattice<P, double, false, BLOCK, KPT, kDirZero>(lds, NQ, nullptr, b, gk, first, dv);
 }
 
 // ---------------------------------------------------------------- dense assembly (coarse levels)
 // Free-free block of the assembled matrix: mat[f_i*ld + f_j] += A^K_ij, f = interior lattice index
-// (I-1) + m*((J-1) + m*(K-1)), m = N1-2.  One thread per (cell, i, j).
+// (I-1) + m*((J-1) + m*(K-1)), m = N1-2.  One thread per (cell, i, j) over the cells of one parity
+// colour (cell coordinates' parities; such cells share no node, so no two threads of a launch
+// touch one entry): one launch per colour in order, plain adds, a fixed summation order.
 template <int P>
 __global__ __launch_bounds__(kBlock) void assemble_dense_kernel(const int* __restrict__ idx, const double* __restrict__ geo,
                                                                 double* __restrict__ mat, int64_t ld, Bricks bk,
-                                                                int64_t N1g, Shape<P, double> sh) {
+                                                                int colour, int64_t N1g, Shape<P, double> sh) {
   using C = Cell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NT = C::NT;
-  const int64_t total = bk.n_bricks * C::NCELL * NQ * NQ;
+  const int n = bk.n;
+  const int px = colour & 1, py = (colour >> 1) & 1, pz = colour >> 2;
+  const int64_t cxn = (n + 1 - px) / 2, cyn = (n + 1 - py) / 2, czn = (n + 1 - pz) / 2;
+  const int64_t total = cxn * cyn * czn * NQ * NQ;
   const int64_t m = N1g - 2;
   for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < total; L += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t cellord = L / (NQ * NQ);
-    const int ij = (int)(L - cellord * NQ * NQ);
+    const int64_t cellc = L / (NQ * NQ);
+    const int ij = (int)(L - cellc * NQ * NQ);
     const int i = ij / NQ, j = ij - (ij / NQ) * NQ;
-    const int64_t ord = cellord / C::NCELL;
-    const int lc = (int)(cellord - ord * C::NCELL);
+    int lc;
+    const int64_t ord = ordinal_of_cell(bk, 2 * (cellc % cxn) + px, 2 * ((cellc / cxn) % cyn) + py,
+                                        2 * (cellc / (cxn * cyn)) + pz, lc);
     const int ai = i % N1, bi = (i / N1) % N1, ci = i / T;
     const int aj = j % N1, bj = (j / N1) % N1, cj = j / T;
     const int gi = idx[ord * (int64_t)C::NL + lattice_of<P>(lc, ai, bi, ci)];
@@ -1062,7 +1079,7 @@ __global__ __launch_bounds__(kBlock) void assemble_dense_kernel(const int* __res
     const int64_t Ij = gj % N1g, Jj = (gj / N1g) % N1g, Kj = gj / (N1g * N1g);
     const int64_t fi = (Ii - 1) + m * ((Ji - 1) + m * (Ki - 1));
     const int64_t fj = (Ij - 1) + m * ((Jj - 1) + m * (Kj - 1));
-    atomic_add(mat + fi * ld + fj, sum);
+    mat[fi * ld + fj] += sum;
   }
 }
 
@@ -1173,16 +1190,24 @@ hipError_t diagonal_p(const OpView& v, int precision, void* diag, hipStream_t st
 
 template <int P>
 hipError_t rhs_p(const OpView& v, double* b, hipStream_t st) {
-  rhs_kernel<P><<<(unsigned)v.bricks.n_bricks, Cell<P>::BLOCK, 0, st>>>(v.idx, b, v.bricks, v.n, v.amplitude, v.alpha,
-                                                                make_shape<P, double>(), make_rule<P>());
+  for (int c = 0; c < kColours; ++c) {
+    const int64_t nb = v.bricks.count[c];
+    if (nb == 0) continue;
+    rhs_kernel<P><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(v.idx, b, v.bricks, c, v.n, v.amplitude, v.alpha,
+                                                        make_shape<P, double>(), make_rule<P>());
+  }
   return hipGetLastError();
 }
 
 template <int P>
 hipError_t assemble_dense_p(const OpView& v, double* mat, int64_t ld, hipStream_t st) {
   using C = Cell<P>;
-  assemble_dense_kernel<P><<<grid_for(v.bricks.n_bricks * C::NCELL * C::NQ * C::NQ), kBlock, 0, st>>>(
-      v.idx, (const double*)v.geo, mat, ld, v.bricks, (int64_t)P * v.n + 1, make_shape<P, double>());
+  for (int c = 0; c < kColours; ++c) {
+    const int64_t cells = (int64_t)((v.n + 1 - (c & 1)) / 2) * ((v.n + 1 - ((c >> 1) & 1)) / 2) * ((v.n + 1 - (c >> 2)) / 2);
+    if (cells == 0) continue;
+    assemble_dense_kernel<P><<<grid_for(cells * C::NQ * C::NQ), kBlock, 0, st>>>(
+        v.idx, (const double*)v.geo, mat, ld, v.bricks, c, (int64_t)P * v.n + 1, make_shape<P, double>());
+  }
   return hipGetLastError();
 }
 

@@ -224,9 +224,6 @@ __device__ __forceinline__ void apply_t2(const Real* M1, const Real (&in1)[N1], 
   }
 }
 
-__device__ __forceinline__ void atomic_add(double* p, double v) { unsafeAtomicAdd(p, v); }
-__device__ __forceinline__ void atomic_add(float* p, float v) { unsafeAtomicAdd(p, v); }
-
 // Quadrature-point geometry of the deformed cube (FP64): the exact map
 // x = X + A sin(pi X1) sin(pi X2) sin(pi X3) (1,1,1) evaluated at the point, X = h*(cell + xhat).
 struct QGeo {

@@ -7,7 +7,10 @@
 // and z.  Nodes on coarse-cell faces are written by every adjacent coarse cell with bitwise
 // equal values (the 1D matrix is exactly the identity there), so plain stores suffice.
 // Restriction is the transpose: fine values are weighted by 1 / (number of coarse cells
-// containing the node) so the per-cell transposes sum to P^T, then added atomically.
+// containing the node) so the per-cell transposes sum to P^T.  Coarse cells are coloured by the
+// parities of their coordinates (cells of one colour share no coarse node); one launch per
+// colour, colours in order, each cell adding its sums into its coarse nodes with plain stores:
+// no atomics, a fixed summation order, bitwise reproducible.
 #include "kernels_common.hpp"
 
 namespace mfq {
@@ -69,12 +72,15 @@ __global__ __launch_bounds__(kTBlock) void prolongate_kernel(const Real* __restr
 
 template <int PC, int NF1, typename Real>
 __global__ __launch_bounds__(kTBlock) void restrict_kernel(const Real* __restrict__ fine, Real* __restrict__ coarse,
-                                                           int nc, int bc, Transfer1D<PC, NF1> tr) {
+                                                           int nc, int bc, int colour, Transfer1D<PC, NF1> tr) {
   constexpr int M = PC + 1;
   __shared__ Real t1[M * NF1 * NF1];  // t1[a][j][l]
   __shared__ Real t2[M * M * NF1];    // t2[a][b][l]
-  const int64_t cell = blockIdx.x;
-  const int ic = (int)(cell % nc), jc = (int)((cell / nc) % nc), kc = (int)(cell / ((int64_t)nc * nc));
+  // cell (ic, jc, kc) of colour (ic & 1) + 2 (jc & 1) + 4 (kc & 1), x fastest within the colour
+  const int px = colour & 1, py = (colour >> 1) & 1, pz = colour >> 2;
+  const int cxn = (nc + 1 - px) / 2, cyn = (nc + 1 - py) / 2;
+  const int64_t b = blockIdx.x;
+  const int ic = 2 * (int)(b % cxn) + px, jc = 2 * (int)((b / cxn) % cyn) + py, kc = 2 * (int)(b / ((int64_t)cxn * cyn)) + pz;
   const int64_t N1c = (int64_t)PC * nc + 1;
   const int stride = NF1 - 1;
   const int64_t N1f = (int64_t)stride * nc + 1;
@@ -108,7 +114,8 @@ __global__ __launch_bounds__(kTBlock) void restrict_kernel(const Real* __restric
     for (int l = 0; l < NF1; ++l) s += (Real)tr.P[l * M + c] * t2[a + M * (b + M * l)];
     const int64_t I = (int64_t)PC * ic + a, J = (int64_t)PC * jc + b, K = (int64_t)PC * kc + c;
     const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1c - 1 || J == N1c - 1 || K == N1c - 1);
-    if (!bnd) atomic_add(coarse + I + N1c * (J + N1c * K), s);
+    // this launch's cells share no coarse node; earlier colours' sums are already in place
+    if (!bnd) coarse[I + N1c * (J + N1c * K)] += s;
   }
 }
 
@@ -128,10 +135,14 @@ hipError_t transfer_pn(const mfq_transfer* t, int precision, bool prolongate, co
   } else {
     hipError_t e = launch_fill(precision, out, t->coarse->n_dofs, 0.0, st);
     if (e != hipSuccess) return e;
-    if (precision == MFQ_FP64)
-      restrict_kernel<PC, NF1, double><<<grid, kTBlock, 0, st>>>((const double*)in, (double*)out, nc, bc, tr);
-    else
-      restrict_kernel<PC, NF1, float><<<grid, kTBlock, 0, st>>>((const float*)in, (float*)out, nc, bc, tr);
+    for (int c = 0; c < 8; ++c) {
+      const int64_t cells = (int64_t)((nc + 1 - (c & 1)) / 2) * ((nc + 1 - ((c >> 1) & 1)) / 2) * ((nc + 1 - (c >> 2)) / 2);
+      if (cells == 0) continue;
+      if (precision == MFQ_FP64)
+        restrict_kernel<PC, NF1, double><<<(unsigned)cells, kTBlock, 0, st>>>((const double*)in, (double*)out, nc, bc, c, tr);
+      else
+        restrict_kernel<PC, NF1, float><<<(unsigned)cells, kTBlock, 0, st>>>((const float*)in, (float*)out, nc, bc, c, tr);
+    }
   }
   return hipGetLastError();
 }

@@ -224,7 +224,8 @@ hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, v
                               hipStream_t st);
 // diag = diagonal of A (1 on Dirichlet rows); every node written, no clearing needed.
 hipError_t launch_diagonal_cells(const OpView& v, int precision, void* diag, hipStream_t st);
-// Setup-time cell loops (they add into b/mat, which the callers zero first).
+// Setup-time cell loops: the manufactured load vector (every entry written) and the dense coarse
+// matrix (added into mat, which the caller zeroes first); colour-ordered, no atomics.
 hipError_t launch_rhs_cells(const OpView& v, double* b, hipStream_t st);
 hipError_t launch_assemble_dense(const OpView& v, double* mat, int64_t ld, hipStream_t st);
 hipError_t launch_transfer(const mfq_transfer* t, int precision, bool prolongate, const void* in,

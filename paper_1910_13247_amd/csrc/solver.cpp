@@ -748,7 +748,11 @@ int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream
   s->z = (double*)((char*)k + 3 * vb);
   s->rout = (double*)((char*)k + 4 * vb);
   s->c = (double*)((char*)k + 5 * vb);
-  if (s->kind == MFQ_SOLVER_CG) return MFQ_OK;
+  if (s->kind == MFQ_SOLVER_CG) {
+    // the state's reduction counter must be zero before a solve starts on any stream
+    MFQ_HIP(hipStreamSynchronize(st));
+    return MFQ_OK;
+  }
 
   const int prec = s->prec_v;
   for (size_t l = 0; l < s->lv.size(); ++l) {

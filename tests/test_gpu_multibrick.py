@@ -1,0 +1,97 @@
+"""Operator parity on meshes more than one brick wide in every direction, for every degree.
+
+The cell loop cuts the mesh into bricks of (32,2,1), (14,2,1), (16,1,1), (5,2,1), (7,1,1),
+(4,1,1), (4,1,1), (3,1,1) cells for p = 1..8 and writes nodes shared between bricks by colour
+(the first colour to touch a node stores, later ones add).  These sizes put at least two bricks
+along x (both x parities, the x-face store/add rule, a ragged last brick) and several along y and
+z.  FP64 bar: ||y - y_o||_inf <= 1e-12 ||y_o||_inf against the oracle's assembled matrix; FP32:
+|y32 - y_o| <= 2 k u32 (|A| |x32|) componentwise, k = 8(p+1) + 16.  At full size the Q8 24^3
+workload is checked on oracle rows for the vector-ALU FP64 and FP32 kernels.
+"""
+import functools
+
+import numpy as np
+import pytest
+
+from oracle import assemble, ebe
+from synthetic import uniform_vector
+
+pytestmark = pytest.mark.gpu
+
+U32 = 2.0 ** -24
+BRICK_X = {1: 32, 2: 14, 3: 16, 4: 5, 5: 7, 6: 4, 7: 4, 8: 3}
+WIDE = {1: 33, 2: 15, 3: 17, 4: 11, 5: 8, 6: 5, 7: 5, 8: 4}
+
+
+@functools.lru_cache(maxsize=2)
+def _oracle(p, n):
+    return assemble.operator_csr(p, n, 0.1, 0.5, 1)
+
+
+def _run(p, n, prec, x_np):
+    import torch
+    import paper_1910_13247_amd as mfq
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.1), p, mfq.MFQ_BC_DIRICHLET0), 0.5, prec)
+    lay = op.layout()
+    assert lay["brick"][0] == BRICK_X[p]
+    assert n > BRICK_X[p], "the mesh must be wider than one brick in x"
+    y = op.vmult(torch.from_numpy(x_np).to(op.dtype).cuda())
+    torch.cuda.synchronize()
+    return y.double().cpu().numpy()
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_multibrick_fp64(p):
+    n = WIDE[p]
+    print(f"multi-brick fp64 p={p} n={n}", flush=True)
+    import paper_1910_13247_amd as mfq
+    x = uniform_vector((p * n + 1) ** 3, seed=80 + p)
+    y = _run(p, n, mfq.MFQ_FP64, x)
+    yo = _oracle(p, n) @ x
+    err = np.abs(y - yo).max() / np.abs(yo).max()
+    print(f"  normwise rel err {err:.2e}")
+    assert err <= 1e-12
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_multibrick_fp32(p):
+    n = WIDE[p]
+    print(f"multi-brick fp32 p={p} n={n}", flush=True)
+    import paper_1910_13247_amd as mfq
+    x = uniform_vector((p * n + 1) ** 3, seed=90 + p)
+    x32 = x.astype(np.float32).astype(np.float64)
+    y = _run(p, n, mfq.MFQ_FP32, x)
+    yo = _oracle(p, n) @ x32
+    mag = ebe.magnitude_bound(p, n, 0.1, 0.5, x32, 1)
+    k = 8 * (p + 1) + 16
+    assert np.all(np.abs(y - yo) <= 2 * k * U32 * mag + 1e-30)
+
+
+@pytest.mark.parametrize("prec", [0, 1])
+def test_sampled_parity_full_size_q8_24_vector_alu(prec):
+    """Q8 on the curved 24^3 mesh (7,189,057 DoFs, eight bricks of 3 cells along x) with the
+    vector-ALU kernels, FP64 and FP32: 28 rows recomputed by the oracle cell by cell."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    p, n = 8, 24
+    print(f"full-size Q8 24^3 vector ALU prec={prec}", flush=True)
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.1), p, mfq.MFQ_BC_DIRICHLET0), 0.5, prec)
+    x_np = uniform_vector(op.n_dofs, seed=12)
+    xin = x_np if prec == 0 else x_np.astype(np.float32).astype(np.float64)
+    y = op.vmult(torch.from_numpy(xin).to(op.dtype).cuda())
+    torch.cuda.synchronize()
+    N1 = p * n + 1
+    rng = np.random.default_rng(13)
+    # random rows plus nodes on brick faces (I = 24 between x bricks 0 and 1), edges and a corner
+    rows = np.concatenate([rng.integers(0, op.n_dofs, 20),
+                           [24 + 7 * N1 + 9 * N1 * N1, 24 + 8 * N1 + 8 * N1 * N1, 48 + 16 * N1 + 17 * N1 * N1,
+                            72 + 5 * N1 + 3 * N1 * N1, 1 + N1 + N1 * N1, N1 ** 3 // 2, 25 + 30 * N1 + 40 * N1 * N1,
+                            96 + 96 * N1 + 96 * N1 * N1]])
+    yo = ebe.ebe_rows(p, n, 0.1, 0.5, xin, 1, rows)
+    yg = y[torch.from_numpy(rows).cuda()].double().cpu().numpy()
+    if prec == 0:
+        assert np.abs(yg - yo).max() <= 1e-12 * np.abs(yo).max()
+    else:
+        mag = ebe.ebe_rows(p, n, 0.1, 0.5, np.abs(xin), 1, rows, magnitude=True)
+        k = 8 * (p + 1) + 16
+        assert np.all(np.abs(yg - yo) <= 2 * k * U32 * mag + 1e-30)

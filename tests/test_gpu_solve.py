@@ -2,7 +2,7 @@
 import numpy as np
 import pytest
 
-from oracle import assemble, gmg, mesh, rhs, solve
+from oracle import assemble, ebe, gmg, mesh, rhs, solve
 from synthetic import uniform_vector
 
 pytestmark = pytest.mark.gpu
@@ -96,20 +96,145 @@ def test_vcycle_matches_oracle_fp64():
     assert np.abs(z - zo).max() <= 1e-11 * np.abs(zo).max()
 
 
-def test_vcycle_fp32_close_to_oracle():
+@pytest.mark.parametrize("p,n,limit", [(4, 2, 8), (3, 4, 30), (6, 2, 30)])
+def test_vcycle_fp32_within_derived_bound(p, n, limit):
+    """One FP32 V-cycle against the oracle's FP64 V-cycle, within the first-order componentwise
+    bound that propagates each FP32 kernel's rounding model through the cycle (tests/fp32_bound.py):
+    3 levels with h- then p-coarsening (4,2) -> (4,1) -> (2,1) and (6,2) -> (6,1) -> (3,1), and
+    3 h-levels (3,4) -> (3,2) -> (3,1) (small coarse limits keep the meshes small enough for the
+    dense analysis)."""
+    from fp32_bound import vcycle_fp32_bound
+    from oracle.ebe import magnitude_csr
     mfq = _mfq()
     torch = _torch()
-    p, n = 3, 8
-    levels, prolong = gmg.build_hierarchy(p, n, 0.1, 0.5, bc=1)
+    print(f"fp32 V-cycle p={p} n={n} coarse_dofs={limit}", flush=True)
+    levels, prolong = gmg.build_hierarchy(p, n, 0.1, 0.5, bc=1, coarse_dofs=limit)
     lhats = [L.estimate() for L in levels[1:]]
     _, s, op = _setup(p, n, 0.1, 0.5)
-    solver = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, lambda_override=[1.2 * l for l in lhats])
-    lam_gpu = solver.lambdas(2)
-    assert abs(lam_gpu[0] - lhats[0]) <= 1e-4 * lhats[0]
+    solver = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, lambda_override=[1.2 * l for l in lhats],
+                        coarse_dofs=limit)
+    assert len(solver.lambdas(len(levels))) == len(levels) - 1
     r = mesh.boundary_mask(p, n) * uniform_vector(op.n_dofs, 22)
     z = solver.precondition(torch.from_numpy(r).cuda()).cpu().numpy()
-    zo = gmg.vcycle(levels, prolong, 1, r)
-    assert np.abs(z - zo).max() <= 1e-4 * np.abs(zo).max()
+    zo = gmg.vcycle(levels, prolong, len(levels) - 1, r)
+    mags = [magnitude_csr(L.p, L.n, 0.1, 0.5, 1) for L in levels]
+    zt, bound = vcycle_fp32_bound(levels, prolong, mags, r)
+    assert np.abs(zt - zo).max() <= 1e-12 * np.abs(zo).max()
+    err = np.abs(z - zo)
+    print(f"  max err / bound {np.max(err / (bound + 1e-300)):.2e}, rel err {err.max() / np.abs(zo).max():.2e}")
+    assert np.all(err <= 1.01 * bound + 1e-12 * np.abs(zo).max())
+
+
+def test_vcycle_three_levels_h_and_p_fp64():
+    """FP64 V-cycle on the hierarchy (2,5) -> (4,5) -> (4,10): an h-transfer and a p-transfer,
+    dense coarse solve; equal to the oracle's V-cycle up to FP64 rounding."""
+    mfq = _mfq()
+    torch = _torch()
+    p, n = 4, 10
+    print("fp64 V-cycle 3 levels", flush=True)
+    levels, prolong = gmg.build_hierarchy(p, n, 0.1, 0.5, bc=1)
+    assert [(L.p, L.n) for L in levels] == [(2, 5), (4, 5), (4, 10)]
+    lhats = [L.estimate() for L in levels[1:]]
+    _, s, op = _setup(p, n, 0.1, 0.5)
+    solver = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_FP64, lambda_override=[1.2 * l for l in lhats])
+    r = mesh.boundary_mask(p, n) * uniform_vector(op.n_dofs, 24)
+    z = solver.precondition(torch.from_numpy(r).cuda()).cpu().numpy()
+    zo = gmg.vcycle(levels, prolong, 2, r)
+    assert np.abs(z - zo).max() <= 1e-11 * np.abs(zo).max()
+    # without the override the device's own eigenvalue estimates match the oracle's
+    lam = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_FP64).lambdas(3)
+    np.testing.assert_allclose(lam, lhats, rtol=1e-8)
+
+
+@pytest.mark.parametrize("p,n,levels_expected", [(1, 38, [(1, 19), (1, 38)]), (2, 19, [(1, 19), (2, 19)])])
+@pytest.mark.parametrize("kind", [1, 2])
+def test_jacobi_cg_coarse_solve(p, n, levels_expected, kind):
+    """Coarsest levels above the dense limit (5,832 free DoFs) are solved by Jacobi-CG to 1e-12 on
+    the host-polled path: an h-hierarchy and a p-hierarchy (odd n), FP64 and mixed V-cycles;
+    solutions certified by the oracle's assembled operator."""
+    mfq = _mfq()
+    print(f"jacobi-cg coarse p={p} n={n} kind={kind}", flush=True)
+    assert gmg.hierarchy(p, n) == levels_expected
+    _, s, op = _setup(p, n, 0.1, 0.5)
+    b = op.rhs_manufactured()
+    x, info, st = mfq.Solver(op, kind).solve(b, rtol=1e-10, max_iter=200)
+    assert st == mfq.MFQ_OK and info.n_levels == 2 and info.rel_residual <= 1e-10
+    At = assemble.operator_csr(p, n, 0.1, 0.5, 1)
+    assert solve.rel_residual(lambda v: At @ v, b.cpu().numpy(), x.cpu().numpy()) <= 1e-10
+
+
+def test_q3_128_gmg_mixed_certified_on_oracle_rows():
+    """The benchmark's Q3 128^3 solve (57,066,625 DoFs, 6 levels, GMG_MIXED to 1e-10): the load
+    vector on 300 rows against the oracle's cell sums, and the residual b - A x on the same rows,
+    each recomputed by the oracle from the row's cells, within 1e-10 ||b||_2."""
+    mfq = _mfq()
+    torch = _torch()
+    p, n = 3, 128
+    print("Q3 128^3 GMG_MIXED certified rows", flush=True)
+    _, s, op = _setup(p, n, 0.1, 0.5)
+    b = op.rhs_manufactured()
+    x, info, st = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED).solve(b, rtol=1e-10, max_iter=200)
+    torch.cuda.synchronize()
+    assert st == mfq.MFQ_OK and info.rel_residual <= 1e-10 and info.n_levels == 6
+    b_np = b.cpu().numpy()
+    x_np = x.cpu().numpy()
+    del x
+    N1 = p * n + 1
+    rng = np.random.default_rng(6)
+    # random rows plus nodes on x-brick faces (bricks of 16 cells: I = 48, 96), cell faces, corners
+    rows = np.concatenate([rng.integers(0, op.n_dofs, 288),
+                           [48 + 10 * N1 + 20 * N1 * N1, 96 + 96 * N1 + 96 * N1 * N1, 1 + N1 + N1 * N1,
+                            N1 ** 3 // 2, 3 + 3 * N1 + 3 * N1 * N1, 192 + 191 * N1 + 190 * N1 * N1,
+                            (N1 - 2) * (1 + N1 + N1 * N1), 49 + 47 * N1 + 300 * N1 * N1, 0, N1 ** 3 - 1,
+                            144 + 3 * N1 + 381 * N1 * N1, 4 + 380 * N1 + 7 * N1 * N1]])
+    f = lambda xx: rhs.manufactured_f(xx, 0.5)
+    bo = rhs.rhs_rows(p, n, 0.1, 0.5, f, rows, 1)
+    assert np.abs(b_np[rows] - bo).max() <= 1e-12 * np.abs(b_np).max()
+    r = bo - ebe.ebe_rows(p, n, 0.1, 0.5, x_np, 1, rows)
+    nb = np.linalg.norm(b_np)
+    print(f"  max sampled |r_i| / ||b|| = {np.abs(r).max() / nb:.2e}")
+    assert np.abs(r).max() <= 1e-10 * nb
+
+
+def test_q8_mixed_ir_certified_in_full():
+    """The high-degree solve reduced to Q8 on the curved 4^3 mesh (35,937 DoFs, levels (8,2) and
+    (8,4)): GMG_MIXED_IR (FP32 inner CG and V-cycle, FP64 refinement) to 1e-10, certified by the
+    oracle's assembled operator and manufactured load vector."""
+    mfq = _mfq()
+    p, n = 8, 4
+    print("Q8 4^3 mixed IR", flush=True)
+    _, s, op = _setup(p, n, 0.1, 0.5)
+    b = op.rhs_manufactured()
+    bo = rhs.rhs_manufactured(p, n, 0.1, 0.5)
+    assert np.abs(b.cpu().numpy() - bo).max() <= 1e-12 * np.abs(bo).max()
+    x, info, st = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED_IR).solve(b, rtol=1e-10, max_iter=300)
+    assert st == mfq.MFQ_OK and info.rel_residual <= 1e-10 and info.n_levels == 2
+    At = assemble.operator_csr(p, n, 0.1, 0.5, 1)
+    assert solve.rel_residual(lambda v: At @ v, bo, x.cpu().numpy()) <= 1e-10
+
+
+def test_q8_24_mixed_ir_certified_on_oracle_rows():
+    """The high-degree workload's solve (Q8, curved 24^3, 7,189,057 DoFs, levels 3^3..24^3):
+    GMG_MIXED_IR to 1e-10, residual rows recomputed by the oracle within 1e-10 ||b||_2."""
+    mfq = _mfq()
+    torch = _torch()
+    p, n = 8, 24
+    print("Q8 24^3 mixed IR certified rows", flush=True)
+    _, s, op = _setup(p, n, 0.1, 0.5)
+    b = op.rhs_manufactured()
+    x, info, st = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED_IR).solve(b, rtol=1e-10, max_iter=300)
+    torch.cuda.synchronize()
+    assert st == mfq.MFQ_OK and info.rel_residual <= 1e-10
+    b_np, x_np = b.cpu().numpy(), x.cpu().numpy()
+    N1 = p * n + 1
+    rng = np.random.default_rng(9)
+    rows = np.concatenate([rng.integers(0, op.n_dofs, 22), [24 + 7 * N1 + 9 * N1 * N1, N1 ** 3 // 2,
+                                                             1 + N1 + N1 * N1, 72 + 72 * N1 + 72 * N1 * N1]])
+    f = lambda xx: rhs.manufactured_f(xx, 0.5)
+    bo = rhs.rhs_rows(p, n, 0.1, 0.5, f, rows, 1)
+    assert np.abs(b_np[rows] - bo).max() <= 1e-12 * np.abs(b_np).max()
+    r = bo - ebe.ebe_rows(p, n, 0.1, 0.5, x_np, 1, rows)
+    assert np.abs(r).max() <= 1e-10 * np.linalg.norm(b_np)
 
 
 def test_nonconvergence_reports_enoconv():

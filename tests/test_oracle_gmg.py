@@ -115,3 +115,16 @@ def test_splitmix_known_values():
     raw = [0xE220A8397B1DCDAF, 0x6E789E6AA1B965F4, 0x06C45D188009454F]
     expect = [2.0 * ((r >> 11) * 2.0 ** -53) - 1.0 for r in raw]
     np.testing.assert_allclose(v, expect, rtol=0, atol=0)
+
+
+@pytest.mark.parametrize("p,n,limit,expect", [
+    (4, 2, 8, [(2, 1), (4, 1), (4, 2)]),      # 343 free -> n/2: 27 -> p/2: 1
+    (3, 4, 30, [(3, 1), (3, 2), (3, 4)]),     # 1331 -> 125 -> 8
+    (6, 2, 30, [(3, 1), (6, 1), (6, 2)]),     # 1331 -> 125 -> p 3: 8
+    (2, 38, 4096, [(1, 19), (2, 19), (2, 38)]),
+    (1, 38, 4096, [(1, 19), (1, 38)]),        # 5832 free on the coarsest level: above the dense limit
+    (1, 33, 4096, [(1, 33)]),
+])
+def test_hierarchy_rule_with_coarse_limit(p, n, limit, expect):
+    from oracle.gmg import hierarchy
+    assert hierarchy(p, n, limit) == expect

@@ -50,3 +50,14 @@ def test_nodal_rhs_mask():
     f = np.arange(mesh.n_dofs(1, 2), dtype=float)
     b = rhs.rhs_nodal(1, 2, f)
     assert b[13] == 13 and b[0] == 0 and np.count_nonzero(b) == 1
+
+
+@pytest.mark.parametrize("p,n,amp,alpha,bc", [(2, 3, 0.1, 0.5, 1), (3, 2, 0.1, 0.9, 0), (1, 4, 0.0, 0.3, 1)])
+def test_rhs_rows_equal_assembled_load_vector(p, n, amp, alpha, bc):
+    """The sampled load-vector rows summed over each node's cells equal the assembled vector at every row."""
+    from oracle import mesh
+    f = lambda x: rhs.manufactured_f(x, alpha)
+    full = rhs.rhs_from_function(p, n, amp, alpha, f, bc)
+    rows = np.arange(mesh.n_dofs(p, n))
+    got = rhs.rhs_rows(p, n, amp, alpha, f, rows, bc)
+    assert np.abs(got - full).max() <= 1e-13 * np.abs(full).max()
