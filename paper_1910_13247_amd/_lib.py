@@ -8,7 +8,8 @@ import ctypes as C
 import os
 
 _HERE = os.path.dirname(os.path.abspath(__file__))
-LIB_PATH = os.path.join(_HERE, "libmfq.so")
+# MFQ_LIBRARY selects another build of the same library (the host-sanitized one)
+LIB_PATH = os.environ.get("MFQ_LIBRARY") or os.path.join(_HERE, "libmfq.so")
 
 MFQ_OK, MFQ_EINVAL, MFQ_ENOMEM, MFQ_EHIP, MFQ_ENOCONV, MFQ_ENONFINITE, MFQ_EBUSY = 0, -1, -2, -3, -4, -5, -6
 MFQ_FP64, MFQ_FP32, MFQ_FP32_MFMA = 0, 1, 2
