@@ -239,6 +239,21 @@ int mfq_restrict(const mfq_transfer* t, int precision, const void* fine, void* c
 int mfq_chebyshev(const mfq_op* op, const void* inv_diag, const void* b, void* x, int x_is_zero,
                   int degree, double lmin, double lmax, void* work, void* hip_stream);
 
+/* For callers that cannot allocate device memory (code under HIP graph capture, serving loops or
+ * harnesses that forbid the allocator): mfq_chebyshev without the `work` argument.  The three
+ * work vectors live in a fixed array of this library on each device (its address looked up once
+ * per device on the first call there, with that device current), so the call allocates nothing;
+ * the caller still passes the inputs and x.  The current device must be the one that holds the
+ * operator and the vectors.  Limit: 3 n_dofs elements of the operator's precision must fit in
+ * mfq_chebyshev_noalloc_max_bytes() (64 MiB: 2,796,202 DoFs in FP64, 5,592,405 in FP32); larger
+ * operators get MFQ_EINVAL.  Every call on a device shares that device's array (its contents are
+ * the last call's work vectors; nothing in it has to start at zero): calls that overlap in time
+ * on one device, on any streams, race and must not be issued.  Same kernels and arithmetic as
+ * mfq_chebyshev (bitwise equal results). */
+int mfq_chebyshev_noalloc(const mfq_op* op, const void* inv_diag, const void* b, void* x, int x_is_zero,
+                          int degree, double lmin, double lmax, void* hip_stream);
+size_t mfq_chebyshev_noalloc_max_bytes(void);
+
 /* ---------------------------------------------------------------- solvers (Sec. 3.5, 6.1)
  * Kinds: CG: unpreconditioned FP64 CG.  GMG_FP64: FP64 CG preconditioned by an FP64 V-cycle.
  * GMG_MIXED: FP64 CG (FP64 operator, vectors and dot products) preconditioned by an FP32

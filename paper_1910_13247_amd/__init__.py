@@ -161,6 +161,14 @@ class Operator:
                            work.data_ptr(), _stream(stream))
         return x
 
+    def chebyshev_noalloc(self, inv_diag, b, x, x_is_zero, degree, lmin, lmax, stream=None):
+        """mfq_chebyshev with the library's fixed per-device work array (no allocation)."""
+        _lib.mfq_chebyshev_noalloc(self.handle, _check_vec(inv_diag, self.n_dofs, self.precision, "inv_diag"),
+                                   _check_vec(b, self.n_dofs, self.precision, "b"),
+                                   _check_vec(x, self.n_dofs, self.precision, "x"), x_is_zero, degree, lmin, lmax,
+                                   _stream(stream))
+        return x
+
     def __del__(self, _release=_release):
         _release(self, "mfq_op_destroy")
 

@@ -99,6 +99,8 @@ _SIGS = {
     "mfq_prolongate": ([P, I, P, P, P], I),
     "mfq_restrict": ([P, I, P, P, P], I),
     "mfq_chebyshev": ([P, P, P, P, I, I, D, D, P, P], I),
+    "mfq_chebyshev_noalloc": ([P, P, P, P, I, I, D, D, P], I),
+    "mfq_chebyshev_noalloc_max_bytes": ([], SZ),
     "mfq_solver_default_params": ([C.POINTER(SolverParams)], None),
     "mfq_solver_create": ([P, I, C.POINTER(SolverParams), PP], I),
     "mfq_solver_destroy": ([P], None),
@@ -352,6 +354,14 @@ def mfq_restrict(t, precision, fine, coarse, stream):
 
 def mfq_chebyshev(op, inv_diag, b, x, x_is_zero, degree, lmin, lmax, work, stream):
     _check(lib().mfq_chebyshev(op, inv_diag, b, x, int(bool(x_is_zero)), degree, lmin, lmax, work, stream))
+
+
+def mfq_chebyshev_noalloc(op, inv_diag, b, x, x_is_zero, degree, lmin, lmax, stream):
+    _check(lib().mfq_chebyshev_noalloc(op, inv_diag, b, x, int(bool(x_is_zero)), degree, lmin, lmax, stream))
+
+
+def mfq_chebyshev_noalloc_max_bytes():
+    return int(lib().mfq_chebyshev_noalloc_max_bytes())
 
 
 def mfq_solver_default_params():

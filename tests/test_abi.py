@@ -219,3 +219,26 @@ def test_dg_host_validation():
     assert e.value.status == lib.MFQ_EINVAL
     lib.mfq_mesh_destroy(md)
     lib.mfq_mesh_destroy(m)
+
+
+def test_chebyshev_noalloc_limits_on_the_host():
+    """The workspace-free smoother states its fixed array size and rejects, before any device
+    call, operators whose three work vectors would not fit and operators not yet bound."""
+    lib = _lib()
+    cap = lib.mfq_chebyshev_noalloc_max_bytes()
+    assert cap == 64 << 20
+    m = lib.mfq_mesh_create(40, 0.1)
+    s = lib.mfq_space_create(m, 4, 1)                      # 161^3 = 4,173,281 DoFs
+    big = lib.mfq_op_create(s, 0.5, 0)
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_chebyshev_noalloc(big, 256, 256, 256, 1, 3, 0.1, 1.0, None)
+    assert e.value.status == lib.MFQ_EINVAL and "fixed device array" in str(e.value)
+    m2 = lib.mfq_mesh_create(8, 0.1)
+    s2 = lib.mfq_space_create(m2, 4, 1)
+    small = lib.mfq_op_create(s2, 0.5, 0)
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_chebyshev_noalloc(small, 256, 256, 256, 1, 3, 0.1, 1.0, None)
+    assert e.value.status == lib.MFQ_EINVAL and "not bound" in str(e.value)
+    for h, f in ((big, "mfq_op_destroy"), (small, "mfq_op_destroy"), (s, "mfq_space_destroy"),
+                 (s2, "mfq_space_destroy"), (m, "mfq_mesh_destroy"), (m2, "mfq_mesh_destroy")):
+        getattr(lib.lib(), f)(h)
