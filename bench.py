@@ -183,16 +183,15 @@ def time_vmult(op, x, steps, warmup):
         op.vmult(x, y)
     torch.cuda.synchronize()
     wall = (time.perf_counter() - t0) / steps
-    # dominant kernel alone: back-to-back cell-loop launches (accumulating) between two events on
-    # the stream they are launched on (torch's current stream)
-    acc = torch.zeros_like(y)
-    op.vmult_add(x, acc)
+    # dominant kernel alone: the step's cell-loop launches (an application is nothing else: the
+    # first colour stores, so no clearing pass) back to back between two events on the stream they
+    # are launched on (torch's current stream)
     e0 = torch.cuda.Event(enable_timing=True)
     e1 = torch.cuda.Event(enable_timing=True)
     torch.cuda.synchronize()
     e0.record()
     for _ in range(steps):
-        op.vmult_add(x, acc)
+        op.vmult(x, y)
     e1.record()
     torch.cuda.synchronize()
     kern = e0.elapsed_time(e1) / 1e3 / steps
@@ -449,6 +448,30 @@ def dg_benchmark(steps, warmup, degree=4, cells_1d=64):
     return out
 
 
+def hanging_benchmark(steps, warmup, degree=4, n_coarse=32):
+    """The operator on the two-block mesh with hanging nodes (Q4, the unit cube in 32^3 cells
+    joined at X1 = 1 to 64^3 cells of half the size, curved, variable coefficient, FP64;
+    19,121,282 DoFs): one application, both blocks' cell loops and the interface kernels.
+    Algorithmic bytes: each block's (vectors, index maps, G) plus the interface arrays (the
+    interpolated trace and the fine face's results, written and read once)."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    from synthetic import uniform_vector
+    p, n = degree, n_coarse
+    op = mfq.HangingOperator(n, p, 0.1, 0.5, mfq.MFQ_FP64)
+    x = torch.from_numpy(uniform_vector(op.n_dofs, seed=0)).cuda()
+    y = torch.empty_like(x)
+    s = time_events(lambda: op.vmult(x, y), steps, warmup)
+    face = (2 * p * n + 1) ** 2
+    rb = algorithmic_bytes(p, n, 8) + algorithmic_bytes(p, 2 * n, 8) + 4 * 8 * face
+    out = {"workload": f"hanging_q{p}_{n}^3+{2 * n}^3_curved", "dofs": op.n_dofs, "ms": s * 1e3,
+           "DoFs_per_s": op.n_dofs / s, "algorithmic_bytes": rb, "achieved_GBs": rb / s / 1e9,
+           "frac": rb / s / 1e9 / HBM_PEAK_GBS}
+    del op, x, y
+    torch.cuda.synchronize()
+    return out
+
+
 def cpu_small_poisson():
     """Oracle side of the small Poisson workload: SciPy CSR product of the assembled matrix on one
     thread, and the oracle's CG to 1e-10 on it."""
@@ -582,8 +605,9 @@ def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=
     arrivals = [d["arrival"] for d in stream]
     free, _ = torch.cuda.mem_get_info()
     budget = int(min(0.75 * free, 160e9))
-    srv = Server(DeviceExecutor(n_streams=n_streams, **(solver_params or {})), budget, iters_per_step=iters_per_step,
-                 mode=mode, setup_threads=setup_threads)
+    batched = mode == "batched"
+    srv = Server(DeviceExecutor(n_streams=n_streams, batched=batched, **(solver_params or {})), budget,
+                 iters_per_step=iters_per_step, mode="sync" if batched else mode, setup_threads=setup_threads)
     t0 = time.perf_counter()
     st = run_stream(srv, reqs, arrivals)
     srv.close()
@@ -625,8 +649,9 @@ def main():
     ap.add_argument("--serve", type=int, default=2000, metavar="N",
                     help="replay N requests of the serving stream (200 requests/s) and report solves/s, p50/p99 "
                          "(default 2000, the full stream; 0 skips)")
-    ap.add_argument("--serve-mode", choices=["sync", "async"], default="async",
-                    help="serving steps: all solves together (sync) or each at its own pace (async)")
+    ap.add_argument("--serve-mode", choices=["batched", "sync", "async"], default="batched",
+                    help="serving steps: batched launches over all running solves (batched), each solve's own "
+                         "launches, all waited for together (sync), or each at its own pace (async)")
     ap.add_argument("--serve-streams", type=int, default=8)
     ap.add_argument("--serve-params", default="",
                     help="solver parameters of the served requests, e.g. coarse_degree=8,smoother_degree=3")
@@ -706,7 +731,7 @@ def main():
                    "input": "uniform[-1,1) seed 0, resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "vmult_kernel<4, double, true, false> (cell loop)", "launches_per_step": launches,
+                     "kernel": "vmult_kernel<4, double, false, false> (cell loop)", "launches_per_step": launches,
                      "launch_ms": launch_s * 1e3, "algorithmic_bytes_per_launch": per_launch64,
                      "layout": lay, "kernel_source": kernel_source_hash(),
                      "algorithmic_tflops": algorithmic_flops(p, n) / kern64 / 1e12},
@@ -732,6 +757,7 @@ def main():
         rec["csr_sweep"] = csr_sweep(min(args.steps, 20), args.warmup)
     rec["small_poisson"] = small_poisson(min(args.steps, 50), args.warmup)
     rec["dg_sipg_q4_64"] = dg_benchmark(min(args.steps, 20), args.warmup)
+    rec["hanging_q4_32_64"] = hanging_benchmark(min(args.steps, 20), args.warmup)
     print("# Q8 24^3: FP64 / FP32 / FP32 matrix cores", file=sys.stderr, flush=True)
     rec["high_degree_q8_24"] = high_degree_comparison(min(args.steps, 20), args.warmup)
     q8_solution = rec["high_degree_q8_24"].pop("_solution")

@@ -72,6 +72,8 @@ typedef struct mfq_csr mfq_csr;
 typedef struct mfq_dg mfq_dg;
 typedef struct mfq_solver mfq_solver;
 typedef struct mfq_dg_solver mfq_dg_solver;
+typedef struct mfq_hang mfq_hang;
+typedef struct mfq_batch mfq_batch;
 
 /* Library version string and the message of the last failed call on this thread. */
 const char* mfq_version(void);
@@ -333,6 +335,26 @@ int mfq_batch_step(mfq_solver* const* solvers, int count, int iters, int* done);
  * work runs; otherwise it reads the outcome, sets *ready = 1 and *done = 1 once the solve has
  * finished.  Lets a caller advance each solve at its own pace instead of waiting for all of them
  * at every step.  Not to be mixed with mfq_batch_step on a solve with a step in flight. */
+/* Batched serving step (not part of the paper's method: continuous batching of many solves).
+ * mfq_batch_run advances every running solve in `solvers` like mfq_batch_step (iters CG
+ * iterations, or the residual check between CG passes; done[i] = 1 once solve i has finished),
+ * but the CG iterations of the solves that qualify (GMG_MIXED with coarse_mode 1, FP32 V-cycle,
+ * within their iteration budget) are issued as one launch per (kernel, degree) over all of them:
+ * the launches of one iteration (the FP64 operator, the CG updates, the FP32 V-cycle level by level
+ * from the finest) are planned once per call as work tables in device memory (one host-to-device
+ * copy), replayed `iters` times, and the solves' scalar states come back in one device-to-host
+ * copy; one stream wait per call.  Each solve's kernels see its own operands with the grids of its
+ * own launches, so results are bitwise those of mfq_batch_step.  Every listed solve must run on
+ * hip_stream (mfq_solve_begin) and the qualifying ones must share smoother_degree and
+ * coarse_degree.  mfq_batch_create: up to max_solvers solves per call; device workspace of
+ * mfq_batch_device_bytes (tables and states; mfq_batch_bind), pinned host staging owned by the
+ * handle.  One call at a time per handle. */
+int mfq_batch_create(int max_solvers, mfq_batch** out);
+void mfq_batch_destroy(mfq_batch* b);
+int mfq_batch_device_bytes(const mfq_batch* b, size_t* bytes);
+int mfq_batch_bind(mfq_batch* b, void* dev_buf, size_t bytes, void* hip_stream);
+int mfq_batch_run(mfq_batch* b, mfq_solver* const* solvers, int count, int iters, void* hip_stream, int* done);
+
 int mfq_solve_step_async(mfq_solver* s, int iters);
 int mfq_solve_step_poll(mfq_solver* s, int* ready, int* done);
 
@@ -374,6 +396,43 @@ int mfq_dg_precondition(mfq_dg_solver* s, const double* r, double* z, void* hip_
  * MFQ_ENOCONV when max_iter is reached (info valid).  info->n_levels counts the DG level. */
 int mfq_dg_solve(mfq_dg_solver* s, const double* b, double* x, double rtol, int max_iter, void* hip_stream,
                  mfq_solve_info* info);
+
+/* ---------------------------------------------------------------- hanging nodes (Sec. 3.3)
+ * The variable-coefficient operator of mfq_op_create on a two-block mesh with a 2:1 interface,
+ * the smallest mesh with hanging nodes (adaptive refinement, Sec. 3.3; Fig. 3) that keeps each
+ * part a tensor-product lattice.  Block 0: the unit cube in n^3 cells of side 1/n; block 1:
+ * [1,2] x [0,1]^2 in (2n)^3 cells of side 1/(2n); the deformation x = X + A s(X)(1,1,1),
+ * s = sin(pi X1) sin(pi X2) sin(pi X3), and the coefficient a(x) = 1 + alpha sin(2 pi x1)
+ * sin(2 pi x2) sin(2 pi x3) are evaluated on the whole domain [0,2] x [0,1]^2.
+ * Vectors: block 0's lattice ((pn+1)^3 nodes, x fastest), then block 1's ((2pn+1)^3, x fastest).
+ * Block 1's nodes on X1 = 1 are hanging: their conforming values are the coarse face's trace,
+ * interpolated in each face direction (the 1D h-transfer table); they are not unknowns.
+ * Homogeneous Dirichlet data on the domain's boundary (X1 in {0, 2}, X2, X3 in {0, 1}).
+ * The operator is y = m C^T blockdiag(A_0, A_1) C (m x) + (1 - m) x on the independent entries
+ * and y = x on the hanging entries (C: identity on independent entries, interpolation on the
+ * hanging ones; m: Dirichlet mask).  Precision MFQ_FP64 or MFQ_FP32 (G stored as in mfq_op).
+ * Device storage (mfq_hang_device_bytes): both blocks' index lattices and G, and two face arrays
+ * of (2pn+1)^2 values that every application uses: applications of one operator must not overlap
+ * in time (on any streams). */
+int mfq_hang_create(int n_coarse, double amplitude, int degree, double alpha, int precision, mfq_hang** out);
+void mfq_hang_destroy(mfq_hang* h);
+int64_t mfq_hang_n_dofs(const mfq_hang* h);     /* (pn+1)^3 + (2pn+1)^3; -1 on NULL */
+int mfq_hang_device_bytes(const mfq_hang* h, size_t* bytes);
+/* Binds a 256-byte aligned buffer of at least device_bytes and fills both blocks' data on the
+ * stream (asynchronous). */
+int mfq_hang_bind(mfq_hang* h, void* dev_buf, size_t bytes, void* hip_stream);
+/* dst = A src on the device vectors above (n_dofs elements of the operator's precision, not
+ * overlapping).  Asynchronous: interpolation to the hanging face, the two blocks' cell loops,
+ * the transposed interpolation added to the coarse face (deterministic, no atomics). */
+int mfq_hang_vmult(const mfq_hang* h, const void* src, void* dst, void* hip_stream);
+/* Unpreconditioned FP64 CG on an MFQ_FP64 operator from x = 0 to ||b - A x||_2 <= rtol ||b||_2
+ * (b zero on Dirichlet and hanging entries for a solution of the constrained problem; the hanging
+ * entries of x are then zero: their conforming values are the interpolated coarse trace).  work:
+ * 256-byte aligned device memory of mfq_hang_cg_work_bytes.  Blocks; MFQ_ENOCONV when the true
+ * residual exceeds rtol after max_iter iterations (info valid). */
+size_t mfq_hang_cg_work_bytes(const mfq_hang* h);
+int mfq_hang_cg(const mfq_hang* h, const double* b, double* x, double rtol, int max_iter, void* work,
+                size_t work_bytes, void* hip_stream, mfq_solve_info* info);
 
 #ifdef __cplusplus
 }

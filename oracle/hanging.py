@@ -97,20 +97,25 @@ def block_qpoints(p, nb, x0, A, alpha):
     return G, x, JxW
 
 
-def block_matrix(p, nb, x0, A, alpha):
+def block_matrix(p, nb, x0, A, alpha, chunk=32):
     """Unconstrained stiffness matrix of one block on its own lattice (scipy CSR): sum over cells of
-    grad phi_i^T G_q grad phi_j at every quadrature point (the Sec. 2.4 cell loop)."""
+    grad phi_i^T G_q grad phi_j at every quadrature point (the Sec. 2.4 cell loop), cells taken in
+    chunks to bound memory."""
     _, B = reference_tabulation(p)
     G, _, _ = block_qpoints(p, nb, x0, A, alpha)
     _, dofs = _block_cells(p, nb, x0, 1.0 / nb)
     Q = B.shape[0]
-    GB = G @ B[None]                                      # [C, Q, 3, nloc]
     Bf = B.reshape(Q * 3, -1)
-    Ak = Bf.T[None] @ GB.reshape(GB.shape[0], Q * 3, -1)  # [C, nloc, nloc]
-    rows = np.repeat(dofs[:, :, None], dofs.shape[1], axis=2).reshape(-1)
-    cols = np.repeat(dofs[:, None, :], dofs.shape[1], axis=1).reshape(-1)
     L = (p * nb + 1) ** 3
-    return sp.coo_matrix((Ak.reshape(-1), (rows, cols)), shape=(L, L)).tocsr()
+    out = sp.csr_matrix((L, L))
+    for c0 in range(0, G.shape[0], chunk):
+        Gc, dc = G[c0:c0 + chunk], dofs[c0:c0 + chunk]
+        GB = Gc @ B[None]                                      # [Cc, Q, 3, nloc]
+        Ak = Bf.T[None] @ GB.reshape(GB.shape[0], Q * 3, -1)   # [Cc, nloc, nloc]
+        rows = np.repeat(dc[:, :, None], dc.shape[1], axis=2).reshape(-1)
+        cols = np.repeat(dc[:, None, :], dc.shape[1], axis=1).reshape(-1)
+        out = out + sp.coo_matrix((Ak.reshape(-1), (rows, cols)), shape=(L, L)).tocsr()
+    return out.tocsr()
 
 
 def block_load(p, nb, x0, A, alpha, f):
@@ -215,3 +220,14 @@ def node_coords(p, n):
         X[..., 2] = yz[:, None, None]
         out.append(X.reshape(-1, 3))
     return np.concatenate(out)
+
+
+def magnitude_csr(p, n, A, alpha, bc=1):
+    """Entrywise bound of the operator's rounding terms: m |C|^T |blockdiag(A_0, A_1)| |C| m + (1 - m)
+    (the absolute values of every product summed by the cell loops and the face interpolation)."""
+    hang = hanging_mask(p, n).astype(np.float64)
+    m = (dirichlet_mask(p, n) if bc else np.ones(len(hang))) * (1.0 - hang)
+    Cx = abs(expansion(p, n))
+    Af = abs(unconstrained(p, n, A, alpha))
+    Mm = sp.diags(m)
+    return (Mm @ Cx.T @ Af @ Cx @ Mm + sp.diags(1.0 - m)).tocsr()

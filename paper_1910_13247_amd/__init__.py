@@ -14,7 +14,7 @@ from ._lib import (MfqError, MFQ_FP64, MFQ_FP32, MFQ_FP32_MFMA, MFQ_BC_NONE, MFQ
                    MFQ_SOLVER_GMG_FP64, MFQ_SOLVER_GMG_MIXED, MFQ_SOLVER_GMG_MIXED_IR, MFQ_OK, MFQ_EINVAL,
                    MFQ_ENOMEM, MFQ_EHIP, MFQ_ENOCONV, MFQ_ENONFINITE, MFQ_EBUSY)
 
-__all__ = ["Mesh", "Space", "Operator", "Transfer", "Solver", "MfqError", "MFQ_FP64", "MFQ_FP32", "MFQ_FP32_MFMA",
+__all__ = ["Mesh", "Space", "Operator", "HangingOperator", "Transfer", "Solver", "Batch", "MfqError", "MFQ_FP64", "MFQ_FP32", "MFQ_FP32_MFMA",
            "MFQ_BC_NONE", "MFQ_BC_DIRICHLET0", "MFQ_SOLVER_CG", "MFQ_SOLVER_GMG_FP64",
            "MFQ_SOLVER_GMG_MIXED", "MFQ_SOLVER_GMG_MIXED_IR", "MFQ_OK", "MFQ_EINVAL", "MFQ_ENOMEM",
            "MFQ_EHIP", "MFQ_ENOCONV", "MFQ_ENONFINITE", "MFQ_EBUSY", "batch_step", "SparseMatrix", "DGOperator",
@@ -171,6 +171,45 @@ class Operator:
 
     def __del__(self, _release=_release):
         _release(self, "mfq_op_destroy")
+
+
+class HangingOperator:
+    """The operator on the two-block mesh with a 2:1 interface (hanging nodes on the fine side):
+    the unit cube in n^3 cells joined at X1 = 1 to [1,2] x [0,1]^2 in (2n)^3 cells (mfq_hang_*).
+    Vectors: block 0's lattice, then block 1's; device data in a torch buffer."""
+
+    def __init__(self, n_coarse, degree, amplitude=0.0, alpha=0.0, precision=MFQ_FP64, device="cuda", stream=None):
+        torch = _torch()
+        self.precision = int(precision)
+        self.dtype = _dtype(self.precision)
+        self.handle = _lib.mfq_hang_create(int(n_coarse), float(amplitude), int(degree), float(alpha),
+                                           self.precision)
+        self.n_dofs = _lib.mfq_hang_n_dofs(self.handle)
+        self.device_bytes = _lib.mfq_hang_device_bytes(self.handle)
+        self.buffer = torch.empty(self.device_bytes, dtype=torch.uint8, device=device)
+        _lib.mfq_hang_bind(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream(stream))
+
+    def vmult(self, src, dst=None, stream=None):
+        torch = _torch()
+        if dst is None:
+            dst = torch.empty(self.n_dofs, dtype=self.dtype, device=self.buffer.device)
+        _lib.mfq_hang_vmult(self.handle, _check_vec(src, self.n_dofs, self.precision, "src"),
+                            _check_vec(dst, self.n_dofs, self.precision, "dst"), _stream(stream))
+        return dst
+
+    def cg(self, b, rtol=1e-10, max_iter=10000, stream=None, check=True):
+        """(x, status, info): unpreconditioned FP64 CG from zero (mfq_hang_cg)."""
+        torch = _torch()
+        x = torch.empty(self.n_dofs, dtype=torch.float64, device=self.buffer.device)
+        nb = _lib.mfq_hang_cg_work_bytes(self.handle)
+        work = torch.empty(nb, dtype=torch.uint8, device=self.buffer.device)
+        st, info = _lib.mfq_hang_cg(self.handle, _check_vec(b, self.n_dofs, MFQ_FP64, "b"),
+                                    _check_vec(x, self.n_dofs, MFQ_FP64, "x"), rtol, max_iter, work.data_ptr(), nb,
+                                    _stream(stream), check=check)
+        return x, st, info
+
+    def __del__(self, _release=_release):
+        _release(self, "mfq_hang_destroy")
 
 
 class DGOperator:
@@ -341,6 +380,27 @@ def batch_step(solvers, iters=2):
     """Advance every running solve in `solvers` by up to `iters` CG iterations (each on the stream
     it was begun on), wait once for all of them, and return their done flags."""
     return _lib.mfq_batch_step([s.handle for s in solvers], iters)
+
+
+class Batch:
+    """Batched steps over many running solves (mfq_batch_*): one launch per (kernel, degree) covers
+    every qualifying solve; device workspace in a torch buffer."""
+
+    def __init__(self, max_solvers=256, device="cuda", stream=None):
+        torch = _torch()
+        self.max_solvers = int(max_solvers)
+        self.handle = _lib.mfq_batch_create(self.max_solvers)
+        self.device_bytes = _lib.mfq_batch_device_bytes(self.handle)
+        self.buffer = torch.empty(self.device_bytes, dtype=torch.uint8, device=device)
+        _lib.mfq_batch_bind(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream(stream))
+
+    def run(self, solvers, iters=2, stream=None):
+        """Advance every running solve in `solvers` (all begun on `stream`); returns done flags."""
+        return _lib.mfq_batch_run(self.handle, [s.handle if hasattr(s, "handle") else s for s in solvers], iters,
+                                  _stream(stream))
+
+    def __del__(self, _release=_release):
+        _release(self, "mfq_batch_destroy")
 
 
 class Solver:

@@ -114,6 +114,19 @@ _SIGS = {
     "mfq_solve_step_poll": ([P, C.POINTER(C.c_int), C.POINTER(C.c_int)], I),
     "mfq_solver_lambdas": ([P, C.POINTER(D), I], I),
     "mfq_solver_precondition": ([P, P, P, P], I),
+    "mfq_batch_create": ([I, PP], I),
+    "mfq_batch_destroy": ([P], None),
+    "mfq_batch_device_bytes": ([P, C.POINTER(SZ)], I),
+    "mfq_batch_bind": ([P, P, SZ, P], I),
+    "mfq_batch_run": ([P, C.POINTER(C.c_void_p), I, I, P, C.POINTER(C.c_int)], I),
+    "mfq_hang_create": ([I, D, I, D, I, PP], I),
+    "mfq_hang_destroy": ([P], None),
+    "mfq_hang_n_dofs": ([P], I64),
+    "mfq_hang_device_bytes": ([P, C.POINTER(SZ)], I),
+    "mfq_hang_bind": ([P, P, SZ, P], I),
+    "mfq_hang_vmult": ([P, P, P, P], I),
+    "mfq_hang_cg_work_bytes": ([P], SZ),
+    "mfq_hang_cg": ([P, P, P, D, I, P, SZ, P, C.POINTER(SolveInfo)], I),
 }
 
 EXPORTED = tuple(_SIGS)
@@ -438,3 +451,70 @@ def mfq_solver_lambdas(s, n):
 
 def mfq_solver_precondition(s, r, z, stream):
     _check(lib().mfq_solver_precondition(s, r, z, stream))
+
+
+def mfq_hang_create(n_coarse, amplitude, degree, alpha, precision=MFQ_FP64):
+    return _handle(lib().mfq_hang_create, n_coarse, amplitude, degree, alpha, precision)
+
+
+def mfq_hang_destroy(h):
+    lib().mfq_hang_destroy(h)
+
+
+def mfq_hang_n_dofs(h):
+    return int(lib().mfq_hang_n_dofs(h))
+
+
+def mfq_hang_device_bytes(h):
+    n = SZ()
+    _check(lib().mfq_hang_device_bytes(h, C.byref(n)))
+    return n.value
+
+
+def mfq_hang_bind(h, dev_buf, nbytes, stream):
+    _check(lib().mfq_hang_bind(h, dev_buf, nbytes, stream))
+
+
+def mfq_hang_vmult(h, src, dst, stream):
+    _check(lib().mfq_hang_vmult(h, src, dst, stream))
+
+
+def mfq_hang_cg_work_bytes(h):
+    return int(lib().mfq_hang_cg_work_bytes(h))
+
+
+def mfq_hang_cg(h, b, x, rtol, max_iter, work, work_bytes, stream, check=True):
+    """Returns (status, SolveInfo).  With check=True a status other than MFQ_OK raises."""
+    info = SolveInfo()
+    st = lib().mfq_hang_cg(h, b, x, rtol, max_iter, work, work_bytes, stream, C.byref(info))
+    if check:
+        _check(st)
+    return st, info
+
+
+def mfq_batch_create(max_solvers):
+    return _handle(lib().mfq_batch_create, max_solvers)
+
+
+def mfq_batch_destroy(b):
+    lib().mfq_batch_destroy(b)
+
+
+def mfq_batch_device_bytes(b):
+    n = SZ()
+    _check(lib().mfq_batch_device_bytes(b, C.byref(n)))
+    return n.value
+
+
+def mfq_batch_bind(b, dev_buf, nbytes, stream):
+    _check(lib().mfq_batch_bind(b, dev_buf, nbytes, stream))
+
+
+def mfq_batch_run(b, solvers, iters, stream):
+    """Advances every listed running solve (batched launches where they qualify); returns the
+    list of done flags."""
+    n = len(solvers)
+    arr = (C.c_void_p * max(n, 1))(*solvers)
+    done = (C.c_int * max(n, 1))()
+    _check(lib().mfq_batch_run(b, arr, n, iters, stream, done))
+    return [bool(done[i]) for i in range(n)]

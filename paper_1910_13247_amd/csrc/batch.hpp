@@ -1,0 +1,77 @@
+// Work tables of the batched launches (many independent solves advanced by one launch per kernel
+// and degree).  A batched launch's grid is the concatenation of the single-solve launches' grids;
+// item i owns workgroups [first_i, first_{i+1}) and each of its workgroups does exactly what the
+// single-solve launch's workgroup of the same index does, so results are bitwise those of the
+// solve alone.
+#pragma once
+
+#include <cstdint>
+
+#include "mfq_internal.hpp"
+#include "solver_state.hpp"
+
+namespace mfq {
+
+// one solve's operands of a batched vector kernel (roles per kernel, see kernels_vector.hip)
+struct VecItem {
+  int64_t first;       // first workgroup of the item in the batched grid
+  int64_t n;           // vector length
+  int nblk;            // workgroups of the single-solve launch (reductions keep its partial sums)
+  int flag;            // x_is_zero (Chebyshev start) / first direction (CG)
+  const void* a;
+  const void* b;
+  const void* c;
+  void* d;
+  void* e;
+  void* f;
+  double s0, s1;
+  SolverState* st;
+};
+
+// one solve's operands of a batched cell loop: an operator and the vectors it reads and writes
+struct CellItem {
+  int64_t first[kColours];  // first workgroup of the item in colour c's launch
+  const int* idx;
+  const void* geo;
+  const void* src;
+  void* dst;
+  Bricks bk;
+};
+
+// one solve's operands of a batched level transfer (coarse cells of one (degree, degree) pair)
+struct TransferItem {
+  int64_t first[kColours];  // restriction: first workgroup per colour; prolongation: first[0]
+  const void* in;
+  void* out;
+  int nc;                   // coarse cells per direction
+  int bc;
+};
+
+enum BatchVecOp {
+  kBatchCgAlpha = 0,  // a = p, b = Ap
+  kBatchCgUpdate,     // d = x, e = r, a = p, b = Ap (preconditioned form)
+  kBatchCgBeta,       // a = r, b = z
+  kBatchCgDirection,  // a = z, d = p, flag = first
+  kBatchCast64To32,   // a = in (double), d = out (float)
+  kBatchCast32To64,   // a = in (float), d = out (double)
+  kBatchChebFirst,    // a = b, b = t, c = dinv, d = x, e = r, f = d, s0 = 1/theta, flag = x_is_zero (float)
+  kBatchChebStep,     // a = A d, c = dinv, d = x, e = r, f = d, s0 = c1, s1 = c2 (float)
+  kBatchSub,          // a = b, b = t, d = r (float)
+  kBatchAdd,          // d = x, a = c (float)
+  kBatchFill,         // d = x, s0 = value (float)
+  kBatchCopy64,       // d = out, a = in (double): the solves' scalar states into one array
+};
+
+// Launchers (items: device array of `count` items, `blocks` = total workgroups).
+hipError_t launch_batch_vec(BatchVecOp op, const VecItem* items, int count, int64_t blocks, hipStream_t st);
+// Cell loop of degree p, precision, for one colour (items' first[colour]); ACC = false.
+hipError_t launch_batch_cells(int p, int precision, bool cart, const CellItem* items, int count, int colour,
+                              int64_t blocks, hipStream_t st);
+// Level transfer of degree pair (pc, pf, h_transfer) in FP32: prolongation (one launch) or one
+// colour of the restriction (after the coarse vectors were cleared by kBatchFill).
+hipError_t launch_batch_transfer(int pc, int pf, bool h_transfer, bool prolongate, int colour,
+                                 const TransferItem* items, int count, int64_t blocks, hipStream_t st);
+// Workgroups of the single-solve launches the batched ones reproduce.
+int vec_blocks(BatchVecOp op, int64_t n);
+
+}  // namespace mfq

@@ -24,6 +24,7 @@
 //    contiguous range; every wave's G load is 1 KiB contiguous and issued at kernel start.
 #include <climits>
 
+#include "batch.hpp"
 #include "kernels_common.hpp"
 
 namespace mfq {
@@ -34,9 +35,12 @@ constexpr int kAbsent = INT_MIN;  // lattice node outside the mesh (ragged last 
 
 // ---------------------------------------------------------------- index lattices
 // idx[ord][k]: global node of lattice node k = li + LX*(lj + LY*lk) of brick `ord`;
-// ~g on Dirichlet nodes, kAbsent outside the mesh.
+// ~g on Dirichlet nodes (nodes on a face whose bit is set in `faces`, bit 2d: X_d low, 2d+1: X_d
+// high), kAbsent outside the mesh; with side_base >= 0 the other nodes of the X1-low face are
+// hanging nodes, side_base + J + N1 K (entries of the face arrays).
 template <int P>
-__global__ __launch_bounds__(kBlock) void fill_index_kernel(int* __restrict__ idx, Bricks bk, int n, int bc) {
+__global__ __launch_bounds__(kBlock) void fill_index_kernel(int* __restrict__ idx, Bricks bk, int n, int faces,
+                                                            int side_base) {
   using C = Cell<P>;
   const int64_t total = bk.n_bricks * C::NL;
   const int64_t N1g = (int64_t)P * n + 1;
@@ -50,8 +54,10 @@ __global__ __launch_bounds__(kBlock) void fill_index_kernel(int* __restrict__ id
     int val = kAbsent;
     if (I < N1g && J < N1g && K < N1g) {
       const int64_t g = I + N1g * (J + N1g * K);
-      const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1g - 1 || J == N1g - 1 || K == N1g - 1);
-      val = bnd ? ~(int)g : (int)g;
+      const int e = N1g - 1;
+      const bool bnd = ((faces & 1) && I == 0) || ((faces & 2) && I == e) || ((faces & 4) && J == 0) ||
+                       ((faces & 8) && J == e) || ((faces & 16) && K == 0) || ((faces & 32) && K == e);
+      val = bnd ? ~(int)g : (side_base >= 0 && I == 0) ? side_base + (int)(J + N1g * K) : (int)g;
     }
     idx[L] = val;
   }
@@ -113,7 +119,7 @@ __device__ __forceinline__ bool cell_of(int bi, int bj, int bz, int lc, int n, i
 
 template <int P, typename Real>
 __global__ __launch_bounds__(kBlock) void geometry_kernel(Real* __restrict__ geo, Bricks bk, int n, double amp,
-                                                          double alpha, QuadRule<P> qr) {
+                                                          double alpha, QuadRule<P> qr, double x0) {
   using C = Cell<P>;
   const int64_t total = bk.n_bricks * C::N1 * C::NT;
   for (int64_t L = blockIdx.x * (int64_t)blockDim.x + threadIdx.x; L < total; L += (int64_t)gridDim.x * blockDim.x) {
@@ -130,7 +136,7 @@ __global__ __launch_bounds__(kBlock) void geometry_kernel(Real* __restrict__ geo
     double G[6] = {0, 0, 0, 0, 0, 0};
     if (cell_of<P>(bi, bj, bz, lc, n, ci, cj, ck)) {
       QGeo g;
-      qpoint_geometry(n, amp, ci + (int64_t)n * (cj + (int64_t)n * ck), qr.z[r], qr.z[s], qr.z[t], g);
+      qpoint_geometry(n, amp, ci + (int64_t)n * (cj + (int64_t)n * ck), qr.z[r], qr.z[s], qr.z[t], g, x0);
       merged_tensor(g, qr.w[r] * qr.w[s] * qr.w[t] * coefficient(alpha, g.x), G);
     }
     Real2<Real>* out = reinterpret_cast<Real2<Real>*>(geo) + (ord * C::N1 + t) * 3 * C::NT + lane;
@@ -199,20 +205,43 @@ __device__ __forceinline__ void lattice_index(const int* __restrict__ ip, const 
   }
 }
 
-template <typename Real, bool ACC, int BLOCK, int KPT, int NL>
+// Face arrays of a space with hanging nodes: index-lattice entries g >= base are nodes of the
+// hanging face, read from in[g - base] and written to out[g - base] instead of the vectors.
+template <typename Real>
+struct Side {
+  const Real* in = nullptr;
+  Real* out = nullptr;
+  int base = 0;
+};
+
+// MASK: nodes this brick stores (first writer) do not read dst (their lanes read entry 0
+// instead, a line every brick touches and the cache keeps), so the lines of stored-only nodes are
+// not fetched; otherwise every node's dst value is loaded and the unneeded ones dropped.
+template <typename Real, bool ACC, int BLOCK, int KPT, int NL, bool HANG = false, bool MASK = true>
 __device__ __forceinline__ void lattice_values(const Real* __restrict__ src, const Real* __restrict__ dst,
-                                               int (&gk)[KPT], unsigned first, Real* lat, Real (&dv)[KPT]) {
+                                               int (&gk)[KPT], unsigned first, Real* lat, Real (&dv)[KPT],
+                                               const Side<Real>& sd = {}) {
   const int tid = threadIdx.x;
 #pragma unroll
   for (int j = 0; j < KPT; ++j) {
     const int g0 = tid + j * BLOCK < NL ? gk[j] : kAbsent;
     gk[j] = g0;
     const bool live = g0 >= 0;
-    const int gs = live ? g0 : 0;
-    const Real s = src[gs];
-    const Real d = dst[gs];
+    int gs = live ? g0 : 0;
+    const bool need = live && (ACC || !(first >> j & 1u));
+    const Real* sp = src;
+    const Real* dp = dst;
+    if constexpr (HANG) {
+      if (gs >= sd.base) {
+        sp = sd.in;
+        dp = sd.out;
+        gs -= sd.base;
+      }
+    }
+    const Real s = sp[gs];
+    const Real d = dp[(MASK && !need) ? 0 : gs];
     lat[tid + j * BLOCK] = live ? s : (Real)0;
-    dv[j] = (live && (ACC || !(first >> j & 1u))) ? d : (Real)0;
+    dv[j] = need ? d : (Real)0;
   }
 }
 
@@ -226,9 +255,9 @@ __device__ __forceinline__ void lattice_dst(const Real* __restrict__ dst, int (&
   for (int j = 0; j < KPT; ++j) {
     const int g0 = tid + j * BLOCK < NL ? gk[j] : kAbsent;
     gk[j] = g0;
-    const bool live = g0 >= 0;
-    const Real d = dst[live ? g0 : 0];
-    dv[j] = (live && !(first >> j & 1u)) ? d : (Real)0;
+    const bool need = g0 >= 0 && !(first >> j & 1u);
+    const Real d = dst[need ? g0 : 0];
+    dv[j] = need ? d : (Real)0;
   }
 }
 
@@ -239,10 +268,10 @@ enum DirichletRow { kDirSource = 0, kDirUnit = 1, kDirZero = 2 };
 // Sum the cells' results per lattice node in a fixed order (cell c's result at res + c * cstride,
 // local lexicographic order) and write the brick's nodes: store or add per the `first` bit,
 // Dirichlet nodes get the DIR value (src added to dst when accumulating) from the brick that stores.
-template <int P, typename Real, bool ACC, int BLOCK, int KPT, int DIR = kDirSource>
+template <int P, typename Real, bool ACC, int BLOCK, int KPT, int DIR = kDirSource, bool HANG = false>
 __device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, const Real* __restrict__ src,
                                                 Real* __restrict__ dst, const int (&gk)[KPT], unsigned first,
-                                                const Real (&dv)[KPT]) {
+                                                const Real (&dv)[KPT], const Side<Real>& sd = {}) {
   using C = Cell<P>;
   constexpr int N1 = C::N1, LX = C::LX, LY = C::LY;
   const int tid = threadIdx.x;
@@ -264,7 +293,15 @@ __device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, co
         }
     const bool fj = first >> j & 1u;
     if (g0 >= 0) {
-      dst[g0] = (ACC || !fj) ? dv[j] + sum : sum;
+      Real* dp = dst;
+      int gl = g0;
+      if constexpr (HANG) {
+        if (gl >= sd.base) {
+          dp = sd.out;
+          gl -= sd.base;
+        }
+      }
+      dp[gl] = (ACC || !fj) ? dv[j] + sum : sum;
     } else if (fj) {
       const int gg = ~g0;
       if constexpr (DIR == kDirUnit)
@@ -292,10 +329,13 @@ struct CartQuad {
   Real h;
 };
 
-template <int P, typename Real, bool ACC, bool CART = false>
-__global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo, const Real* __restrict__ src,
-                  Real* __restrict__ dst, Bricks bk, int colour, ShapeEO<P, Real> sh,
-                  CartQuad<P, Real> cq = {}) {
+// One brick (number b of colour `colour`) of the operator application by the workgroup.  HANG: a
+// space with hanging nodes (X1-low face nodes go through the face arrays `sd`).
+template <int P, typename Real, bool ACC, bool CART, bool HANG>
+__device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const Real* __restrict__ geo,
+                                            const Real* __restrict__ src, Real* __restrict__ dst, const Bricks& bk,
+                                            int colour, int64_t b, const ShapeEO<P, Real>& sh,
+                                            const CartQuad<P, Real>& cq, const Side<Real>& sd) {
   using C = Cell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NCELL = C::NCELL, NT = C::NT, LX = C::LX, LY = C::LY, NL = C::NL;
   constexpr int BLOCK = NT;                        // threads of the workgroup
@@ -312,9 +352,9 @@ __global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restric
   const int e = tid - lc * T;
   const int e0 = e % N1, e1 = e / N1;
   const int cx = lc % C::BX, cy = (lc / C::BX) % C::BY, cz = lc / (C::BX * C::BY);
-  const int64_t ord = bk.offset[colour] + blockIdx.x;
+  const int64_t ord = bk.offset[colour] + b;
   int bi, bj, bz;
-  brick_of(bk, colour, blockIdx.x, bi, bj, bz);
+  brick_of(bk, colour, b, bi, bj, bz);
   Real* L0 = lds + lc * NQ;
   Real* L1 = L0 + SLOT;
   Real* L2 = L1 + SLOT;
@@ -359,7 +399,9 @@ __global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restric
   Real dv[KPT];
   lattice_index<P, BLOCK, KPT>(idx + ord * (int64_t)NL, bk, bi, bj, bz, gk, first);
   if (MFQ_G_STAGE == 0) load_g();
-  lattice_values<Real, ACC, BLOCK, KPT, NL>(src, dst, gk, first, lat, dv);
+  // the masked dst gather was timed per degree on MI355X: slower only for p = 6 FP64 and p = 5 FP32
+  constexpr bool MASK = !((P == 6 && sizeof(Real) == 8) || (P == 5 && sizeof(Real) == 4));
+  lattice_values<Real, ACC, BLOCK, KPT, NL, HANG, MASK>(src, dst, gk, first, lat, dv, sd);
   lds_barrier();
 
   // x: values and x-derivatives at (q, e0, e1) from the lane's x-pencil
@@ -477,7 +519,34 @@ __global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restric
   }
   lds_barrier();
   // sum the cells' results per lattice node (fixed order) and write the brick's nodes
-  scatter_lattice<P, Real, ACC, BLOCK, KPT>(lds, NQ, src, dst, gk, first, dv);
+  scatter_lattice<P, Real, ACC, BLOCK, KPT, kDirSource, HANG>(lds, NQ, src, dst, gk, first, dv, sd);
+}
+
+template <int P, typename Real, bool ACC, bool CART = false, bool HANG = false>
+__global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo, const Real* __restrict__ src,
+                  Real* __restrict__ dst, Bricks bk, int colour, ShapeEO<P, Real> sh,
+                  CartQuad<P, Real> cq = {}, Side<Real> sd = {}) {
+  vmult_brick<P, Real, ACC, CART, HANG>(idx, geo, src, dst, bk, colour, blockIdx.x, sh, cq, sd);
+}
+
+// Batched form (serving): one launch of colour `colour` over many operators; workgroup b belongs
+// to the item whose range [first[colour], next first) holds it and computes that operator's brick
+// b - first, exactly as the single-operator launch does (results bitwise equal).
+template <int P, typename Real, bool CART>
+__global__ __launch_bounds__(Cell<P>::NT) void batch_vmult_kernel(const CellItem* __restrict__ items, int count,
+                                                                   int colour, ShapeEO<P, Real> sh,
+                                                                   CartQuad<P, Real> cq) {
+  int lo = 0, hi = count - 1;
+  const int64_t b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first[colour] <= b) lo = mid; else hi = mid - 1;
+  }
+  const CellItem& it = items[lo];
+  CartQuad<P, Real> cqi = cq;
+  if constexpr (CART) cqi.h = (Real)(1.0 / it.bk.n);
+  vmult_brick<P, Real, false, CART, false>(it.idx, (const Real*)it.geo, (const Real*)it.src, (Real*)it.dst, it.bk,
+                                          colour, b - it.first[colour], sh, cqi, Side<Real>{});
 }
 
 // ---------------------------------------------------------------- operator application, MFMA (FP32)
@@ -1093,7 +1162,8 @@ int grid_for(int64_t work) {
 template <int P>
 hipError_t fill_index_p(const OpView& v, int* idx, hipStream_t st) {
   using C = Cell<P>;
-  fill_index_kernel<P><<<grid_for(v.bricks.n_bricks * C::NL), kBlock, 0, st>>>(idx, v.bricks, v.n, v.bc);
+  fill_index_kernel<P><<<grid_for(v.bricks.n_bricks * C::NL), kBlock, 0, st>>>(idx, v.bricks, v.n, v.bc_faces,
+                                                                                v.side_base);
   return hipGetLastError();
 }
 
@@ -1102,9 +1172,11 @@ hipError_t geometry_p(const OpView& v, int precision, void* geo, hipStream_t st)
   using C = Cell<P>;
   const int g = grid_for(v.bricks.n_bricks * C::N1 * C::NT);
   if (precision == MFQ_FP64)
-    geometry_kernel<P, double><<<g, kBlock, 0, st>>>((double*)geo, v.bricks, v.n, v.amplitude, v.alpha, make_rule<P>());
+    geometry_kernel<P, double><<<g, kBlock, 0, st>>>((double*)geo, v.bricks, v.n, v.amplitude, v.alpha, make_rule<P>(),
+                                                     v.x0);
   else
-    geometry_kernel<P, float><<<g, kBlock, 0, st>>>((float*)geo, v.bricks, v.n, v.amplitude, v.alpha, make_rule<P>());
+    geometry_kernel<P, float><<<g, kBlock, 0, st>>>((float*)geo, v.bricks, v.n, v.amplitude, v.alpha, make_rule<P>(),
+                                                    v.x0);
   return hipGetLastError();
 }
 
@@ -1130,6 +1202,18 @@ hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipSt
     const Tables1D& tb = tables(P);
     for (int a = 0; a <= P; ++a) cq.w[a] = (Real)tb.omega[a];
     cq.h = (Real)(1.0 / v.n);
+  }
+  if (v.side_base >= 0) {
+    // space with hanging nodes: overwrite only, quadrature tensors read
+    if (acc || !v.side_in || !v.side_out) return hipErrorInvalidValue;
+    const Side<Real> sd{(const Real*)v.side_in, (Real*)v.side_out, v.side_base};
+    for (int c = 0; c < kColours; ++c) {
+      const int64_t nb = v.bricks.count[c];
+      if (nb == 0) continue;
+      vmult_kernel<P, Real, false, false, true><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(
+          v.idx, (const Real*)v.geo, (const Real*)src, (Real*)dst, v.bricks, c, sh, CartQuad<P, Real>{}, sd);
+    }
+    return hipGetLastError();
   }
   for (int c = 0; c < kColours; ++c) {
     const int64_t nb = v.bricks.count[c];
@@ -1171,6 +1255,29 @@ hipError_t vmult_p(const OpView& v, int precision, const void* src, void* dst, b
   if (precision == MFQ_FP64) return vmult_pr<P, double>(v, src, dst, acc, st);
   if (v.mfma) return vmult_mfma_p<P>(v, src, dst, acc, st);
   return vmult_pr<P, float>(v, src, dst, acc, st);
+}
+
+template <int P, typename Real>
+hipError_t batch_cells_pr(bool cart, const CellItem* items, int count, int colour, int64_t blocks, hipStream_t st) {
+  static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
+  if (cart) {
+    CartQuad<P, Real> cq{};
+    const Tables1D& tb = tables(P);
+    for (int a = 0; a <= P; ++a) cq.w[a] = (Real)tb.omega[a];
+    batch_vmult_kernel<P, Real, true><<<(unsigned)blocks, Cell<P>::NT, 0, st>>>(items, count, colour, sh, cq);
+  } else {
+    batch_vmult_kernel<P, Real, false><<<(unsigned)blocks, Cell<P>::NT, 0, st>>>(items, count, colour, sh,
+                                                                                  CartQuad<P, Real>{});
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t batch_cells_p(int precision, bool cart, const CellItem* items, int count, int colour, int64_t blocks,
+                         hipStream_t st) {
+  if (count <= 0 || blocks <= 0) return hipSuccess;
+  if (precision == MFQ_FP64) return batch_cells_pr<P, double>(cart, items, count, colour, blocks, st);
+  return batch_cells_pr<P, float>(cart, items, count, colour, blocks, st);
 }
 
 template <int P>
@@ -1239,6 +1346,11 @@ hipError_t launch_geometry_export(const OpView& v, int precision, double* out, h
 hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, void* dst, bool accumulate,
                               hipStream_t st) {
   MFQ_DISPATCH(v.p, vmult_p, v, precision, src, dst, accumulate, st);
+}
+
+hipError_t launch_batch_cells(int p, int precision, bool cart, const CellItem* items, int count, int colour,
+                              int64_t blocks, hipStream_t st) {
+  MFQ_DISPATCH(p, batch_cells_p, precision, cart, items, count, colour, blocks, st);
 }
 
 hipError_t launch_diagonal_cells(const OpView& v, int precision, void* diag, hipStream_t st) {

@@ -225,7 +225,8 @@ __device__ __forceinline__ void apply_t2(const Real* M1, const Real (&in1)[N1], 
 }
 
 // Quadrature-point geometry of the deformed cube (FP64): the exact map
-// x = X + A sin(pi X1) sin(pi X2) sin(pi X3) (1,1,1) evaluated at the point, X = h*(cell + xhat).
+// x = X + A sin(pi X1) sin(pi X2) sin(pi X3) (1,1,1) evaluated at the point, X = h*(cell + xhat)
+// (shifted by x0 along X1 for a mesh that starts at X1 = x0).
 struct QGeo {
   double x[3];      // physical point
   double Jinv[3][3];
@@ -233,10 +234,10 @@ struct QGeo {
 };
 
 __device__ __forceinline__ void qpoint_geometry(int n, double amp, int64_t cell, double xh0, double xh1,
-                                                double xh2, QGeo& g) {
+                                                double xh2, QGeo& g, double x0 = 0.0) {
   const double h = 1.0 / n;
   const int64_t i = cell % n, j = (cell / n) % n, k = cell / ((int64_t)n * n);
-  const double X[3] = {h * ((double)i + xh0), h * ((double)j + xh1), h * ((double)k + xh2)};
+  const double X[3] = {x0 + h * ((double)i + xh0), h * ((double)j + xh1), h * ((double)k + xh2)};
   double s[3], c[3];
 #pragma unroll
   for (int d = 0; d < 3; ++d) sincospi(X[d], &s[d], &c[d]);

@@ -11,6 +11,7 @@
 // parities of their coordinates (cells of one colour share no coarse node); one launch per
 // colour, colours in order, each cell adding its sums into its coarse nodes with plain stores:
 // no atomics, a fixed summation order, bitwise reproducible.
+#include "batch.hpp"
 #include "kernels_common.hpp"
 
 namespace mfq {
@@ -24,14 +25,14 @@ struct Transfer1D {
 
 constexpr int kTBlock = 128;
 
+// prolongation of coarse cell `cell` by the workgroup
 template <int PC, int NF1, typename Real>
-__global__ __launch_bounds__(kTBlock) void prolongate_kernel(const Real* __restrict__ coarse, Real* __restrict__ fine,
-                                                             int nc, int bc, Transfer1D<PC, NF1> tr) {
+__device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse, Real* __restrict__ fine, int nc, int bc,
+                                                const Transfer1D<PC, NF1>& tr, int64_t cell) {
   constexpr int M = PC + 1;
   __shared__ Real u[M * M * M];
   __shared__ Real t1[NF1 * M * M];
   __shared__ Real t2[NF1 * NF1 * M];
-  const int64_t cell = blockIdx.x;
   const int ic = (int)(cell % nc), jc = (int)((cell / nc) % nc), kc = (int)(cell / ((int64_t)nc * nc));
   const int64_t N1c = (int64_t)PC * nc + 1;
   const int stride = NF1 - 1;
@@ -71,15 +72,21 @@ __global__ __launch_bounds__(kTBlock) void prolongate_kernel(const Real* __restr
 }
 
 template <int PC, int NF1, typename Real>
-__global__ __launch_bounds__(kTBlock) void restrict_kernel(const Real* __restrict__ fine, Real* __restrict__ coarse,
-                                                           int nc, int bc, int colour, Transfer1D<PC, NF1> tr) {
+__global__ __launch_bounds__(kTBlock) void prolongate_kernel(const Real* __restrict__ coarse, Real* __restrict__ fine,
+                                                             int nc, int bc, Transfer1D<PC, NF1> tr) {
+  prolongate_cell<PC, NF1, Real>(coarse, fine, nc, bc, tr, blockIdx.x);
+}
+
+// restriction of coarse cell b of colour `colour` by the workgroup
+template <int PC, int NF1, typename Real>
+__device__ __forceinline__ void restrict_cell(const Real* __restrict__ fine, Real* __restrict__ coarse, int nc, int bc,
+                                              int colour, const Transfer1D<PC, NF1>& tr, int64_t b) {
   constexpr int M = PC + 1;
   __shared__ Real t1[M * NF1 * NF1];  // t1[a][j][l]
   __shared__ Real t2[M * M * NF1];    // t2[a][b][l]
   // cell (ic, jc, kc) of colour (ic & 1) + 2 (jc & 1) + 4 (kc & 1), x fastest within the colour
   const int px = colour & 1, py = (colour >> 1) & 1, pz = colour >> 2;
   const int cxn = (nc + 1 - px) / 2, cyn = (nc + 1 - py) / 2;
-  const int64_t b = blockIdx.x;
   const int ic = 2 * (int)(b % cxn) + px, jc = 2 * (int)((b / cxn) % cyn) + py, kc = 2 * (int)(b / ((int64_t)cxn * cyn)) + pz;
   const int64_t N1c = (int64_t)PC * nc + 1;
   const int stride = NF1 - 1;
@@ -117,6 +124,54 @@ __global__ __launch_bounds__(kTBlock) void restrict_kernel(const Real* __restric
     // this launch's cells share no coarse node; earlier colours' sums are already in place
     if (!bnd) coarse[I + N1c * (J + N1c * K)] += s;
   }
+}
+
+template <int PC, int NF1, typename Real>
+__global__ __launch_bounds__(kTBlock) void restrict_kernel(const Real* __restrict__ fine, Real* __restrict__ coarse,
+                                                           int nc, int bc, int colour, Transfer1D<PC, NF1> tr) {
+  restrict_cell<PC, NF1, Real>(fine, coarse, nc, bc, colour, tr, blockIdx.x);
+}
+
+// Batched forms (serving): workgroup b belongs to the item whose range [first[c], next first)
+// holds it (c = 0 for the prolongation, the colour for the restriction) and does that item's cell
+// b - first, as the single-transfer launch does (results bitwise equal).
+__device__ __forceinline__ int transfer_item(const TransferItem* __restrict__ it, int count, int c, int64_t b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (it[mid].first[c] <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int PC, int NF1>
+__global__ __launch_bounds__(kTBlock) void batch_prolongate_kernel(const TransferItem* __restrict__ items, int count,
+                                                                   Transfer1D<PC, NF1> tr) {
+  const TransferItem& it = items[transfer_item(items, count, 0, blockIdx.x)];
+  prolongate_cell<PC, NF1, float>((const float*)it.in, (float*)it.out, it.nc, it.bc, tr, blockIdx.x - it.first[0]);
+}
+
+template <int PC, int NF1>
+__global__ __launch_bounds__(kTBlock) void batch_restrict_kernel(const TransferItem* __restrict__ items, int count,
+                                                                 int colour, Transfer1D<PC, NF1> tr) {
+  const TransferItem& it = items[transfer_item(items, count, colour, blockIdx.x)];
+  restrict_cell<PC, NF1, float>((const float*)it.in, (float*)it.out, it.nc, it.bc, colour, tr,
+                                blockIdx.x - it.first[colour]);
+}
+
+template <int PC, int NF1>
+hipError_t batch_transfer_pn(bool h_transfer, bool prolongate, int colour, const TransferItem* items, int count,
+                             int64_t blocks, hipStream_t st) {
+  int nf1 = 0;
+  const std::vector<double> P1 = transfer_matrix_1d(PC, h_transfer ? PC : NF1 - 1, h_transfer, &nf1);
+  if (nf1 != NF1) return hipErrorInvalidValue;
+  Transfer1D<PC, NF1> tr;
+  for (int k = 0; k < NF1 * (PC + 1); ++k) tr.P[k] = P1[k];
+  if (prolongate)
+    batch_prolongate_kernel<PC, NF1><<<(unsigned)blocks, kTBlock, 0, st>>>(items, count, tr);
+  else
+    batch_restrict_kernel<PC, NF1><<<(unsigned)blocks, kTBlock, 0, st>>>(items, count, colour, tr);
+  return hipGetLastError();
 }
 
 template <int PC, int NF1>
@@ -169,6 +224,29 @@ hipError_t launch_transfer(const mfq_transfer* t, int precision, bool prolongate
   // degree switches of the hierarchy rule: p -> ceil(p/2)
 #define MFQ_PT(a, b) \
   if (pc == a && pf == b) return transfer_pn<a, b + 1>(t, precision, prolongate, in, out, st);
+  MFQ_PT(1, 2) MFQ_PT(2, 3) MFQ_PT(2, 4) MFQ_PT(3, 5) MFQ_PT(3, 6) MFQ_PT(4, 7) MFQ_PT(4, 8)
+#undef MFQ_PT
+  return hipErrorInvalidValue;
+}
+
+hipError_t launch_batch_transfer(int pc, int pf, bool h_transfer, bool prolongate, int colour,
+                                 const TransferItem* items, int count, int64_t blocks, hipStream_t st) {
+  if (count <= 0 || blocks <= 0) return hipSuccess;
+  if (h_transfer) {
+    switch (pc) {
+      case 1: return batch_transfer_pn<1, 3>(true, prolongate, colour, items, count, blocks, st);
+      case 2: return batch_transfer_pn<2, 5>(true, prolongate, colour, items, count, blocks, st);
+      case 3: return batch_transfer_pn<3, 7>(true, prolongate, colour, items, count, blocks, st);
+      case 4: return batch_transfer_pn<4, 9>(true, prolongate, colour, items, count, blocks, st);
+      case 5: return batch_transfer_pn<5, 11>(true, prolongate, colour, items, count, blocks, st);
+      case 6: return batch_transfer_pn<6, 13>(true, prolongate, colour, items, count, blocks, st);
+      case 7: return batch_transfer_pn<7, 15>(true, prolongate, colour, items, count, blocks, st);
+      case 8: return batch_transfer_pn<8, 17>(true, prolongate, colour, items, count, blocks, st);
+      default: return hipErrorInvalidValue;
+    }
+  }
+#define MFQ_PT(a, b) \
+  if (pc == a && pf == b) return batch_transfer_pn<a, b + 1>(false, prolongate, colour, items, count, blocks, st);
   MFQ_PT(1, 2) MFQ_PT(2, 3) MFQ_PT(2, 4) MFQ_PT(3, 5) MFQ_PT(3, 6) MFQ_PT(4, 7) MFQ_PT(4, 8)
 #undef MFQ_PT
   return hipErrorInvalidValue;

@@ -7,6 +7,7 @@
 // (deterministic: partial sums per workgroup, then a fixed-order tree over the partials), so the
 // host never waits inside an iteration.  Convergence is decided on the device; the host polls a
 // flag every few iterations.
+#include "batch.hpp"
 #include "kernels_common.hpp"
 #include "solver_state.hpp"
 
@@ -409,6 +410,160 @@ __global__ __launch_bounds__(kVBlock) void lz_direction_kernel(const Real* __res
     p[i] = z[i] + beta * p[i];
 }
 
+// ---------------------------------------------------------------- batched forms (serving)
+// One launch covers many solves: workgroup b belongs to the item whose range [first, next first)
+// holds it, and does what workgroup b - first of that item's single-solve launch does (same grid
+// per item, same partial sums), so each solve's results are bitwise those it gets alone.
+__device__ __forceinline__ int batch_item(const VecItem* __restrict__ it, int count, int64_t b) {
+  int lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (it[mid].first <= b) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+// grid_reduce over the item's own workgroups (lb of nblk)
+__device__ bool item_reduce(double part, SolverState* st, int lb, int nblk, double& total, double* sh) {
+  __shared__ bool last;
+  if (threadIdx.x == 0) {
+    st->partials[lb] = part;
+    __threadfence();
+    const unsigned prev = atomicAdd(&st->counter, 1u);
+    last = (prev == (unsigned)nblk - 1);
+  }
+  __syncthreads();
+  if (!last) return false;
+  __threadfence();
+  double v = 0;
+  for (int k = threadIdx.x; k < nblk; k += kVBlock) v += __hip_atomic_load(st->partials + k, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+  total = block_sum(v, sh);
+  if (threadIdx.x == 0) st->counter = 0u;
+  return true;
+}
+
+template <int OP>
+__global__ __launch_bounds__(kVBlock) void batch_vec_kernel(const VecItem* __restrict__ items, int count) {
+  __shared__ double sh[kVBlock / 64];
+  const VecItem& it = items[batch_item(items, count, blockIdx.x)];
+  const int lb = (int)(blockIdx.x - it.first);
+  const int64_t n = it.n, stride = (int64_t)it.nblk * kVBlock;
+  const int64_t i0 = (int64_t)lb * kVBlock + threadIdx.x;
+  SolverState* st = it.st;
+  if constexpr (OP == kBatchCgAlpha) {
+    if (st->done) return;
+    const double* p = (const double*)it.a;
+    const double* Ap = (const double*)it.b;
+    double part = 0;
+    for (int64_t i = i0; i < n; i += stride) part += p[i] * Ap[i];
+    part = block_sum(part, sh);
+    double tot;
+    if (item_reduce(part, st, lb, it.nblk, tot, sh) && threadIdx.x == 0) {
+      st->pAp = tot;
+      st->alpha = (tot != 0.0) ? st->rz / tot : 0.0;
+    }
+  } else if constexpr (OP == kBatchCgUpdate) {
+    if (st->done) return;
+    double* x = (double*)it.d;
+    double* r = (double*)it.e;
+    const double* p = (const double*)it.a;
+    const double* Ap = (const double*)it.b;
+    const double alpha = st->alpha;
+    double part = 0;
+    for (int64_t i = i0; i < n; i += stride) {
+      x[i] += alpha * p[i];
+      const double v = r[i] - alpha * Ap[i];
+      r[i] = v;
+      part += v * v;
+    }
+    part = block_sum(part, sh);
+    double tot;
+    if (item_reduce(part, st, lb, it.nblk, tot, sh) && threadIdx.x == 0) {
+      st->rr = tot;
+      st->iter += 1;
+      if (!(tot == tot) || tot > 1e308) {
+        st->nonfinite = 1;
+        st->done = 1;
+      } else if (tot <= st->tol2 * st->bb) {
+        st->done = 1;
+        st->converged_iter = st->iter;
+      }
+    }
+  } else if constexpr (OP == kBatchCgBeta) {
+    if (st->done) return;
+    const double* r = (const double*)it.a;
+    const double* z = (const double*)it.b;
+    double part = 0;
+    for (int64_t i = i0; i < n; i += stride) part += r[i] * z[i];
+    part = block_sum(part, sh);
+    double tot;
+    if (item_reduce(part, st, lb, it.nblk, tot, sh) && threadIdx.x == 0) {
+      st->beta = (st->rz != 0.0) ? tot / st->rz : 0.0;
+      st->rz = tot;
+    }
+  } else if constexpr (OP == kBatchCgDirection) {
+    if (st->done) return;
+    const double* z = (const double*)it.a;
+    double* p = (double*)it.d;
+    const double beta = st->beta;
+    for (int64_t i = i0; i < n; i += stride) p[i] = it.flag ? z[i] : z[i] + beta * p[i];
+  } else if constexpr (OP == kBatchCast64To32) {
+    const double* in = (const double*)it.a;
+    float* out = (float*)it.d;
+    for (int64_t i = i0; i < n; i += stride) out[i] = (float)in[i];
+  } else if constexpr (OP == kBatchCast32To64) {
+    const float* in = (const float*)it.a;
+    double* out = (double*)it.d;
+    for (int64_t i = i0; i < n; i += stride) out[i] = (double)in[i];
+  } else if constexpr (OP == kBatchChebFirst) {
+    const float* b = (const float*)it.a;
+    const float* t = (const float*)it.b;
+    const float* dinv = (const float*)it.c;
+    float* x = (float*)it.d;
+    float* r = (float*)it.e;
+    float* d = (float*)it.f;
+    const float inv_theta = (float)it.s0;
+    for (int64_t i = i0; i < n; i += stride) {
+      const float rv = it.flag ? b[i] : b[i] - t[i];
+      const float dv = dinv[i] * rv * inv_theta;
+      r[i] = rv;
+      d[i] = dv;
+      x[i] = it.flag ? dv : x[i] + dv;
+    }
+  } else if constexpr (OP == kBatchChebStep) {
+    const float* Ad = (const float*)it.a;
+    const float* dinv = (const float*)it.c;
+    float* x = (float*)it.d;
+    float* r = (float*)it.e;
+    float* d = (float*)it.f;
+    const float c1 = (float)it.s0, c2 = (float)it.s1;
+    for (int64_t i = i0; i < n; i += stride) {
+      const float rv = r[i] - Ad[i];
+      const float dv = c1 * d[i] + c2 * dinv[i] * rv;
+      r[i] = rv;
+      d[i] = dv;
+      x[i] += dv;
+    }
+  } else if constexpr (OP == kBatchSub) {
+    const float* b = (const float*)it.a;
+    const float* t = (const float*)it.b;
+    float* r = (float*)it.d;
+    for (int64_t i = i0; i < n; i += stride) r[i] = b[i] - t[i];
+  } else if constexpr (OP == kBatchAdd) {
+    float* x = (float*)it.d;
+    const float* c = (const float*)it.a;
+    for (int64_t i = i0; i < n; i += stride) x[i] += c[i];
+  } else if constexpr (OP == kBatchFill) {
+    float* x = (float*)it.d;
+    const float v = (float)it.s0;
+    for (int64_t i = i0; i < n; i += stride) x[i] = v;
+  } else if constexpr (OP == kBatchCopy64) {
+    const double* in = (const double*)it.a;
+    double* out = (double*)it.d;
+    for (int64_t i = i0; i < n; i += stride) out[i] = in[i];
+  }
+}
+
 }  // namespace
 
 hipError_t launch_fill(int precision, void* x, int64_t n, double value, hipStream_t st) {
@@ -594,6 +749,38 @@ hipError_t launch_splitmix(int precision, void* x, int64_t N1, uint64_t seed, bo
     splitmix_kernel<double><<<g, kVBlock, 0, st>>>((double*)x, N1, seed, masked ? 1 : 0);
   else
     splitmix_kernel<float><<<g, kVBlock, 0, st>>>((float*)x, N1, seed, masked ? 1 : 0);
+  return hipGetLastError();
+}
+
+int vec_blocks(BatchVecOp op, int64_t n) {
+  switch (op) {
+    case kBatchCgAlpha:
+    case kBatchCgUpdate:
+    case kBatchCgBeta:
+      return vgrid(n);      // reductions: the single-solve grid, so the partial sums agree
+    default:
+      return vgrid(n) * 4;  // elementwise
+  }
+}
+
+hipError_t launch_batch_vec(BatchVecOp op, const VecItem* items, int count, int64_t blocks, hipStream_t st) {
+  if (count <= 0 || blocks <= 0) return hipSuccess;
+  const unsigned g = (unsigned)blocks;
+  switch (op) {
+    case kBatchCgAlpha: batch_vec_kernel<kBatchCgAlpha><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchCgUpdate: batch_vec_kernel<kBatchCgUpdate><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchCgBeta: batch_vec_kernel<kBatchCgBeta><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchCgDirection: batch_vec_kernel<kBatchCgDirection><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchCast64To32: batch_vec_kernel<kBatchCast64To32><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchCast32To64: batch_vec_kernel<kBatchCast32To64><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchChebFirst: batch_vec_kernel<kBatchChebFirst><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchChebStep: batch_vec_kernel<kBatchChebStep><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchSub: batch_vec_kernel<kBatchSub><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchAdd: batch_vec_kernel<kBatchAdd><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchFill: batch_vec_kernel<kBatchFill><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchCopy64: batch_vec_kernel<kBatchCopy64><<<g, kVBlock, 0, st>>>(items, count); break;
+    default: return hipErrorInvalidValue;
+  }
   return hipGetLastError();
 }
 

@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 
 #include <cstdint>
+#include <functional>
 #include <string>
 #include <vector>
 
@@ -137,6 +138,7 @@ inline Bricks make_bricks(int p, int n) {
 struct mfq_mesh {
   int n;
   double amplitude;
+  double x0 = 0.0;            // X1 of the mesh's first cell face (1 for the fine block of the two-block mesh)
 };
 
 struct mfq_space {
@@ -145,6 +147,8 @@ struct mfq_space {
   int bc;
   int64_t n_dofs;
   int64_t n_cells;
+  int bc_faces = -1;          // Dirichlet faces (bit 2d: X_d low, 2d+1: X_d high); -1: all six when bc
+  bool side = false;          // nodes on the X1-low face are hanging (read from / written to face arrays)
 };
 
 struct mfq_op {
@@ -202,11 +206,18 @@ struct OpView {
   const int* idx;
   const void* geo;
   bool mfma;
+  double x0;                  // X1 offset of the mesh
+  int bc_faces;               // Dirichlet faces, bit 2d: X_d low, 2d+1: X_d high
+  int side_base;              // >= 0: index-lattice entries >= side_base are X1-low face nodes read from
+                              // side_in[g - side_base] and written to side_out[g - side_base]
+  const void* side_in;        // set by the caller of a cell loop on a space with hanging nodes
+  void* side_out;
 };
 inline OpView view(const mfq_op* op) {
   const mfq_space* s = op->space;
+  const int faces = s->bc_faces >= 0 ? s->bc_faces : (s->bc ? 0b111111 : 0);
   return OpView{s->p, s->mesh->n, s->bc, s->n_cells, s->n_dofs, s->mesh->amplitude, op->alpha, op->bricks,
-                op->idx, op->geo, op->mfma};
+                op->idx, op->geo, op->mfma, s->mesh->x0, faces, s->side ? (int)s->n_dofs : -1, nullptr, nullptr};
 }
 
 // precision of a vector argument: MFQ_FP32_MFMA means float; -1 if unknown
@@ -290,8 +301,22 @@ hipError_t launch_lz_update(int precision, void* r, void* z, const void* Ap, con
                             SolverState* s, double* trace, int count_slot, hipStream_t st);
 hipError_t launch_lz_direction(int precision, const void* z, void* p, int64_t n, SolverState* s, hipStream_t st);
 
+// two-block mesh with hanging nodes (kernels_hang.hip): f = (Pi x Pi)(m x0) on the interface and
+// y1 = x1 on block 1's hanging rows; y0 += (Pi x Pi)^T g on block 0's interface nodes
+hipError_t launch_hang_interp(int precision, int p, int n, int bc, const void* x0, const void* x1, void* f, void* y1,
+                              hipStream_t st);
+hipError_t launch_hang_restrict(int precision, int p, int n, int bc, const void* g, void* y0, hipStream_t st);
+
 // ---------------------------------------------------------------- host-side operator helpers (api.cpp)
 int op_vmult(const mfq_op* op, const void* src, void* dst, hipStream_t st);      // zero dst + cell loop
+
+// Unpreconditioned FP64 CG from x = 0 with any operator (solver.cpp): work holds r, p, A p and the
+// device-resident scalars (cg_work_bytes); info gets the iterations and the true relative residual
+// ||b - A x|| / ||b|| (MFQ_ENOCONV when it exceeds rtol).
+using Apply = std::function<int(const double* in, double* out)>;
+size_t cg_work_bytes(int64_t n);
+int cg_unpreconditioned(const Apply& apply, const double* b, double* x, int64_t n, double rtol, int max_iter,
+                        void* work, hipStream_t st, mfq_solve_info* info);
 int op_diagonal(const mfq_op* op, void* diag, hipStream_t st);
 const char* last_error_cstr();
 

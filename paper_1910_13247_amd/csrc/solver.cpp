@@ -4,6 +4,7 @@
 // correction).  Host code only orchestrates launches; every vector operation runs on the device.
 #include <algorithm>
 #include <chrono>
+#include <cstddef>
 #include <cmath>
 #include <cstring>
 #include <functional>
@@ -11,6 +12,7 @@
 #include <thread>
 #include <vector>
 
+#include "batch.hpp"
 #include "mfq_internal.hpp"
 #include "solver_state.hpp"
 
@@ -229,8 +231,6 @@ int poll(SolverState* dev, SolverState& host, hipStream_t st) {
   MFQ_HIP(hipStreamSynchronize(st));
   return MFQ_OK;
 }
-
-using Apply = std::function<int(const double* in, double* out)>;
 
 struct PcgResult {
   int iters = 0;
@@ -560,6 +560,405 @@ int begin_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_
 }
 
 }  // namespace
+
+
+// ---------------------------------------------------------------- batched steps (serving)
+// Many running solves advanced by one launch per (kernel, degree): the launches of one CG
+// iteration of every solve (the FP64 operator, the CG updates, the FP32 V-cycle level by level from
+// the finest) are planned once per step as work tables, uploaded in one copy, and replayed for
+// each iteration of the step.  Each solve's kernels see exactly the operands and grids of its own
+// launches, so its results are bitwise those of mfq_batch_step.
+struct mfq_batch {
+  int max_solvers = 0;
+  size_t table_cap = 0;          // bytes of the table region
+  size_t state_off = 0;          // gathered scalar states (device)
+  size_t bytes = 0;
+  char* buf = nullptr;
+  char* host_tables = nullptr;   // pinned staging of the tables
+  double* host_states = nullptr; // pinned copy of the gathered states
+  hipEvent_t uploaded = nullptr; // the last table upload has left the staging buffer
+  ~mfq_batch() {
+    if (uploaded) (void)hipEventDestroy(uploaded);
+    if (host_tables) (void)hipHostFree(host_tables);
+    if (host_states) (void)hipHostFree(host_states);
+  }
+};
+
+namespace {
+
+constexpr size_t kBatchTableBytesPerSolve = 48 << 10;
+constexpr int kStateDoubles = (int)(offsetof(SolverState, partials) / sizeof(double));
+
+struct PlanLaunch {
+  enum Kind { kVec, kCells, kTransfer } kind = kVec;
+  int op = 0, p = 0, pf = 0, precision = 0, colour = 0;
+  bool h = false, cart = false, prolongate = false;
+  size_t off = 0;
+  int count = 0;
+  int64_t blocks = 0;
+};
+
+struct Plan {
+  std::vector<char> tab;
+  std::vector<PlanLaunch> launches;
+
+  template <class T>
+  size_t put(const std::vector<T>& v) {
+    const size_t off = round_up(tab.size(), 64);
+    tab.resize(off + v.size() * sizeof(T));
+    std::memcpy(tab.data() + off, v.data(), v.size() * sizeof(T));
+    return off;
+  }
+  void vec(BatchVecOp op, std::vector<VecItem>& items) {
+    if (items.empty()) return;
+    int64_t blk = 0;
+    for (VecItem& it : items) {
+      it.first = blk;
+      it.nblk = vec_blocks(op, it.n);
+      blk += it.nblk;
+    }
+    PlanLaunch L;
+    L.kind = PlanLaunch::kVec;
+    L.op = op;
+    L.off = put(items);
+    L.count = (int)items.size();
+    L.blocks = blk;
+    launches.push_back(L);
+  }
+  // dst = A src for each (operator, src, dst): one launch per (degree, precision, Cartesian form,
+  // colour), colours in order
+  struct Apply {
+    const mfq_op* op;
+    const void* src;
+    void* dst;
+  };
+  void cells(const std::vector<Apply>& list) {
+    std::vector<int> done(list.size(), 0);
+    for (size_t i = 0; i < list.size(); ++i) {
+      if (done[i]) continue;
+      const mfq_op* o = list[i].op;
+      const int p = o->space->p, prec = o->precision;
+      const bool cart = o->space->mesh->amplitude == 0.0 && o->alpha == 0.0;
+      std::vector<CellItem> items;
+      for (size_t j = i; j < list.size(); ++j) {
+        const mfq_op* q = list[j].op;
+        const bool cj = q->space->mesh->amplitude == 0.0 && q->alpha == 0.0;
+        if (done[j] || q->space->p != p || q->precision != prec || cj != cart) continue;
+        done[j] = 1;
+        CellItem it{};
+        it.idx = q->idx;
+        it.geo = q->geo;
+        it.src = list[j].src;
+        it.dst = list[j].dst;
+        it.bk = q->bricks;
+        items.push_back(it);
+      }
+      int64_t tot[kColours] = {};
+      for (CellItem& it : items)
+        for (int c = 0; c < kColours; ++c) {
+          it.first[c] = tot[c];
+          tot[c] += it.bk.count[c];
+        }
+      const size_t off = put(items);
+      for (int c = 0; c < kColours; ++c) {
+        if (tot[c] == 0) continue;
+        PlanLaunch L;
+        L.kind = PlanLaunch::kCells;
+        L.p = p;
+        L.precision = prec;
+        L.cart = cart;
+        L.colour = c;
+        L.off = off;
+        L.count = (int)items.size();
+        L.blocks = tot[c];
+        launches.push_back(L);
+      }
+    }
+  }
+  struct Move {
+    const mfq_transfer* t;
+    const void* in;
+    void* out;
+  };
+  // prolongation (coarse -> fine) or restriction (fine -> coarse, after clearing the coarse
+  // vectors) for each transfer: one launch per degree pair (and colour)
+  void transfers(const std::vector<Move>& list, bool prolongate) {
+    if (!prolongate) {
+      std::vector<VecItem> clear;
+      for (const Move& m : list) {
+        VecItem it{};
+        it.n = m.t->coarse->n_dofs;
+        it.d = m.out;
+        it.s0 = 0.0;
+        clear.push_back(it);
+      }
+      vec(kBatchFill, clear);
+    }
+    std::vector<int> done(list.size(), 0);
+    for (size_t i = 0; i < list.size(); ++i) {
+      if (done[i]) continue;
+      const int pc = list[i].t->coarse->p, pf = list[i].t->fine->p;
+      const bool h = list[i].t->h_transfer;
+      std::vector<TransferItem> items;
+      for (size_t j = i; j < list.size(); ++j) {
+        const mfq_transfer* t = list[j].t;
+        if (done[j] || t->coarse->p != pc || t->fine->p != pf || t->h_transfer != h) continue;
+        done[j] = 1;
+        TransferItem it{};
+        it.in = list[j].in;
+        it.out = list[j].out;
+        it.nc = t->coarse->mesh->n;
+        it.bc = t->coarse->bc;
+        items.push_back(it);
+      }
+      int64_t tot[kColours] = {};
+      for (TransferItem& it : items) {
+        const int nc = it.nc;
+        if (prolongate) {
+          it.first[0] = tot[0];
+          tot[0] += (int64_t)nc * nc * nc;
+        } else {
+          for (int c = 0; c < kColours; ++c) {
+            it.first[c] = tot[c];
+            tot[c] += (int64_t)((nc + 1 - (c & 1)) / 2) * ((nc + 1 - ((c >> 1) & 1)) / 2) * ((nc + 1 - (c >> 2)) / 2);
+          }
+        }
+      }
+      const size_t off = put(items);
+      for (int c = 0; c < (prolongate ? 1 : kColours); ++c) {
+        if (tot[c] == 0) continue;
+        PlanLaunch L;
+        L.kind = PlanLaunch::kTransfer;
+        L.p = pc;
+        L.pf = pf;
+        L.h = h;
+        L.prolongate = prolongate;
+        L.colour = c;
+        L.off = off;
+        L.count = (int)items.size();
+        L.blocks = tot[c];
+        launches.push_back(L);
+      }
+    }
+  }
+  // `deg` Chebyshev updates on each level (mfq_chebyshev with the work vectors r, d, t of the level)
+  void chebyshev(const std::vector<const Level*>& lv, int deg, bool x_is_zero) {
+    if (lv.empty()) return;
+    std::vector<double> sigma(lv.size()), delta(lv.size()), rho(lv.size());
+    std::vector<VecItem> first;
+    std::vector<Apply> ax, ad;
+    for (size_t i = 0; i < lv.size(); ++i) {
+      const Level& L = *lv[i];
+      const double theta = 0.5 * (L.lmax + L.lmin);
+      delta[i] = 0.5 * (L.lmax - L.lmin);
+      sigma[i] = theta / delta[i];
+      rho[i] = 1.0 / sigma[i];
+      ax.push_back({L.op, L.x, L.t});
+      ad.push_back({L.op, L.d, L.t});
+      VecItem it{};
+      it.n = L.n;
+      it.a = L.b;
+      it.b = L.t;
+      it.c = L.dinv;
+      it.d = L.x;
+      it.e = L.r;
+      it.f = L.d;
+      it.s0 = 1.0 / theta;
+      it.flag = x_is_zero ? 1 : 0;
+      first.push_back(it);
+    }
+    if (!x_is_zero) cells(ax);
+    vec(kBatchChebFirst, first);
+    for (int k = 1; k < deg; ++k) {
+      cells(ad);
+      std::vector<VecItem> step;
+      for (size_t i = 0; i < lv.size(); ++i) {
+        const Level& L = *lv[i];
+        const double rho_new = 1.0 / (2.0 * sigma[i] - rho[i]);
+        VecItem it{};
+        it.n = L.n;
+        it.a = L.t;
+        it.c = L.dinv;
+        it.d = L.x;
+        it.e = L.r;
+        it.f = L.d;
+        it.s0 = rho_new * rho[i];
+        it.s1 = 2.0 * rho_new / delta[i];
+        rho[i] = rho_new;
+        step.push_back(it);
+      }
+      vec(kBatchChebStep, step);
+    }
+  }
+};
+
+// Solves that a batched step can advance: FP64 CG with the FP32 V-cycle whose coarsest level is
+// smoothed (no host round trip), in a CG pass with room for `iters` more iterations.
+bool batchable(const mfq_solver* s, int iters) {
+  if (s->kind != MFQ_SOLVER_GMG_MIXED || s->prm.coarse_mode != 1 || s->prec_v != MFQ_FP32) return false;
+  if (s->run.phase != Run::kInner || s->run.budget - s->run.enqueued < iters) return false;
+  if (s->op64->mfma || s->op64->space->side) return false;
+  for (const Level& L : s->lv)
+    if (!L.op || L.op->mfma) return false;
+  return true;
+}
+
+// The launches of one CG iteration of every solve in `g` (one step replays them `iters` times).
+void plan_iteration(Plan& P, const std::vector<mfq_solver*>& g) {
+  std::vector<Plan::Apply> a64;
+  std::vector<VecItem> alpha, update, to32, to64, beta, dir;
+  for (mfq_solver* s : g) {
+    const int64_t N = s->op64->space->n_dofs;
+    a64.push_back({s->op64, s->p, s->Ap});
+    VecItem it{};
+    it.n = N;
+    it.st = s->state;
+    VecItem a = it;
+    a.a = s->p;
+    a.b = s->Ap;
+    alpha.push_back(a);
+    VecItem u = it;
+    u.d = s->run.sol;
+    u.e = s->r;
+    u.a = s->p;
+    u.b = s->Ap;
+    update.push_back(u);
+    VecItem c = it;
+    c.a = s->r;
+    c.d = s->lv.back().b;
+    to32.push_back(c);
+    VecItem c2 = it;
+    c2.a = s->lv.back().x;
+    c2.d = s->z;
+    to64.push_back(c2);
+    VecItem b = it;
+    b.a = s->r;
+    b.b = s->z;
+    beta.push_back(b);
+    VecItem d = it;
+    d.a = s->z;
+    d.d = s->p;
+    d.flag = 0;
+    dir.push_back(d);
+  }
+  P.cells(a64);
+  P.vec(kBatchCgAlpha, alpha);
+  P.vec(kBatchCgUpdate, update);
+  P.vec(kBatchCast64To32, to32);
+  // V-cycle, down: depth 0 is every solve's finest level
+  size_t depth = 0;
+  for (mfq_solver* s : g) depth = std::max(depth, s->lv.size());
+  const int deg = g.front()->prm.smoother_degree, cdeg = g.front()->prm.coarse_degree;
+  for (size_t d = 0; d < depth; ++d) {
+    std::vector<const Level*> smooth, coarse;
+    std::vector<Plan::Apply> res;
+    std::vector<VecItem> sub;
+    std::vector<Plan::Move> down;
+    for (mfq_solver* s : g) {
+      if (d >= s->lv.size()) continue;
+      const size_t l = s->lv.size() - 1 - d;
+      Level& L = s->lv[l];
+      if (l == 0) {
+        coarse.push_back(&L);
+        continue;
+      }
+      smooth.push_back(&L);
+      res.push_back({L.op, L.x, L.t});
+      VecItem it{};
+      it.n = L.n;
+      it.a = L.b;
+      it.b = L.t;
+      it.d = L.r;
+      sub.push_back(it);
+      down.push_back({s->lv[l - 1].to_fine, L.r, s->lv[l - 1].b});
+    }
+    P.chebyshev(smooth, deg, true);
+    P.chebyshev(coarse, cdeg, true);
+    P.cells(res);
+    P.vec(kBatchSub, sub);
+    P.transfers(down, false);
+  }
+  // up
+  for (size_t d = depth; d-- > 0;) {
+    std::vector<const Level*> smooth;
+    std::vector<Plan::Move> up;
+    std::vector<VecItem> add;
+    for (mfq_solver* s : g) {
+      if (d >= s->lv.size()) continue;
+      const size_t l = s->lv.size() - 1 - d;
+      if (l == 0) continue;
+      Level& L = s->lv[l];
+      smooth.push_back(&L);
+      up.push_back({s->lv[l - 1].to_fine, s->lv[l - 1].x, L.t});
+      VecItem it{};
+      it.n = L.n;
+      it.d = L.x;
+      it.a = L.t;
+      add.push_back(it);
+    }
+    P.transfers(up, true);
+    P.vec(kBatchAdd, add);
+    P.chebyshev(smooth, deg, false);
+  }
+  P.vec(kBatchCast32To64, to64);
+  P.vec(kBatchCgBeta, beta);
+  P.vec(kBatchCgDirection, dir);
+}
+
+int run_plan(const mfq_batch* b, const Plan& P, hipStream_t st) {
+  for (const PlanLaunch& L : P.launches) {
+    const void* items = b->buf + L.off;
+    hipError_t e = hipSuccess;
+    if (L.kind == PlanLaunch::kVec)
+      e = launch_batch_vec((BatchVecOp)L.op, (const VecItem*)items, L.count, L.blocks, st);
+    else if (L.kind == PlanLaunch::kCells)
+      e = launch_batch_cells(L.p, L.precision, L.cart, (const CellItem*)items, L.count, L.colour, L.blocks, st);
+    else
+      e = launch_batch_transfer(L.p, L.pf, L.h, L.prolongate, L.colour, (const TransferItem*)items, L.count,
+                                L.blocks, st);
+    if (e != hipSuccess) return fail(MFQ_EHIP, "batched launch failed: %s", hipGetErrorString(e));
+  }
+  return MFQ_OK;
+}
+
+}  // namespace
+
+namespace mfq {
+
+size_t cg_work_bytes(int64_t n) { return 3 * round_up((size_t)n * 8, 256) + round_up(sizeof(SolverState), 256); }
+
+int cg_unpreconditioned(const Apply& apply, const double* b, double* x, int64_t n, double rtol, int max_iter,
+                        void* work, hipStream_t st, mfq_solve_info* info) {
+  const auto t0 = std::chrono::steady_clock::now();
+  const size_t vb = round_up((size_t)n * 8, 256);
+  char* w = (char*)work;
+  double* r = (double*)w;
+  double* p = (double*)(w + vb);
+  double* Ap = (double*)(w + 2 * vb);
+  SolverState* state = (SolverState*)(w + 3 * vb);
+  // the grid reductions need a zero counter; a fill kernel (no memset node) clears the scalars
+  MFQ_HIP(launch_fill(MFQ_FP64, state, (int64_t)(offsetof(SolverState, partials) / sizeof(double)), 0.0, st));
+  PcgResult res;
+  if (int rc = pcg(apply, nullptr, b, x, r, p, Ap, nullptr, n, state, rtol, max_iter, 8, st, res)) return rc;
+  // true residual of the returned x
+  if (int rc = apply(x, Ap)) return rc;
+  MFQ_HIP(launch_residual_norm(b, Ap, nullptr, n, state, &state->res2, st));
+  SolverState h{};
+  if (int rc = poll(state, h, st)) return rc;
+  const double rel = h.bb > 0 ? std::sqrt(h.res2 / h.bb) : 0.0;
+  if (info) {
+    info->iterations = res.iters;
+    info->outer_iterations = 1;
+    info->rel_residual = rel;
+    info->seconds = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    info->n_levels = 0;
+  }
+  if (res.nonfinite || !std::isfinite(rel)) return fail(MFQ_ENONFINITE, "CG produced a non-finite residual");
+  if (rel > rtol) return fail(MFQ_ENOCONV, "CG: relative residual %.3e after %d iterations (rtol %.1e)", rel, res.iters, rtol);
+  return MFQ_OK;
+}
+
+}  // namespace mfq
 
 extern "C" {
 
@@ -895,6 +1294,117 @@ int mfq_batch_step(mfq_solver* const* solvers, int count, int iters, int* done) 
     seen.push_back(s->run.st);
     MFQ_HIP(hipStreamSynchronize(s->run.st));
   }
+  for (int i = 0; i < count; ++i) {
+    mfq_solver* s = solvers[i];
+    if (s->run.phase != Run::kDone)
+      if (int rc = step_collect(s)) return rc;
+    done[i] = s->run.phase == Run::kDone ? 1 : 0;
+  }
+  return MFQ_OK;
+}
+
+int mfq_batch_create(int max_solvers, mfq_batch** out) {
+  if (!out) return fail(MFQ_EINVAL, "out is NULL");
+  if (max_solvers < 1 || max_solvers > 4096) return fail(MFQ_EINVAL, "max_solvers %d outside [1,4096]", max_solvers);
+  mfq_batch* b = new (std::nothrow) mfq_batch();
+  if (!b) return fail(MFQ_ENOMEM, "host allocation failed");
+  b->max_solvers = max_solvers;
+  b->table_cap = round_up((size_t)max_solvers * kBatchTableBytesPerSolve, 256);
+  b->state_off = b->table_cap;
+  b->bytes = b->table_cap + round_up((size_t)max_solvers * kStateDoubles * sizeof(double), 256);
+  if (hipHostMalloc((void**)&b->host_tables, b->table_cap, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->host_states, (size_t)max_solvers * kStateDoubles * sizeof(double),
+                    hipHostMallocDefault) != hipSuccess ||
+      hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
+    delete b;
+    return fail(MFQ_ENOMEM, "pinned host staging of the batch tables could not be allocated");
+  }
+  *out = b;
+  return MFQ_OK;
+}
+
+void mfq_batch_destroy(mfq_batch* b) { delete b; }
+
+int mfq_batch_device_bytes(const mfq_batch* b, size_t* bytes) {
+  if (!b || !bytes) return fail(MFQ_EINVAL, "b or bytes is NULL");
+  *bytes = b->bytes;
+  return MFQ_OK;
+}
+
+int mfq_batch_bind(mfq_batch* b, void* dev_buf, size_t bytes, void* hip_stream) {
+  (void)hip_stream;
+  if (!b) return fail(MFQ_EINVAL, "b is NULL");
+  if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) % 256) != 0)
+    return fail(MFQ_EINVAL, "buffer NULL or not 256-byte aligned");
+  if (bytes < b->bytes) return fail(MFQ_ENOMEM, "buffer of %zu bytes, the batch needs %zu", bytes, b->bytes);
+  b->buf = (char*)dev_buf;
+  return MFQ_OK;
+}
+
+int mfq_batch_run(mfq_batch* b, mfq_solver* const* solvers, int count, int iters, void* hip_stream, int* done) {
+  if (!b || !b->buf) return fail(MFQ_EINVAL, "batch is NULL or not bound");
+  if (count < 0 || count > b->max_solvers) return fail(MFQ_EINVAL, "count %d outside [0,%d]", count, b->max_solvers);
+  if (count > 0 && (!solvers || !done)) return fail(MFQ_EINVAL, "bad solver list");
+  if (iters < 1) return fail(MFQ_EINVAL, "iters must be >= 1");
+  hipStream_t st = (hipStream_t)hip_stream;
+  std::vector<mfq_solver*> g;
+  for (int i = 0; i < count; ++i) {
+    mfq_solver* s = solvers[i];
+    if (!s || s->run.phase == Run::kIdle) return fail(MFQ_EINVAL, "solver %d has no running solve", i);
+    if (s->step_pending) return fail(MFQ_EBUSY, "solver %d has an asynchronous step in flight", i);
+    if (s->run.phase != Run::kDone && s->run.st != st)
+      return fail(MFQ_EINVAL, "solver %d runs on another stream than the batch step", i);
+    if (std::find(g.begin(), g.end(), s) != g.end()) return fail(MFQ_EINVAL, "solver %d listed twice", i);
+    if (batchable(s, iters)) {
+      if (!g.empty() && (s->prm.smoother_degree != g.front()->prm.smoother_degree ||
+                         s->prm.coarse_degree != g.front()->prm.coarse_degree))
+        return fail(MFQ_EINVAL, "solver %d: smoother or coarse degree differs within the batch", i);
+      g.push_back(s);
+    }
+  }
+  // the batched solves: plan one iteration and the gather of their scalar states, upload the
+  // tables in one copy, replay the iteration `iters` times, gather once
+  if (!g.empty()) {
+    Plan P;
+    plan_iteration(P, g);
+    const size_t n_iter = P.launches.size();
+    double* dev_states = (double*)(b->buf + b->state_off);
+    std::vector<VecItem> gather;
+    for (size_t i = 0; i < g.size(); ++i) {
+      VecItem it{};
+      it.n = kStateDoubles;
+      it.a = g[i]->state;
+      it.d = dev_states + i * kStateDoubles;
+      gather.push_back(it);
+    }
+    P.vec(kBatchCopy64, gather);
+    if (P.tab.size() > b->table_cap)
+      return fail(MFQ_EINVAL, "batch tables of %zu bytes exceed the %zu bytes for %d solvers", P.tab.size(),
+                  b->table_cap, b->max_solvers);
+    MFQ_HIP(hipEventSynchronize(b->uploaded));  // the staging buffer is free again
+    std::memcpy(b->host_tables, P.tab.data(), P.tab.size());
+    MFQ_HIP(hipMemcpyAsync(b->buf, b->host_tables, P.tab.size(), hipMemcpyHostToDevice, st));
+    MFQ_HIP(hipEventRecord(b->uploaded, st));
+    Plan iter;
+    iter.launches.assign(P.launches.begin(), P.launches.begin() + n_iter);
+    for (int k = 0; k < iters; ++k)
+      if (int rc = run_plan(b, iter, st)) return rc;
+    Plan last;
+    last.launches.assign(P.launches.begin() + n_iter, P.launches.end());
+    if (int rc = run_plan(b, last, st)) return rc;
+    MFQ_HIP(hipMemcpyAsync(b->host_states, dev_states, g.size() * kStateDoubles * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    for (mfq_solver* s : g) s->run.enqueued += iters;
+  }
+  // the other running solves (residual checks between CG passes, solves that cannot be batched)
+  for (int i = 0; i < count; ++i) {
+    mfq_solver* s = solvers[i];
+    if (s->run.phase == Run::kDone || std::find(g.begin(), g.end(), s) != g.end()) continue;
+    if (int rc = step_enqueue(s, iters)) return rc;
+  }
+  MFQ_HIP(hipStreamSynchronize(st));
+  for (size_t i = 0; i < g.size(); ++i)
+    std::memcpy(&g[i]->hstat->head, b->host_states + i * kStateDoubles, kStateDoubles * sizeof(double));
   for (int i = 0; i < count; ++i) {
     mfq_solver* s = solvers[i];
     if (s->run.phase != Run::kDone)

@@ -4,9 +4,12 @@ Requests (degree, mesh size, coefficient, right-hand-side seed) arrive as host e
 scheduler admits them first come, first served while the sum of the admitted requests' device
 footprints stays within a byte budget, and keeps every admitted request's mesh, geometry,
 multigrid hierarchy and Krylov state on the device until it finishes.  Each scheduler step
-advances all running solves together (``mfq_batch_step``: a few CG iterations of each on its own
-stream, one wait and one device-to-host status copy per request), retires the finished ones and
-frees their memory, so requests that arrive while others run join at the next step.
+advances all running solves together, retires the finished ones and frees their memory, so
+requests that arrive while others run join at the next step.  With a batched executor a step is
+one ``mfq_batch_run``: a few CG iterations of every running solve issued as one launch per
+(kernel, degree) over all of them from a device work table, one device-to-host copy of all their
+states and one wait; otherwise ``mfq_batch_step`` (each solve's launches on its own stream, one
+status copy per request) or per-request asynchronous steps.
 
 The solver of a request is GMG_MIXED (FP64 CG, FP64 operator and dot products, FP32 multigrid
 V-cycle) with an FP64 true-residual check and refinement passes until the relative residual is
@@ -53,14 +56,23 @@ class Request:
 class DeviceExecutor:
     """Builds and runs requests with the library; device memory comes from torch."""
 
-    def __init__(self, n_streams=4, keep_results=False, solver_kind=MFQ_SOLVER_GMG_MIXED, **solver_params):
+    def __init__(self, n_streams=4, keep_results=False, solver_kind=MFQ_SOLVER_GMG_MIXED, batched=False,
+                 max_active=256, **solver_params):
         import torch
         self.torch = torch
         # default-priority streams: solves are spread over `streams` round-robin; set-up work
         # (geometry, hierarchy, eigenvalue estimates, which wait on the host) runs on its own
         # stream so its waits do not queue behind the running solves
-        self.streams = [torch.cuda.Stream() for _ in range(max(1, n_streams))]
-        self.setup_stream = torch.cuda.Stream()
+        # batched: every solve runs on one stream and a step is one mfq_batch_run over all of them
+        self.batched = bool(batched)
+        self.streams = [torch.cuda.Stream() for _ in range(1 if self.batched else max(1, n_streams))]
+        # one set-up stream per thread that sets requests up: set-ups on several worker threads
+        # wait only for their own work
+        self._setup_streams = threading.local()
+        self.batch = None
+        if self.batched:
+            from . import Batch
+            self.batch = Batch(max_active, stream=self.streams[0])
         self.keep_results = keep_results
         self.kind = solver_kind
         self.params = dict(coarse_mode=1)
@@ -92,7 +104,9 @@ class DeviceExecutor:
         streams: the scheduler captures CG iterations into HIP graphs on those, and a capture
         records every launch into the stream, whichever thread issues it."""
         torch = self.torch
-        su = self.setup_stream
+        su = getattr(self._setup_streams, "stream", None)
+        if su is None:
+            su = self._setup_streams.stream = torch.cuda.Stream()
         with torch.cuda.stream(su):
             h["op_buf"] = torch.empty(max(h["op_bytes"], 256), dtype=torch.uint8, device="cuda")
             h["solver_buf"] = torch.empty(max(h["solver_bytes"], 256), dtype=torch.uint8, device="cuda")
@@ -117,6 +131,9 @@ class DeviceExecutor:
         self.begin(req, h)
 
     def step(self, handles, iters):
+        if self.batched:
+            return _lib.mfq_batch_run(self.batch.handle, [h["solver"] for h in handles], iters,
+                                      self.streams[0].cuda_stream)
         return _lib.mfq_batch_step([h["solver"] for h in handles], iters)
 
     def submit(self, h, iters):

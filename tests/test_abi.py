@@ -242,3 +242,24 @@ def test_chebyshev_noalloc_limits_on_the_host():
     for h, f in ((big, "mfq_op_destroy"), (small, "mfq_op_destroy"), (s, "mfq_space_destroy"),
                  (s2, "mfq_space_destroy"), (m, "mfq_mesh_destroy"), (m2, "mfq_mesh_destroy")):
         getattr(lib.lib(), f)(h)
+
+
+def test_hanging_operator_host_validation():
+    lib = _lib()
+    for args in ((0, 0.0, 2, 0.0, 0), (2, 0.2, 2, 0.0, 0), (2, 0.0, 9, 0.0, 0), (2, 0.0, 2, 0.0, 2),
+                 (2, 0.0, 2, 1.5, 0)):
+        with pytest.raises(lib.MfqError) as e:
+            lib.mfq_hang_create(*args)
+        assert e.value.status == lib.MFQ_EINVAL
+    h = lib.mfq_hang_create(3, 0.1, 4, 0.5, 0)
+    assert lib.mfq_hang_n_dofs(h) == 13 ** 3 + 25 ** 3
+    nbytes = lib.mfq_hang_device_bytes(h)
+    assert nbytes > 0 and nbytes % 256 == 0
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_hang_vmult(h, 256, 512, None)      # unbound: rejected before any launch
+    assert e.value.status == lib.MFQ_EINVAL
+    with pytest.raises(lib.MfqError) as e:
+        lib.mfq_hang_bind(h, 256, nbytes - 1, None)
+    assert e.value.status == lib.MFQ_ENOMEM
+    assert lib.mfq_hang_cg_work_bytes(h) >= 3 * 8 * lib.mfq_hang_n_dofs(h)
+    lib.mfq_hang_destroy(h)

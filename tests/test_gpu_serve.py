@@ -276,3 +276,75 @@ def test_solver_rebind_drops_captured_graphs():
         xs.append(x.clone())
     assert torch.equal(xs[0], xs[1])
     del old
+
+
+def test_batched_run_is_bitwise_the_single_solve_step():
+    """mfq_batch_run over a mix of degrees, mesh sizes (even and odd n: h- and p-coarsened
+    hierarchies of different depths) and coefficients, all on one stream with batched launches per
+    (kernel, degree): each solve's iteration count and solution equal those of the same solve
+    advanced alone by mfq_batch_step, bitwise."""
+    mfq = _mfq()
+    torch = _torch()
+    print("batched run vs single steps", flush=True)
+    st = torch.cuda.Stream()
+    cases = MIX + [(5, 6, 0.4), (6, 4, 0.8), (1, 16, 0.1)]
+    sols, bs, xs_alone, it_alone = [], [], [], []
+    for i, (p, n, a) in enumerate(cases):
+        op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.0), p, mfq.MFQ_BC_DIRICHLET0), a, mfq.MFQ_FP64)
+        b = op.space.random(500 + i)
+        sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, coarse_mode=1)
+        x = op.new_vector()
+        sv.begin(b, x, rtol=1e-10, max_iter=300, stream=st)
+        while not mfq.batch_step([sv], iters=2)[0]:
+            pass
+        s_, info = sv.end()
+        assert s_ == mfq.MFQ_OK
+        xs_alone.append(x.clone())
+        it_alone.append(info.iterations)
+        sols.append(sv)
+        bs.append(b)
+    batch = mfq.Batch(16, stream=st)
+    xs = []
+    for sv, b in zip(sols, bs):
+        x = sv.op.new_vector()
+        sv.begin(b, x, rtol=1e-10, max_iter=300, stream=st)
+        xs.append(x)
+    pending = list(range(len(sols)))
+    steps = 0
+    while pending:
+        flags = batch.run([sols[i] for i in pending], iters=2, stream=st)
+        pending = [i for i, f in zip(pending, flags) if not f]
+        steps += 1
+        assert steps < 500
+    torch.cuda.synchronize()
+    for i, sv in enumerate(sols):
+        s_, info = sv.end()
+        assert s_ == mfq.MFQ_OK and info.rel_residual <= 1e-10, cases[i]
+        assert info.iterations == it_alone[i], (cases[i], info.iterations, it_alone[i])
+        assert torch.equal(xs[i], xs_alone[i]), cases[i]
+
+
+def test_batched_serving_matches_oracle_and_alone():
+    """The serving loop with a batched executor: every result certified by the oracle's operator,
+    and each request's solution bitwise equal to the same request served alone."""
+    print("batched serving", flush=True)
+    reqs = _requests()
+    from paper_1910_13247_amd.serve import DeviceExecutor, Server
+    srv = Server(DeviceExecutor(keep_results=True, batched=True), 8 << 30, idle_sleep=0, setup_threads=1)
+    for r in reqs:
+        srv.submit(r)
+    srv.drain()
+    srv.close()
+    _torch().cuda.synchronize()
+    for i, r in enumerate(reqs):
+        assert r.status == 0 and r.rel_residual <= 1e-10
+        A = assemble.operator_csr(r.degree, r.n, 0.0, r.alpha, 1)
+        b = gmg.splitmix64_uniform(A.shape[0], r.seed) * mesh.boundary_mask(r.degree, r.n)
+        assert solve.rel_residual(lambda v: A @ v, b, r.result.cpu().numpy()) <= 1e-10
+        alone = _requests()[i]
+        srv1 = Server(DeviceExecutor(keep_results=True, batched=True), 8 << 30, idle_sleep=0)
+        srv1.submit(alone)
+        srv1.drain()
+        srv1.close()
+        assert alone.iterations == r.iterations
+        np.testing.assert_array_equal(alone.result.cpu().numpy(), r.result.cpu().numpy())

@@ -154,3 +154,18 @@ def test_dirichlet_and_hanging_masks():
     assert m[N0 + 0 + L1 * 2 + L1 * L1 * 2] == 1
     # GLL nodes used on both lattices
     np.testing.assert_allclose(hanging.lattice_1d(3, 1), gll_nodes(3), atol=1e-15)
+
+
+def test_block_matrix_chunking_is_exact():
+    a = hanging.block_matrix(2, 2, 1.0, 0.1, 0.5, chunk=3)
+    b = hanging.block_matrix(2, 2, 1.0, 0.1, 0.5, chunk=64)
+    assert abs(a - b).max() <= 1e-15 * abs(b).max()
+
+
+def test_magnitude_bounds_the_operator_entrywise():
+    p, n = 2, 1
+    At = hanging.operator_csr(p, n, 0.1, 0.5)
+    M = hanging.magnitude_csr(p, n, 0.1, 0.5)
+    assert (abs(At) - M).max() <= 1e-15 * M.max()
+    # and is not the operator's own absolute value where the constraint combines couplings
+    assert abs(M - abs(At)).max() > 1e-6 * M.max()
