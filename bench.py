@@ -653,6 +653,7 @@ def main():
                     help="serving steps: batched launches over all running solves (batched), each solve's own "
                          "launches, all waited for together (sync), or each at its own pace (async)")
     ap.add_argument("--serve-streams", type=int, default=8)
+    ap.add_argument("--serve-iters", type=int, default=2, help="CG iterations per serving step")
     ap.add_argument("--serve-params", default="",
                     help="solver parameters of the served requests, e.g. coarse_degree=8,smoother_degree=3")
     ap.add_argument("--serve-setup-threads", type=int, default=1,
@@ -775,6 +776,7 @@ def main():
             k, v = kv.split("=")
             prm[k.strip()] = float(v) if "." in v else int(v)
         rec["serving"] = serve_benchmark(args.serve, mode=args.serve_mode, n_streams=args.serve_streams,
+                                         iters_per_step=args.serve_iters,
                                          setup_threads=args.serve_setup_threads, solver_params=prm)
     if not args.no_cpu_baseline:
         print("# cpu baseline (oracle, bounded sample)", file=sys.stderr, flush=True)
