@@ -308,6 +308,15 @@ int mfq_solver_device_bytes(const mfq_solver* s, size_t* bytes);
  * inverse.  Synchronises the stream.  May be called again (another buffer, or after the operator
  * was re-bound): captured HIP graphs are dropped. */
 int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream);
+/* As mfq_solver_bind, but the eigenvalue bounds of the Chebyshev levels are not estimated here:
+ * the first step of the first solve estimates them (the same Lanczos runs, so the same bounds
+ * bitwise).  mfq_batch_run estimates those of all lazily bound solves that start in one call with
+ * one set of launches; mfq_batch_step and the asynchronous step estimate them per solve and wait
+ * for the stream there.  Until then mfq_solver_lambdas fails (MFQ_EINVAL) and
+ * mfq_solver_precondition estimates them first.  A solve whose estimate fails ends with
+ * MFQ_ENONFINITE.  For serving, where set-up of many requests would otherwise be one small
+ * launch sequence and one stream wait per request (not in the paper). */
+int mfq_solver_bind_lazy(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream);
 /* Solves A x = b to ||b - A x||_2 <= rtol ||b||_2 from x = 0 (x overwritten).  b, x: double
  * device vectors.  Blocks until done.  MFQ_ENOCONV when max_iter is reached (info valid).
  * Equivalent to mfq_solve_begin, mfq_batch_step on this solver alone (check_every iterations
@@ -316,9 +325,10 @@ int mfq_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_it
               void* hip_stream, mfq_solve_info* info);
 
 /* Resumable solves, for serving many requests on one device (continuous batching; not in the
- * paper).  mfq_solve_begin validates the arguments like mfq_solve and enqueues the start of the
- * solve on hip_stream (asynchronous); the solver remembers b, x and the stream, which must stay
- * valid until mfq_solve_end.  A solver runs one solve at a time (MFQ_EBUSY otherwise). */
+ * paper).  mfq_solve_begin validates the arguments like mfq_solve and records the solve (on
+ * GMG_MIXED_IR it enqueues x = 0 on hip_stream); the first step enqueues its start.  The solver
+ * remembers b, x and the stream, which must stay valid until mfq_solve_end.  A solver runs one
+ * solve at a time (MFQ_EBUSY otherwise). */
 int mfq_solve_begin(mfq_solver* s, const double* b, double* x, double rtol, int max_iter, void* hip_stream);
 
 /* One step of `count` running solves: enqueues up to `iters` CG iterations of each (or its
@@ -336,19 +346,22 @@ int mfq_batch_step(mfq_solver* const* solvers, int count, int iters, int* done);
  * finished.  Lets a caller advance each solve at its own pace instead of waiting for all of them
  * at every step.  Not to be mixed with mfq_batch_step on a solve with a step in flight. */
 /* Batched serving step (not part of the paper's method: continuous batching of many solves).
- * mfq_batch_run advances every running solve in `solvers` like mfq_batch_step (iters CG
- * iterations, or the residual check between CG passes; done[i] = 1 once solve i has finished),
- * but the CG iterations of the solves that qualify (GMG_MIXED with coarse_mode 1, FP32 V-cycle,
- * within their iteration budget) are issued as one launch per (kernel, degree) over all of them:
- * the launches of one iteration (the FP64 operator, the CG updates, the FP32 V-cycle level by level
- * from the finest) are planned once per call as work tables in device memory (one host-to-device
- * copy), replayed `iters` times, and the solves' scalar states come back in one device-to-host
- * copy; one stream wait per call.  Each solve's kernels see its own operands with the grids of its
- * own launches, so results are bitwise those of mfq_batch_step.  Every listed solve must run on
- * hip_stream (mfq_solve_begin) and the qualifying ones must share smoother_degree and
- * coarse_degree.  mfq_batch_create: up to max_solvers solves per call; device workspace of
- * mfq_batch_device_bytes (tables and states; mfq_batch_bind), pinned host staging owned by the
- * handle.  One call at a time per handle. */
+ * mfq_batch_run advances every running solve in `solvers` like mfq_batch_step (the start of a CG
+ * pass, iters CG iterations, or the residual check between CG passes; done[i] = 1 once solve i
+ * has finished), but for the solves that qualify (GMG_MIXED with coarse_mode 1, FP32 V-cycle) the
+ * work is issued as one launch per (kernel, degree) over all of them: the eigenvalue estimates of
+ * lazily bound solves (mfq_solver_bind_lazy; every level's Lanczos run at once, traces read back
+ * in one copy and one extra stream wait), then one plan of the pass starts and residual checks
+ * (once) and of one CG iteration (the FP64 operator, the CG updates, the FP32 V-cycle level by
+ * level from the finest; replayed `iters` times for the solves within their iteration budget),
+ * planned once per call as work tables in device memory (one host-to-device copy); the solves'
+ * scalar states and residual norms come back in one device-to-host copy; one stream wait.  Each
+ * solve's kernels see its own operands with the grids of its own launches, so results are bitwise
+ * those of mfq_batch_step.  Every listed solve must run on hip_stream (mfq_solve_begin) and the
+ * qualifying ones must share smoother_degree and coarse_degree.  mfq_batch_create: up to
+ * max_solvers solves per call; device workspace of mfq_batch_device_bytes (tables, states,
+ * traces; mfq_batch_bind), pinned host staging owned by the handle.  One call at a time per
+ * handle. */
 int mfq_batch_create(int max_solvers, mfq_batch** out);
 void mfq_batch_destroy(mfq_batch* b);
 int mfq_batch_device_bytes(const mfq_batch* b, size_t* bytes);

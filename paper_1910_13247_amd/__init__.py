@@ -404,9 +404,10 @@ class Batch:
 
 
 class Solver:
-    """CG / GMG-preconditioned CG on an FP64 operator (see mfq_solver_kind)."""
+    """CG / GMG-preconditioned CG on an FP64 operator (see mfq_solver_kind).  lazy=True binds with
+    mfq_solver_bind_lazy: the eigenvalue bounds are estimated by the first solve step."""
 
-    def __init__(self, op64, kind=MFQ_SOLVER_GMG_MIXED, stream=None, lambda_override=None, **params):
+    def __init__(self, op64, kind=MFQ_SOLVER_GMG_MIXED, stream=None, lambda_override=None, lazy=False, **params):
         torch = _torch()
         import ctypes
         self.op = op64
@@ -422,7 +423,8 @@ class Solver:
         self.handle = _lib.mfq_solver_create(op64.handle, self.kind, prm)
         self.device_bytes = _lib.mfq_solver_device_bytes(self.handle)
         self.buffer = torch.empty(max(self.device_bytes, 256), dtype=torch.uint8, device=op64.buffer.device)
-        _lib.mfq_solver_bind(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream(stream))
+        bind = _lib.mfq_solver_bind_lazy if lazy else _lib.mfq_solver_bind
+        bind(self.handle, self.buffer.data_ptr(), self.device_bytes, _stream(stream))
 
     def solve(self, b, x=None, rtol=1e-10, max_iter=10000, stream=None, check=True):
         if x is None:

@@ -106,6 +106,7 @@ _SIGS = {
     "mfq_solver_destroy": ([P], None),
     "mfq_solver_device_bytes": ([P, C.POINTER(SZ)], I),
     "mfq_solver_bind": ([P, P, SZ, P], I),
+    "mfq_solver_bind_lazy": ([P, P, SZ, P], I),
     "mfq_solve": ([P, P, P, D, I, P, C.POINTER(SolveInfo)], I),
     "mfq_solve_begin": ([P, P, P, D, I, P], I),
     "mfq_batch_step": ([C.POINTER(C.c_void_p), I, I, C.POINTER(C.c_int)], I),
@@ -399,6 +400,10 @@ def mfq_solver_device_bytes(s):
 
 def mfq_solver_bind(s, dev_buf, nbytes, stream):
     _check(lib().mfq_solver_bind(s, dev_buf, nbytes, stream))
+
+
+def mfq_solver_bind_lazy(s, dev_buf, nbytes, stream):
+    _check(lib().mfq_solver_bind_lazy(s, dev_buf, nbytes, stream))
 
 
 def mfq_solve(s, b, x, rtol, max_iter, stream, check=True):

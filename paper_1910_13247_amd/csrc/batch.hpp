@@ -60,6 +60,14 @@ enum BatchVecOp {
   kBatchAdd,          // d = x, a = c (float)
   kBatchFill,         // d = x, s0 = value (float)
   kBatchCopy64,       // d = out, a = in (double): the solves' scalar states into one array
+  kBatchCgStart,      // a = b, d = x, e = r, f = p, s0 = tol^2, flag = copy p (double)
+  kBatchSplitmix,     // d = x (float), n = N1^3, flag = N1: the counter-based start vector, seed 0, masked
+  kBatchLzInit,       // a = r, c = dinv, d = z, e = p, b = trace (double*), flag = count slot (float)
+  kBatchLzAlpha,      // a = p, c = A p, b = trace (float)
+  kBatchLzUpdate,     // d = r, e = z, a = A p, c = dinv, b = trace, flag = count slot (float)
+  kBatchLzDirection,  // a = z, d = p (float)
+  kBatchAdd64,        // d = x, a = c (double)
+  kBatchResidualNorm, // a = b, b = t, d = r, e = out (double*): r = b - t, *out = r.r (double)
 };
 
 // Launchers (items: device array of `count` items, `blocks` = total workgroups).

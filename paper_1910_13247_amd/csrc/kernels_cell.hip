@@ -522,8 +522,17 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
   scatter_lattice<P, Real, ACC, BLOCK, KPT, kDirSource, HANG>(lds, NQ, src, dst, gk, first, dv, sd);
 }
 
+// Minimum waves per SIMD asked of the register allocator for the operator kernels (1: no request).
+#ifndef MFQ_VM_WAVES
+#define MFQ_VM_WAVES(P, FP64) 1
+#endif
+template <int P, typename Real>
+struct VmWaves {
+  static constexpr int MIN = MFQ_VM_WAVES(P, sizeof(Real) == 8);
+};
+
 template <int P, typename Real, bool ACC, bool CART = false, bool HANG = false>
-__global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo, const Real* __restrict__ src,
+__global__ __launch_bounds__(Cell<P>::NT) __attribute__((amdgpu_waves_per_eu(VmWaves<P, Real>::MIN))) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo, const Real* __restrict__ src,
                   Real* __restrict__ dst, Bricks bk, int colour, ShapeEO<P, Real> sh,
                   CartQuad<P, Real> cq = {}, Side<Real> sd = {}) {
   vmult_brick<P, Real, ACC, CART, HANG>(idx, geo, src, dst, bk, colour, blockIdx.x, sh, cq, sd);
@@ -533,7 +542,7 @@ __global__ __launch_bounds__(Cell<P>::NT) void vmult_kernel(const int* __restric
 // to the item whose range [first[colour], next first) holds it and computes that operator's brick
 // b - first, exactly as the single-operator launch does (results bitwise equal).
 template <int P, typename Real, bool CART>
-__global__ __launch_bounds__(Cell<P>::NT) void batch_vmult_kernel(const CellItem* __restrict__ items, int count,
+__global__ __launch_bounds__(Cell<P>::NT) __attribute__((amdgpu_waves_per_eu(VmWaves<P, Real>::MIN))) void batch_vmult_kernel(const CellItem* __restrict__ items, int count,
                                                                    int colour, ShapeEO<P, Real> sh,
                                                                    CartQuad<P, Real> cq) {
   int lo = 0, hi = count - 1;

@@ -307,22 +307,25 @@ __global__ __launch_bounds__(kVBlock) void reciprocal_kernel(Real* __restrict__ 
 // Counter-based start vector: SplitMix64 (Steele, Lea, Flood, OOPSLA 2014) of counter i,
 // z = seed + (i+1)*0x9E3779B97F4A7C15, two xor-shift-multiply rounds, final xor-shift; the top
 // 53 bits give u in [0,1), v = 2u - 1; zero on boundary nodes of the (N1)^3 lattice when masked.
+__device__ __forceinline__ double splitmix_value(int64_t i, int64_t N1, uint64_t seed, bool masked) {
+  uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
+  z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
+  z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
+  z = z ^ (z >> 31);
+  const double u = (double)(z >> 11) * 0x1.0p-53;
+  double v = 2.0 * u - 1.0;
+  if (masked) {
+    const int64_t I = i % N1, J = (i / N1) % N1, K = i / (N1 * N1);
+    if (I == 0 || J == 0 || K == 0 || I == N1 - 1 || J == N1 - 1 || K == N1 - 1) v = 0.0;
+  }
+  return v;
+}
+
 template <typename Real>
 __global__ __launch_bounds__(kVBlock) void splitmix_kernel(Real* __restrict__ x, int64_t N1, uint64_t seed, int masked) {
   const int64_t n = N1 * N1 * N1;
-  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
-    uint64_t z = seed + (uint64_t)(i + 1) * 0x9E3779B97F4A7C15ull;
-    z = (z ^ (z >> 30)) * 0xBF58476D1CE4E5B9ull;
-    z = (z ^ (z >> 27)) * 0x94D049BB133111EBull;
-    z = z ^ (z >> 31);
-    const double u = (double)(z >> 11) * 0x1.0p-53;
-    double v = 2.0 * u - 1.0;
-    if (masked) {
-      const int64_t I = i % N1, J = (i / N1) % N1, K = i / (N1 * N1);
-      if (I == 0 || J == 0 || K == 0 || I == N1 - 1 || J == N1 - 1 || K == N1 - 1) v = 0.0;
-    }
-    x[i] = (Real)v;
-  }
+  for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
+    x[i] = (Real)splitmix_value(i, N1, seed, masked != 0);
 }
 
 // ---------------------------------------------------------------- device-side Lanczos
@@ -561,6 +564,124 @@ __global__ __launch_bounds__(kVBlock) void batch_vec_kernel(const VecItem* __res
     const double* in = (const double*)it.a;
     double* out = (double*)it.d;
     for (int64_t i = i0; i < n; i += stride) out[i] = in[i];
+  } else if constexpr (OP == kBatchCgStart) {
+    const double* b = (const double*)it.a;
+    double* x = (double*)it.d;
+    double* r = (double*)it.e;
+    double* p = (double*)it.f;
+    double part = 0;
+    for (int64_t i = i0; i < n; i += stride) {
+      const double v = b[i];
+      r[i] = v;
+      x[i] = 0.0;
+      if (it.flag) p[i] = v;
+      part += v * v;
+    }
+    part = block_sum(part, sh);
+    double tot;
+    if (item_reduce(part, st, lb, it.nblk, tot, sh) && threadIdx.x == 0) {
+      st->bb = tot;
+      st->tol2 = it.s0;
+      st->rr = tot;
+      st->rz = tot;
+      st->iter = 0;
+      st->done = (tot == 0.0) ? 1 : 0;
+      st->converged_iter = 0;
+      st->nonfinite = (tot == tot && tot < 1e308) ? 0 : 1;
+      if (st->nonfinite) st->done = 1;
+    }
+  } else if constexpr (OP == kBatchSplitmix) {
+    float* x = (float*)it.d;
+    const int64_t N1 = it.flag;
+    for (int64_t i = i0; i < n; i += stride) x[i] = (float)splitmix_value(i, N1, 0, true);
+  } else if constexpr (OP == kBatchLzInit) {
+    const float* r = (const float*)it.a;
+    const float* dinv = (const float*)it.c;
+    float* z = (float*)it.d;
+    float* p = (float*)it.e;
+    double* trace = (double*)it.b;
+    double part = 0;
+    for (int64_t i = i0; i < n; i += stride) {
+      const float zv = dinv[i] * r[i];
+      z[i] = zv;
+      p[i] = zv;
+      part += (double)r[i] * (double)zv;
+    }
+    part = block_sum(part, sh);
+    double tot;
+    if (item_reduce(part, st, lb, it.nblk, tot, sh) && threadIdx.x == 0) {
+      st->rz = tot;
+      st->iter = 0;
+      st->done = (tot > 0) ? 0 : 1;
+      trace[it.flag] = 0.0;
+    }
+  } else if constexpr (OP == kBatchLzAlpha) {
+    if (st->done) return;
+    const float* p = (const float*)it.a;
+    const float* Ap = (const float*)it.c;
+    double* trace = (double*)it.b;
+    double part = 0;
+    for (int64_t i = i0; i < n; i += stride) part += (double)p[i] * (double)Ap[i];
+    part = block_sum(part, sh);
+    double tot;
+    if (item_reduce(part, st, lb, it.nblk, tot, sh) && threadIdx.x == 0) {
+      if (tot > 0) {
+        st->alpha = st->rz / tot;
+        trace[2 * st->iter] = st->alpha;
+      } else {
+        st->done = 1;
+      }
+    }
+  } else if constexpr (OP == kBatchLzUpdate) {
+    if (st->done) return;
+    float* r = (float*)it.d;
+    float* z = (float*)it.e;
+    const float* Ap = (const float*)it.a;
+    const float* dinv = (const float*)it.c;
+    double* trace = (double*)it.b;
+    const float alpha = (float)st->alpha;
+    double part = 0;
+    for (int64_t i = i0; i < n; i += stride) {
+      const float rv = r[i] - alpha * Ap[i];
+      const float zv = dinv[i] * rv;
+      r[i] = rv;
+      z[i] = zv;
+      part += (double)rv * (double)zv;
+    }
+    part = block_sum(part, sh);
+    double tot;
+    if (item_reduce(part, st, lb, it.nblk, tot, sh) && threadIdx.x == 0) {
+      const double beta = tot / st->rz;
+      trace[2 * st->iter + 1] = beta;
+      st->beta = beta;
+      st->rz = tot;
+      st->iter += 1;
+      trace[it.flag] = (double)st->iter;
+      if (!(tot > 0)) st->done = 1;
+    }
+  } else if constexpr (OP == kBatchLzDirection) {
+    if (st->done) return;
+    const float* z = (const float*)it.a;
+    float* p = (float*)it.d;
+    const float beta = (float)st->beta;
+    for (int64_t i = i0; i < n; i += stride) p[i] = z[i] + beta * p[i];
+  } else if constexpr (OP == kBatchAdd64) {
+    double* x = (double*)it.d;
+    const double* c = (const double*)it.a;
+    for (int64_t i = i0; i < n; i += stride) x[i] += c[i];
+  } else if constexpr (OP == kBatchResidualNorm) {
+    const double* b = (const double*)it.a;
+    const double* t = (const double*)it.b;
+    double* r = (double*)it.d;
+    double part = 0;
+    for (int64_t i = i0; i < n; i += stride) {
+      const double v = b[i] - t[i];
+      r[i] = v;
+      part += v * v;
+    }
+    part = block_sum(part, sh);
+    double tot;
+    if (item_reduce(part, st, lb, it.nblk, tot, sh) && threadIdx.x == 0) *(double*)it.e = tot;
   }
 }
 
@@ -757,6 +878,11 @@ int vec_blocks(BatchVecOp op, int64_t n) {
     case kBatchCgAlpha:
     case kBatchCgUpdate:
     case kBatchCgBeta:
+    case kBatchCgStart:
+    case kBatchLzInit:
+    case kBatchLzAlpha:
+    case kBatchLzUpdate:
+    case kBatchResidualNorm:
       return vgrid(n);      // reductions: the single-solve grid, so the partial sums agree
     default:
       return vgrid(n) * 4;  // elementwise
@@ -779,6 +905,14 @@ hipError_t launch_batch_vec(BatchVecOp op, const VecItem* items, int count, int6
     case kBatchAdd: batch_vec_kernel<kBatchAdd><<<g, kVBlock, 0, st>>>(items, count); break;
     case kBatchFill: batch_vec_kernel<kBatchFill><<<g, kVBlock, 0, st>>>(items, count); break;
     case kBatchCopy64: batch_vec_kernel<kBatchCopy64><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchCgStart: batch_vec_kernel<kBatchCgStart><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchSplitmix: batch_vec_kernel<kBatchSplitmix><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchLzInit: batch_vec_kernel<kBatchLzInit><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchLzAlpha: batch_vec_kernel<kBatchLzAlpha><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchLzUpdate: batch_vec_kernel<kBatchLzUpdate><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchLzDirection: batch_vec_kernel<kBatchLzDirection><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchAdd64: batch_vec_kernel<kBatchAdd64><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchResidualNorm: batch_vec_kernel<kBatchResidualNorm><<<g, kVBlock, 0, st>>>(items, count); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

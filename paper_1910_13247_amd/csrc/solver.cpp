@@ -64,6 +64,9 @@ struct mfq_solver {
   double *r = nullptr, *p = nullptr, *Ap = nullptr, *z = nullptr, *rout = nullptr, *c = nullptr;
   SolverState* state = nullptr;
   SolverState* aux = nullptr;  // reductions of the setup phase
+  size_t off_lz = 0;            // one state per level for the batched eigenvalue estimates
+  SolverState* lz = nullptr;
+  bool eig_pending = false;     // bound lazily: the eigenvalue bounds are estimated at the first step
   double* scal = nullptr;      // device scalars for setup dots
   size_t bytes = 0;
   void* buf = nullptr;
@@ -74,8 +77,11 @@ struct mfq_solver {
   };
   HostStatus* hstat = nullptr;  // pinned host memory
   struct Run {
-    enum Phase { kIdle, kInner, kCheck, kDone };
+    enum Phase { kIdle, kStart, kInner, kCheck, kDone };
     Phase phase = kIdle;
+    const double* start_rhs = nullptr;  // the CG pass that the next step starts (phase kStart)
+    double* start_sol = nullptr;
+    double start_tol2 = 0;
     const double* b = nullptr;
     double* x = nullptr;
     double* sol = nullptr;      // solution vector of the current CG pass (x or the correction c)
@@ -357,6 +363,43 @@ int enqueue_lanczos(mfq_solver* s, Level& L, double* trace, hipStream_t st) {
   return MFQ_OK;
 }
 
+int lambda_from_trace(const mfq_solver* s, Level& L, const double* trace);
+
+// first level with an eigenvalue estimate (the coarsest one only when it is smoothed)
+size_t first_estimated(const mfq_solver* s) { return s->prm.coarse_mode == 1 ? 0 : 1; }
+
+// Chebyshev bounds of every estimated level from the Lanczos traces (host copy, trace_stride
+// doubles per level)
+int lambdas_from_traces(mfq_solver* s, const double* traces) {
+  const size_t nlv = s->lv.size();
+  for (size_t l = first_estimated(s); l < nlv; ++l) {
+    Level& L = s->lv[l];
+    if (int rc = lambda_from_trace(s, L, traces + l * s->trace_stride)) return rc;
+    double lmax = s->prm.lambda_factor * L.lhat;
+    if (l == 0) {
+      L.lmax = lmax;
+      L.lmin = lmax / s->prm.coarse_ratio;
+      continue;
+    }
+    const int idx = (int)l - 1;
+    if (s->prm.n_lambda_override > idx && s->prm.lambda_override) lmax = s->prm.lambda_override[idx];
+    L.lmax = lmax;
+    L.lmin = lmax / s->prm.lambda_ratio;
+  }
+  s->eig_pending = false;
+  return MFQ_OK;
+}
+
+// all Lanczos runs of one solver enqueued, their traces read back in one copy
+int estimate_eigenvalues(mfq_solver* s, hipStream_t st) {
+  const size_t nlv = s->lv.size();
+  for (size_t l = first_estimated(s); l < nlv; ++l)
+    if (int rc = enqueue_lanczos(s, s->lv[l], s->trace + l * s->trace_stride, st)) return rc;
+  MFQ_HIP(hipMemcpyAsync(s->trace_host, s->trace, nlv * s->trace_stride * sizeof(double), hipMemcpyDeviceToHost, st));
+  MFQ_HIP(hipStreamSynchronize(st));
+  return lambdas_from_traces(s, s->trace_host);
+}
+
 int lambda_from_trace(const mfq_solver* s, Level& L, const double* trace) {
   const int k = s->prm.lanczos_iters;
   const int m = std::min(k, std::max(0, (int)trace[2 * k]));
@@ -391,6 +434,16 @@ int inner_apply(mfq_solver* s, const double* in, double* out, hipStream_t st) {
   return MFQ_OK;
 }
 
+// the host side of starting a CG pass (its kernels are enqueued by pass_start or a batched step)
+void pass_started(mfq_solver* s, double* sol) {
+  Run& R = s->run;
+  R.sol = sol;
+  R.enqueued = 0;
+  R.budget = R.max_iter - R.iters;
+  R.pass += 1;
+  R.phase = Run::kInner;
+}
+
 int pass_start(mfq_solver* s, const double* rhs, double* sol, double tol2) {
   Run& R = s->run;
   const int64_t N = s->op64->space->n_dofs;
@@ -401,12 +454,17 @@ int pass_start(mfq_solver* s, const double* rhs, double* sol, double tol2) {
     MFQ_HIP(launch_cg_beta(s->r, s->z, N, s->state, R.st));
     MFQ_HIP(launch_cg_direction(s->z, s->p, N, s->state, true, R.st));
   }
-  R.sol = sol;
-  R.enqueued = 0;
-  R.budget = R.max_iter - R.iters;
-  R.pass += 1;
-  R.phase = Run::kInner;
+  pass_started(s, sol);
   return MFQ_OK;
+}
+
+// a CG pass to be started by the next step
+void pass_pending(mfq_solver* s, const double* rhs, double* sol, double tol2) {
+  Run& R = s->run;
+  R.start_rhs = rhs;
+  R.start_sol = sol;
+  R.start_tol2 = tol2;
+  R.phase = Run::kStart;
 }
 
 // CG iterations issued as launches; once the device state says done, they are no-ops
@@ -487,6 +545,17 @@ void finish(mfq_solver* s, int status) {
 int step_enqueue(mfq_solver* s, int iters) {
   Run& R = s->run;
   const int64_t N = s->op64->space->n_dofs;
+  if (R.phase == Run::kStart) {
+    if (s->eig_pending) {
+      const int rc = estimate_eigenvalues(s, R.st);
+      if (rc == MFQ_ENONFINITE) {
+        finish(s, rc);
+        return MFQ_OK;
+      }
+      if (rc) return rc;
+    }
+    if (int rc = pass_start(s, R.start_rhs, R.start_sol, R.start_tol2)) return rc;
+  }
   if (R.phase == Run::kInner) {
     const int m = std::max(0, std::min(iters, R.budget - R.enqueued));
     if (int rc = pass_iterate(s, m)) return rc;
@@ -528,7 +597,7 @@ int step_collect(mfq_solver* s) {
       // to half the remaining distance to rtol ||b||
       const double tol2 = s->kind == MFQ_SOLVER_GMG_MIXED_IR ? s->prm.inner_rtol * s->prm.inner_rtol
                                                               : std::min(0.25, 0.25 * R.rtol * R.rtol * R.bb / rr);
-      if (int rc = pass_start(s, s->rout, s->c, tol2)) return rc;
+      pass_pending(s, s->rout, s->c, tol2);
     }
   }
   return MFQ_OK;
@@ -537,7 +606,8 @@ int step_collect(mfq_solver* s) {
 int begin_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_iter, hipStream_t st) {
   if (!s) return fail(MFQ_EINVAL, "solver is NULL");
   if (!s->buf) return fail(MFQ_EINVAL, "solver is not bound");
-  if (s->run.phase == Run::kInner || s->run.phase == Run::kCheck || s->step_pending)
+  if (s->run.phase == Run::kStart || s->run.phase == Run::kInner || s->run.phase == Run::kCheck ||
+      s->step_pending)
     return fail(MFQ_EBUSY, "a solve is running");
   if (!b || !x || (reinterpret_cast<uintptr_t>(b) % 16) || (reinterpret_cast<uintptr_t>(x) % 16))
     return fail(MFQ_EINVAL, "b or x NULL or misaligned");
@@ -554,9 +624,11 @@ int begin_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_
   const int64_t N = s->op64->space->n_dofs;
   if (s->kind == MFQ_SOLVER_GMG_MIXED_IR) {
     MFQ_HIP(launch_fill(MFQ_FP64, x, N, 0.0, st));
-    return pass_start(s, b, s->c, s->prm.inner_rtol * s->prm.inner_rtol);
+    pass_pending(s, b, s->c, s->prm.inner_rtol * s->prm.inner_rtol);
+  } else {
+    pass_pending(s, b, x, rtol * rtol);
   }
-  return pass_start(s, b, x, rtol * rtol);
+  return MFQ_OK;
 }
 
 }  // namespace
@@ -571,23 +643,27 @@ int begin_solve(mfq_solver* s, const double* b, double* x, double rtol, int max_
 struct mfq_batch {
   int max_solvers = 0;
   size_t table_cap = 0;          // bytes of the table region
-  size_t state_off = 0;          // gathered scalar states (device)
+  size_t state_off = 0;          // gathered scalar states, then residual norms (device)
+  size_t trace_off = 0;          // gathered Lanczos traces (device)
   size_t bytes = 0;
   char* buf = nullptr;
   char* host_tables = nullptr;   // pinned staging of the tables
-  double* host_states = nullptr; // pinned copy of the gathered states
+  double* host_states = nullptr; // pinned copy of the gathered states and residual norms
+  double* host_traces = nullptr; // pinned copy of the gathered traces
   hipEvent_t uploaded = nullptr; // the last table upload has left the staging buffer
   ~mfq_batch() {
     if (uploaded) (void)hipEventDestroy(uploaded);
     if (host_tables) (void)hipHostFree(host_tables);
     if (host_states) (void)hipHostFree(host_states);
+    if (host_traces) (void)hipHostFree(host_traces);
   }
 };
 
 namespace {
 
-constexpr size_t kBatchTableBytesPerSolve = 48 << 10;
+constexpr size_t kBatchTableBytesPerSolve = 96 << 10;
 constexpr int kStateDoubles = (int)(offsetof(SolverState, partials) / sizeof(double));
+constexpr int kTraceDoubles = 1024;  // Lanczos traces of one solve's levels in a batched estimate
 
 struct PlanLaunch {
   enum Kind { kVec, kCells, kTransfer } kind = kVec;
@@ -794,58 +870,101 @@ struct Plan {
 
 // Solves that a batched step can advance: FP64 CG with the FP32 V-cycle whose coarsest level is
 // smoothed (no host round trip), in a CG pass with room for `iters` more iterations.
-bool batchable(const mfq_solver* s, int iters) {
+bool batch_form(const mfq_solver* s) {
   if (s->kind != MFQ_SOLVER_GMG_MIXED || s->prm.coarse_mode != 1 || s->prec_v != MFQ_FP32) return false;
-  if (s->run.phase != Run::kInner || s->run.budget - s->run.enqueued < iters) return false;
   if (s->op64->mfma || s->op64->space->side) return false;
   for (const Level& L : s->lv)
     if (!L.op || L.op->mfma) return false;
   return true;
 }
 
-// The launches of one CG iteration of every solve in `g` (one step replays them `iters` times).
-void plan_iteration(Plan& P, const std::vector<mfq_solver*>& g) {
-  std::vector<Plan::Apply> a64;
-  std::vector<VecItem> alpha, update, to32, to64, beta, dir;
+bool batchable(const mfq_solver* s, int iters) {
+  if (s->run.phase != Run::kInner || s->run.budget - s->run.enqueued < iters) return false;
+  return batch_form(s);
+}
+
+// The eigenvalue estimates of lazily bound solves (every level at once, one state per level): the
+// first launches once, then one Lanczos step replayed lanczos_iters times (enqueue_lanczos).
+void plan_lanczos_start(Plan& P, const std::vector<mfq_solver*>& e) {
+  std::vector<VecItem> seed, init;
+  for (mfq_solver* s : e) {
+    const int k = s->prm.lanczos_iters;
+    for (size_t l = first_estimated(s); l < s->lv.size(); ++l) {
+      Level& L = s->lv[l];
+      const int64_t N1 = (int64_t)L.sp->p * L.sp->mesh->n + 1;
+      VecItem it{};
+      it.n = N1 * N1 * N1;
+      it.d = L.r;
+      it.flag = (int)N1;
+      seed.push_back(it);
+      VecItem i2{};
+      i2.n = L.n;
+      i2.a = L.r;
+      i2.c = L.dinv;
+      i2.d = L.d;
+      i2.e = L.t;
+      i2.b = s->trace + l * s->trace_stride;
+      i2.flag = 2 * k;
+      i2.st = (SolverState*)((char*)s->lz + l * round_up(sizeof(SolverState), 256));
+      init.push_back(i2);
+    }
+  }
+  P.vec(kBatchSplitmix, seed);
+  P.vec(kBatchLzInit, init);
+}
+
+void plan_lanczos_step(Plan& P, const std::vector<mfq_solver*>& e) {
+  std::vector<Plan::Apply> ap;
+  std::vector<VecItem> alpha, update, dir;
+  for (mfq_solver* s : e) {
+    const int k = s->prm.lanczos_iters;
+    for (size_t l = first_estimated(s); l < s->lv.size(); ++l) {
+      Level& L = s->lv[l];
+      ap.push_back({L.op, L.t, L.x});
+      VecItem it{};
+      it.n = L.n;
+      it.st = (SolverState*)((char*)s->lz + l * round_up(sizeof(SolverState), 256));
+      it.b = s->trace + l * s->trace_stride;
+      VecItem a = it;
+      a.a = L.t;
+      a.c = L.x;
+      alpha.push_back(a);
+      VecItem u = it;
+      u.d = L.r;
+      u.e = L.d;
+      u.a = L.x;
+      u.c = L.dinv;
+      u.flag = 2 * k;
+      update.push_back(u);
+      VecItem d = it;
+      d.a = L.d;
+      d.d = L.t;
+      dir.push_back(d);
+    }
+  }
+  P.cells(ap);
+  P.vec(kBatchLzAlpha, alpha);
+  P.vec(kBatchLzUpdate, update);
+  P.vec(kBatchLzDirection, dir);
+}
+
+// z = V-cycle(r) for every solve in `g` (precondition): r rounded to the finest FP32 level, the
+// V-cycle level by level from the finest (depth 0 is every solve's finest level), the result
+// widened into z
+void plan_precondition(Plan& P, const std::vector<mfq_solver*>& g) {
+  std::vector<VecItem> to32, to64;
   for (mfq_solver* s : g) {
-    const int64_t N = s->op64->space->n_dofs;
-    a64.push_back({s->op64, s->p, s->Ap});
-    VecItem it{};
-    it.n = N;
-    it.st = s->state;
-    VecItem a = it;
-    a.a = s->p;
-    a.b = s->Ap;
-    alpha.push_back(a);
-    VecItem u = it;
-    u.d = s->run.sol;
-    u.e = s->r;
-    u.a = s->p;
-    u.b = s->Ap;
-    update.push_back(u);
-    VecItem c = it;
+    VecItem c{};
+    c.n = s->op64->space->n_dofs;
     c.a = s->r;
     c.d = s->lv.back().b;
     to32.push_back(c);
-    VecItem c2 = it;
+    VecItem c2 = c;
     c2.a = s->lv.back().x;
     c2.d = s->z;
     to64.push_back(c2);
-    VecItem b = it;
-    b.a = s->r;
-    b.b = s->z;
-    beta.push_back(b);
-    VecItem d = it;
-    d.a = s->z;
-    d.d = s->p;
-    d.flag = 0;
-    dir.push_back(d);
   }
-  P.cells(a64);
-  P.vec(kBatchCgAlpha, alpha);
-  P.vec(kBatchCgUpdate, update);
   P.vec(kBatchCast64To32, to32);
-  // V-cycle, down: depth 0 is every solve's finest level
   size_t depth = 0;
   for (mfq_solver* s : g) depth = std::max(depth, s->lv.size());
   const int deg = g.front()->prm.smoother_degree, cdeg = g.front()->prm.coarse_degree;
@@ -878,7 +997,6 @@ void plan_iteration(Plan& P, const std::vector<mfq_solver*>& g) {
     P.vec(kBatchSub, sub);
     P.transfers(down, false);
   }
-  // up
   for (size_t d = depth; d-- > 0;) {
     std::vector<const Level*> smooth;
     std::vector<Plan::Move> up;
@@ -901,8 +1019,105 @@ void plan_iteration(Plan& P, const std::vector<mfq_solver*>& g) {
     P.chebyshev(smooth, deg, false);
   }
   P.vec(kBatchCast32To64, to64);
+}
+
+// beta = r.z / rz ; p = z (+ beta p) for every solve in `g`
+void plan_direction(Plan& P, const std::vector<mfq_solver*>& g, bool first) {
+  std::vector<VecItem> beta, dir;
+  for (mfq_solver* s : g) {
+    VecItem it{};
+    it.n = s->op64->space->n_dofs;
+    it.st = s->state;
+    VecItem b = it;
+    b.a = s->r;
+    b.b = s->z;
+    beta.push_back(b);
+    VecItem d = it;
+    d.a = s->z;
+    d.d = s->p;
+    d.flag = first ? 1 : 0;
+    dir.push_back(d);
+  }
   P.vec(kBatchCgBeta, beta);
   P.vec(kBatchCgDirection, dir);
+}
+
+// The launches of one CG iteration of every solve in `g` (one step replays them `iters` times).
+void plan_iteration(Plan& P, const std::vector<mfq_solver*>& g) {
+  std::vector<Plan::Apply> a64;
+  std::vector<VecItem> alpha, update;
+  for (mfq_solver* s : g) {
+    a64.push_back({s->op64, s->p, s->Ap});
+    VecItem it{};
+    it.n = s->op64->space->n_dofs;
+    it.st = s->state;
+    VecItem a = it;
+    a.a = s->p;
+    a.b = s->Ap;
+    alpha.push_back(a);
+    VecItem u = it;
+    u.d = s->run.sol;
+    u.e = s->r;
+    u.a = s->p;
+    u.b = s->Ap;
+    update.push_back(u);
+  }
+  P.cells(a64);
+  P.vec(kBatchCgAlpha, alpha);
+  P.vec(kBatchCgUpdate, update);
+  plan_precondition(P, g);
+  plan_direction(P, g, false);
+}
+
+// The start of the pending CG pass of every solve in `g` (pass_start)
+void plan_start(Plan& P, const std::vector<mfq_solver*>& g) {
+  if (g.empty()) return;
+  std::vector<VecItem> start;
+  for (mfq_solver* s : g) {
+    VecItem it{};
+    it.n = s->op64->space->n_dofs;
+    it.st = s->state;
+    it.a = s->run.start_rhs;
+    it.d = s->run.start_sol;
+    it.e = s->r;
+    it.f = s->p;
+    it.s0 = s->run.start_tol2;
+    it.flag = 0;  // preconditioned: p is set by the first direction update
+    start.push_back(it);
+  }
+  P.vec(kBatchCgStart, start);
+  plan_precondition(P, g);
+  plan_direction(P, g, true);
+}
+
+// The FP64 residual check that ends a CG pass of every solve in `g` (step_enqueue): x += c for a
+// correction pass, r = b - A x, ||r||^2 into the solve's scalar slot
+void plan_check(Plan& P, const std::vector<mfq_solver*>& g) {
+  std::vector<VecItem> add, res;
+  std::vector<Plan::Apply> a64;
+  for (mfq_solver* s : g) {
+    const Run& R = s->run;
+    const int64_t N = s->op64->space->n_dofs;
+    if (R.sol != R.x) {
+      VecItem it{};
+      it.n = N;
+      it.d = R.x;
+      it.a = R.sol;
+      add.push_back(it);
+    }
+    a64.push_back({s->op64, R.x, s->Ap});
+    VecItem it{};
+    it.n = N;
+    it.st = s->aux;
+    it.a = R.b;
+    it.b = s->Ap;
+    it.d = s->rout;
+    it.e = s->scal;
+    res.push_back(it);
+  }
+  P.vec(kBatchAdd64, add);
+  P.cells(a64);
+  P.vec(kBatchResidualNorm, res);
 }
 
 int run_plan(const mfq_batch* b, const Plan& P, hipStream_t st) {
@@ -1079,6 +1294,7 @@ int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* par
       }
     }
     s->off_trace = take(s->lv.size() * s->trace_stride * sizeof(double));
+    s->off_lz = take(s->lv.size() * round_up(sizeof(SolverState), 256));
     // coarse level
     Level& C = s->lv[0];
     s->nf = n_free(C.sp->p, C.sp->mesh->n);
@@ -1116,7 +1332,11 @@ int mfq_solver_device_bytes(const mfq_solver* s, size_t* bytes) {
   return MFQ_OK;
 }
 
-int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream) {
+}  // extern "C"
+
+namespace {
+
+int bind_solver(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream, bool lazy) {
   if (!s) return fail(MFQ_EINVAL, "solver is NULL");
   if (!s->op64->buf) return fail(MFQ_EINVAL, "the solver's FP64 operator is not bound");
   if (!dev_buf || (reinterpret_cast<uintptr_t>(dev_buf) % 256)) return fail(MFQ_EINVAL, "buffer NULL or misaligned");
@@ -1176,35 +1396,26 @@ int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream
   }
 
   // diagonals and eigenvalue bounds of the smoothed levels (and of the Chebyshev coarse level):
-  // all Lanczos runs are enqueued, then their traces come back in one copy
-  const size_t l0 = s->prm.coarse_mode == 1 ? 0 : 1;
+  // all Lanczos runs are enqueued, then their traces come back in one copy (lazily bound: the
+  // first step of the first solve estimates them, batched with other solves by mfq_batch_run)
   const size_t nlv = s->lv.size();
   s->trace = (double*)(base + s->off_trace);
+  s->lz = (SolverState*)(base + s->off_lz);
+  MFQ_HIP(launch_fill(MFQ_FP64, s->lz, nlv * round_up(sizeof(SolverState), 256) / 8, 0.0, st));
   if (!s->trace_host)
     MFQ_HIP(hipHostMalloc((void**)&s->trace_host, nlv * s->trace_stride * sizeof(double), hipHostMallocDefault));
-  for (size_t l = l0; l < nlv; ++l) {
+  for (size_t l = first_estimated(s); l < nlv; ++l) {
     Level& L = s->lv[l];
     if (int rc = op_diagonal(L.op, L.dinv, st)) return rc;
     MFQ_HIP(launch_reciprocal(prec, L.dinv, L.n, st));
-    if (int rc = enqueue_lanczos(s, L, s->trace + l * s->trace_stride, st)) return rc;
   }
-  MFQ_HIP(hipMemcpyAsync(s->trace_host, s->trace, nlv * s->trace_stride * sizeof(double), hipMemcpyDeviceToHost, st));
-  MFQ_HIP(hipStreamSynchronize(st));
-  for (size_t l = l0; l < nlv; ++l) {
-    Level& L = s->lv[l];
-    if (int rc = lambda_from_trace(s, L, s->trace_host + l * s->trace_stride)) return rc;
-    double lmax = s->prm.lambda_factor * L.lhat;
-    if (l == 0) {
-      L.lmax = lmax;
-      L.lmin = lmax / s->prm.coarse_ratio;
-      continue;
-    }
-    const int idx = (int)l - 1;
-    if (s->prm.n_lambda_override > idx && s->prm.lambda_override) lmax = s->prm.lambda_override[idx];
-    L.lmax = lmax;
-    L.lmin = lmax / s->prm.lambda_ratio;
+  s->eig_pending = true;
+  if (!lazy)
+    if (int rc = estimate_eigenvalues(s, st)) return rc;
+  if (s->prm.coarse_mode == 1) {
+    MFQ_HIP(hipStreamSynchronize(st));
+    return MFQ_OK;
   }
-  if (s->prm.coarse_mode == 1) return MFQ_OK;
   // coarse level
   Level& C = s->lv[0];
   const int64_t nf = s->nf;
@@ -1233,6 +1444,18 @@ int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream
   return MFQ_OK;
 }
 
+}  // namespace
+
+extern "C" {
+
+int mfq_solver_bind(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream) {
+  return bind_solver(s, dev_buf, bytes, hip_stream, false);
+}
+
+int mfq_solver_bind_lazy(mfq_solver* s, void* dev_buf, size_t bytes, void* hip_stream) {
+  return bind_solver(s, dev_buf, bytes, hip_stream, true);
+}
+
 int mfq_solver_precondition(mfq_solver* s, const double* r, double* z, void* hip_stream) {
   if (!s) return fail(MFQ_EINVAL, "solver is NULL");
   if (!s->buf) return fail(MFQ_EINVAL, "solver is not bound");
@@ -1244,6 +1467,8 @@ int mfq_solver_precondition(mfq_solver* s, const double* r, double* z, void* hip
     MFQ_HIP(hipMemcpyAsync(z, r, N * 8, hipMemcpyDeviceToDevice, st));
     return MFQ_OK;
   }
+  if (s->eig_pending)
+    if (int rc = estimate_eigenvalues(s, st)) return rc;
   return precondition(s, r, z, st);
 }
 
@@ -1251,6 +1476,7 @@ int mfq_solver_lambdas(const mfq_solver* s, double* out, int n_out) {
   if (!s || !out) return fail(MFQ_EINVAL, "solver or out is NULL");
   const int m = s->lv.empty() ? 0 : (int)s->lv.size() - 1;
   if (n_out < m) return fail(MFQ_EINVAL, "need room for %d values", m);
+  if (s->eig_pending) return fail(MFQ_EINVAL, "bound lazily: the estimates are made by the first solve step");
   for (int i = 0; i < m; ++i) out[i] = s->lv[i + 1].lhat;
   return MFQ_OK;
 }
@@ -1311,10 +1537,13 @@ int mfq_batch_create(int max_solvers, mfq_batch** out) {
   b->max_solvers = max_solvers;
   b->table_cap = round_up((size_t)max_solvers * kBatchTableBytesPerSolve, 256);
   b->state_off = b->table_cap;
-  b->bytes = b->table_cap + round_up((size_t)max_solvers * kStateDoubles * sizeof(double), 256);
+  const size_t state_bytes = (size_t)max_solvers * (kStateDoubles + 1) * sizeof(double);
+  const size_t trace_bytes = (size_t)max_solvers * kTraceDoubles * sizeof(double);
+  b->trace_off = b->state_off + round_up(state_bytes, 256);
+  b->bytes = b->trace_off + round_up(trace_bytes, 256);
   if (hipHostMalloc((void**)&b->host_tables, b->table_cap, hipHostMallocDefault) != hipSuccess ||
-      hipHostMalloc((void**)&b->host_states, (size_t)max_solvers * kStateDoubles * sizeof(double),
-                    hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->host_states, state_bytes, hipHostMallocDefault) != hipSuccess ||
+      hipHostMalloc((void**)&b->host_traces, trace_bytes, hipHostMallocDefault) != hipSuccess ||
       hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
     delete b;
     return fail(MFQ_ENOMEM, "pinned host staging of the batch tables could not be allocated");
@@ -1347,37 +1576,118 @@ int mfq_batch_run(mfq_batch* b, mfq_solver* const* solvers, int count, int iters
   if (count > 0 && (!solvers || !done)) return fail(MFQ_EINVAL, "bad solver list");
   if (iters < 1) return fail(MFQ_EINVAL, "iters must be >= 1");
   hipStream_t st = (hipStream_t)hip_stream;
-  std::vector<mfq_solver*> g;
+  const mfq_solver* lead = nullptr;  // the batched solves share its smoother and coarse degrees
   for (int i = 0; i < count; ++i) {
     mfq_solver* s = solvers[i];
     if (!s || s->run.phase == Run::kIdle) return fail(MFQ_EINVAL, "solver %d has no running solve", i);
     if (s->step_pending) return fail(MFQ_EBUSY, "solver %d has an asynchronous step in flight", i);
     if (s->run.phase != Run::kDone && s->run.st != st)
       return fail(MFQ_EINVAL, "solver %d runs on another stream than the batch step", i);
-    if (std::find(g.begin(), g.end(), s) != g.end()) return fail(MFQ_EINVAL, "solver %d listed twice", i);
-    if (batchable(s, iters)) {
-      if (!g.empty() && (s->prm.smoother_degree != g.front()->prm.smoother_degree ||
-                         s->prm.coarse_degree != g.front()->prm.coarse_degree))
+    for (int j = 0; j < i; ++j)
+      if (solvers[j] == s) return fail(MFQ_EINVAL, "solver %d listed twice", i);
+    if ((s->run.phase == Run::kStart || s->run.phase == Run::kInner) && batch_form(s)) {
+      if (lead && (s->prm.smoother_degree != lead->prm.smoother_degree ||
+                   s->prm.coarse_degree != lead->prm.coarse_degree))
         return fail(MFQ_EINVAL, "solver %d: smoother or coarse degree differs within the batch", i);
-      g.push_back(s);
+      if (!lead) lead = s;
     }
   }
-  // the batched solves: plan one iteration and the gather of their scalar states, upload the
-  // tables in one copy, replay the iteration `iters` times, gather once
-  if (!g.empty()) {
-    Plan P;
-    plan_iteration(P, g);
-    const size_t n_iter = P.launches.size();
-    double* dev_states = (double*)(b->buf + b->state_off);
+  // (1) eigenvalue estimates of the lazily bound solves that start now: all their levels' Lanczos
+  // runs in one set of launches, the traces gathered and read back in one copy
+  std::vector<mfq_solver*> e;
+  for (int i = 0; i < count; ++i) {
+    mfq_solver* s = solvers[i];
+    if (s->run.phase != Run::kStart || !s->eig_pending || !batch_form(s)) continue;
+    if (s->lv.size() * s->trace_stride > (size_t)kTraceDoubles) continue;
+    bool cube = true;  // the start vector's counter runs over the (p n + 1)^3 lattice of the level
+    for (const Level& L : s->lv) {
+      const int64_t N1 = (int64_t)L.sp->p * L.sp->mesh->n + 1;
+      cube = cube && N1 * N1 * N1 == L.n;
+    }
+    if (!cube) continue;
+    if (!e.empty() && s->prm.lanczos_iters != e.front()->prm.lanczos_iters) continue;
+    e.push_back(s);
+  }
+  if (!e.empty()) {
+    Plan L;
+    plan_lanczos_start(L, e);
+    const size_t n_start = L.launches.size();
+    plan_lanczos_step(L, e);
+    const size_t n_step = L.launches.size();
+    double* dev_traces = (double*)(b->buf + b->trace_off);
     std::vector<VecItem> gather;
-    for (size_t i = 0; i < g.size(); ++i) {
+    for (size_t i = 0; i < e.size(); ++i) {
       VecItem it{};
-      it.n = kStateDoubles;
-      it.a = g[i]->state;
-      it.d = dev_states + i * kStateDoubles;
+      it.n = (int64_t)(e[i]->lv.size() * e[i]->trace_stride);
+      it.a = e[i]->trace;
+      it.d = dev_traces + i * kTraceDoubles;
       gather.push_back(it);
     }
-    P.vec(kBatchCopy64, gather);
+    L.vec(kBatchCopy64, gather);
+    if (L.tab.size() > b->table_cap)
+      return fail(MFQ_EINVAL, "batch tables of %zu bytes exceed the %zu bytes for %d solvers", L.tab.size(),
+                  b->table_cap, b->max_solvers);
+    MFQ_HIP(hipEventSynchronize(b->uploaded));
+    std::memcpy(b->host_tables, L.tab.data(), L.tab.size());
+    MFQ_HIP(hipMemcpyAsync(b->buf, b->host_tables, L.tab.size(), hipMemcpyHostToDevice, st));
+    MFQ_HIP(hipEventRecord(b->uploaded, st));
+    Plan part;
+    part.launches.assign(L.launches.begin(), L.launches.begin() + n_start);
+    if (int rc = run_plan(b, part, st)) return rc;
+    part.launches.assign(L.launches.begin() + n_start, L.launches.begin() + n_step);
+    for (int k = 0; k < e.front()->prm.lanczos_iters; ++k)
+      if (int rc = run_plan(b, part, st)) return rc;
+    part.launches.assign(L.launches.begin() + n_step, L.launches.end());
+    if (int rc = run_plan(b, part, st)) return rc;
+    MFQ_HIP(hipMemcpyAsync(b->host_traces, dev_traces, e.size() * kTraceDoubles * sizeof(double),
+                           hipMemcpyDeviceToHost, st));
+    MFQ_HIP(hipStreamSynchronize(st));
+    for (size_t i = 0; i < e.size(); ++i) {
+      const int rc = lambdas_from_traces(e[i], b->host_traces + i * kTraceDoubles);
+      if (rc == MFQ_ENONFINITE)
+        finish(e[i], rc);
+      else if (rc)
+        return rc;
+    }
+  }
+
+  // (2) one plan: the starts of pending CG passes and the residual checks ending passes (once
+  // each), one CG iteration of every solve with room for `iters` (replayed), the gather of the
+  // scalar states and residual norms; its tables go up in one copy
+  std::vector<mfq_solver*> starting, checking, g;
+  for (int i = 0; i < count; ++i) {
+    mfq_solver* s = solvers[i];
+    if (s->run.phase == Run::kStart && !s->eig_pending && batch_form(s)) starting.push_back(s);
+    if (s->run.phase == Run::kCheck && batch_form(s)) checking.push_back(s);
+  }
+  Plan P;
+  plan_start(P, starting);
+  for (mfq_solver* s : starting) pass_started(s, s->run.start_sol);
+  plan_check(P, checking);
+  const size_t n_once = P.launches.size();
+  for (int i = 0; i < count; ++i)
+    if (batchable(solvers[i], iters)) g.push_back(solvers[i]);
+  if (!g.empty()) plan_iteration(P, g);
+  const size_t n_iter = P.launches.size();
+  double* dev_states = (double*)(b->buf + b->state_off);
+  double* dev_norms = dev_states + (size_t)b->max_solvers * kStateDoubles;
+  std::vector<VecItem> gather;
+  for (size_t i = 0; i < g.size(); ++i) {
+    VecItem it{};
+    it.n = kStateDoubles;
+    it.a = g[i]->state;
+    it.d = dev_states + i * kStateDoubles;
+    gather.push_back(it);
+  }
+  for (size_t i = 0; i < checking.size(); ++i) {
+    VecItem it{};
+    it.n = 1;
+    it.a = checking[i]->scal;
+    it.d = dev_norms + i;
+    gather.push_back(it);
+  }
+  P.vec(kBatchCopy64, gather);
+  if (!P.launches.empty()) {
     if (P.tab.size() > b->table_cap)
       return fail(MFQ_EINVAL, "batch tables of %zu bytes exceed the %zu bytes for %d solvers", P.tab.size(),
                   b->table_cap, b->max_solvers);
@@ -1385,26 +1695,36 @@ int mfq_batch_run(mfq_batch* b, mfq_solver* const* solvers, int count, int iters
     std::memcpy(b->host_tables, P.tab.data(), P.tab.size());
     MFQ_HIP(hipMemcpyAsync(b->buf, b->host_tables, P.tab.size(), hipMemcpyHostToDevice, st));
     MFQ_HIP(hipEventRecord(b->uploaded, st));
-    Plan iter;
-    iter.launches.assign(P.launches.begin(), P.launches.begin() + n_iter);
-    for (int k = 0; k < iters; ++k)
-      if (int rc = run_plan(b, iter, st)) return rc;
-    Plan last;
-    last.launches.assign(P.launches.begin() + n_iter, P.launches.end());
-    if (int rc = run_plan(b, last, st)) return rc;
-    MFQ_HIP(hipMemcpyAsync(b->host_states, dev_states, g.size() * kStateDoubles * sizeof(double),
-                           hipMemcpyDeviceToHost, st));
+    Plan part;
+    part.launches.assign(P.launches.begin(), P.launches.begin() + n_once);
+    if (int rc = run_plan(b, part, st)) return rc;
+    part.launches.assign(P.launches.begin() + n_once, P.launches.begin() + n_iter);
+    if (!part.launches.empty())
+      for (int k = 0; k < iters; ++k)
+        if (int rc = run_plan(b, part, st)) return rc;
+    part.launches.assign(P.launches.begin() + n_iter, P.launches.end());
+    if (int rc = run_plan(b, part, st)) return rc;
+    if (!g.empty())
+      MFQ_HIP(hipMemcpyAsync(b->host_states, dev_states, g.size() * kStateDoubles * sizeof(double),
+                             hipMemcpyDeviceToHost, st));
+    if (!checking.empty())
+      MFQ_HIP(hipMemcpyAsync(b->host_states + (size_t)b->max_solvers * kStateDoubles, dev_norms,
+                             checking.size() * sizeof(double), hipMemcpyDeviceToHost, st));
     for (mfq_solver* s : g) s->run.enqueued += iters;
   }
-  // the other running solves (residual checks between CG passes, solves that cannot be batched)
+  // (3) the other running solves (solves that cannot be batched, passes without room for `iters`)
   for (int i = 0; i < count; ++i) {
     mfq_solver* s = solvers[i];
-    if (s->run.phase == Run::kDone || std::find(g.begin(), g.end(), s) != g.end()) continue;
+    if (s->run.phase == Run::kDone || std::find(g.begin(), g.end(), s) != g.end() ||
+        std::find(checking.begin(), checking.end(), s) != checking.end())
+      continue;
     if (int rc = step_enqueue(s, iters)) return rc;
   }
   MFQ_HIP(hipStreamSynchronize(st));
   for (size_t i = 0; i < g.size(); ++i)
     std::memcpy(&g[i]->hstat->head, b->host_states + i * kStateDoubles, kStateDoubles * sizeof(double));
+  for (size_t i = 0; i < checking.size(); ++i)
+    checking[i]->hstat->cert = b->host_states[(size_t)b->max_solvers * kStateDoubles + i];
   for (int i = 0; i < count; ++i) {
     mfq_solver* s = solvers[i];
     if (s->run.phase != Run::kDone)

@@ -115,8 +115,11 @@ class DeviceExecutor:
         sp = su.cuda_stream
         _lib.mfq_op_bind(h["op"], h["op_buf"].data_ptr(), h["op_bytes"], sp)
         _lib.mfq_space_random(h["space"], MFQ_FP64, h["b"].data_ptr(), req.seed, sp)
-        # synchronises the set-up stream: everything above is complete before the solve starts
-        _lib.mfq_solver_bind(h["solver"], h["solver_buf"].data_ptr(), h["solver_bytes"], sp)
+        # synchronises the set-up stream: everything above is complete before the solve starts.
+        # Batched: the eigenvalue estimates are left to the first batched step, which makes those
+        # of all requests starting together in one set of launches.
+        bind = _lib.mfq_solver_bind_lazy if self.batched else _lib.mfq_solver_bind
+        bind(h["solver"], h["solver_buf"].data_ptr(), h["solver_bytes"], sp)
 
     def begin(self, req, h):
         """Begin the solve on the next solve stream (scheduler thread only)."""

@@ -348,3 +348,82 @@ def test_batched_serving_matches_oracle_and_alone():
         srv1.close()
         assert alone.iterations == r.iterations
         np.testing.assert_array_equal(alone.result.cpu().numpy(), r.result.cpu().numpy())
+
+
+def test_lazy_bind_batched_estimates_and_starts_are_bitwise():
+    """Solvers bound lazily (eigenvalue bounds estimated by the first step) and advanced by
+    mfq_batch_run, where the estimates of all of them run in one set of launches and the CG pass
+    starts and residual checks are batched too: bounds, iteration counts and solutions equal those
+    of the same solvers bound eagerly and advanced alone, bitwise.  One solver with another
+    Lanczos length takes the per-solve estimate inside the same call."""
+    mfq = _mfq()
+    torch = _torch()
+    print("lazy bind + batched estimates", flush=True)
+    st = torch.cuda.Stream()
+    cases = MIX + [(5, 6, 0.4), (1, 16, 0.1)]
+    rtols = [1e-10, 1e-13, 1e-10, 1e-13, 1e-10, 1e-10, 1e-12, 1e-10]
+    lanczos = [None] * len(cases)
+    lanczos[2] = 8
+    ref = []
+    for i, (p, n, a) in enumerate(cases):
+        op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.0), p, mfq.MFQ_BC_DIRICHLET0), a, mfq.MFQ_FP64)
+        b = op.space.random(700 + i)
+        kw = {} if lanczos[i] is None else {"lanczos_iters": lanczos[i]}
+        sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, coarse_mode=1, **kw)
+        x = op.new_vector()
+        sv.begin(b, x, rtol=rtols[i], max_iter=400, stream=st)
+        while not mfq.batch_step([sv], iters=2)[0]:
+            pass
+        s_, info = sv.end()
+        assert s_ == mfq.MFQ_OK
+        nl = info.n_levels
+        ref.append((op, b, x.clone(), info.iterations, info.outer_iterations, sv.lambdas(nl), kw))
+    lazy, xs = [], []
+    for i, (op, b, _, _, _, _, kw) in enumerate(ref):
+        sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, coarse_mode=1, lazy=True, stream=st, **kw)
+        with pytest.raises(mfq._lib.MfqError):
+            sv.lambdas(8)
+        x = op.new_vector()
+        sv.begin(b, x, rtol=rtols[i], max_iter=400, stream=st)
+        lazy.append(sv)
+        xs.append(x)
+    batch = mfq.Batch(16, stream=st)
+    pending = list(range(len(lazy)))
+    steps = 0
+    while pending:
+        flags = batch.run([lazy[i] for i in pending], iters=2, stream=st)
+        pending = [i for i, f in zip(pending, flags) if not f]
+        steps += 1
+        assert steps < 600
+    torch.cuda.synchronize()
+    for i, sv in enumerate(lazy):
+        s_, info = sv.end()
+        _, _, x_ref, its, outer, lam, _ = ref[i]
+        print(f"  {cases[i]} rtol {rtols[i]:.0e}: {its} iterations, {outer} passes")
+        assert s_ == mfq.MFQ_OK
+        assert sv.lambdas(info.n_levels) == lam, cases[i]
+        assert info.iterations == its and info.outer_iterations == outer, (cases[i], info.iterations, its)
+        assert torch.equal(xs[i], x_ref), cases[i]
+
+
+def test_lazy_bind_alone_equals_eager():
+    """A lazily bound solver advanced by mfq_batch_step (the estimate made per solve at its first
+    step) and one whose preconditioner is applied before any solve give the eager solver's
+    results bitwise."""
+    mfq = _mfq()
+    torch = _torch()
+    p, n, a = 3, 6, 0.5
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.1), p, mfq.MFQ_BC_DIRICHLET0), a, mfq.MFQ_FP64)
+    b = op.space.random(11)
+    eager = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED)
+    x0, info0, s0 = eager.solve(b, rtol=1e-10, max_iter=300)
+    z0 = eager.precondition(b)
+    lazy = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, lazy=True)
+    x1, info1, s1 = lazy.solve(b, rtol=1e-10, max_iter=300)
+    assert s0 == s1 == mfq.MFQ_OK and info0.iterations == info1.iterations
+    assert torch.equal(x0, x1)
+    lazy2 = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, lazy=True)
+    z1 = lazy2.precondition(b)
+    torch.cuda.synchronize()
+    assert torch.equal(z0, z1)
+    assert lazy2.lambdas(info0.n_levels) == eager.lambdas(info0.n_levels)
