@@ -523,8 +523,12 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
 }
 
 // Minimum waves per SIMD asked of the register allocator for the operator kernels (1: no request).
+// Degree 4 in FP64 otherwise takes 131 VGPRs, 3 waves per SIMD; the request for 4 costs no spills
+// and is about 1% faster (the single-operator kernel without hanging nodes only: the others spill
+// under it).  Requests that force spills (5 waves at degree 4 FP64, 8 in FP32, one
+// more wave at degrees 2, 3, 5-8) were measured 10-90% slower.
 #ifndef MFQ_VM_WAVES
-#define MFQ_VM_WAVES(P, FP64) 1
+#define MFQ_VM_WAVES(P, FP64) ((P) == 4 && (FP64) ? 4 : 1)
 #endif
 template <int P, typename Real>
 struct VmWaves {
@@ -532,7 +536,7 @@ struct VmWaves {
 };
 
 template <int P, typename Real, bool ACC, bool CART = false, bool HANG = false>
-__global__ __launch_bounds__(Cell<P>::NT) __attribute__((amdgpu_waves_per_eu(VmWaves<P, Real>::MIN))) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo, const Real* __restrict__ src,
+__global__ __launch_bounds__(Cell<P>::NT) __attribute__((amdgpu_waves_per_eu(HANG ? 1 : VmWaves<P, Real>::MIN))) void vmult_kernel(const int* __restrict__ idx, const Real* __restrict__ geo, const Real* __restrict__ src,
                   Real* __restrict__ dst, Bricks bk, int colour, ShapeEO<P, Real> sh,
                   CartQuad<P, Real> cq = {}, Side<Real> sd = {}) {
   vmult_brick<P, Real, ACC, CART, HANG>(idx, geo, src, dst, bk, colour, blockIdx.x, sh, cq, sd);
@@ -542,7 +546,7 @@ __global__ __launch_bounds__(Cell<P>::NT) __attribute__((amdgpu_waves_per_eu(VmW
 // to the item whose range [first[colour], next first) holds it and computes that operator's brick
 // b - first, exactly as the single-operator launch does (results bitwise equal).
 template <int P, typename Real, bool CART>
-__global__ __launch_bounds__(Cell<P>::NT) __attribute__((amdgpu_waves_per_eu(VmWaves<P, Real>::MIN))) void batch_vmult_kernel(const CellItem* __restrict__ items, int count,
+__global__ __launch_bounds__(Cell<P>::NT) void batch_vmult_kernel(const CellItem* __restrict__ items, int count,
                                                                    int colour, ShapeEO<P, Real> sh,
                                                                    CartQuad<P, Real> cq) {
   int lo = 0, hi = count - 1;
