@@ -237,9 +237,21 @@ int mfq_restrict(const mfq_transfer* t, int precision, const void* fine, void* c
 /* ---------------------------------------------------------------- smoother (Sec. 3.5, 6.1)
  * `degree` Chebyshev updates of x for A x = b with the Jacobi preconditioner inv_diag on the
  * interval [lmin, lmax] of D^{-1}A (Chebyshev semi-iteration).  x_is_zero != 0 starts from
- * x = 0 (x is overwritten).  work must hold 3*n_dofs elements of the operator's precision. */
+ * x = 0 (x is overwritten).  work must hold 3*n_dofs elements of the operator's precision.
+ * With fused updates enabled on the operator (mfq_op_set_fused_updates), each update that
+ * follows an operator application is done inside it. */
 int mfq_chebyshev(const mfq_op* op, const void* inv_diag, const void* b, void* x, int x_is_zero,
                   int degree, double lmin, double lmax, void* work, void* hip_stream);
+/* Fused vector updates (not in the paper; its smoother steps are separate vector operations):
+ * with enable != 0 a Chebyshev step of mfq_chebyshev, and the multigrid residual r = b - A x of
+ * the V-cycles of solvers created afterwards from this operator, is done inside the operator
+ * application: the brick that completes a node's product applies the update there, so the
+ * product is never stored or read back (the third work vector keeps only partial sums of nodes
+ * shared between bricks).  enable = 0 (the default) issues the application and a separate vector
+ * kernel.  Both give bitwise equal results; on MI355X the separate form is the faster one (the
+ * cell loop is bound by per-brick latency at its occupancy, and the update's operands lengthen
+ * it more than a streaming vector kernel costs).  Matrix-core operators never fuse.  Host only. */
+int mfq_op_set_fused_updates(mfq_op* op, int enable);
 
 /* For callers that cannot allocate device memory (code under HIP graph capture, serving loops or
  * harnesses that forbid the allocator): mfq_chebyshev without the `work` argument.  The three

@@ -128,6 +128,10 @@ class Operator:
         """Work decomposition of the cell loop: brick shape, launches per vmult, workgroups."""
         return _lib.mfq_op_get_layout(self.handle)
 
+    def set_fused_updates(self, enable):
+        """Smoother steps and multigrid residuals fused into the operator application (default on)."""
+        _lib.mfq_op_set_fused_updates(self.handle, enable)
+
     def vmult_add(self, src, dst, stream=None):
         _lib.mfq_vmult_add(self.handle, _check_vec(src, self.n_dofs, self.precision, "src"),
                            _check_vec(dst, self.n_dofs, self.precision, "dst"), _stream(stream))

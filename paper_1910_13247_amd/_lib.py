@@ -67,6 +67,7 @@ _SIGS = {
     "mfq_op_create": ([P, D, I, PP], I),
     "mfq_op_destroy": ([P], None),
     "mfq_op_device_bytes": ([P, C.POINTER(SZ)], I),
+    "mfq_op_set_fused_updates": ([P, I], I),
     "mfq_op_bind": ([P, P, SZ, P], I),
     "mfq_vmult": ([P, P, P, P], I),
     "mfq_vmult_add": ([P, P, P, P], I),
@@ -224,6 +225,10 @@ def mfq_op_device_bytes(op):
     n = SZ()
     _check(lib().mfq_op_device_bytes(op, C.byref(n)))
     return n.value
+
+
+def mfq_op_set_fused_updates(op, enable):
+    _check(lib().mfq_op_set_fused_updates(op, 1 if enable else 0))
 
 
 def mfq_op_bind(op, dev_buf, nbytes, stream):

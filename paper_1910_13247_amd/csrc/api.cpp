@@ -3,6 +3,7 @@
 #include <cstring>
 #include <new>
 
+#include "batch.hpp"
 #include "mfq_internal.hpp"
 
 using namespace mfq;
@@ -262,6 +263,12 @@ int mfq_restrict(const mfq_transfer* t, int precision, const void* fine, void* c
   return MFQ_OK;
 }
 
+int mfq_op_set_fused_updates(mfq_op* op, int enable) {
+  if (!op) return fail(MFQ_EINVAL, "op is NULL");
+  op->fuse = enable != 0;
+  return MFQ_OK;
+}
+
 int mfq_chebyshev(const mfq_op* op, const void* inv_diag, const void* b, void* x, int x_is_zero, int degree,
                   double lmin, double lmax, void* work, void* hip_stream) {
   if (int rc = check_op(op)) return rc;
@@ -281,13 +288,40 @@ int mfq_chebyshev(const mfq_op* op, const void* inv_diag, const void* b, void* x
   const double theta = 0.5 * (lmax + lmin), delta = 0.5 * (lmax - lmin);
   const double sigma = theta / delta;
   double rho = 1.0 / sigma;
-  if (!x_is_zero)
+  // With fused updates enabled on the operator, each step's vector update is done inside the
+  // operator application (applied where a node's product completes; t keeps only partial sums);
+  // otherwise, and always on the matrix cores and with hanging nodes, the product is stored and a
+  // vector kernel follows.
+  const OpView v = view(op);
+  const bool fuse = op->fuse && !op->mfma && v.side_base < 0;
+  CellEpilogue ep;
+  ep.b = b;
+  ep.dinv = inv_diag;
+  ep.x = x;
+  ep.r = r;
+  ep.d = d;
+  if (x_is_zero) {
+    MFQ_HIP(launch_cheb_first(op->precision, b, t, inv_diag, x, r, d, n, 1.0 / theta, true, st));
+  } else if (fuse) {
+    ep.mode = kEpiChebFirst;
+    ep.s0 = 1.0 / theta;
+    MFQ_HIP(launch_vmult_epilogue(v, op->precision, x, t, ep, st));
+  } else {
     if (int rc = op_vmult(op, x, t, st)) return rc;
-  MFQ_HIP(launch_cheb_first(op->precision, b, t, inv_diag, x, r, d, n, 1.0 / theta, x_is_zero != 0, st));
+    MFQ_HIP(launch_cheb_first(op->precision, b, t, inv_diag, x, r, d, n, 1.0 / theta, false, st));
+  }
   for (int k = 1; k < degree; ++k) {
-    if (int rc = op_vmult(op, d, t, st)) return rc;
     const double rho_new = 1.0 / (2.0 * sigma - rho);
-    MFQ_HIP(launch_cheb_step(op->precision, t, inv_diag, x, r, d, n, rho_new * rho, 2.0 * rho_new / delta, st));
+    const double c1 = rho_new * rho, c2 = 2.0 * rho_new / delta;
+    if (fuse) {
+      ep.mode = kEpiChebStep;
+      ep.s0 = c1;
+      ep.s1 = c2;
+      MFQ_HIP(launch_vmult_epilogue(v, op->precision, d, t, ep, st));
+    } else {
+      if (int rc = op_vmult(op, d, t, st)) return rc;
+      MFQ_HIP(launch_cheb_step(op->precision, t, inv_diag, x, r, d, n, c1, c2, st));
+    }
     rho = rho_new;
   }
   return MFQ_OK;

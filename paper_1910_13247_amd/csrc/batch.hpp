@@ -28,6 +28,24 @@ struct VecItem {
   SolverState* st;
 };
 
+// Vector update fused into a cell loop (kernels_cell.hip): at each node the brick that completes
+// the product t = (A src)_i applies it there; the other bricks leave partial sums in dst.
+enum CellEpilogueMode {
+  kEpiNone = 0,
+  kEpiChebFirst = 1,  // src = x (not zero): r = b - t; d = dinv r / theta; x += d   (s0 = 1/theta)
+  kEpiChebStep = 2,   // src = d: r -= t; d = c1 d + c2 dinv r; x += d              (s0 = c1, s1 = c2)
+  kEpiResidual = 3,   // src = x: r = b - t
+};
+struct CellEpilogue {
+  int mode = kEpiNone;
+  const void* b = nullptr;
+  const void* dinv = nullptr;
+  void* x = nullptr;
+  void* r = nullptr;
+  void* d = nullptr;
+  double s0 = 0, s1 = 0;
+};
+
 // one solve's operands of a batched cell loop: an operator and the vectors it reads and writes
 struct CellItem {
   int64_t first[kColours];  // first workgroup of the item in colour c's launch
@@ -36,6 +54,7 @@ struct CellItem {
   const void* src;
   void* dst;
   Bricks bk;
+  CellEpilogue ep;          // fused launches only
 };
 
 // one solve's operands of a batched level transfer (coarse cells of one (degree, degree) pair)
@@ -72,13 +91,18 @@ enum BatchVecOp {
 
 // Launchers (items: device array of `count` items, `blocks` = total workgroups).
 hipError_t launch_batch_vec(BatchVecOp op, const VecItem* items, int count, int64_t blocks, hipStream_t st);
-// Cell loop of degree p, precision, for one colour (items' first[colour]); ACC = false.
-hipError_t launch_batch_cells(int p, int precision, bool cart, const CellItem* items, int count, int colour,
-                              int64_t blocks, hipStream_t st);
+// Cell loop of degree p, precision, for one colour (items' first[colour]); ACC = false.  fused: with
+// the items' epilogues (FP32 only).
+hipError_t launch_batch_cells(int p, int precision, bool cart, bool fused, const CellItem* items, int count,
+                              int colour, int64_t blocks, hipStream_t st);
 // Level transfer of degree pair (pc, pf, h_transfer) in FP32: prolongation (one launch) or one
 // colour of the restriction (after the coarse vectors were cleared by kBatchFill).
 hipError_t launch_batch_transfer(int pc, int pf, bool h_transfer, bool prolongate, int colour,
                                  const TransferItem* items, int count, int64_t blocks, hipStream_t st);
+// dst = A src with the fused update `ep` (not for matrix-core operators or spaces with hanging
+// nodes); dst receives partial sums of shared nodes only.
+hipError_t launch_vmult_epilogue(const OpView& v, int precision, const void* src, void* dst, const CellEpilogue& ep,
+                                 hipStream_t st);
 // Workgroups of the single-solve launches the batched ones reproduce.
 int vec_blocks(BatchVecOp op, int64_t n);
 

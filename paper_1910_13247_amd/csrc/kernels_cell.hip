@@ -314,6 +314,113 @@ __device__ __forceinline__ void scatter_lattice(const Real* res, int cstride, co
   }
 }
 
+// Fused form of scatter_lattice (ACC = false, no hanging nodes): a node's last writer, the brick
+// that is odd in every direction in which the node is shared (its colour comes last), completes
+// t = (A src)_i and applies the epilogue there (Dirichlet rows: t = src_i) instead of storing t;
+// the other bricks store or add their partial sums into dst as scatter_lattice does.  No later
+// launch touches a completed node, so the epilogue may overwrite src there.  The epilogue's
+// operands are loaded with the source lattice (epilogue_prefetch), so their latency hides behind
+// the cell computation instead of lengthening the brick's store pass.
+template <typename Real, int KPT>
+struct EpiRegs {
+  unsigned last;     // bit j: this brick completes node j
+  int gi[KPT];       // vector index of node j (Dirichlet nodes included), 0 when not completed here
+  Real a[KPT];       // r (step) or b (first step, residual)
+  Real dinv[KPT];
+  Real x[KPT];       // x (step)
+  Real s[KPT];       // src: d (step) or x (first step); t itself on Dirichlet rows
+};
+
+template <int P, typename Real, int BLOCK, int KPT>
+__device__ __forceinline__ void epilogue_prefetch(const CellEpilogue& ep, const Real* src, const int (&gk)[KPT],
+                                                  const Bricks& bk, int bi, int bj, int bz, EpiRegs<Real, KPT>& e) {
+  using C = Cell<P>;
+  constexpr int LX = C::LX, LY = C::LY;
+  const int tid = threadIdx.x;
+  const Real* b = (const Real*)ep.b;
+  const Real* dinv = (const Real*)ep.dinv;
+  const Real* x = (const Real*)ep.x;
+  const Real* r = (const Real*)ep.r;
+  e.last = 0;
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    const int k = tid + j * BLOCK;
+    const int g0 = gk[j];
+    const int li = k % LX, lj = (k / LX) % LY, lk = k / (LX * LY);
+    const bool sx = ((li == 0) & (bi > 0)) | ((li == LX - 1) & (bi < bk.nbx - 1));
+    const bool sy = ((lj == 0) & (bj > 0)) | ((lj == LY - 1) & (bj < bk.nby - 1));
+    const bool sz = ((lk == 0) & (bz > 0)) | ((lk == C::LZ - 1) & (bz < bk.nbz - 1));
+    const bool last = (g0 != kAbsent) & ((!sx) | (bi & 1)) & ((!sy) | (bj & 1)) & ((!sz) | (bz & 1));
+    e.last |= last ? 1u << j : 0u;
+    const int gi = last ? (g0 >= 0 ? g0 : ~g0) : 0;
+    e.gi[j] = gi;
+    // branch-free: nodes not completed here read entry 0 (a line every brick touches)
+    if (ep.mode == kEpiChebStep) {
+      e.a[j] = r[gi];
+      e.dinv[j] = dinv[gi];
+      e.x[j] = x[gi];
+    } else if (ep.mode == kEpiChebFirst) {
+      e.a[j] = b[gi];
+      e.dinv[j] = dinv[gi];
+    } else {
+      e.a[j] = b[gi];
+    }
+    e.s[j] = src[gi];
+  }
+}
+
+template <int P, typename Real, int BLOCK, int KPT>
+__device__ __forceinline__ void scatter_epilogue(const Real* res, int cstride, Real* __restrict__ dst,
+                                                 const int (&gk)[KPT], unsigned first, const Real (&dv)[KPT],
+                                                 const CellEpilogue& ep, const EpiRegs<Real, KPT>& e) {
+  using C = Cell<P>;
+  constexpr int N1 = C::N1, LX = C::LX, LY = C::LY;
+  const int tid = threadIdx.x;
+  Real* x = (Real*)ep.x;
+  Real* r = (Real*)ep.r;
+  Real* d = (Real*)ep.d;
+#pragma unroll
+  for (int j = 0; j < KPT; ++j) {
+    const int k = tid + j * BLOCK;
+    const int g0 = gk[j];
+    if (g0 == kAbsent) continue;
+    const int li = k % LX, lj = (k / LX) % LY, lk = k / (LX * LY);
+    const int xhi = min(li / P, C::BX - 1), xlo = (li % P == 0 && li > 0) ? li / P - 1 : xhi;
+    const int yhi = min(lj / P, C::BY - 1), ylo = (lj % P == 0 && lj > 0) ? lj / P - 1 : yhi;
+    const int zhi = min(lk / P, C::BZ - 1), zlo = (lk % P == 0 && lk > 0) ? lk / P - 1 : zhi;
+    Real sum = 0;
+    for (int ccz = zlo; ccz <= zhi; ++ccz)
+      for (int ccy = ylo; ccy <= yhi; ++ccy)
+        for (int ccx = xlo; ccx <= xhi; ++ccx) {
+          const int cell = ccx + C::BX * (ccy + C::BY * ccz);
+          sum += res[cell * cstride + (li - ccx * P) + N1 * ((lj - ccy * P) + N1 * (lk - ccz * P))];
+        }
+    const bool fj = first >> j & 1u;
+    const bool last = e.last >> j & 1u;
+    if (!last) {
+      if (g0 >= 0) dst[g0] = fj ? sum : dv[j] + sum;
+      continue;
+    }
+    const int i = e.gi[j];
+    const Real t = g0 >= 0 ? (fj ? sum : dv[j] + sum) : e.s[j];
+    if (ep.mode == kEpiChebStep) {
+      Real rv = e.a[j], dd = e.s[j], xv = e.x[j];
+      cheb_step_entry<Real>(t, e.dinv[j], (Real)ep.s0, (Real)ep.s1, rv, dd, xv);
+      r[i] = rv;
+      d[i] = dd;
+      x[i] = xv;
+    } else if (ep.mode == kEpiChebFirst) {
+      Real rv, dd, xv = e.s[j];
+      cheb_first_entry<Real>(e.a[j], t, e.dinv[j], (Real)ep.s0, false, rv, dd, xv);
+      r[i] = rv;
+      d[i] = dd;
+      x[i] = xv;
+    } else {
+      r[i] = e.a[j] - t;
+    }
+  }
+}
+
 #ifndef MFQ_G_STAGE
 #define MFQ_G_STAGE 0
 #endif
@@ -331,11 +438,12 @@ struct CartQuad {
 
 // One brick (number b of colour `colour`) of the operator application by the workgroup.  HANG: a
 // space with hanging nodes (X1-low face nodes go through the face arrays `sd`).
-template <int P, typename Real, bool ACC, bool CART, bool HANG>
+template <int P, typename Real, bool ACC, bool CART, bool HANG, bool EPI = false>
 __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const Real* __restrict__ geo,
                                             const Real* __restrict__ src, Real* __restrict__ dst, const Bricks& bk,
                                             int colour, int64_t b, const ShapeEO<P, Real>& sh,
-                                            const CartQuad<P, Real>& cq, const Side<Real>& sd) {
+                                            const CartQuad<P, Real>& cq, const Side<Real>& sd,
+                                            const CellEpilogue& ep = CellEpilogue{}) {
   using C = Cell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NCELL = C::NCELL, NT = C::NT, LX = C::LX, LY = C::LY, NL = C::NL;
   constexpr int BLOCK = NT;                        // threads of the workgroup
@@ -402,6 +510,8 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
   // the masked dst gather was timed per degree on MI355X: slower only for p = 6 FP64 and p = 5 FP32
   constexpr bool MASK = !((P == 6 && sizeof(Real) == 8) || (P == 5 && sizeof(Real) == 4));
   lattice_values<Real, ACC, BLOCK, KPT, NL, HANG, MASK>(src, dst, gk, first, lat, dv, sd);
+  EpiRegs<Real, EPI ? KPT : 1> er;
+  if constexpr (EPI) epilogue_prefetch<P, Real, BLOCK, KPT>(ep, src, gk, bk, bi, bj, bz, er);
   lds_barrier();
 
   // x: values and x-derivatives at (q, e0, e1) from the lane's x-pencil
@@ -519,7 +629,10 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
   }
   lds_barrier();
   // sum the cells' results per lattice node (fixed order) and write the brick's nodes
-  scatter_lattice<P, Real, ACC, BLOCK, KPT, kDirSource, HANG>(lds, NQ, src, dst, gk, first, dv, sd);
+  if constexpr (EPI)
+    scatter_epilogue<P, Real, BLOCK, KPT>(lds, NQ, dst, gk, first, dv, ep, er);
+  else
+    scatter_lattice<P, Real, ACC, BLOCK, KPT, kDirSource, HANG>(lds, NQ, src, dst, gk, first, dv, sd);
 }
 
 // Minimum waves per SIMD asked of the register allocator for the operator kernels (1: no request).
@@ -542,6 +655,15 @@ __global__ __launch_bounds__(Cell<P>::NT) __attribute__((amdgpu_waves_per_eu(HAN
   vmult_brick<P, Real, ACC, CART, HANG>(idx, geo, src, dst, bk, colour, blockIdx.x, sh, cq, sd);
 }
 
+// Operator application with a fused vector update (see scatter_epilogue); dst holds partial sums.
+template <int P, typename Real, bool CART>
+__global__ __launch_bounds__(Cell<P>::NT) void vmult_epi_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
+                                                                const Real* src, Real* __restrict__ dst, Bricks bk,
+                                                                int colour, ShapeEO<P, Real> sh, CartQuad<P, Real> cq,
+                                                                CellEpilogue ep) {
+  vmult_brick<P, Real, false, CART, false, true>(idx, geo, src, dst, bk, colour, blockIdx.x, sh, cq, Side<Real>{}, ep);
+}
+
 // Batched form (serving): one launch of colour `colour` over many operators; workgroup b belongs
 // to the item whose range [first[colour], next first) holds it and computes that operator's brick
 // b - first, exactly as the single-operator launch does (results bitwise equal).
@@ -560,6 +682,24 @@ __global__ __launch_bounds__(Cell<P>::NT) void batch_vmult_kernel(const CellItem
   if constexpr (CART) cqi.h = (Real)(1.0 / it.bk.n);
   vmult_brick<P, Real, false, CART, false>(it.idx, (const Real*)it.geo, (const Real*)it.src, (Real*)it.dst, it.bk,
                                           colour, b - it.first[colour], sh, cqi, Side<Real>{});
+}
+
+// Batched form with each item's fused vector update.
+template <int P, typename Real, bool CART>
+__global__ __launch_bounds__(Cell<P>::NT) void batch_vmult_epi_kernel(const CellItem* __restrict__ items, int count,
+                                                                       int colour, ShapeEO<P, Real> sh,
+                                                                       CartQuad<P, Real> cq) {
+  int lo = 0, hi = count - 1;
+  const int64_t b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first[colour] <= b) lo = mid; else hi = mid - 1;
+  }
+  const CellItem& it = items[lo];
+  CartQuad<P, Real> cqi = cq;
+  if constexpr (CART) cqi.h = (Real)(1.0 / it.bk.n);
+  vmult_brick<P, Real, false, CART, false, true>(it.idx, (const Real*)it.geo, (const Real*)it.src, (Real*)it.dst,
+                                                it.bk, colour, b - it.first[colour], sh, cqi, Side<Real>{}, it.ep);
 }
 
 // ---------------------------------------------------------------- operator application, MFMA (FP32)
@@ -1247,6 +1387,36 @@ hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipSt
   return hipGetLastError();
 }
 
+template <int P, typename Real>
+hipError_t vmult_epi_pr(const OpView& v, const void* src, void* dst, const CellEpilogue& ep, hipStream_t st) {
+  static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
+  const bool cart = v.amplitude == 0.0 && v.alpha == 0.0;
+  CartQuad<P, Real> cq{};
+  if (cart) {
+    const Tables1D& tb = tables(P);
+    for (int a = 0; a <= P; ++a) cq.w[a] = (Real)tb.omega[a];
+    cq.h = (Real)(1.0 / v.n);
+  }
+  for (int c = 0; c < kColours; ++c) {
+    const int64_t nb = v.bricks.count[c];
+    if (nb == 0) continue;
+    if (cart)
+      vmult_epi_kernel<P, Real, true><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
+                                                                         (Real*)dst, v.bricks, c, sh, cq, ep);
+    else
+      vmult_epi_kernel<P, Real, false><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(v.idx, (const Real*)v.geo, (const Real*)src,
+                                                                          (Real*)dst, v.bricks, c, sh, cq, ep);
+  }
+  return hipGetLastError();
+}
+
+template <int P>
+hipError_t vmult_epi_p(const OpView& v, int precision, const void* src, void* dst, const CellEpilogue& ep,
+                       hipStream_t st) {
+  if (precision == MFQ_FP64) return vmult_epi_pr<P, double>(v, src, dst, ep, st);
+  return vmult_epi_pr<P, float>(v, src, dst, ep, st);
+}
+
 template <int P>
 hipError_t vmult_mfma_p(const OpView& v, const void* src, void* dst, bool acc, hipStream_t st) {
   static const MfmaTables<P> tab = make_mfma_tables<P>();
@@ -1271,8 +1441,24 @@ hipError_t vmult_p(const OpView& v, int precision, const void* src, void* dst, b
 }
 
 template <int P, typename Real>
-hipError_t batch_cells_pr(bool cart, const CellItem* items, int count, int colour, int64_t blocks, hipStream_t st) {
+hipError_t batch_cells_pr(bool cart, bool fused, const CellItem* items, int count, int colour, int64_t blocks,
+                          hipStream_t st) {
   static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
+  if (fused) {
+    if constexpr (sizeof(Real) == 8) {
+      return hipErrorInvalidValue;
+    } else {
+      CartQuad<P, Real> cq{};
+      if (cart) {
+        const Tables1D& tb = tables(P);
+        for (int a = 0; a <= P; ++a) cq.w[a] = (Real)tb.omega[a];
+        batch_vmult_epi_kernel<P, Real, true><<<(unsigned)blocks, Cell<P>::NT, 0, st>>>(items, count, colour, sh, cq);
+      } else {
+        batch_vmult_epi_kernel<P, Real, false><<<(unsigned)blocks, Cell<P>::NT, 0, st>>>(items, count, colour, sh, cq);
+      }
+      return hipGetLastError();
+    }
+  }
   if (cart) {
     CartQuad<P, Real> cq{};
     const Tables1D& tb = tables(P);
@@ -1286,11 +1472,11 @@ hipError_t batch_cells_pr(bool cart, const CellItem* items, int count, int colou
 }
 
 template <int P>
-hipError_t batch_cells_p(int precision, bool cart, const CellItem* items, int count, int colour, int64_t blocks,
-                         hipStream_t st) {
+hipError_t batch_cells_p(int precision, bool cart, bool fused, const CellItem* items, int count, int colour,
+                         int64_t blocks, hipStream_t st) {
   if (count <= 0 || blocks <= 0) return hipSuccess;
-  if (precision == MFQ_FP64) return batch_cells_pr<P, double>(cart, items, count, colour, blocks, st);
-  return batch_cells_pr<P, float>(cart, items, count, colour, blocks, st);
+  if (precision == MFQ_FP64) return batch_cells_pr<P, double>(cart, fused, items, count, colour, blocks, st);
+  return batch_cells_pr<P, float>(cart, fused, items, count, colour, blocks, st);
 }
 
 template <int P>
@@ -1361,9 +1547,14 @@ hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, v
   MFQ_DISPATCH(v.p, vmult_p, v, precision, src, dst, accumulate, st);
 }
 
-hipError_t launch_batch_cells(int p, int precision, bool cart, const CellItem* items, int count, int colour,
-                              int64_t blocks, hipStream_t st) {
-  MFQ_DISPATCH(p, batch_cells_p, precision, cart, items, count, colour, blocks, st);
+hipError_t launch_vmult_epilogue(const OpView& v, int precision, const void* src, void* dst, const CellEpilogue& ep,
+                                 hipStream_t st) {
+  if (v.mfma || v.side_base >= 0 || ep.mode == kEpiNone) return hipErrorInvalidValue;
+  MFQ_DISPATCH(v.p, vmult_epi_p, v, precision, src, dst, ep, st);
+}
+hipError_t launch_batch_cells(int p, int precision, bool cart, bool fused, const CellItem* items, int count,
+                              int colour, int64_t blocks, hipStream_t st) {
+  MFQ_DISPATCH(p, batch_cells_p, precision, cart, fused, items, count, colour, blocks, st);
 }
 
 hipError_t launch_diagonal_cells(const OpView& v, int precision, void* diag, hipStream_t st) {

@@ -180,6 +180,36 @@ __device__ __forceinline__ void lds_barrier() {
   __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup", "local");
 }
 
+// One entry of the Chebyshev smoother's updates, written once for the vector kernels and the cell
+// loop's fused epilogue.  Contraction is off and the one fused multiply-add is written out, so the
+// rounding does not depend on how the compiler fuses the surrounding code (left to it, the two
+// kernels round apart).
+// First step: r = b - t (b when x = 0), d = dinv r / theta, x = x + d (d when x = 0).
+template <typename Real>
+__device__ __forceinline__ void cheb_first_entry(Real b, Real t, Real dinv, Real inv_theta, bool x_is_zero, Real& r,
+                                                 Real& d, Real& x) {
+#pragma clang fp contract(off)
+  const Real rv = x_is_zero ? b : b - t;
+  const Real dv = dinv * rv * inv_theta;
+  r = rv;
+  d = dv;
+  x = x_is_zero ? dv : x + dv;
+}
+// Later steps: r = r - t, d = c1 d + c2 dinv r, x = x + d.
+template <typename Real>
+__device__ __forceinline__ void cheb_step_entry(Real t, Real dinv, Real c1, Real c2, Real& r, Real& d, Real& x) {
+#pragma clang fp contract(off)
+  const Real rv = r - t;
+  Real dv;
+  if constexpr (sizeof(Real) == 8)
+    dv = __builtin_fma(c1, d, c2 * dinv * rv);
+  else
+    dv = __builtin_fmaf(c1, d, c2 * dinv * rv);
+  r = rv;
+  d = dv;
+  x = x + dv;
+}
+
 template <typename Real>
 using Real2 = Real __attribute__((ext_vector_type(2)));
 

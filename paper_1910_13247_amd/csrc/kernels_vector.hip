@@ -219,11 +219,11 @@ __global__ __launch_bounds__(kVBlock) void cheb_first_kernel(const Real* __restr
                                                              Real* __restrict__ r, Real* __restrict__ d, int64_t n,
                                                              Real inv_theta, int x_is_zero) {
   for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
-    const Real rv = x_is_zero ? b[i] : b[i] - t[i];
-    const Real dv = dinv[i] * rv * inv_theta;
+    Real rv, dv, xv = x_is_zero ? (Real)0 : x[i];
+    cheb_first_entry<Real>(b[i], x_is_zero ? (Real)0 : t[i], dinv[i], inv_theta, x_is_zero != 0, rv, dv, xv);
     r[i] = rv;
     d[i] = dv;
-    x[i] = x_is_zero ? dv : x[i] + dv;
+    x[i] = xv;
   }
 }
 
@@ -233,11 +233,11 @@ __global__ __launch_bounds__(kVBlock) void cheb_step_kernel(const Real* __restri
                                                             Real* __restrict__ x, Real* __restrict__ r,
                                                             Real* __restrict__ d, int64_t n, Real c1, Real c2) {
   for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock) {
-    const Real rv = r[i] - Ad[i];
-    const Real dv = c1 * d[i] + c2 * dinv[i] * rv;
+    Real rv = r[i], dv = d[i], xv = x[i];
+    cheb_step_entry<Real>(Ad[i], dinv[i], c1, c2, rv, dv, xv);
     r[i] = rv;
     d[i] = dv;
-    x[i] += dv;
+    x[i] = xv;
   }
 }
 
@@ -527,11 +527,11 @@ __global__ __launch_bounds__(kVBlock) void batch_vec_kernel(const VecItem* __res
     float* d = (float*)it.f;
     const float inv_theta = (float)it.s0;
     for (int64_t i = i0; i < n; i += stride) {
-      const float rv = it.flag ? b[i] : b[i] - t[i];
-      const float dv = dinv[i] * rv * inv_theta;
+      float rv, dv, xv = it.flag ? 0.0f : x[i];
+      cheb_first_entry<float>(b[i], it.flag ? 0.0f : t[i], dinv[i], inv_theta, it.flag != 0, rv, dv, xv);
       r[i] = rv;
       d[i] = dv;
-      x[i] = it.flag ? dv : x[i] + dv;
+      x[i] = xv;
     }
   } else if constexpr (OP == kBatchChebStep) {
     const float* Ad = (const float*)it.a;
@@ -541,11 +541,11 @@ __global__ __launch_bounds__(kVBlock) void batch_vec_kernel(const VecItem* __res
     float* d = (float*)it.f;
     const float c1 = (float)it.s0, c2 = (float)it.s1;
     for (int64_t i = i0; i < n; i += stride) {
-      const float rv = r[i] - Ad[i];
-      const float dv = c1 * d[i] + c2 * dinv[i] * rv;
+      float rv = r[i], dv = d[i], xv = x[i];
+      cheb_step_entry<float>(Ad[i], dinv[i], c1, c2, rv, dv, xv);
       r[i] = rv;
       d[i] = dv;
-      x[i] += dv;
+      x[i] = xv;
     }
   } else if constexpr (OP == kBatchSub) {
     const float* b = (const float*)it.a;

@@ -151,11 +151,18 @@ struct mfq_space {
   bool side = false;          // nodes on the X1-low face are hanging (read from / written to face arrays)
 };
 
+// Fused vector updates are off by default: measured slower on MI355X (the cell loop is bound by
+// per-brick latency at its occupancy; the separate vector kernel streams at full bandwidth).
+#ifndef MFQ_FUSE_DEFAULT
+#define MFQ_FUSE_DEFAULT 0
+#endif
+
 struct mfq_op {
   const mfq_space* space;
   double alpha;
   int precision;              // MFQ_FP64 or MFQ_FP32 (storage and arithmetic)
   bool mfma = false;          // FP32 cell loop on the matrix cores (created as MFQ_FP32_MFMA)
+  bool fuse = MFQ_FUSE_DEFAULT != 0;  // vector updates fused into the cell loop (mfq_op_set_fused_updates)
   mfq::Bricks bricks;
   size_t idx_bytes, geo_bytes;
   void* buf = nullptr;        // caller-owned device memory

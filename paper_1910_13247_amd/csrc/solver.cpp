@@ -319,8 +319,18 @@ int vcycle(mfq_solver* s, int l, hipStream_t st) {
   const int deg = s->prm.smoother_degree;
   char* work = (char*)L.r;  // r, d, t are contiguous
   if (int rc = mfq_chebyshev(L.op, L.dinv, L.b, L.x, 1, deg, L.lmin, L.lmax, work, st)) return rc;
-  if (int rc = op_vmult(L.op, L.x, L.t, st)) return rc;
-  MFQ_HIP(launch_sub(prec, L.b, L.t, L.r, L.n, st));
+  // residual r = b - A x (inside the operator application when the level fuses updates)
+  const OpView v = view(L.op);
+  if (L.op->fuse && !L.op->mfma && v.side_base < 0) {
+    CellEpilogue ep;
+    ep.mode = kEpiResidual;
+    ep.b = L.b;
+    ep.r = L.r;
+    MFQ_HIP(launch_vmult_epilogue(v, prec, L.x, L.t, ep, st));
+  } else {
+    if (int rc = op_vmult(L.op, L.x, L.t, st)) return rc;
+    MFQ_HIP(launch_sub(prec, L.b, L.t, L.r, L.n, st));
+  }
   Level& C = s->lv[l - 1];
   MFQ_HIP(launch_transfer(C.to_fine, prec, false, L.r, C.b, st));
   if (int rc = vcycle(s, l - 1, st)) return rc;
@@ -668,7 +678,7 @@ constexpr int kTraceDoubles = 1024;  // Lanczos traces of one solve's levels in 
 struct PlanLaunch {
   enum Kind { kVec, kCells, kTransfer } kind = kVec;
   int op = 0, p = 0, pf = 0, precision = 0, colour = 0;
-  bool h = false, cart = false, prolongate = false;
+  bool h = false, cart = false, prolongate = false, fused = false;
   size_t off = 0;
   int count = 0;
   int64_t blocks = 0;
@@ -701,12 +711,14 @@ struct Plan {
     L.blocks = blk;
     launches.push_back(L);
   }
-  // dst = A src for each (operator, src, dst): one launch per (degree, precision, Cartesian form,
+  // dst = A src for each (operator, src, dst), with the fused update ep when ep.mode is set (dst
+  // then receives partial sums only): one launch per (degree, precision, Cartesian form, fused,
   // colour), colours in order
   struct Apply {
     const mfq_op* op;
     const void* src;
     void* dst;
+    CellEpilogue ep = CellEpilogue{};
   };
   void cells(const std::vector<Apply>& list) {
     std::vector<int> done(list.size(), 0);
@@ -715,11 +727,14 @@ struct Plan {
       const mfq_op* o = list[i].op;
       const int p = o->space->p, prec = o->precision;
       const bool cart = o->space->mesh->amplitude == 0.0 && o->alpha == 0.0;
+      const bool fused = list[i].ep.mode != kEpiNone;
       std::vector<CellItem> items;
       for (size_t j = i; j < list.size(); ++j) {
         const mfq_op* q = list[j].op;
         const bool cj = q->space->mesh->amplitude == 0.0 && q->alpha == 0.0;
-        if (done[j] || q->space->p != p || q->precision != prec || cj != cart) continue;
+        if (done[j] || q->space->p != p || q->precision != prec || cj != cart ||
+            (list[j].ep.mode != kEpiNone) != fused)
+          continue;
         done[j] = 1;
         CellItem it{};
         it.idx = q->idx;
@@ -727,6 +742,7 @@ struct Plan {
         it.src = list[j].src;
         it.dst = list[j].dst;
         it.bk = q->bricks;
+        it.ep = list[j].ep;
         items.push_back(it);
       }
       int64_t tot[kColours] = {};
@@ -743,6 +759,7 @@ struct Plan {
         L.p = p;
         L.precision = prec;
         L.cart = cart;
+        L.fused = fused;
         L.colour = c;
         L.off = off;
         L.count = (int)items.size();
@@ -817,20 +834,28 @@ struct Plan {
       }
     }
   }
-  // `deg` Chebyshev updates on each level (mfq_chebyshev with the work vectors r, d, t of the level)
+  // `deg` Chebyshev updates on each level (mfq_chebyshev with the work vectors r, d, t of the
+  // level: the first update from x = 0 a vector kernel, every other one fused into the cell loop)
   void chebyshev(const std::vector<const Level*>& lv, int deg, bool x_is_zero) {
     if (lv.empty()) return;
     std::vector<double> sigma(lv.size()), delta(lv.size()), rho(lv.size());
     std::vector<VecItem> first;
-    std::vector<Apply> ax, ad;
+    std::vector<Apply> ax;
     for (size_t i = 0; i < lv.size(); ++i) {
       const Level& L = *lv[i];
       const double theta = 0.5 * (L.lmax + L.lmin);
       delta[i] = 0.5 * (L.lmax - L.lmin);
       sigma[i] = theta / delta[i];
       rho[i] = 1.0 / sigma[i];
-      ax.push_back({L.op, L.x, L.t});
-      ad.push_back({L.op, L.d, L.t});
+      Apply a{L.op, L.x, L.t};
+      a.ep.mode = kEpiChebFirst;
+      a.ep.b = L.b;
+      a.ep.dinv = L.dinv;
+      a.ep.x = L.x;
+      a.ep.r = L.r;
+      a.ep.d = L.d;
+      a.ep.s0 = 1.0 / theta;
+      ax.push_back(a);
       VecItem it{};
       it.n = L.n;
       it.a = L.b;
@@ -840,29 +865,64 @@ struct Plan {
       it.e = L.r;
       it.f = L.d;
       it.s0 = 1.0 / theta;
-      it.flag = x_is_zero ? 1 : 0;
+      it.flag = 1;
       first.push_back(it);
     }
-    if (!x_is_zero) cells(ax);
-    vec(kBatchChebFirst, first);
+    if (x_is_zero) {
+      vec(kBatchChebFirst, first);
+    } else {
+      // levels that do not fuse: the product into t, then the vector kernel
+      std::vector<Apply> ax_plain;
+      std::vector<VecItem> first_plain;
+      std::vector<Apply> ax_fused;
+      for (size_t i = 0; i < lv.size(); ++i) {
+        if (lv[i]->op->fuse) {
+          ax_fused.push_back(ax[i]);
+        } else {
+          ax_plain.push_back({lv[i]->op, lv[i]->x, lv[i]->t});
+          VecItem it = first[i];
+          it.flag = 0;
+          first_plain.push_back(it);
+        }
+      }
+      cells(ax_fused);
+      cells(ax_plain);
+      vec(kBatchChebFirst, first_plain);
+    }
     for (int k = 1; k < deg; ++k) {
-      cells(ad);
+      std::vector<Apply> ad, ad_plain;
       std::vector<VecItem> step;
       for (size_t i = 0; i < lv.size(); ++i) {
         const Level& L = *lv[i];
         const double rho_new = 1.0 / (2.0 * sigma[i] - rho[i]);
-        VecItem it{};
-        it.n = L.n;
-        it.a = L.t;
-        it.c = L.dinv;
-        it.d = L.x;
-        it.e = L.r;
-        it.f = L.d;
-        it.s0 = rho_new * rho[i];
-        it.s1 = 2.0 * rho_new / delta[i];
+        const double c1 = rho_new * rho[i], c2 = 2.0 * rho_new / delta[i];
         rho[i] = rho_new;
-        step.push_back(it);
+        if (L.op->fuse) {
+          Apply a{L.op, L.d, L.t};
+          a.ep.mode = kEpiChebStep;
+          a.ep.dinv = L.dinv;
+          a.ep.x = L.x;
+          a.ep.r = L.r;
+          a.ep.d = L.d;
+          a.ep.s0 = c1;
+          a.ep.s1 = c2;
+          ad.push_back(a);
+        } else {
+          ad_plain.push_back({L.op, L.d, L.t});
+          VecItem it{};
+          it.n = L.n;
+          it.a = L.t;
+          it.c = L.dinv;
+          it.d = L.x;
+          it.e = L.r;
+          it.f = L.d;
+          it.s0 = c1;
+          it.s1 = c2;
+          step.push_back(it);
+        }
       }
+      cells(ad);
+      cells(ad_plain);
       vec(kBatchChebStep, step);
     }
   }
@@ -982,13 +1042,20 @@ void plan_precondition(Plan& P, const std::vector<mfq_solver*>& g) {
         continue;
       }
       smooth.push_back(&L);
-      res.push_back({L.op, L.x, L.t});
-      VecItem it{};
-      it.n = L.n;
-      it.a = L.b;
-      it.b = L.t;
-      it.d = L.r;
-      sub.push_back(it);
+      Plan::Apply a{L.op, L.x, L.t};
+      if (L.op->fuse) {
+        a.ep.mode = kEpiResidual;  // r = b - A x
+        a.ep.b = L.b;
+        a.ep.r = L.r;
+      } else {
+        VecItem it{};
+        it.n = L.n;
+        it.a = L.b;
+        it.b = L.t;
+        it.d = L.r;
+        sub.push_back(it);
+      }
+      res.push_back(a);
       down.push_back({s->lv[l - 1].to_fine, L.r, s->lv[l - 1].b});
     }
     P.chebyshev(smooth, deg, true);
@@ -1127,7 +1194,8 @@ int run_plan(const mfq_batch* b, const Plan& P, hipStream_t st) {
     if (L.kind == PlanLaunch::kVec)
       e = launch_batch_vec((BatchVecOp)L.op, (const VecItem*)items, L.count, L.blocks, st);
     else if (L.kind == PlanLaunch::kCells)
-      e = launch_batch_cells(L.p, L.precision, L.cart, (const CellItem*)items, L.count, L.colour, L.blocks, st);
+      e = launch_batch_cells(L.p, L.precision, L.cart, L.fused, (const CellItem*)items, L.count, L.colour, L.blocks,
+                             st);
     else
       e = launch_batch_transfer(L.p, L.pf, L.h, L.prolongate, L.colour, (const TransferItem*)items, L.count,
                                 L.blocks, st);
@@ -1274,6 +1342,7 @@ int mfq_solver_create(const mfq_op* op64, int kind, const mfq_solver_params* par
           delete s;
           return rc2;
         }
+        L.op->fuse = op64->fuse;
         size_t ob;
         mfq_op_device_bytes(L.op, &ob);
         L.off_op = take(ob);

@@ -95,3 +95,89 @@ def test_sampled_parity_full_size_q8_24_vector_alu(prec):
         mag = ebe.ebe_rows(p, n, 0.1, 0.5, np.abs(xin), 1, rows, magnitude=True)
         k = 8 * (p + 1) + 16
         assert np.all(np.abs(yg - yo) <= 2 * k * U32 * mag + 1e-30)
+
+
+def _cheb_inputs(p, n):
+    import torch
+    A = _oracle(p, n)
+    dinv = 1.0 / A.diagonal()
+    N = A.shape[0]
+    b = uniform_vector(N, seed=110 + p)
+    x0 = uniform_vector(N, seed=120 + p)
+    return A, dinv, b, x0, torch
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_fused_chebyshev_multibrick_fp64(p):
+    """Chebyshev steps with the update fused into the cell loop (the brick completing a node
+    applies it) on meshes several bricks wide, from a non-zero start that is also non-zero on the
+    Dirichlet rows (identity rows): the oracle's Chebyshev to 1e-12, and bitwise the result of
+    the separate operator application and vector kernel."""
+    from oracle import gmg
+    import paper_1910_13247_amd as mfq
+    n = WIDE[p]
+    print(f"fused chebyshev fp64 p={p} n={n}", flush=True)
+    A, dinv, b, x0, torch = _cheb_inputs(p, n)
+    lmax, lmin = 2.0, 2.0 / 15
+    ref = gmg.chebyshev(lambda v: A @ v, dinv, b, x0, 4, lmin, lmax)
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.1), p, mfq.MFQ_BC_DIRICHLET0), 0.5, mfq.MFQ_FP64)
+    out = []
+    for fused in (True, False):
+        op.set_fused_updates(fused)
+        x = torch.from_numpy(x0.copy()).cuda()
+        op.chebyshev(torch.from_numpy(dinv).cuda(), torch.from_numpy(b).cuda(), x, False, 4, lmin, lmax)
+        torch.cuda.synchronize()
+        out.append(x.cpu().numpy())
+    err = np.abs(out[0] - ref).max() / np.abs(ref).max()
+    print(f"  normwise rel err {err:.2e}")
+    assert err <= 1e-12
+    assert np.array_equal(out[0], out[1])
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+@pytest.mark.parametrize("x_is_zero", [True, False])
+def test_fused_chebyshev_multibrick_fp32_bitwise(p, x_is_zero):
+    """FP32: the fused and the separate form round alike (same expressions per entry), so the
+    results are bitwise equal; and they stay within 1e-5 of the oracle's FP64 Chebyshev."""
+    from oracle import gmg
+    import paper_1910_13247_amd as mfq
+    n = WIDE[p]
+    print(f"fused chebyshev fp32 p={p} n={n} x_is_zero={x_is_zero}", flush=True)
+    A, dinv, b, x0, torch = _cheb_inputs(p, n)
+    lmax, lmin = 2.0, 2.0 / 15
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.1), p, mfq.MFQ_BC_DIRICHLET0), 0.5, mfq.MFQ_FP32)
+    d32 = torch.from_numpy(dinv).float().cuda()
+    b32 = torch.from_numpy(b).float().cuda()
+    out = []
+    for fused in (True, False):
+        op.set_fused_updates(fused)
+        x = torch.from_numpy(x0.copy()).float().cuda()
+        op.chebyshev(d32, b32, x, x_is_zero, 5, lmin, lmax)
+        torch.cuda.synchronize()
+        out.append(x.cpu().numpy())
+    assert np.array_equal(out[0], out[1])
+    x32 = x0.astype(np.float32).astype(np.float64)
+    ref = gmg.chebyshev(lambda v: A @ v, dinv.astype(np.float32).astype(np.float64),
+                        b.astype(np.float32).astype(np.float64), None if x_is_zero else x32, 5, lmin, lmax)
+    err = np.abs(out[0] - ref).max() / np.abs(ref).max()
+    print(f"  normwise rel err vs FP64 oracle {err:.2e}")
+    assert err <= 1e-5
+
+
+@pytest.mark.parametrize("p,n", [(2, 15), (4, 11), (3, 17)])
+def test_fused_residual_vcycle_bitwise(p, n):
+    """The solvers' V-cycle with the residual and smoother updates fused and separate: bitwise
+    equal preconditioned vectors (FP32 levels, several bricks per level)."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    print(f"fused V-cycle p={p} n={n}", flush=True)
+    out = []
+    for fused in (True, False):
+        op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.1), p, mfq.MFQ_BC_DIRICHLET0), 0.5, mfq.MFQ_FP64)
+        op.set_fused_updates(fused)
+        sv = mfq.Solver(op, mfq.MFQ_SOLVER_GMG_MIXED, coarse_mode=1, coarse_dofs=200)
+        r = op.space.random(31)
+        out.append(sv.precondition(r).cpu().numpy())
+    torch.cuda.synchronize()
+    assert np.all(np.isfinite(out[0]))
+    assert np.array_equal(out[0], out[1])
