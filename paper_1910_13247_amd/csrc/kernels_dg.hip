@@ -202,12 +202,34 @@ __device__ __forceinline__ int face_local(int d, int ad, int a1, int a2) {
 // The neighbours' normal lines are read from the caches (they are the same workgroup's or a
 // nearby one's cells); the result is never re-read.  Workgroups are mapped so that each XCD runs
 // a contiguous range of cells, keeping the y and z neighbours in that XCD's L2 more often.
-template <int P>
+// Two forms of the face terms, equal bitwise (same operations in the same order per entry):
+//  direction by direction: per direction each lane forms its node's four face values, and the
+//    two 1D passes of the face mass matrix run one lane per face node (two barriers per
+//    direction); the result is kept in LDS and written by a coalesced pass;
+//  all directions at once (LEAN): the twelve face arrays of a cell are formed together (the
+//    neighbour loads of all three directions in flight at once), the 1D passes run one lane per
+//    row (then column) of an array, a whole 1D contraction each (about half the LDS accesses, two
+//    barriers in all), and each lane writes its x-pencil of the result from registers.
+// Timed per degree and precision on MI355X (ms, direction by direction -> all at once), the
+// faster form is used: FP32 p=3 0.059 -> 0.053, p=4 0.232 -> 0.209, p=5 0.181 -> 0.158,
+// p=6 0.190 -> 0.157, p=8 0.204 -> 0.182 (p=1 0.026 -> 0.030, p=2 and 7 equal); FP64 p=1
+// 0.042 -> 0.041, p=4 0.385 -> 0.367, p=5 0.294 -> 0.277, p=6 0.316 -> 0.289 (p=2 0.086 -> 0.093,
+// p=3 0.093 -> 0.097, p=7 0.240 -> 0.371, p=8 0.447 -> 0.588: more registers and LDS per cell).
+constexpr bool dg_lean_faces(int p, bool fp64) {
+  return fp64 ? (p == 1 || p == 4 || p == 5 || p == 6) : (p == 3 || p == 4 || p == 5 || p == 6 || p == 8);
+}
+
+template <int P, bool LEAN = false>
 struct DgFused {
   static constexpr int N1 = P + 1, T = N1 * N1, NQ = N1 * T, CPW = DgCell<P>::CPW;
-  // per cell: the cell term's three arrays, or the result plus 8 face arrays (the 4 inputs of one
-  // direction's two faces and the 4 outputs of the first 1D pass)
-  static constexpr int PER_CELL = 3 * NQ > NQ + 8 * T ? 3 * NQ : NQ + 8 * T;
+  // per cell: the cell term's three arrays, or
+  //   direction by direction: the result plus 8 face arrays (the 4 inputs of one direction's two
+  //   faces and the 4 outputs of the first 1D pass);
+  //   all at once: region A (12 face arrays, later the second pass's outputs) and region B (the
+  //   first pass's outputs, later two arrays of line contributions)
+  static constexpr int REGB = 12 * T > 2 * NQ ? 12 * T : 2 * NQ;
+  static constexpr int FACE = LEAN ? 12 * T + REGB : NQ + 8 * T;
+  static constexpr int PER_CELL = 3 * NQ > FACE ? 3 * NQ : FACE;
 };
 
 // What the kernel does with its result v = (A src)_i before storing (one pass over the vectors,
@@ -234,7 +256,8 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) MFQ_DG_WAVES void dg_fused_kern
                                                                       int64_t n_cells, Real h, Real sigma,
                                                                       ShapeEO<P, Real> sh, DgTables<P, Real> tb,
                                                                       DgEpilogue<Real> ep) {
-  using F = DgFused<P>;
+  constexpr bool LEAN = dg_lean_faces(P, sizeof(Real) == 8);
+  using F = DgFused<P, LEAN>;
   constexpr int N1 = F::N1, T = F::T, NQ = F::NQ, CPW = F::CPW;
   __shared__ Real lds[CPW * F::PER_CELL];
   const int tid = threadIdx.x;
@@ -253,93 +276,235 @@ __global__ __launch_bounds__(DgCell<P>::THREADS) MFQ_DG_WAVES void dg_fused_kern
   Real y[N1];
   dg_cell_term<P, Real>(src, base, live, lds, lc, e, h, sh, tb.w, y);
   __syncthreads();
-  Real* R = lds + lc * NQ;  // this cell's result, node order (contiguous over the workgroup's cells)
+  if constexpr (LEAN) {
+    // Face terms of all three directions at once.  Lane (e0, e1) is the tangential node of each
+    // direction: it forms the jump and mean normal derivative of both faces from its own and the
+    // neighbours' normal lines (12 face arrays per cell).  The face mass matrix h^2 (M x M) is then
+    // applied to all 12 arrays in two 1D passes whose work items are rows (then columns) of an
+    // array, a 1D contraction each, spread over all lanes; the last pass leaves the results where
+    // the face arrays were.
+    Real* FA = lds + lc * F::PER_CELL;  // region A: face arrays, later the results of both passes
+    const int64_t ijk[3] = {K % n, (K / n) % n, K / ((int64_t)n * n)};
+    const int64_t nn = (int64_t)n * n;
+    const Real ih = (Real)1 / h;
 #pragma unroll
-  for (int a = 0; a < N1; ++a) R[a + N1 * e] = y[a];
-  Real* Fa = lds + CPW * NQ + lc * 4 * T;  // four face arrays of this cell
-  Real* Ga = lds + CPW * NQ + CPW * 4 * T + lc * 4 * T;
-  const int64_t ijk[3] = {K % n, (K / n) % n, K / ((int64_t)n * n)};
-  const int64_t nn = (int64_t)n * n;
-  const Real ih = (Real)1 / h;
-#pragma unroll 1
-  for (int d = 0; d < 3; ++d) {
-    const int64_t stride = d == 0 ? 1 : d == 1 ? n : nn;
-    const bool hasLo = live && ijk[d] > 0, hasHi = live && ijk[d] < n - 1;
-    Real uK[N1], uLo[N1], uHi[N1];
+    for (int d = 0; d < 3; ++d) {
+      const int64_t stride = d == 0 ? 1 : d == 1 ? n : nn;
+      const bool hasLo = live && ijk[d] > 0, hasHi = live && ijk[d] < n - 1;
+      Real uK[N1], uLo[N1], uHi[N1];
 #pragma unroll
-    for (int a = 0; a < N1; ++a) {
-      const int loc = face_local<N1>(d, a, e0, e1);
-      uK[a] = live ? src[base + loc] : (Real)0;
-      uLo[a] = hasLo ? src[base - stride * NQ + loc] : (Real)0;
-      uHi[a] = hasHi ? src[base + stride * NQ + loc] : (Real)0;
+      for (int a = 0; a < N1; ++a) {
+        const int loc = face_local<N1>(d, a, e0, e1);
+        uK[a] = live ? src[base + loc] : (Real)0;
+        uLo[a] = hasLo ? src[base - stride * NQ + loc] : (Real)0;
+        uHi[a] = hasHi ? src[base + stride * NQ + loc] : (Real)0;
+      }
+      Real dK0 = 0, dK1 = 0, dLo = 0, dHi = 0;
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        dK0 = fmad(tb.d0[a], uK[a], dK0);
+        dK1 = fmad(tb.d1[a], uK[a], dK1);
+        dLo = fmad(tb.d1[a], uLo[a], dLo);
+        dHi = fmad(tb.d0[a], uHi[a], dHi);
+      }
+      // lower face (this cell on its upper side) and upper face (this cell on its lower side): jump
+      // and mean normal derivative at the face nodes
+      Real* Fd = FA + 4 * d * T;
+      Fd[e] = uLo[N1 - 1] - uK[0];
+      Fd[T + e] = hasLo ? (Real)0.5 * ih * (dLo + dK0) : ih * dK0;
+      Fd[2 * T + e] = uK[N1 - 1] - uHi[0];
+      Fd[3 * T + e] = hasHi ? (Real)0.5 * ih * (dK1 + dHi) : ih * dK1;
     }
-    Real dK0 = 0, dK1 = 0, dLo = 0, dHi = 0;
-#pragma unroll
-    for (int a = 0; a < N1; ++a) {
-      dK0 = fmad(tb.d0[a], uK[a], dK0);
-      dK1 = fmad(tb.d1[a], uK[a], dK1);
-      dLo = fmad(tb.d1[a], uLo[a], dLo);
-      dHi = fmad(tb.d0[a], uHi[a], dHi);
-    }
-    // lower face (this cell on its upper side) and upper face (this cell on its lower side): jump
-    // and mean normal derivative at the face nodes
-    Fa[e] = uLo[N1 - 1] - uK[0];
-    Fa[T + e] = hasLo ? (Real)0.5 * ih * (dLo + dK0) : ih * dK0;
-    Fa[2 * T + e] = uK[N1 - 1] - uHi[0];
-    Fa[3 * T + e] = hasHi ? (Real)0.5 * ih * (dK1 + dHi) : ih * dK1;
     __syncthreads();
     // The face terms are the face mass matrix h^2 (M x M) applied to sigma [u] - {d_n u} (value
     // part) and to [u] (derivative part); M = S^T diag(w) S is the Gauss rule's 1D mass matrix,
     // so the interpolation to the face points and back collapses into one 1D pass per direction.
-    // First tangential direction: lane (a1 = e0, a2 = e1)
+    // First tangential direction: item (cell, array, row a2) contracts the row into region B.
+    constexpr int ITEMS = CPW * 12 * N1;
+    for (int w = tid; w < ITEMS; w += DgCell<P>::THREADS) {
+      const int wc = w / (12 * N1), rem = w - wc * 12 * N1;
+      const int arr = rem / N1, a2 = rem - arr * N1;
+      const Real* in = lds + wc * F::PER_CELL + arr * T + N1 * a2;
+      Real* out = lds + wc * F::PER_CELL + 12 * T + arr * T + N1 * a2;
+      Real f[N1];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      Real acc = 0;
+      for (int b1 = 0; b1 < N1; ++b1) f[b1] = in[b1];
 #pragma unroll
-      for (int b1 = 0; b1 < N1; ++b1) acc = fmad(tb.M[e0 * N1 + b1], Fa[k * T + b1 + N1 * e1], acc);
-      Ga[k * T + e] = acc;
+      for (int a1 = 0; a1 < N1; ++a1) {
+        Real acc = 0;
+#pragma unroll
+        for (int b1 = 0; b1 < N1; ++b1) acc = fmad(tb.M[a1 * N1 + b1], f[b1], acc);
+        out[a1] = acc;
+      }
     }
     __syncthreads();
-    Real g[4];
+    // second tangential direction: item (cell, array, column a1), back into region A
+    for (int w = tid; w < ITEMS; w += DgCell<P>::THREADS) {
+      const int wc = w / (12 * N1), rem = w - wc * 12 * N1;
+      const int arr = rem / N1, a1 = rem - arr * N1;
+      const Real* in = lds + wc * F::PER_CELL + 12 * T + arr * T + a1;
+      Real* out = lds + wc * F::PER_CELL + arr * T + a1;
+      Real gcol[N1];
 #pragma unroll
-    for (int k = 0; k < 4; ++k) {
-      Real acc = 0;
+      for (int b2 = 0; b2 < N1; ++b2) gcol[b2] = in[N1 * b2];
 #pragma unroll
-      for (int b2 = 0; b2 < N1; ++b2) acc = fmad(tb.M[e1 * N1 + b2], Ga[k * T + e0 + N1 * b2], acc);
-      g[k] = acc;
-    }
-    const Real fLo = hasLo ? (Real)0.5 : (Real)1, fHi = hasHi ? (Real)0.5 : (Real)1;
-    const Real h2 = h * h;
-    const Real VLo = h2 * (sigma * g[0] - g[1]), DLo = -fLo * h * g[0];
-    const Real VHi = h2 * (sigma * g[2] - g[3]), DHi = -fHi * h * g[2];
-    // value part on the face layer, derivative part along the normal line (this lane's own line:
-    // no other lane touches it in this direction)
+      for (int a2 = 0; a2 < N1; ++a2) {
+        Real acc = 0;
 #pragma unroll
-    for (int a = 0; a < N1; ++a) {
-      const int loc = face_local<N1>(d, a, e0, e1);
-      R[loc] += (a == 0 ? -VLo : (Real)0) + (a == N1 - 1 ? VHi : (Real)0) + DLo * tb.d0[a] + DHi * tb.d1[a];
-    }
-  }
-  __syncthreads();
-  // coalesced pass over the workgroup's cells
-  const int64_t limit = (n_cells - cell0) * NQ;
-  const int64_t g0 = cell0 * NQ;
-  if (ep.mode == kStore) {
-    for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
-      if (i < limit) ep.dst[g0 + i] = lds[i];
-  } else if (ep.mode == kChebStep) {
-    for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
-      if (i < limit) {
-        const int64_t gi = g0 + i;
-        const Real rv = ep.r[gi] - lds[i];
-        const Real dv = ep.c1 * src[gi] + ep.c2 * ep.dinv[gi] * rv;
-        ep.r[gi] = rv;
-        ep.dnew[gi] = dv;
-        ep.x[gi] += dv;
+        for (int b2 = 0; b2 < N1; ++b2) acc = fmad(tb.M[a2 * N1 + b2], gcol[b2], acc);
+        out[N1 * a2] = acc;
       }
+    }
+    __syncthreads();
+    // Value part on the face layer, derivative part along the normal line.  Direction 0: the
+    // lane's normal line is the x-pencil of the result it holds in y.  Directions 1 and 2: lines
+    // through other lanes' pencils, written to two arrays in region B (one writer per node) and
+    // added by the pencils' lanes after a barrier, in the order of the directions.
+    Real* R1 = lds + lc * F::PER_CELL + 12 * T;
+    Real* R2 = R1 + NQ;
+    const Real h2 = h * h;
+#pragma unroll
+    for (int d = 0; d < 3; ++d) {
+      const bool hasLo = live && ijk[d] > 0, hasHi = live && ijk[d] < n - 1;
+      const Real* Gd = FA + 4 * d * T;
+      const Real g0 = Gd[e], g1 = Gd[T + e], g2 = Gd[2 * T + e], g3 = Gd[3 * T + e];
+      const Real fLo = hasLo ? (Real)0.5 : (Real)1, fHi = hasHi ? (Real)0.5 : (Real)1;
+      const Real VLo = h2 * (sigma * g0 - g1), DLo = -fLo * h * g0;
+      const Real VHi = h2 * (sigma * g2 - g3), DHi = -fHi * h * g2;
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        const Real c = (a == 0 ? -VLo : (Real)0) + (a == N1 - 1 ? VHi : (Real)0) + DLo * tb.d0[a] + DHi * tb.d1[a];
+        if (d == 0)
+          y[a] += c;
+        else
+          (d == 1 ? R1 : R2)[face_local<N1>(d, a, e0, e1)] = c;
+      }
+    }
+    __syncthreads();
+#pragma unroll
+    for (int a = 0; a < N1; ++a) y[a] += R1[a + N1 * e];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) y[a] += R2[a + N1 * e];
+    if (ep.mode == kStore) {
+      if (!live) return;
+      // this lane's x-pencil of the cell result, N1 consecutive entries
+      const int64_t g0i = base + N1 * e;
+#pragma unroll
+      for (int a = 0; a < N1; ++a) ep.dst[g0i + a] = y[a];
+      return;
+    }
+    // smoother step or residual (several vectors read and written per entry): the result goes
+    // through LDS in node order and a coalesced pass covers the workgroup's cells
+    __syncthreads();
+    Real* Rc = lds + lc * NQ;
+#pragma unroll
+    for (int a = 0; a < N1; ++a) Rc[a + N1 * e] = y[a];
+    __syncthreads();
+    const int64_t limit = (n_cells - cell0) * NQ;
+    const int64_t gb = cell0 * NQ;
+    if (ep.mode == kChebStep) {
+      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
+        if (i < limit) {
+          const int64_t gi = gb + i;
+          const Real rv = ep.r[gi] - lds[i];
+          const Real dv = ep.c1 * src[gi] + ep.c2 * ep.dinv[gi] * rv;
+          ep.r[gi] = rv;
+          ep.dnew[gi] = dv;
+          ep.x[gi] += dv;
+        }
+    } else {
+      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
+        if (i < limit) ep.r[gb + i] = ep.b[gb + i] - lds[i];
+    }
   } else {
-    for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
-      if (i < limit) ep.r[g0 + i] = ep.b[g0 + i] - lds[i];
+    Real* R = lds + lc * NQ;  // this cell's result, node order (contiguous over the workgroup's cells)
+#pragma unroll
+    for (int a = 0; a < N1; ++a) R[a + N1 * e] = y[a];
+    Real* Fa = lds + CPW * NQ + lc * 4 * T;  // four face arrays of this cell
+    Real* Ga = lds + CPW * NQ + CPW * 4 * T + lc * 4 * T;
+    const int64_t ijk[3] = {K % n, (K / n) % n, K / ((int64_t)n * n)};
+    const int64_t nn = (int64_t)n * n;
+    const Real ih = (Real)1 / h;
+#pragma unroll 1
+    for (int d = 0; d < 3; ++d) {
+      const int64_t stride = d == 0 ? 1 : d == 1 ? n : nn;
+      const bool hasLo = live && ijk[d] > 0, hasHi = live && ijk[d] < n - 1;
+      Real uK[N1], uLo[N1], uHi[N1];
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        const int loc = face_local<N1>(d, a, e0, e1);
+        uK[a] = live ? src[base + loc] : (Real)0;
+        uLo[a] = hasLo ? src[base - stride * NQ + loc] : (Real)0;
+        uHi[a] = hasHi ? src[base + stride * NQ + loc] : (Real)0;
+      }
+      Real dK0 = 0, dK1 = 0, dLo = 0, dHi = 0;
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        dK0 = fmad(tb.d0[a], uK[a], dK0);
+        dK1 = fmad(tb.d1[a], uK[a], dK1);
+        dLo = fmad(tb.d1[a], uLo[a], dLo);
+        dHi = fmad(tb.d0[a], uHi[a], dHi);
+      }
+      // lower face (this cell on its upper side) and upper face (this cell on its lower side): jump
+      // and mean normal derivative at the face nodes
+      Fa[e] = uLo[N1 - 1] - uK[0];
+      Fa[T + e] = hasLo ? (Real)0.5 * ih * (dLo + dK0) : ih * dK0;
+      Fa[2 * T + e] = uK[N1 - 1] - uHi[0];
+      Fa[3 * T + e] = hasHi ? (Real)0.5 * ih * (dK1 + dHi) : ih * dK1;
+      __syncthreads();
+      // The face terms are the face mass matrix h^2 (M x M) applied to sigma [u] - {d_n u} (value
+      // part) and to [u] (derivative part); M = S^T diag(w) S is the Gauss rule's 1D mass matrix,
+      // so the interpolation to the face points and back collapses into one 1D pass per direction.
+      // First tangential direction: lane (a1 = e0, a2 = e1)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Real acc = 0;
+#pragma unroll
+        for (int b1 = 0; b1 < N1; ++b1) acc = fmad(tb.M[e0 * N1 + b1], Fa[k * T + b1 + N1 * e1], acc);
+        Ga[k * T + e] = acc;
+      }
+      __syncthreads();
+      Real g[4];
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        Real acc = 0;
+#pragma unroll
+        for (int b2 = 0; b2 < N1; ++b2) acc = fmad(tb.M[e1 * N1 + b2], Ga[k * T + e0 + N1 * b2], acc);
+        g[k] = acc;
+      }
+      const Real fLo = hasLo ? (Real)0.5 : (Real)1, fHi = hasHi ? (Real)0.5 : (Real)1;
+      const Real h2 = h * h;
+      const Real VLo = h2 * (sigma * g[0] - g[1]), DLo = -fLo * h * g[0];
+      const Real VHi = h2 * (sigma * g[2] - g[3]), DHi = -fHi * h * g[2];
+      // value part on the face layer, derivative part along the normal line (this lane's own line:
+      // no other lane touches it in this direction)
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        const int loc = face_local<N1>(d, a, e0, e1);
+        R[loc] += (a == 0 ? -VLo : (Real)0) + (a == N1 - 1 ? VHi : (Real)0) + DLo * tb.d0[a] + DHi * tb.d1[a];
+      }
+    }
+    __syncthreads();
+    // coalesced pass over the workgroup's cells
+    const int64_t limit = (n_cells - cell0) * NQ;
+    const int64_t g0 = cell0 * NQ;
+    if (ep.mode == kStore) {
+      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
+        if (i < limit) ep.dst[g0 + i] = lds[i];
+    } else if (ep.mode == kChebStep) {
+      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
+        if (i < limit) {
+          const int64_t gi = g0 + i;
+          const Real rv = ep.r[gi] - lds[i];
+          const Real dv = ep.c1 * src[gi] + ep.c2 * ep.dinv[gi] * rv;
+          ep.r[gi] = rv;
+          ep.dnew[gi] = dv;
+          ep.x[gi] += dv;
+        }
+    } else {
+      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
+        if (i < limit) ep.r[g0 + i] = ep.b[g0 + i] - lds[i];
+    }
   }
 }
 
