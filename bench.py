@@ -102,12 +102,19 @@ def hierarchy(p, n, limit=4096):
     return lv[::-1]
 
 
-def vcycle_bytes(levels, b, smoother_degree=3, coarse_mode=0, coarse_degree=16, cart=False):
+def geo_saving(p, n, b, cart=False, coef=False):
+    """G bytes an operator application does not read: all 6 values per point on undeformed cells
+    with coefficient 1 (formed in registers), 5 of them with a variable coefficient (only the
+    diagonal a(x_q) h w_q is read)."""
+    return (6 if cart else 5 if coef else 0) * b * n ** 3 * (p + 1) ** 3
+
+
+def vcycle_bytes(levels, b, smoother_degree=3, coarse_mode=0, coarse_degree=16, cart=False, coef=False):
     """Algorithmic bytes of one V-cycle over `levels` (coarsest first) in value size b."""
     N = [(p_ * n_ + 1) ** 3 for p_, n_ in levels]
     k = smoother_degree
-    op = lambda l: algorithmic_bytes(levels[l][0], levels[l][1], b) - (6 * b * levels[l][1] ** 3 *
-                                                                        (levels[l][0] + 1) ** 3 if cart else 0)
+    op = lambda l: algorithmic_bytes(levels[l][0], levels[l][1], b) - geo_saving(levels[l][0], levels[l][1], b,
+                                                                                  cart, coef)
     tot = 0
     for l in range(1, len(levels)):
         streams = 5 + 8 * (k - 1) + 3 + 3 + 7 + 8 * (k - 1)
@@ -121,40 +128,47 @@ def vcycle_bytes(levels, b, smoother_degree=3, coarse_mode=0, coarse_degree=16, 
     return tot
 
 
-def solve_bytes(kind, p, n, iterations, passes, smoother_degree=3, coarse_mode=0, coarse_degree=16, cart=False):
+def solve_bytes(kind, p, n, iterations, passes, smoother_degree=3, coarse_mode=0, coarse_degree=16, cart=False,
+                coef=False):
     """Algorithmic bytes of a whole solve (iterations summed over passes, `passes` residual checks)."""
     N = (p * n + 1) ** 3
-    op64 = algorithmic_bytes(p, n, 8) - (48 * n ** 3 * (p + 1) ** 3 if cart else 0)
+    op64 = algorithmic_bytes(p, n, 8) - geo_saving(p, n, 8, cart, coef)
     check = op64 + 3 * 8 * N
     if kind == "cg_fp64":
         return iterations * (op64 + 11 * 8 * N) + passes * check
     lv = hierarchy(p, n)
     if kind == "gmg_fp64":
-        vc = vcycle_bytes(lv, 8, smoother_degree, coarse_mode, coarse_degree, cart)
+        vc = vcycle_bytes(lv, 8, smoother_degree, coarse_mode, coarse_degree, cart, coef)
         return iterations * (op64 + 13 * 8 * N + vc) + passes * check
-    vc = vcycle_bytes(lv, 4, smoother_degree, coarse_mode, coarse_degree, cart) + 24 * N
+    vc = vcycle_bytes(lv, 4, smoother_degree, coarse_mode, coarse_degree, cart, coef) + 24 * N
     if kind == "gmg_mixed":
         return iterations * (op64 + 13 * 8 * N + vc) + passes * check
     # gmg_mixed_ir: inner CG on the FP32 operator (casts p in and Ap out: 24 B per DoF) with FP64
     # vectors; each pass also adds its correction into x (3 x 8 N)
-    op32 = algorithmic_bytes(p, n, 4) - (24 * n ** 3 * (p + 1) ** 3 if cart else 0)
+    op32 = algorithmic_bytes(p, n, 4) - geo_saving(p, n, 4, cart, coef)
     return iterations * (op32 + 24 * N + 13 * 8 * N + vc) + passes * (check + 3 * 8 * N)
 
 
-def setup_bytes(p, n, smoother_degree=3, coarse_mode=1, lanczos=12):
+def setup_bytes(p, n, smoother_degree=3, coarse_mode=1, lanczos=12, coef=False):
     """Algorithmic bytes of a solver's set-up on the device: index maps and geometry written for the
-    FP64 operator and every FP32 level, each level's diagonal (operator data read, diagonal
+    FP64 operator and every FP32 level (with a variable coefficient on undeformed cells also the
+    diagonal of G, one value per point), each level's diagonal (operator data read, diagonal
     written), and the Lanczos steps (operator + about 10 vector streams each)."""
     lv = hierarchy(p, n)
     tot = 0
     for l, (pl, nl) in enumerate(lv):
         Nl = (pl * nl + 1) ** 3
+        Ql = nl ** 3 * (pl + 1) ** 3
         geo4 = algorithmic_bytes(pl, nl, 4) - 8 * Nl           # idx + G in FP32
         tot += geo4 + geo4 + 4 * Nl                             # written, read back by the diagonal
+        if coef:
+            tot += 6 * 4 * Ql + 4 * Ql                          # G read again, its diagonal written
         if l > 0 or coarse_mode == 1:
-            tot += lanczos * (algorithmic_bytes(pl, nl, 4) + 10 * 4 * Nl)
+            tot += lanczos * (algorithmic_bytes(pl, nl, 4) - geo_saving(pl, nl, 4, coef=coef) + 10 * 4 * Nl)
     N = (p * n + 1) ** 3
     tot += algorithmic_bytes(p, n, 8) - 16 * N                 # FP64 operator's idx + G written
+    if coef:
+        tot += 7 * 8 * n ** 3 * (p + 1) ** 3                    # its G read again, the diagonal written
     return tot
 
 
@@ -623,13 +637,16 @@ def serve_benchmark(n_requests, rate=200.0, seed=0, iters_per_step=2, n_streams=
     st["dofs_total"] = sum((r.degree * r.n + 1) ** 3 for r in reqs)
     st["iterations_mean"] = sum(r.iterations for r in srv.done) / max(len(srv.done), 1)
     st["not_converged"] = sum(1 for r in srv.done if r.status != 0)
-    # aggregate algorithmic traffic: every request's set-up and solve (Cartesian cell loop: the
-    # requests' meshes are undeformed; FP64 operator with its coefficient reads G)
+    # aggregate algorithmic traffic: every request's set-up and solve (the requests' meshes are
+    # undeformed: with a variable coefficient the cell loops read only the diagonal of G, with
+    # coefficient 1 none of it)
     prm = solver_params or {}
     kw = dict(smoother_degree=prm.get("smoother_degree", 3), coarse_mode=prm.get("coarse_mode", 1),
               coarse_degree=prm.get("coarse_degree", 16))
-    tot = sum(solve_bytes("gmg_mixed", r.degree, r.n, r.iterations, 1, **kw) +
-              setup_bytes(r.degree, r.n, kw["smoother_degree"], kw["coarse_mode"]) for r in srv.done)
+    lz = prm.get("lanczos_iters", srv.ex.params.get("lanczos_iters", 12))
+    tot = sum(solve_bytes("gmg_mixed", r.degree, r.n, r.iterations, 1, cart=r.alpha == 0, coef=r.alpha != 0, **kw) +
+              setup_bytes(r.degree, r.n, kw["smoother_degree"], kw["coarse_mode"], lz, coef=r.alpha != 0)
+              for r in srv.done)
     st["algorithmic_bytes"] = tot
     st["aggregate_algorithmic_GBs"] = tot / st["wall_s"] / 1e9
     st["aggregate_frac_of_peak"] = tot / st["wall_s"] / 1e9 / HBM_PEAK_GBS

@@ -129,6 +129,8 @@ int mfq_op_create(const mfq_space* space, double alpha, int precision, mfq_op** 
   const size_t lanes = (size_t)lanes_per_brick(p);
   op->idx_bytes = round_up(nb * (size_t)lattice_per_brick(p) * sizeof(int), 256);
   op->geo_bytes = round_up(nb * (p + 1) * 3 * lanes * 2 * real_size(precision), 256);
+  if (space->mesh->amplitude == 0.0 && alpha != 0.0 && !op->mfma && !space->side)
+    op->coef_bytes = round_up(nb * (p + 1) * lanes * real_size(precision), 256);
   *out = op;
   return MFQ_OK;
 }
@@ -137,7 +139,7 @@ void mfq_op_destroy(mfq_op* op) { delete op; }
 
 int mfq_op_device_bytes(const mfq_op* op, size_t* bytes) {
   if (!op || !bytes) return fail(MFQ_EINVAL, "op or bytes is NULL");
-  *bytes = op->idx_bytes + op->geo_bytes;
+  *bytes = op->idx_bytes + op->geo_bytes + op->coef_bytes;
   return MFQ_OK;
 }
 
@@ -159,15 +161,17 @@ int mfq_op_get_layout(const mfq_op* op, mfq_op_layout* out) {
 int mfq_op_bind(mfq_op* op, void* dev_buf, size_t bytes, void* hip_stream) {
   if (!op) return fail(MFQ_EINVAL, "op is NULL");
   if (!dev_buf || !aligned(dev_buf, 256)) return fail(MFQ_EINVAL, "buffer NULL or not 256-byte aligned");
-  if (bytes < op->idx_bytes + op->geo_bytes)
-    return fail(MFQ_ENOMEM, "buffer of %zu bytes, operator needs %zu", bytes, op->idx_bytes + op->geo_bytes);
+  const size_t need = op->idx_bytes + op->geo_bytes + op->coef_bytes;
+  if (bytes < need) return fail(MFQ_ENOMEM, "buffer of %zu bytes, operator needs %zu", bytes, need);
   hipStream_t st = (hipStream_t)hip_stream;
   op->buf = dev_buf;
   op->idx = (int*)dev_buf;
   op->geo = (char*)dev_buf + op->idx_bytes;
+  op->coef = op->coef_bytes ? (char*)op->geo + op->geo_bytes : nullptr;
   const OpView v = view(op);
   hipError_t e = launch_fill_index(v, op->idx, st);
   if (e == hipSuccess) e = launch_geometry(v, op->precision, op->geo, st);
+  if (e == hipSuccess && op->coef) e = launch_coef_from_geo(v, op->precision, op->geo, op->coef, st);
   if (e != hipSuccess) {
     op->buf = nullptr;
     return fail(MFQ_EHIP, "operator setup launch failed: %s", hipGetErrorString(e));

@@ -55,6 +55,7 @@ struct CellItem {
   void* dst;
   Bricks bk;
   CellEpilogue ep;          // fused launches only
+  const void* coef;         // diagonal of G per point (undeformed mesh, variable coefficient) or null
 };
 
 // one solve's operands of a batched level transfer (coarse cells of one (degree, degree) pair)
@@ -91,10 +92,11 @@ enum BatchVecOp {
 
 // Launchers (items: device array of `count` items, `blocks` = total workgroups).
 hipError_t launch_batch_vec(BatchVecOp op, const VecItem* items, int count, int64_t blocks, hipStream_t st);
-// Cell loop of degree p, precision, for one colour (items' first[colour]); ACC = false.  fused: with
-// the items' epilogues (FP32 only).
-hipError_t launch_batch_cells(int p, int precision, bool cart, bool fused, const CellItem* items, int count,
-                              int colour, int64_t blocks, hipStream_t st);
+// Cell loop of degree p, precision, for one colour (items' first[colour]); ACC = false.  coef: the
+// items' operators read the diagonal of G (CellItem::coef); fused: with the items' epilogues (FP32
+// only, stored G).
+hipError_t launch_batch_cells(int p, int precision, bool cart, bool coef, bool fused, const CellItem* items,
+                              int count, int colour, int64_t blocks, hipStream_t st);
 // Level transfer of degree pair (pc, pf, h_transfer) in FP32: prolongation (one launch) or one
 // colour of the restriction (after the coarse vectors were cleared by kBatchFill).
 hipError_t launch_batch_transfer(int pc, int pf, bool h_transfer, bool prolongate, int colour,

@@ -438,12 +438,13 @@ struct CartQuad {
 
 // One brick (number b of colour `colour`) of the operator application by the workgroup.  HANG: a
 // space with hanging nodes (X1-low face nodes go through the face arrays `sd`).
-template <int P, typename Real, bool ACC, bool CART, bool HANG, bool EPI = false>
+template <int P, typename Real, bool ACC, bool CART, bool HANG, bool EPI = false, bool COEF = false>
 __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const Real* __restrict__ geo,
                                             const Real* __restrict__ src, Real* __restrict__ dst, const Bricks& bk,
                                             int colour, int64_t b, const ShapeEO<P, Real>& sh,
                                             const CartQuad<P, Real>& cq, const Side<Real>& sd,
-                                            const CellEpilogue& ep = CellEpilogue{}) {
+                                            const CellEpilogue& ep = CellEpilogue{},
+                                            const Real* __restrict__ coef = nullptr) {
   using C = Cell<P>;
   constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, NCELL = C::NCELL, NT = C::NT, LX = C::LX, LY = C::LY, NL = C::NL;
   constexpr int BLOCK = NT;                        // threads of the workgroup
@@ -477,7 +478,15 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
   // the wave fetches anyway) and zero them.  A branch around the loads would make the compiler wait
   // for all outstanding loads at the join, G included, before the dependent source gather.
   auto load_g = [&]() {
-    if constexpr (CART) {
+    if constexpr (COEF) {
+      // undeformed cell, variable coefficient: G = c I with c = a(x_q) h w_q, one value per point
+      const Real* cp = coef + ord * (int64_t)(N1 * NT) + (cell_in ? tid : 0);
+#pragma unroll
+      for (int t = 0; t < N1; ++t) {
+        const Real v = __builtin_nontemporal_load(cp + t * NT);
+        g[t][0] = Real2<Real>{cell_in ? v : (Real)0, 0};
+      }
+    } else if constexpr (CART) {
       // G = h w_r w_s w_t I: kept in g[t][0].x (the diagonal), weights selected with compile-time indices
       Real w0 = 0, w1 = 0;
 #pragma unroll
@@ -568,7 +577,7 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
     Real vx[N1], vy[N1], vz[N1];
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
-      if constexpr (CART) {
+      if constexpr (CART || COEF) {
         const Real c = g[t][0].x;
         vx[t] = c * gx[t];
         vy[t] = c * gy[t];
@@ -655,6 +664,15 @@ __global__ __launch_bounds__(Cell<P>::NT) __attribute__((amdgpu_waves_per_eu(HAN
   vmult_brick<P, Real, ACC, CART, HANG>(idx, geo, src, dst, bk, colour, blockIdx.x, sh, cq, sd);
 }
 
+// Undeformed mesh with a variable coefficient: the diagonal of G read per quadrature point.
+template <int P, typename Real, bool ACC>
+__global__ __launch_bounds__(Cell<P>::NT) void vmult_coef_kernel(const int* __restrict__ idx, const Real* __restrict__ coef,
+                                                                 const Real* __restrict__ src, Real* __restrict__ dst,
+                                                                 Bricks bk, int colour, ShapeEO<P, Real> sh) {
+  vmult_brick<P, Real, ACC, false, false, false, true>(idx, nullptr, src, dst, bk, colour, blockIdx.x, sh,
+                                                       CartQuad<P, Real>{}, Side<Real>{}, CellEpilogue{}, coef);
+}
+
 // Operator application with a fused vector update (see scatter_epilogue); dst holds partial sums.
 template <int P, typename Real, bool CART>
 __global__ __launch_bounds__(Cell<P>::NT) void vmult_epi_kernel(const int* __restrict__ idx, const Real* __restrict__ geo,
@@ -682,6 +700,22 @@ __global__ __launch_bounds__(Cell<P>::NT) void batch_vmult_kernel(const CellItem
   if constexpr (CART) cqi.h = (Real)(1.0 / it.bk.n);
   vmult_brick<P, Real, false, CART, false>(it.idx, (const Real*)it.geo, (const Real*)it.src, (Real*)it.dst, it.bk,
                                           colour, b - it.first[colour], sh, cqi, Side<Real>{});
+}
+
+// Batched form for operators with the coefficient diagonal (CellItem::coef).
+template <int P, typename Real>
+__global__ __launch_bounds__(Cell<P>::NT) void batch_vmult_coef_kernel(const CellItem* __restrict__ items, int count,
+                                                                        int colour, ShapeEO<P, Real> sh) {
+  int lo = 0, hi = count - 1;
+  const int64_t b = blockIdx.x;
+  while (lo < hi) {
+    const int mid = (lo + hi + 1) >> 1;
+    if (items[mid].first[colour] <= b) lo = mid; else hi = mid - 1;
+  }
+  const CellItem& it = items[lo];
+  vmult_brick<P, Real, false, false, false, false, true>(it.idx, nullptr, (const Real*)it.src, (Real*)it.dst, it.bk,
+                                                        colour, b - it.first[colour], sh, CartQuad<P, Real>{},
+                                                        Side<Real>{}, CellEpilogue{}, (const Real*)it.coef);
 }
 
 // Batched form with each item's fused vector update.
@@ -1368,6 +1402,19 @@ hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipSt
     }
     return hipGetLastError();
   }
+  if (v.coef) {
+    for (int c = 0; c < kColours; ++c) {
+      const int64_t nb = v.bricks.count[c];
+      if (nb == 0) continue;
+      if (acc)
+        vmult_coef_kernel<P, Real, true><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(
+            v.idx, (const Real*)v.coef, (const Real*)src, (Real*)dst, v.bricks, c, sh);
+      else
+        vmult_coef_kernel<P, Real, false><<<(unsigned)nb, Cell<P>::NT, 0, st>>>(
+            v.idx, (const Real*)v.coef, (const Real*)src, (Real*)dst, v.bricks, c, sh);
+    }
+    return hipGetLastError();
+  }
   for (int c = 0; c < kColours; ++c) {
     const int64_t nb = v.bricks.count[c];
     if (nb == 0) continue;
@@ -1441,9 +1488,13 @@ hipError_t vmult_p(const OpView& v, int precision, const void* src, void* dst, b
 }
 
 template <int P, typename Real>
-hipError_t batch_cells_pr(bool cart, bool fused, const CellItem* items, int count, int colour, int64_t blocks,
-                          hipStream_t st) {
+hipError_t batch_cells_pr(bool cart, bool coef, bool fused, const CellItem* items, int count, int colour,
+                          int64_t blocks, hipStream_t st) {
   static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
+  if (coef && !fused) {
+    batch_vmult_coef_kernel<P, Real><<<(unsigned)blocks, Cell<P>::NT, 0, st>>>(items, count, colour, sh);
+    return hipGetLastError();
+  }
   if (fused) {
     if constexpr (sizeof(Real) == 8) {
       return hipErrorInvalidValue;
@@ -1472,11 +1523,11 @@ hipError_t batch_cells_pr(bool cart, bool fused, const CellItem* items, int coun
 }
 
 template <int P>
-hipError_t batch_cells_p(int precision, bool cart, bool fused, const CellItem* items, int count, int colour,
-                         int64_t blocks, hipStream_t st) {
+hipError_t batch_cells_p(int precision, bool cart, bool coef, bool fused, const CellItem* items, int count,
+                         int colour, int64_t blocks, hipStream_t st) {
   if (count <= 0 || blocks <= 0) return hipSuccess;
-  if (precision == MFQ_FP64) return batch_cells_pr<P, double>(cart, fused, items, count, colour, blocks, st);
-  return batch_cells_pr<P, float>(cart, fused, items, count, colour, blocks, st);
+  if (precision == MFQ_FP64) return batch_cells_pr<P, double>(cart, coef, fused, items, count, colour, blocks, st);
+  return batch_cells_pr<P, float>(cart, coef, fused, items, count, colour, blocks, st);
 }
 
 template <int P>
@@ -1552,9 +1603,34 @@ hipError_t launch_vmult_epilogue(const OpView& v, int precision, const void* src
   if (v.mfma || v.side_base >= 0 || ep.mode == kEpiNone) return hipErrorInvalidValue;
   MFQ_DISPATCH(v.p, vmult_epi_p, v, precision, src, dst, ep, st);
 }
-hipError_t launch_batch_cells(int p, int precision, bool cart, bool fused, const CellItem* items, int count,
-                              int colour, int64_t blocks, hipStream_t st) {
-  MFQ_DISPATCH(p, batch_cells_p, precision, cart, fused, items, count, colour, blocks, st);
+hipError_t launch_batch_cells(int p, int precision, bool cart, bool coef, bool fused, const CellItem* items,
+                              int count, int colour, int64_t blocks, hipStream_t st) {
+  MFQ_DISPATCH(p, batch_cells_p, precision, cart, coef, fused, items, count, colour, blocks, st);
+}
+
+// coef[brick][t][lane] = diagonal G_xx of the stored G (layout [brick][t][3 pairs][lane], pair 0 =
+// (xx, xy)) for operators on undeformed meshes with a variable coefficient
+template <typename Real>
+__global__ __launch_bounds__(kBlock) void coef_from_geo_kernel(const Real2<Real>* __restrict__ geo, Real* __restrict__ coef,
+                                                               int64_t total, int n1, int nt) {
+  for (int64_t i = blockIdx.x * (int64_t)kBlock + threadIdx.x; i < total; i += (int64_t)gridDim.x * kBlock) {
+    const int64_t per = (int64_t)n1 * nt;
+    const int64_t ord = i / per, rem = i - ord * per;
+    const int t = (int)(rem / nt), lane = (int)(rem - (int64_t)t * nt);
+    coef[i] = geo[ord * 3 * per + (int64_t)(t * 3) * nt + lane].x;
+  }
+}
+
+hipError_t launch_coef_from_geo(const OpView& v, int precision, const void* geo, void* coef, hipStream_t st) {
+  const int n1 = v.p + 1, nt = lanes_per_brick(v.p);
+  const int64_t total = v.bricks.n_bricks * n1 * (int64_t)nt;
+  const int64_t g64 = (total + kBlock - 1) / kBlock;
+  const unsigned g = (unsigned)(g64 < 8192 ? (g64 > 0 ? g64 : 1) : 8192);
+  if (precision == MFQ_FP64)
+    coef_from_geo_kernel<double><<<g, kBlock, 0, st>>>((const Real2<double>*)geo, (double*)coef, total, n1, nt);
+  else
+    coef_from_geo_kernel<float><<<g, kBlock, 0, st>>>((const Real2<float>*)geo, (float*)coef, total, n1, nt);
+  return hipGetLastError();
 }
 
 hipError_t launch_diagonal_cells(const OpView& v, int precision, void* diag, hipStream_t st) {

@@ -169,6 +169,10 @@ struct mfq_op {
   int* idx = nullptr;         // [n_bricks][lattice]: global node of each brick-lattice node,
                               // ~g on Dirichlet nodes, INT_MIN outside the mesh
   void* geo = nullptr;        // [n_bricks][p+1][3][lanes][2] of the precision's type
+  // undeformed mesh with a variable coefficient: G_q = a(x_q) h w_q I, so the cell loop reads
+  // only its diagonal, kept once more as [n_bricks][p+1][lanes] (the other kernels read geo)
+  size_t coef_bytes = 0;
+  void* coef = nullptr;
 };
 
 struct mfq_csr {
@@ -219,12 +223,14 @@ struct OpView {
                               // side_in[g - side_base] and written to side_out[g - side_base]
   const void* side_in;        // set by the caller of a cell loop on a space with hanging nodes
   void* side_out;
+  const void* coef;           // diagonal of G per quadrature point (undeformed mesh, variable coefficient) or null
 };
 inline OpView view(const mfq_op* op) {
   const mfq_space* s = op->space;
   const int faces = s->bc_faces >= 0 ? s->bc_faces : (s->bc ? 0b111111 : 0);
   return OpView{s->p, s->mesh->n, s->bc, s->n_cells, s->n_dofs, s->mesh->amplitude, op->alpha, op->bricks,
-                op->idx, op->geo, op->mfma, s->mesh->x0, faces, s->side ? (int)s->n_dofs : -1, nullptr, nullptr};
+                op->idx, op->geo, op->mfma, s->mesh->x0, faces, s->side ? (int)s->n_dofs : -1, nullptr, nullptr,
+                op->coef};
 }
 
 // precision of a vector argument: MFQ_FP32_MFMA means float; -1 if unknown
@@ -238,6 +244,7 @@ hipError_t launch_fill_index(const OpView& v, int* idx, hipStream_t st);
 hipError_t launch_geometry(const OpView& v, int precision, void* geo, hipStream_t st);
 hipError_t launch_geometry_export(const OpView& v, int precision, double* out, hipStream_t st);
 // dst = A src (accumulate = false: every node written, no clearing needed) or dst += A src.
+hipError_t launch_coef_from_geo(const OpView& v, int precision, const void* geo, void* coef, hipStream_t st);
 hipError_t launch_vmult_cells(const OpView& v, int precision, const void* src, void* dst, bool accumulate,
                               hipStream_t st);
 // diag = diagonal of A (1 on Dirichlet rows); every node written, no clearing needed.

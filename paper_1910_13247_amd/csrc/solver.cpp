@@ -678,7 +678,7 @@ constexpr int kTraceDoubles = 1024;  // Lanczos traces of one solve's levels in 
 struct PlanLaunch {
   enum Kind { kVec, kCells, kTransfer } kind = kVec;
   int op = 0, p = 0, pf = 0, precision = 0, colour = 0;
-  bool h = false, cart = false, prolongate = false, fused = false;
+  bool h = false, cart = false, prolongate = false, fused = false, coef = false;
   size_t off = 0;
   int count = 0;
   int64_t blocks = 0;
@@ -728,12 +728,14 @@ struct Plan {
       const int p = o->space->p, prec = o->precision;
       const bool cart = o->space->mesh->amplitude == 0.0 && o->alpha == 0.0;
       const bool fused = list[i].ep.mode != kEpiNone;
+      const bool coef = o->coef != nullptr && !fused;
       std::vector<CellItem> items;
       for (size_t j = i; j < list.size(); ++j) {
         const mfq_op* q = list[j].op;
         const bool cj = q->space->mesh->amplitude == 0.0 && q->alpha == 0.0;
-        if (done[j] || q->space->p != p || q->precision != prec || cj != cart ||
-            (list[j].ep.mode != kEpiNone) != fused)
+        const bool fj = list[j].ep.mode != kEpiNone;
+        if (done[j] || q->space->p != p || q->precision != prec || cj != cart || fj != fused ||
+            (q->coef != nullptr && !fj) != coef)
           continue;
         done[j] = 1;
         CellItem it{};
@@ -743,6 +745,7 @@ struct Plan {
         it.dst = list[j].dst;
         it.bk = q->bricks;
         it.ep = list[j].ep;
+        it.coef = q->coef;
         items.push_back(it);
       }
       int64_t tot[kColours] = {};
@@ -760,6 +763,7 @@ struct Plan {
         L.precision = prec;
         L.cart = cart;
         L.fused = fused;
+        L.coef = coef;
         L.colour = c;
         L.off = off;
         L.count = (int)items.size();
@@ -1194,8 +1198,8 @@ int run_plan(const mfq_batch* b, const Plan& P, hipStream_t st) {
     if (L.kind == PlanLaunch::kVec)
       e = launch_batch_vec((BatchVecOp)L.op, (const VecItem*)items, L.count, L.blocks, st);
     else if (L.kind == PlanLaunch::kCells)
-      e = launch_batch_cells(L.p, L.precision, L.cart, L.fused, (const CellItem*)items, L.count, L.colour, L.blocks,
-                             st);
+      e = launch_batch_cells(L.p, L.precision, L.cart, L.coef, L.fused, (const CellItem*)items, L.count, L.colour,
+                             L.blocks, st);
     else
       e = launch_batch_transfer(L.p, L.pf, L.h, L.prolongate, L.colour, (const TransferItem*)items, L.count,
                                 L.blocks, st);

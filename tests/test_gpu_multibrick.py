@@ -181,3 +181,47 @@ def test_fused_residual_vcycle_bitwise(p, n):
     torch.cuda.synchronize()
     assert np.all(np.isfinite(out[0]))
     assert np.array_equal(out[0], out[1])
+
+
+@functools.lru_cache(maxsize=2)
+def _oracle_undeformed(p, n):
+    return assemble.operator_csr(p, n, 0.0, 0.5, 1)
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_undeformed_variable_coefficient_fp64(p):
+    """Undeformed mesh with the variable coefficient: the cell loop reads only the diagonal of
+    G_q = a(x_q) h w_q I (one value per quadrature point); vmult and vmult_add against the
+    oracle's assembled matrix to 1e-12 on meshes several bricks wide."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    n = WIDE[p]
+    print(f"undeformed variable coefficient fp64 p={p} n={n}", flush=True)
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.0), p, mfq.MFQ_BC_DIRICHLET0), 0.5, mfq.MFQ_FP64)
+    x = uniform_vector(op.n_dofs, seed=130 + p)
+    y0 = uniform_vector(op.n_dofs, seed=140 + p)
+    xt = torch.from_numpy(x).cuda()
+    y = op.vmult(xt)
+    ya = op.vmult_add(xt, torch.from_numpy(y0).cuda())
+    torch.cuda.synchronize()
+    yo = _oracle_undeformed(p, n) @ x
+    err = np.abs(y.cpu().numpy() - yo).max() / np.abs(yo).max()
+    erra = np.abs(ya.cpu().numpy() - (yo + y0)).max() / np.abs(yo + y0).max()
+    print(f"  normwise rel err {err:.2e}, accumulate {erra:.2e}")
+    assert err <= 1e-12 and erra <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 3, 4, 6, 8])
+def test_undeformed_variable_coefficient_fp32(p):
+    import torch
+    import paper_1910_13247_amd as mfq
+    n = WIDE[p]
+    print(f"undeformed variable coefficient fp32 p={p} n={n}", flush=True)
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.0), p, mfq.MFQ_BC_DIRICHLET0), 0.5, mfq.MFQ_FP32)
+    x32 = uniform_vector(op.n_dofs, seed=150 + p).astype(np.float32).astype(np.float64)
+    y = op.vmult(torch.from_numpy(x32).float().cuda())
+    torch.cuda.synchronize()
+    yo = _oracle_undeformed(p, n) @ x32
+    mag = ebe.magnitude_bound(p, n, 0.0, 0.5, x32, 1)
+    k = 8 * (p + 1) + 16
+    assert np.all(np.abs(y.double().cpu().numpy() - yo) <= 2 * k * U32 * mag + 1e-30)
