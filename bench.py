@@ -749,7 +749,7 @@ def main():
                    "input": "uniform[-1,1) seed 0, resident in HBM"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": measured_traffic(),
-                     "kernel": "vmult_kernel<4, double, false, false> (cell loop)", "launches_per_step": launches,
+                     "kernel": "vmult_kernel<4, double, false, false, false> (cell loop)", "launches_per_step": launches,
                      "launch_ms": launch_s * 1e3, "algorithmic_bytes_per_launch": per_launch64,
                      "layout": lay, "kernel_source": kernel_source_hash(),
                      "algorithmic_tflops": algorithmic_flops(p, n) / kern64 / 1e12},
