@@ -4,10 +4,12 @@
 // hierarchy may also switch to a lower degree on the same mesh (as the paper's Sec. 6.1
 // hierarchy switches spaces).  Prolongation evaluates the coarse function at the fine nodes
 // inside each coarse cell: a tensor product of one 1D matrix P1 [nf1 x (pc+1)] applied in x, y
-// and z.  Nodes on coarse-cell faces are written by every adjacent coarse cell with bitwise
-// equal values (the 1D matrix is exactly the identity there), so plain stores suffice.
+// and z.  Nodes on coarse-cell faces get bitwise equal values from every adjacent coarse cell
+// (the 1D matrix is exactly the identity there); each is stored once, by the cell on its upper
+// side (the mesh's last cell also stores its upper face), with plain stores.
 // Restriction is the transpose: fine values are weighted by 1 / (number of coarse cells
-// containing the node) so the per-cell transposes sum to P^T.  Coarse cells are coloured by the
+// containing the node) so the per-cell transposes sum to P^T; each cell stages its block of fine
+// values in LDS once (one global read per value) before the three 1D passes.  Coarse cells are coloured by the
 // parities of their coordinates (cells of one colour share no coarse node); one launch per
 // colour, colours in order, each cell adding its sums into its coarse nodes with plain stores:
 // no atomics, a fixed summation order, bitwise reproducible.
@@ -60,8 +62,12 @@ __device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse,
     t2[k] = s;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < NF1 * NF1 * NF1; k += kTBlock) {
-    const int i = k % NF1, j = (k / NF1) % NF1, l = k / (NF1 * NF1);
+  // each fine node written once: a cell writes the fine nodes of its lower faces and interior,
+  // the mesh's last cell in a direction also its upper face (the other cells' values there are
+  // bitwise equal, so the choice of writer does not change the result)
+  const int ni = ic == nc - 1 ? NF1 : NF1 - 1, nj = jc == nc - 1 ? NF1 : NF1 - 1, nl = kc == nc - 1 ? NF1 : NF1 - 1;
+  for (int k = threadIdx.x; k < ni * nj * nl; k += kTBlock) {
+    const int i = k % ni, j = (k / ni) % nj, l = k / (ni * nj);
     Real s = 0;
 #pragma unroll
     for (int c = 0; c < M; ++c) s += (Real)tr.P[l * M + c] * t2[i + NF1 * (j + NF1 * c)];
@@ -82,6 +88,7 @@ template <int PC, int NF1, typename Real>
 __device__ __forceinline__ void restrict_cell(const Real* __restrict__ fine, Real* __restrict__ coarse, int nc, int bc,
                                               int colour, const Transfer1D<PC, NF1>& tr, int64_t b) {
   constexpr int M = PC + 1;
+  __shared__ Real f[NF1 * NF1 * NF1]; // the cell's fine nodes, zero on Dirichlet nodes
   __shared__ Real t1[M * NF1 * NF1];  // t1[a][j][l]
   __shared__ Real t2[M * M * NF1];    // t2[a][b][l]
   // cell (ic, jc, kc) of colour (ic & 1) + 2 (jc & 1) + 4 (kc & 1), x fastest within the colour
@@ -94,17 +101,19 @@ __device__ __forceinline__ void restrict_cell(const Real* __restrict__ fine, Rea
   auto shared_factor = [&](int i, int icell) -> Real {
     return ((i == 0 && icell > 0) || (i == NF1 - 1 && icell < nc - 1)) ? (Real)0.5 : (Real)1;
   };
+  // the fine block once into LDS (rows along x coalesced), then the three 1D passes from LDS
+  for (int k = threadIdx.x; k < NF1 * NF1 * NF1; k += kTBlock) {
+    const int i = k % NF1, j = (k / NF1) % NF1, l = k / (NF1 * NF1);
+    const int64_t I = (int64_t)stride * ic + i, J = (int64_t)stride * jc + j, K = (int64_t)stride * kc + l;
+    const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1f - 1 || J == N1f - 1 || K == N1f - 1);
+    f[k] = bnd ? (Real)0 : fine[I + N1f * (J + N1f * K)];
+  }
+  __syncthreads();
   for (int k = threadIdx.x; k < M * NF1 * NF1; k += kTBlock) {
     const int a = k % M, j = (k / M) % NF1, l = k / (M * NF1);
-    const int64_t J = (int64_t)stride * jc + j, K = (int64_t)stride * kc + l;
     const Real wjl = shared_factor(j, jc) * shared_factor(l, kc);
     Real s = 0;
-    for (int i = 0; i < NF1; ++i) {
-      const int64_t I = (int64_t)stride * ic + i;
-      const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1f - 1 || J == N1f - 1 || K == N1f - 1);
-      const Real v = bnd ? (Real)0 : fine[I + N1f * (J + N1f * K)];
-      s += (Real)tr.P[i * M + a] * shared_factor(i, ic) * v;
-    }
+    for (int i = 0; i < NF1; ++i) s += (Real)tr.P[i * M + a] * shared_factor(i, ic) * f[i + NF1 * (j + NF1 * l)];
     t1[k] = s * wjl;
   }
   __syncthreads();
