@@ -69,7 +69,7 @@ struct TransferItem {
 
 enum BatchVecOp {
   kBatchCgAlpha = 0,  // a = p, b = Ap
-  kBatchCgUpdate,     // d = x, e = r, a = p, b = Ap (preconditioned form)
+  kBatchCgUpdate,     // d = x, e = r, a = p, b = Ap (preconditioned form); f = r rounded to FP32 (optional)
   kBatchCgBeta,       // a = r, b = z
   kBatchCgDirection,  // a = z, d = p, flag = first
   kBatchCast64To32,   // a = in (double), d = out (float)
@@ -88,6 +88,8 @@ enum BatchVecOp {
   kBatchLzDirection,  // a = z, d = p (float)
   kBatchAdd64,        // d = x, a = c (double)
   kBatchResidualNorm, // a = b, b = t, d = r, e = out (double*): r = b - t, *out = r.r (double)
+  kBatchCgBeta32,     // a = r (double), b = z (float)
+  kBatchCgDirection32,// a = z (float), d = p (double), flag = first
 };
 
 // Launchers (items: device array of `count` items, `blocks` = total workgroups).
@@ -105,6 +107,13 @@ hipError_t launch_batch_transfer(int pc, int pf, bool h_transfer, bool prolongat
 // nodes); dst receives partial sums of shared nodes only.
 hipError_t launch_vmult_epilogue(const OpView& v, int precision, const void* src, void* dst, const CellEpilogue& ep,
                                  hipStream_t st);
+// CG steps whose preconditioner is the FP32 V-cycle: the update also writes the residual in FP32
+// (the V-cycle's right-hand side), and r.z and the new direction read the V-cycle's FP32 result
+// directly (widened on the fly: the values of its FP64 copy, which is never stored).
+hipError_t launch_cg_update_cast(double* x, double* r, const double* p, const double* Ap, float* r32, int64_t n,
+                                 SolverState* s, hipStream_t st);
+hipError_t launch_cg_beta32(const double* r, const float* z, int64_t n, SolverState* s, hipStream_t st);
+hipError_t launch_cg_direction32(const float* z, double* p, int64_t n, SolverState* s, bool first, hipStream_t st);
 // Workgroups of the single-solve launches the batched ones reproduce.
 int vec_blocks(BatchVecOp op, int64_t n);
 

@@ -7,6 +7,8 @@
 // (deterministic: partial sums per workgroup, then a fixed-order tree over the partials), so the
 // host never waits inside an iteration.  Convergence is decided on the device; the host polls a
 // flag every few iterations.
+#include <type_traits>
+
 #include "batch.hpp"
 #include "kernels_common.hpp"
 #include "solver_state.hpp"
@@ -130,10 +132,12 @@ __global__ __launch_bounds__(kVBlock) void cg_alpha_kernel(const double* __restr
 }
 
 // x += alpha p ; r -= alpha Ap ; rr = r.r ; convergence test rr <= tol2 * bb.
-// Unpreconditioned (z = r): also beta = rr_new / rr_old, rz = rr_new.
+// Unpreconditioned (z = r): also beta = rr_new / rr_old, rz = rr_new.  r32 (optional): the new
+// residual rounded to FP32 as well, the right-hand side of an FP32 V-cycle.
 __global__ __launch_bounds__(kVBlock) void cg_update_kernel(double* __restrict__ x, double* __restrict__ r,
                                                             const double* __restrict__ p, const double* __restrict__ Ap,
-                                                            int64_t n, SolverState* st, int unpreconditioned) {
+                                                            int64_t n, SolverState* st, int unpreconditioned,
+                                                            float* __restrict__ r32) {
   __shared__ double sh[kVBlock / 64];
   if (st->done) return;
   const double alpha = st->alpha;
@@ -142,6 +146,7 @@ __global__ __launch_bounds__(kVBlock) void cg_update_kernel(double* __restrict__
     x[i] += alpha * p[i];
     const double v = r[i] - alpha * Ap[i];
     r[i] = v;
+    if (r32) r32[i] = (float)v;
     part += v * v;
   }
   part = block_sum(part, sh);
@@ -163,14 +168,16 @@ __global__ __launch_bounds__(kVBlock) void cg_update_kernel(double* __restrict__
   }
 }
 
-// rz_new = r.z ; beta = rz_new / rz
-__global__ __launch_bounds__(kVBlock) void cg_beta_kernel(const double* __restrict__ r, const double* __restrict__ z,
+// rz_new = r.z ; beta = rz_new / rz (z in FP64, or the FP32 V-cycle's result widened on the fly:
+// the same values as its FP64 copy)
+template <typename ZT>
+__global__ __launch_bounds__(kVBlock) void cg_beta_kernel(const double* __restrict__ r, const ZT* __restrict__ z,
                                                           int64_t n, SolverState* st) {
   __shared__ double sh[kVBlock / 64];
   if (st->done) return;
   double part = 0;
   for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
-    part += r[i] * z[i];
+    part += r[i] * (double)z[i];
   part = block_sum(part, sh);
   double tot;
   if (grid_reduce(part, st->partials, &st->counter, tot, sh) && threadIdx.x == 0) {
@@ -180,12 +187,13 @@ __global__ __launch_bounds__(kVBlock) void cg_beta_kernel(const double* __restri
 }
 
 // p = z + beta p; the first direction is p = z, without reading p (which holds no value yet)
-__global__ __launch_bounds__(kVBlock) void cg_direction_kernel(const double* __restrict__ z, double* __restrict__ p,
+template <typename ZT>
+__global__ __launch_bounds__(kVBlock) void cg_direction_kernel(const ZT* __restrict__ z, double* __restrict__ p,
                                                                int64_t n, SolverState* st, int first) {
   if (st->done) return;
   const double beta = st->beta;
   for (int64_t i = blockIdx.x * (int64_t)kVBlock + threadIdx.x; i < n; i += (int64_t)gridDim.x * kVBlock)
-    p[i] = first ? z[i] : z[i] + beta * p[i];
+    p[i] = first ? (double)z[i] : (double)z[i] + beta * p[i];
 }
 
 // r = b - t (true residual), rr = r.r ; used by iterative refinement and final certificates.
@@ -473,10 +481,12 @@ __global__ __launch_bounds__(kVBlock) void batch_vec_kernel(const VecItem* __res
     const double* Ap = (const double*)it.b;
     const double alpha = st->alpha;
     double part = 0;
+    float* r32 = (float*)it.f;
     for (int64_t i = i0; i < n; i += stride) {
       x[i] += alpha * p[i];
       const double v = r[i] - alpha * Ap[i];
       r[i] = v;
+      if (r32) r32[i] = (float)v;
       part += v * v;
     }
     part = block_sum(part, sh);
@@ -492,24 +502,26 @@ __global__ __launch_bounds__(kVBlock) void batch_vec_kernel(const VecItem* __res
         st->converged_iter = st->iter;
       }
     }
-  } else if constexpr (OP == kBatchCgBeta) {
+  } else if constexpr (OP == kBatchCgBeta || OP == kBatchCgBeta32) {
     if (st->done) return;
+    using ZT = std::conditional_t<OP == kBatchCgBeta32, float, double>;
     const double* r = (const double*)it.a;
-    const double* z = (const double*)it.b;
+    const ZT* z = (const ZT*)it.b;
     double part = 0;
-    for (int64_t i = i0; i < n; i += stride) part += r[i] * z[i];
+    for (int64_t i = i0; i < n; i += stride) part += r[i] * (double)z[i];
     part = block_sum(part, sh);
     double tot;
     if (item_reduce(part, st, lb, it.nblk, tot, sh) && threadIdx.x == 0) {
       st->beta = (st->rz != 0.0) ? tot / st->rz : 0.0;
       st->rz = tot;
     }
-  } else if constexpr (OP == kBatchCgDirection) {
+  } else if constexpr (OP == kBatchCgDirection || OP == kBatchCgDirection32) {
     if (st->done) return;
-    const double* z = (const double*)it.a;
+    using ZT = std::conditional_t<OP == kBatchCgDirection32, float, double>;
+    const ZT* z = (const ZT*)it.a;
     double* p = (double*)it.d;
     const double beta = st->beta;
-    for (int64_t i = i0; i < n; i += stride) p[i] = it.flag ? z[i] : z[i] + beta * p[i];
+    for (int64_t i = i0; i < n; i += stride) p[i] = it.flag ? (double)z[i] : (double)z[i] + beta * p[i];
   } else if constexpr (OP == kBatchCast64To32) {
     const double* in = (const double*)it.a;
     float* out = (float*)it.d;
@@ -729,15 +741,28 @@ hipError_t launch_cg_alpha(const double* p, const double* Ap, int64_t n, SolverS
 }
 hipError_t launch_cg_update(double* x, double* r, const double* p, const double* Ap, int64_t n, SolverState* s,
                             bool unprec, hipStream_t st) {
-  cg_update_kernel<<<vgrid(n), kVBlock, 0, st>>>(x, r, p, Ap, n, s, unprec ? 1 : 0);
+  cg_update_kernel<<<vgrid(n), kVBlock, 0, st>>>(x, r, p, Ap, n, s, unprec ? 1 : 0, nullptr);
+  return hipGetLastError();
+}
+hipError_t launch_cg_update_cast(double* x, double* r, const double* p, const double* Ap, float* r32, int64_t n,
+                                 SolverState* s, hipStream_t st) {
+  cg_update_kernel<<<vgrid(n), kVBlock, 0, st>>>(x, r, p, Ap, n, s, 0, r32);
   return hipGetLastError();
 }
 hipError_t launch_cg_beta(const double* r, const double* z, int64_t n, SolverState* s, hipStream_t st) {
-  cg_beta_kernel<<<vgrid(n), kVBlock, 0, st>>>(r, z, n, s);
+  cg_beta_kernel<double><<<vgrid(n), kVBlock, 0, st>>>(r, z, n, s);
+  return hipGetLastError();
+}
+hipError_t launch_cg_beta32(const double* r, const float* z, int64_t n, SolverState* s, hipStream_t st) {
+  cg_beta_kernel<float><<<vgrid(n), kVBlock, 0, st>>>(r, z, n, s);
   return hipGetLastError();
 }
 hipError_t launch_cg_direction(const double* z, double* p, int64_t n, SolverState* s, bool first, hipStream_t st) {
-  cg_direction_kernel<<<vgrid(n) * 4, kVBlock, 0, st>>>(z, p, n, s, first ? 1 : 0);
+  cg_direction_kernel<double><<<vgrid(n) * 4, kVBlock, 0, st>>>(z, p, n, s, first ? 1 : 0);
+  return hipGetLastError();
+}
+hipError_t launch_cg_direction32(const float* z, double* p, int64_t n, SolverState* s, bool first, hipStream_t st) {
+  cg_direction_kernel<float><<<vgrid(n) * 4, kVBlock, 0, st>>>(z, p, n, s, first ? 1 : 0);
   return hipGetLastError();
 }
 hipError_t launch_residual_norm(const double* b, const double* t, double* r, int64_t n, SolverState* s, double* out,
@@ -878,6 +903,7 @@ int vec_blocks(BatchVecOp op, int64_t n) {
     case kBatchCgAlpha:
     case kBatchCgUpdate:
     case kBatchCgBeta:
+    case kBatchCgBeta32:
     case kBatchCgStart:
     case kBatchLzInit:
     case kBatchLzAlpha:
@@ -913,6 +939,8 @@ hipError_t launch_batch_vec(BatchVecOp op, const VecItem* items, int count, int6
     case kBatchLzDirection: batch_vec_kernel<kBatchLzDirection><<<g, kVBlock, 0, st>>>(items, count); break;
     case kBatchAdd64: batch_vec_kernel<kBatchAdd64><<<g, kVBlock, 0, st>>>(items, count); break;
     case kBatchResidualNorm: batch_vec_kernel<kBatchResidualNorm><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchCgBeta32: batch_vec_kernel<kBatchCgBeta32><<<g, kVBlock, 0, st>>>(items, count); break;
+    case kBatchCgDirection32: batch_vec_kernel<kBatchCgDirection32><<<g, kVBlock, 0, st>>>(items, count); break;
     default: return hipErrorInvalidValue;
   }
   return hipGetLastError();

@@ -454,12 +454,22 @@ void pass_started(mfq_solver* s, double* sol) {
   R.phase = Run::kInner;
 }
 
+// The FP32 V-cycle preconditions the CG (GMG_MIXED, GMG_MIXED_IR): the CG steps then read its FP32
+// result directly instead of an FP64 copy z (the same values; two vector passes fewer)
+bool vcycle32(const mfq_solver* s) { return preconditioned(s) && s->prec_v == MFQ_FP32 && !s->lv.empty(); }
+
 int pass_start(mfq_solver* s, const double* rhs, double* sol, double tol2) {
   Run& R = s->run;
   const int64_t N = s->op64->space->n_dofs;
   const bool pre = preconditioned(s);
   MFQ_HIP(launch_cg_start(rhs, sol, s->r, s->p, N, s->state, !pre, tol2, R.st));
-  if (pre) {
+  if (vcycle32(s)) {
+    Level& F = s->lv.back();
+    MFQ_HIP(launch_cast(MFQ_FP64, s->r, MFQ_FP32, F.b, F.n, R.st));
+    if (int rc = vcycle(s, (int)s->lv.size() - 1, R.st)) return rc;
+    MFQ_HIP(launch_cg_beta32(s->r, (const float*)F.x, N, s->state, R.st));
+    MFQ_HIP(launch_cg_direction32((const float*)F.x, s->p, N, s->state, true, R.st));
+  } else if (pre) {
     if (int rc = precondition(s, s->r, s->z, R.st)) return rc;
     MFQ_HIP(launch_cg_beta(s->r, s->z, N, s->state, R.st));
     MFQ_HIP(launch_cg_direction(s->z, s->p, N, s->state, true, R.st));
@@ -485,6 +495,14 @@ int pass_iterate_direct(mfq_solver* s, int k) {
   for (int i = 0; i < k; ++i) {
     if (int rc = inner_apply(s, s->p, s->Ap, R.st)) return rc;
     MFQ_HIP(launch_cg_alpha(s->p, s->Ap, N, s->state, R.st));
+    if (vcycle32(s)) {
+      Level& F = s->lv.back();
+      MFQ_HIP(launch_cg_update_cast(R.sol, s->r, s->p, s->Ap, (float*)F.b, N, s->state, R.st));
+      if (int rc = vcycle(s, (int)s->lv.size() - 1, R.st)) return rc;
+      MFQ_HIP(launch_cg_beta32(s->r, (const float*)F.x, N, s->state, R.st));
+      MFQ_HIP(launch_cg_direction32((const float*)F.x, s->p, N, s->state, false, R.st));
+      continue;
+    }
     MFQ_HIP(launch_cg_update(R.sol, s->r, s->p, s->Ap, N, s->state, !pre, R.st));
     if (pre) {
       if (int rc = precondition(s, s->r, s->z, R.st)) return rc;
@@ -1012,23 +1030,9 @@ void plan_lanczos_step(Plan& P, const std::vector<mfq_solver*>& e) {
   P.vec(kBatchLzDirection, dir);
 }
 
-// z = V-cycle(r) for every solve in `g` (precondition): r rounded to the finest FP32 level, the
-// V-cycle level by level from the finest (depth 0 is every solve's finest level), the result
-// widened into z
-void plan_precondition(Plan& P, const std::vector<mfq_solver*>& g) {
-  std::vector<VecItem> to32, to64;
-  for (mfq_solver* s : g) {
-    VecItem c{};
-    c.n = s->op64->space->n_dofs;
-    c.a = s->r;
-    c.d = s->lv.back().b;
-    to32.push_back(c);
-    VecItem c2 = c;
-    c2.a = s->lv.back().x;
-    c2.d = s->z;
-    to64.push_back(c2);
-  }
-  P.vec(kBatchCast64To32, to32);
+// The FP32 V-cycle of every solve in `g` on its finest level's b (level by level from the
+// finest: depth 0 is every solve's finest level), result in the finest level's x
+void plan_vcycle(Plan& P, const std::vector<mfq_solver*>& g) {
   size_t depth = 0;
   for (mfq_solver* s : g) depth = std::max(depth, s->lv.size());
   const int deg = g.front()->prm.smoother_degree, cdeg = g.front()->prm.coarse_degree;
@@ -1089,10 +1093,9 @@ void plan_precondition(Plan& P, const std::vector<mfq_solver*>& g) {
     P.vec(kBatchAdd, add);
     P.chebyshev(smooth, deg, false);
   }
-  P.vec(kBatchCast32To64, to64);
 }
 
-// beta = r.z / rz ; p = z (+ beta p) for every solve in `g`
+// beta = r.z / rz ; p = z (+ beta p) for every solve in `g`, z the V-cycle's FP32 result
 void plan_direction(Plan& P, const std::vector<mfq_solver*>& g, bool first) {
   std::vector<VecItem> beta, dir;
   for (mfq_solver* s : g) {
@@ -1101,16 +1104,16 @@ void plan_direction(Plan& P, const std::vector<mfq_solver*>& g, bool first) {
     it.st = s->state;
     VecItem b = it;
     b.a = s->r;
-    b.b = s->z;
+    b.b = s->lv.back().x;
     beta.push_back(b);
     VecItem d = it;
-    d.a = s->z;
+    d.a = s->lv.back().x;
     d.d = s->p;
     d.flag = first ? 1 : 0;
     dir.push_back(d);
   }
-  P.vec(kBatchCgBeta, beta);
-  P.vec(kBatchCgDirection, dir);
+  P.vec(kBatchCgBeta32, beta);
+  P.vec(kBatchCgDirection32, dir);
 }
 
 // The launches of one CG iteration of every solve in `g` (one step replays them `iters` times).
@@ -1131,12 +1134,13 @@ void plan_iteration(Plan& P, const std::vector<mfq_solver*>& g) {
     u.e = s->r;
     u.a = s->p;
     u.b = s->Ap;
+    u.f = s->lv.back().b;  // the residual in FP32: the V-cycle's right-hand side
     update.push_back(u);
   }
   P.cells(a64);
   P.vec(kBatchCgAlpha, alpha);
   P.vec(kBatchCgUpdate, update);
-  plan_precondition(P, g);
+  plan_vcycle(P, g);
   plan_direction(P, g, false);
 }
 
@@ -1157,7 +1161,16 @@ void plan_start(Plan& P, const std::vector<mfq_solver*>& g) {
     start.push_back(it);
   }
   P.vec(kBatchCgStart, start);
-  plan_precondition(P, g);
+  std::vector<VecItem> to32;
+  for (mfq_solver* s : g) {
+    VecItem c{};
+    c.n = s->op64->space->n_dofs;
+    c.a = s->r;
+    c.d = s->lv.back().b;
+    to32.push_back(c);
+  }
+  P.vec(kBatchCast64To32, to32);
+  plan_vcycle(P, g);
   plan_direction(P, g, true);
 }
 
