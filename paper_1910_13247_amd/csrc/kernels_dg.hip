@@ -9,65 +9,19 @@
 // boundary faces with the outside values zero and the inside value instead of the mean
 // (homogeneous Dirichlet data imposed weakly).
 //
-// One kernel computes everything, cell by cell: CPW consecutive cells per workgroup, one lane per
-// 1D pencil of a cell.  Cell term: the sum factorisation of the continuous operator (even-odd forms
-// of the 1D tables) with the quadrature tensor h w_r w_s w_t I of the affine cube.  Face terms: the
-// cell evaluates all six of its faces itself (an interior face is evaluated by both its cells, each
-// keeping its own half), one lane per tangential node: it reads its own and the neighbour's normal
-// line (the trace is the end node of the GLL line, the normal derivative a dot product with l'_a
-// at the end point), forms jump and mean normal derivative at the face nodes, applies the face
-// rule's tensor-product mass matrix in two 1D passes through LDS, and adds the value part at the
-// face node and the derivative part along the normal line.  A cell's DoFs are contiguous, so the
-// result is written once with coalesced stores; the neighbours' lines come from the caches.
+// One kernel computes the whole operator per cell in tensor-product form (dg_kron_kernel, below):
+// CPW consecutive cells of an x-row per workgroup, one lane per 1D line of a cell; each cell's
+// result is written once.
 #include "kernels_common.hpp"
 
-// Ask for at least 5 waves per SIMD: the register allocation then fits 5 workgroups per CU at
-// p = 4 FP64 (96 instead of 126 VGPRs, no spills at any degree), which the LDS use also allows.
-// Lanes per workgroup that the cells fill (one lane per 1D pencil): 128 up to degree 4 (5 cells of
-// 25 lanes at p = 4; fewer waves wait at each of the kernel's barriers), 256 above (at p >= 6 a
-// 128-lane workgroup holds a single cell).
+// Lanes per workgroup that the cells fill (one lane per 1D line): 128 up to degree 4 (5 cells of
+// 25 lanes at p = 4), 256 above (at p >= 6 a 128-lane workgroup would hold a single cell).
 #ifndef MFQ_DG_LANES
 #define MFQ_DG_LANES(P) ((P) <= 4 ? 128 : 256)
 #endif
 
-#ifndef MFQ_DG_WAVES
-#define MFQ_DG_WAVES __attribute__((amdgpu_waves_per_eu(5, 8)))
-#endif
-
 namespace mfq {
 namespace {
-
-template <int P, typename Real>
-struct DgTables {
-  Real S[(P + 1) * (P + 1)];  // [q*(P+1)+a]: l_a(zeta_q)
-  Real D[(P + 1) * (P + 1)];  // l_a'(zeta_q)
-  Real w[P + 1];              // Gauss weights on [0,1]
-  Real d0[P + 1];             // l_a'(0)
-  Real d1[P + 1];             // l_a'(1)
-  Real M[(P + 1) * (P + 1)];  // 1D mass matrix of the face rule: M[a*(P+1)+b] = sum_q w_q l_a(zeta_q) l_b(zeta_q)
-};
-
-template <int P, typename Real>
-DgTables<P, Real> make_dg_tables() {
-  DgTables<P, Real> t{};
-  const Tables1D& tb = tables(P);
-  for (int k = 0; k < (P + 1) * (P + 1); ++k) {
-    t.S[k] = (Real)tb.S[k];
-    t.D[k] = (Real)tb.D[k];
-  }
-  for (int a = 0; a <= P; ++a) {
-    t.w[a] = (Real)tb.omega[a];
-    t.d0[a] = (Real)lagrange_derivative(tb.xi, a, 0.0);
-    t.d1[a] = (Real)lagrange_derivative(tb.xi, a, 1.0);
-  }
-  for (int a = 0; a <= P; ++a)
-    for (int b = 0; b <= P; ++b) {
-      double m = 0;
-      for (int q = 0; q <= P; ++q) m += tb.omega[q] * tb.S[q * (P + 1) + a] * tb.S[q * (P + 1) + b];
-      t.M[a * (P + 1) + b] = (Real)m;
-    }
-  return t;
-}
 
 template <int P>
 struct DgCell {
@@ -78,159 +32,11 @@ struct DgCell {
   static constexpr int THREADS = CPW * T;
 };
 
-// Cell term of one cell per T lanes: on return, lane e = b + N1 c holds the x-pencil (b, c) of the
-// cell's result in y.  lds holds 3 CPW NQ values (three arrays of CPW cells); ends after its last
-// read of the first two arrays (the caller synchronises before reusing them).
-template <int P, typename Real>
-__device__ __forceinline__ void dg_cell_term(const Real* __restrict__ src, int64_t base, bool live, Real* lds,
-                                             int lc, int e, Real h, const ShapeEO<P, Real>& sh,
-                                             const Real (&wq)[P + 1], Real (&y)[P + 1]) {
-  using C = DgCell<P>;
-  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, CPW = C::CPW;
-  const int e0 = e % N1, e1 = e / N1;
-  Real* L0 = lds + lc * NQ;
-  Real* L1 = L0 + CPW * NQ;
-  Real* L2 = L1 + CPW * NQ;
-  {  // x: values and x-derivatives at (q, e0, e1)
-    Real u[N1], A[N1], B[N1];
-#pragma unroll
-    for (int a = 0; a < N1; ++a) u[a] = live ? src[base + a + N1 * e] : (Real)0;
-    eo_apply<N1, 1, false>(sh.S, u, A);
-    eo_apply<N1, -1, false>(sh.D, u, B);
-#pragma unroll
-    for (int q = 0; q < N1; ++q) {
-      L0[q + N1 * e] = A[q];
-      L1[q + N1 * e] = B[q];
-    }
-  }
-  __syncthreads();
-  {  // y: lane (r = e0, c = e1)
-    Real a1[N1], b1[N1], A2[N1], B2[N1], C2[N1];
-#pragma unroll
-    for (int b = 0; b < N1; ++b) {
-      a1[b] = L0[e0 + N1 * b + T * e1];
-      b1[b] = L1[e0 + N1 * b + T * e1];
-    }
-    eo_apply<N1, 1, false>(sh.S, a1, A2);
-    eo_apply<N1, -1, false>(sh.D, a1, C2);
-    eo_apply<N1, 1, false>(sh.S, b1, B2);
-    __syncthreads();
-#pragma unroll
-    for (int s = 0; s < N1; ++s) {
-      L0[e0 + N1 * s + T * e1] = A2[s];
-      L1[e0 + N1 * s + T * e1] = B2[s];
-      L2[e0 + N1 * s + T * e1] = C2[s];
-    }
-  }
-  __syncthreads();
-  {  // z: lane (r = e0, s = e1): gradient, weight, transposed z contraction
-    Real a2[N1], b2[N1], c2[N1], gx[N1], gy[N1], gz[N1];
-#pragma unroll
-    for (int c = 0; c < N1; ++c) {
-      a2[c] = L0[e + T * c];
-      b2[c] = L1[e + T * c];
-      c2[c] = L2[e + T * c];
-    }
-    eo_apply<N1, 1, false>(sh.S, b2, gx);
-    eo_apply<N1, 1, false>(sh.S, c2, gy);
-    eo_apply<N1, -1, false>(sh.D, a2, gz);
-    Real w0 = 0, w1 = 0;  // weights of this lane's (r, s), selected with compile-time indices
-#pragma unroll
-    for (int k = 0; k < N1; ++k) {
-      w0 = e0 == k ? wq[k] : w0;
-      w1 = e1 == k ? wq[k] : w1;
-    }
-    const Real wrs = h * w0 * w1;
-#pragma unroll
-    for (int t = 0; t < N1; ++t) {
-      const Real w = wrs * wq[t];
-      gx[t] *= w;
-      gy[t] *= w;
-      gz[t] *= w;
-    }
-    Real Az[N1], Bz[N1], Cz[N1];
-    eo_apply<N1, -1, true>(sh.D, gz, Az);
-    eo_apply<N1, 1, true>(sh.S, gx, Bz);
-    eo_apply<N1, 1, true>(sh.S, gy, Cz);
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < N1; ++c) {
-      L0[e + T * c] = Az[c];
-      L1[e + T * c] = Bz[c];
-      L2[e + T * c] = Cz[c];
-    }
-  }
-  __syncthreads();
-  {  // transposed y: lane (r = e0, c = e1)
-    Real az[N1], bz[N1], cz[N1], Ap[N1], Bp[N1];
-#pragma unroll
-    for (int s = 0; s < N1; ++s) {
-      az[s] = L0[e0 + N1 * s + T * e1];
-      bz[s] = L1[e0 + N1 * s + T * e1];
-      cz[s] = L2[e0 + N1 * s + T * e1];
-    }
-    eo_apply_t2<N1>(sh.S, az, sh.D, cz, Ap);
-    eo_apply<N1, 1, true>(sh.S, bz, Bp);
-    __syncthreads();
-#pragma unroll
-    for (int b = 0; b < N1; ++b) {
-      L0[e0 + N1 * b + T * e1] = Ap[b];
-      L1[e0 + N1 * b + T * e1] = Bp[b];
-    }
-  }
-  __syncthreads();
-  {  // transposed x: lane (b = e0, c = e1) forms its x-pencil of the cell result
-    Real ap[N1], bp[N1];
-#pragma unroll
-    for (int r = 0; r < N1; ++r) {
-      ap[r] = L0[r + N1 * e];
-      bp[r] = L1[r + N1 * e];
-    }
-    eo_apply_t2<N1>(sh.S, ap, sh.D, bp, y);
-  }
-}
-
 // local index of node a_d along the normal direction d at tangential node (a1, a2)
 template <int N1>
 __device__ __forceinline__ int face_local(int d, int ad, int a1, int a2) {
   return d == 0 ? ad + N1 * a1 + N1 * N1 * a2 : d == 1 ? a1 + N1 * ad + N1 * N1 * a2 : a1 + N1 * a2 + N1 * N1 * ad;
 }
-
-// Cell-centric form of the whole operator: one workgroup per CPW consecutive cells computes each
-// cell's volume term and all six of its face terms (every interior face is evaluated by both of its
-// cells, each keeping its own half), then writes each cell's result once with coalesced stores.
-// The neighbours' normal lines are read from the caches (they are the same workgroup's or a
-// nearby one's cells); the result is never re-read.  Workgroups are mapped so that each XCD runs
-// a contiguous range of cells, keeping the y and z neighbours in that XCD's L2 more often.
-// Two forms of the face terms, equal bitwise (same operations in the same order per entry):
-//  direction by direction: per direction each lane forms its node's four face values, and the
-//    two 1D passes of the face mass matrix run one lane per face node (two barriers per
-//    direction); the result is kept in LDS and written by a coalesced pass;
-//  all directions at once (LEAN): the twelve face arrays of a cell are formed together (the
-//    neighbour loads of all three directions in flight at once), the 1D passes run one lane per
-//    row (then column) of an array, a whole 1D contraction each (about half the LDS accesses, two
-//    barriers in all), and each lane writes its x-pencil of the result from registers.
-// Timed per degree and precision on MI355X (ms, direction by direction -> all at once), the
-// faster form is used: FP32 p=3 0.059 -> 0.053, p=4 0.232 -> 0.209, p=5 0.181 -> 0.158,
-// p=6 0.190 -> 0.157, p=8 0.204 -> 0.182 (p=1 0.026 -> 0.030, p=2 and 7 equal); FP64 p=1
-// 0.042 -> 0.041, p=4 0.385 -> 0.367, p=5 0.294 -> 0.277, p=6 0.316 -> 0.289 (p=2 0.086 -> 0.093,
-// p=3 0.093 -> 0.097, p=7 0.240 -> 0.371, p=8 0.447 -> 0.588: more registers and LDS per cell).
-constexpr bool dg_lean_faces(int p, bool fp64) {
-  return fp64 ? (p == 1 || p == 4 || p == 5 || p == 6) : (p == 3 || p == 4 || p == 5 || p == 6 || p == 8);
-}
-
-template <int P, bool LEAN = false>
-struct DgFused {
-  static constexpr int N1 = P + 1, T = N1 * N1, NQ = N1 * T, CPW = DgCell<P>::CPW;
-  // per cell: the cell term's three arrays, or
-  //   direction by direction: the result plus 8 face arrays (the 4 inputs of one direction's two
-  //   faces and the 4 outputs of the first 1D pass);
-  //   all at once: region A (12 face arrays, later the second pass's outputs) and region B (the
-  //   first pass's outputs, later two arrays of line contributions)
-  static constexpr int REGB = 12 * T > 2 * NQ ? 12 * T : 2 * NQ;
-  static constexpr int FACE = LEAN ? 12 * T + REGB : NQ + 8 * T;
-  static constexpr int PER_CELL = 3 * NQ > FACE ? 3 * NQ : FACE;
-};
 
 // What the kernel does with its result v = (A src)_i before storing (one pass over the vectors,
 // fused with the operator):
@@ -251,260 +57,253 @@ struct DgEpilogue {
   Real c1, c2;
 };
 
+// Tensor-product form of the whole operator.  On the affine cube mesh every term of a(u, v)
+// factorises over the three directions: with the Gauss rule's 1D mass matrix M = S^T diag(w) S
+// and stiffness matrix K = D^T diag(w) D on the reference interval,
+//
+//   A u = sum_d (M x M)_{tangential to d} w_d,   w_d = h K u + (face terms of the faces normal to d)
+//
+// along every line of the cell in direction d: the cell term of direction d is h (K x M x M)
+// (h^3 from the cell measure, h^-2 from the two derivatives), and the terms of a face normal to d
+// are h^2 (M x M) applied to sigma [u] - {d_n u} at the face layer and, from d_n v = l'_a / h, to
+// -f h [u] times l'_a at the face end along the line (f = 1/2 on interior faces, 1 on boundary
+// faces).  The trace of a line on a face is its GLL end node and its normal derivative a dot
+// product with l'_a at the end point, so w_d needs only the cell's own line and the two
+// neighbours' lines through the faces it touches.  Per cell one lane per 1D line forms w_d for the
+// three directions, and the tangential mass matrices act in five 1D passes,
+//
+//   A u = M_y (M_z w_x + M_x w_z) + M_x M_z w_y,
+//
+// in place in two LDS arrays per cell (each pass reads and writes only its own lane's line, with a
+// barrier between passes).  K and M are symmetric about their centre, so every 1D contraction
+// uses the even-odd form: eight per line in all.
 template <int P, typename Real>
-__global__ __launch_bounds__(DgCell<P>::THREADS) MFQ_DG_WAVES void dg_fused_kernel(const Real* __restrict__ src, int n,
-                                                                      int64_t n_cells, Real h, Real sigma,
-                                                                      ShapeEO<P, Real> sh, DgTables<P, Real> tb,
-                                                                      DgEpilogue<Real> ep) {
-  constexpr bool LEAN = dg_lean_faces(P, sizeof(Real) == 8);
-  using F = DgFused<P, LEAN>;
-  constexpr int N1 = F::N1, T = F::T, NQ = F::NQ, CPW = F::CPW;
-  __shared__ Real lds[CPW * F::PER_CELL];
+struct DgKron {
+  EvenOdd<P + 1, Real> K;  // sum_q w_q l_a'(zeta_q) l_b'(zeta_q)
+  EvenOdd<P + 1, Real> M;  // sum_q w_q l_a(zeta_q) l_b(zeta_q)
+  Real d0[P + 1];          // l_a'(0)
+  Real d1[P + 1];          // l_a'(1)
+};
+
+template <int P, typename Real>
+DgKron<P, Real> make_dg_kron() {
+  constexpr int N1 = P + 1;
+  const Tables1D& tb = tables(P);
+  double K[N1 * N1], M[N1 * N1];
+  for (int a = 0; a < N1; ++a)
+    for (int b = 0; b < N1; ++b) {
+      double k = 0, m = 0;
+      for (int q = 0; q < N1; ++q) {
+        k += tb.omega[q] * tb.D[q * N1 + a] * tb.D[q * N1 + b];
+        m += tb.omega[q] * tb.S[q * N1 + a] * tb.S[q * N1 + b];
+      }
+      K[a * N1 + b] = k;
+      M[a * N1 + b] = m;
+    }
+  DgKron<P, Real> t{};
+  t.K = make_even_odd<N1, Real>(K);
+  t.M = make_even_odd<N1, Real>(M);
+  for (int a = 0; a < N1; ++a) {
+    t.d0[a] = (Real)lagrange_derivative(tb.xi, a, 0.0);
+    t.d1[a] = (Real)lagrange_derivative(tb.xi, a, 1.0);
+  }
+  return t;
+}
+
+// w = h K u + the face terms of one line's two faces, from the line u of the cell and the lines
+// uLo, uHi of its neighbours below and above along the line (zero where absent)
+template <int N1, typename Real, typename KT>
+__device__ __forceinline__ void dg_line_terms(const Real (&u)[N1], const Real (&uLo)[N1], const Real (&uHi)[N1],
+                                              bool hasLo, bool hasHi, Real h, Real ih, Real h2, Real sigma,
+                                              const KT& kt, Real (&w)[N1]) {
+  Real dK0 = 0, dK1 = 0, dLo = 0, dHi = 0;
+#pragma unroll
+  for (int a = 0; a < N1; ++a) {
+    dK0 = fmad(kt.d0[a], u[a], dK0);
+    dK1 = fmad(kt.d1[a], u[a], dK1);
+    dLo = fmad(kt.d1[a], uLo[a], dLo);
+    dHi = fmad(kt.d0[a], uHi[a], dHi);
+  }
+  // jump and mean normal derivative on the lower face (this cell its upper side) and the upper
+  // face; on a boundary face the outside is zero and the inside derivative replaces the mean
+  const Real jLo = uLo[N1 - 1] - u[0], jHi = u[N1 - 1] - uHi[0];
+  const Real mLo = hasLo ? (Real)0.5 * ih * (dLo + dK0) : ih * dK0;
+  const Real mHi = hasHi ? (Real)0.5 * ih * (dK1 + dHi) : ih * dK1;
+  const Real fLo = hasLo ? (Real)0.5 : (Real)1, fHi = hasHi ? (Real)0.5 : (Real)1;
+  const Real VLo = h2 * (sigma * jLo - mLo), DLo = -fLo * h * jLo;
+  const Real VHi = h2 * (sigma * jHi - mHi), DHi = -fHi * h * jHi;
+  Real ku[N1];
+  eo_apply<N1, 1, false>(kt.K, u, ku);
+#pragma unroll
+  for (int a = 0; a < N1; ++a) {
+    Real v = h * ku[a];
+    if (a == 0) v -= VLo;
+    if (a == N1 - 1) v += VHi;
+    v = fmad(DLo, kt.d0[a], v);
+    w[a] = fmad(DHi, kt.d1[a], v);
+  }
+}
+
+// Waves per SIMD the tensor-product kernel asks for: 5 where that fits its registers without
+// spilling, fewer at the high FP64 degrees
+constexpr int dg_kron_waves(int p, bool fp64) { return !fp64 ? 5 : p <= 5 ? 5 : p <= 7 ? 4 : 1; }
+
+template <int P, typename Real>
+__global__ __launch_bounds__(DgCell<P>::THREADS) __attribute__((amdgpu_waves_per_eu(dg_kron_waves(P, sizeof(Real) == 8))))
+void dg_kron_kernel(const Real* __restrict__ src, int n, int slab_planes, Real h, Real sigma, DgKron<P, Real> kt,
+                    DgEpilogue<Real> ep) {
+  using C = DgCell<P>;
+  constexpr int N1 = C::N1, T = C::T, NQ = C::NQ, CPW = C::CPW;
+  __shared__ Real lds[2 * CPW * NQ];
   const int tid = threadIdx.x;
   const int lc = tid / T, e = tid - lc * T;
   const int e0 = e % N1, e1 = e / N1;
-  // XCD-contiguous block order: block b runs on XCD b % 8 and takes the (b / 8)-th block of that
-  // XCD's contiguous share (a bijection for any grid size)
+  // A workgroup takes CPW consecutive cells of one x-row of cells.  Its place in the launch order
+  // (XCD-contiguous: block b runs on XCD b % 8 and takes the (b / 8)-th item of that XCD's
+  // contiguous share) walks slabs of slab_planes z-planes (n/8 rounded up: about one slab per
+  // XCD): within a slab z fastest, then the row segments along x, then y.  The z- and
+  // x-neighbours' lines are then read a few workgroups after they were fetched, the
+  // y-neighbours' one slab-row later, from the XCD's L2; only the lines across a slab boundary
+  // come from HBM again.
   const int64_t G = gridDim.x, q8 = G / 8, r8 = G % 8;
   const int64_t x8 = blockIdx.x % 8, i8 = blockIdx.x / 8;
   const int64_t blk = (x8 < r8 ? x8 * (q8 + 1) : r8 * (q8 + 1) + (x8 - r8) * q8) + i8;
-  const int64_t cell0 = blk * CPW;
-  const int64_t cell = cell0 + lc;
-  const bool live = cell < n_cells;
-  const int64_t K = live ? cell : 0;
+  const int nxb = (n + CPW - 1) / CPW;                 // row segments per x-row
+  const int64_t slab = (int64_t)slab_planes * n * nxb;  // workgroups per full slab
+  const int kb = (int)(blk / slab);
+  const int64_t rs = blk - kb * slab;
+  const int tz = min(slab_planes, n - kb * slab_planes);  // planes of this slab (the last may be thinner)
+  const int jrow = (int)(rs / ((int64_t)nxb * tz));
+  const int r2 = (int)(rs - (int64_t)jrow * nxb * tz);
+  const int xb = r2 / tz;
+  const int kz = kb * slab_planes + (r2 - xb * tz);
+  const int i0 = xb * CPW;
+  const int cnt = min(CPW, n - i0);                    // cells of this row segment
+  const int64_t nn = (int64_t)n * n;
+  const int64_t cell0 = i0 + (int64_t)n * jrow + nn * kz;
+  const bool live = lc < cnt;
+  const int64_t K = live ? cell0 + lc : cell0;
   const int64_t base = K * NQ;
-  Real y[N1];
-  dg_cell_term<P, Real>(src, base, live, lds, lc, e, h, sh, tb.w, y);
+  const int64_t ijk[3] = {i0 + (live ? lc : 0), jrow, kz};
+  const Real ih = (Real)1 / h, h2 = h * h;
+  // two arrays of this cell, node order (a + N1 b + T c)
+  Real* W0 = lds + lc * NQ;
+  Real* W1 = W0 + CPW * NQ;
+  // The own cells through LDS: each lane loads its z-line (contiguous across lanes) into
+  // registers and W1, and the x- and y-lines of the own cells, and of the x-neighbours inside the
+  // row segment, are read back from W1.  The other neighbours' lines come from global memory (the
+  // z-neighbours' z-lines contiguous across lanes).
+  Real uz[N1];
+#pragma unroll
+  for (int c = 0; c < N1; ++c) uz[c] = live ? src[base + e + T * c] : (Real)0;
+#pragma unroll
+  for (int c = 0; c < N1; ++c) W1[e + T * c] = uz[c];
   __syncthreads();
-  if constexpr (LEAN) {
-    // Face terms of all three directions at once.  Lane (e0, e1) is the tangential node of each
-    // direction: it forms the jump and mean normal derivative of both faces from its own and the
-    // neighbours' normal lines (12 face arrays per cell).  The face mass matrix h^2 (M x M) is then
-    // applied to all 12 arrays in two 1D passes whose work items are rows (then columns) of an
-    // array, a 1D contraction each, spread over all lanes; the last pass leaves the results where
-    // the face arrays were.
-    Real* FA = lds + lc * F::PER_CELL;  // region A: face arrays, later the results of both passes
-    const int64_t ijk[3] = {K % n, (K / n) % n, K / ((int64_t)n * n)};
-    const int64_t nn = (int64_t)n * n;
-    const Real ih = (Real)1 / h;
+  Real w[N1], wy[N1], wz[N1];
 #pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const int64_t stride = d == 0 ? 1 : d == 1 ? n : nn;
-      const bool hasLo = live && ijk[d] > 0, hasHi = live && ijk[d] < n - 1;
-      Real uK[N1], uLo[N1], uHi[N1];
+  for (int d = 0; d < 3; ++d) {
+    const int64_t stride = d == 0 ? 1 : d == 1 ? n : nn;
+    const bool hasLo = live && ijk[d] > 0, hasHi = live && ijk[d] < n - 1;
+    Real u[N1], uLo[N1], uHi[N1];
 #pragma unroll
-      for (int a = 0; a < N1; ++a) {
-        const int loc = face_local<N1>(d, a, e0, e1);
-        uK[a] = live ? src[base + loc] : (Real)0;
+    for (int a = 0; a < N1; ++a) {
+      const int loc = face_local<N1>(d, a, e0, e1);
+      u[a] = d == 2 ? uz[a] : W1[loc];
+      if (d == 0) {
+        uLo[a] = lc > 0 ? W1[loc - NQ] : hasLo ? src[base - NQ + loc] : (Real)0;
+        uHi[a] = lc + 1 < cnt ? W1[loc + NQ] : hasHi ? src[base + NQ + loc] : (Real)0;
+      } else {
         uLo[a] = hasLo ? src[base - stride * NQ + loc] : (Real)0;
         uHi[a] = hasHi ? src[base + stride * NQ + loc] : (Real)0;
       }
-      Real dK0 = 0, dK1 = 0, dLo = 0, dHi = 0;
+    }
+    dg_line_terms<N1>(u, uLo, uHi, hasLo, hasHi, h, ih, h2, sigma, kt, w);
 #pragma unroll
-      for (int a = 0; a < N1; ++a) {
-        dK0 = fmad(tb.d0[a], uK[a], dK0);
-        dK1 = fmad(tb.d1[a], uK[a], dK1);
-        dLo = fmad(tb.d1[a], uLo[a], dLo);
-        dHi = fmad(tb.d0[a], uHi[a], dHi);
+    for (int a = 0; a < N1; ++a) {
+      if (d == 0) W0[a + N1 * e] = w[a];  // nobody reads W0 before the passes
+      if (d == 1) wy[a] = w[a];
+      if (d == 2) wz[a] = w[a];
+    }
+  }
+  // A u = M_y (M_z w_x + M_x w_z) + M_x M_z w_y: w_y replaces the copy of the source once every
+  // lane has read it; w_z enters after M_z w_y has been read out of its array
+  __syncthreads();
+#pragma unroll
+  for (int b = 0; b < N1; ++b) W1[e0 + N1 * b + T * e1] = wy[b];
+  __syncthreads();
+  {  // z-lines, lane (a, b): W0 <- M_z w_x, W1 <- M_z w_y
+    Real v[N1], r[N1];
+#pragma unroll
+    for (int c = 0; c < N1; ++c) v[c] = W0[e + T * c];
+    eo_apply<N1, 1, false>(kt.M, v, r);
+#pragma unroll
+    for (int c = 0; c < N1; ++c) W0[e + T * c] = r[c];
+#pragma unroll
+    for (int c = 0; c < N1; ++c) v[c] = W1[e + T * c];
+    eo_apply<N1, 1, false>(kt.M, v, r);
+#pragma unroll
+    for (int c = 0; c < N1; ++c) W1[e + T * c] = r[c];
+  }
+  __syncthreads();
+  Real r1[N1];  // x-lines, lane (b, c): M_x M_z w_y
+  {
+    Real v[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) v[a] = W1[a + N1 * e];
+    eo_apply<N1, 1, false>(kt.M, v, r1);
+  }
+  __syncthreads();
+#pragma unroll
+  for (int c = 0; c < N1; ++c) W1[e + T * c] = wz[c];  // z-line (a, b) of w_z
+  __syncthreads();
+  {  // x-lines, lane (b, c): W0 <- M_x w_z + W0
+    Real v[N1], r[N1];
+#pragma unroll
+    for (int a = 0; a < N1; ++a) v[a] = W1[a + N1 * e];
+    eo_apply<N1, 1, false>(kt.M, v, r);
+#pragma unroll
+    for (int a = 0; a < N1; ++a) W0[a + N1 * e] += r[a];
+  }
+  __syncthreads();
+  {  // y-lines, lane (a, c): W0 <- M_y W0
+    Real v[N1], r[N1];
+#pragma unroll
+    for (int b = 0; b < N1; ++b) v[b] = W0[e0 + N1 * b + T * e1];
+    eo_apply<N1, 1, false>(kt.M, v, r);
+#pragma unroll
+    for (int b = 0; b < N1; ++b) W0[e0 + N1 * b + T * e1] = r[b];
+  }
+  __syncthreads();
+  Real y[N1];  // x-line (b, c) of the result
+#pragma unroll
+  for (int a = 0; a < N1; ++a) y[a] = W0[a + N1 * e] + r1[a];
+  if (ep.mode == kStore) {
+    if (!live) return;
+    const int64_t g0i = base + N1 * e;
+#pragma unroll
+    for (int a = 0; a < N1; ++a) ep.dst[g0i + a] = y[a];
+    return;
+  }
+  // smoother step or residual: the result goes through LDS in node order (this lane's own x-line
+  // of W0, which no other lane reads) and a coalesced pass covers the workgroup's cells
+#pragma unroll
+  for (int a = 0; a < N1; ++a) W0[a + N1 * e] = y[a];
+  __syncthreads();
+  const int64_t limit = (int64_t)cnt * NQ;
+  const int64_t gb = cell0 * NQ;
+  if (ep.mode == kChebStep) {
+    for (int i = tid; i < CPW * NQ; i += C::THREADS)
+      if (i < limit) {
+        const int64_t gi = gb + i;
+        const Real rv = ep.r[gi] - lds[i];
+        const Real dv = ep.c1 * src[gi] + ep.c2 * ep.dinv[gi] * rv;
+        ep.r[gi] = rv;
+        ep.dnew[gi] = dv;
+        ep.x[gi] += dv;
       }
-      // lower face (this cell on its upper side) and upper face (this cell on its lower side): jump
-      // and mean normal derivative at the face nodes
-      Real* Fd = FA + 4 * d * T;
-      Fd[e] = uLo[N1 - 1] - uK[0];
-      Fd[T + e] = hasLo ? (Real)0.5 * ih * (dLo + dK0) : ih * dK0;
-      Fd[2 * T + e] = uK[N1 - 1] - uHi[0];
-      Fd[3 * T + e] = hasHi ? (Real)0.5 * ih * (dK1 + dHi) : ih * dK1;
-    }
-    __syncthreads();
-    // The face terms are the face mass matrix h^2 (M x M) applied to sigma [u] - {d_n u} (value
-    // part) and to [u] (derivative part); M = S^T diag(w) S is the Gauss rule's 1D mass matrix,
-    // so the interpolation to the face points and back collapses into one 1D pass per direction.
-    // First tangential direction: item (cell, array, row a2) contracts the row into region B.
-    constexpr int ITEMS = CPW * 12 * N1;
-    for (int w = tid; w < ITEMS; w += DgCell<P>::THREADS) {
-      const int wc = w / (12 * N1), rem = w - wc * 12 * N1;
-      const int arr = rem / N1, a2 = rem - arr * N1;
-      const Real* in = lds + wc * F::PER_CELL + arr * T + N1 * a2;
-      Real* out = lds + wc * F::PER_CELL + 12 * T + arr * T + N1 * a2;
-      Real f[N1];
-#pragma unroll
-      for (int b1 = 0; b1 < N1; ++b1) f[b1] = in[b1];
-#pragma unroll
-      for (int a1 = 0; a1 < N1; ++a1) {
-        Real acc = 0;
-#pragma unroll
-        for (int b1 = 0; b1 < N1; ++b1) acc = fmad(tb.M[a1 * N1 + b1], f[b1], acc);
-        out[a1] = acc;
-      }
-    }
-    __syncthreads();
-    // second tangential direction: item (cell, array, column a1), back into region A
-    for (int w = tid; w < ITEMS; w += DgCell<P>::THREADS) {
-      const int wc = w / (12 * N1), rem = w - wc * 12 * N1;
-      const int arr = rem / N1, a1 = rem - arr * N1;
-      const Real* in = lds + wc * F::PER_CELL + 12 * T + arr * T + a1;
-      Real* out = lds + wc * F::PER_CELL + arr * T + a1;
-      Real gcol[N1];
-#pragma unroll
-      for (int b2 = 0; b2 < N1; ++b2) gcol[b2] = in[N1 * b2];
-#pragma unroll
-      for (int a2 = 0; a2 < N1; ++a2) {
-        Real acc = 0;
-#pragma unroll
-        for (int b2 = 0; b2 < N1; ++b2) acc = fmad(tb.M[a2 * N1 + b2], gcol[b2], acc);
-        out[N1 * a2] = acc;
-      }
-    }
-    __syncthreads();
-    // Value part on the face layer, derivative part along the normal line.  Direction 0: the
-    // lane's normal line is the x-pencil of the result it holds in y.  Directions 1 and 2: lines
-    // through other lanes' pencils, written to two arrays in region B (one writer per node) and
-    // added by the pencils' lanes after a barrier, in the order of the directions.
-    Real* R1 = lds + lc * F::PER_CELL + 12 * T;
-    Real* R2 = R1 + NQ;
-    const Real h2 = h * h;
-#pragma unroll
-    for (int d = 0; d < 3; ++d) {
-      const bool hasLo = live && ijk[d] > 0, hasHi = live && ijk[d] < n - 1;
-      const Real* Gd = FA + 4 * d * T;
-      const Real g0 = Gd[e], g1 = Gd[T + e], g2 = Gd[2 * T + e], g3 = Gd[3 * T + e];
-      const Real fLo = hasLo ? (Real)0.5 : (Real)1, fHi = hasHi ? (Real)0.5 : (Real)1;
-      const Real VLo = h2 * (sigma * g0 - g1), DLo = -fLo * h * g0;
-      const Real VHi = h2 * (sigma * g2 - g3), DHi = -fHi * h * g2;
-#pragma unroll
-      for (int a = 0; a < N1; ++a) {
-        const Real c = (a == 0 ? -VLo : (Real)0) + (a == N1 - 1 ? VHi : (Real)0) + DLo * tb.d0[a] + DHi * tb.d1[a];
-        if (d == 0)
-          y[a] += c;
-        else
-          (d == 1 ? R1 : R2)[face_local<N1>(d, a, e0, e1)] = c;
-      }
-    }
-    __syncthreads();
-#pragma unroll
-    for (int a = 0; a < N1; ++a) y[a] += R1[a + N1 * e];
-#pragma unroll
-    for (int a = 0; a < N1; ++a) y[a] += R2[a + N1 * e];
-    if (ep.mode == kStore) {
-      if (!live) return;
-      // this lane's x-pencil of the cell result, N1 consecutive entries
-      const int64_t g0i = base + N1 * e;
-#pragma unroll
-      for (int a = 0; a < N1; ++a) ep.dst[g0i + a] = y[a];
-      return;
-    }
-    // smoother step or residual (several vectors read and written per entry): the result goes
-    // through LDS in node order and a coalesced pass covers the workgroup's cells
-    __syncthreads();
-    Real* Rc = lds + lc * NQ;
-#pragma unroll
-    for (int a = 0; a < N1; ++a) Rc[a + N1 * e] = y[a];
-    __syncthreads();
-    const int64_t limit = (n_cells - cell0) * NQ;
-    const int64_t gb = cell0 * NQ;
-    if (ep.mode == kChebStep) {
-      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
-        if (i < limit) {
-          const int64_t gi = gb + i;
-          const Real rv = ep.r[gi] - lds[i];
-          const Real dv = ep.c1 * src[gi] + ep.c2 * ep.dinv[gi] * rv;
-          ep.r[gi] = rv;
-          ep.dnew[gi] = dv;
-          ep.x[gi] += dv;
-        }
-    } else {
-      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
-        if (i < limit) ep.r[gb + i] = ep.b[gb + i] - lds[i];
-    }
   } else {
-    Real* R = lds + lc * NQ;  // this cell's result, node order (contiguous over the workgroup's cells)
-#pragma unroll
-    for (int a = 0; a < N1; ++a) R[a + N1 * e] = y[a];
-    Real* Fa = lds + CPW * NQ + lc * 4 * T;  // four face arrays of this cell
-    Real* Ga = lds + CPW * NQ + CPW * 4 * T + lc * 4 * T;
-    const int64_t ijk[3] = {K % n, (K / n) % n, K / ((int64_t)n * n)};
-    const int64_t nn = (int64_t)n * n;
-    const Real ih = (Real)1 / h;
-#pragma unroll 1
-    for (int d = 0; d < 3; ++d) {
-      const int64_t stride = d == 0 ? 1 : d == 1 ? n : nn;
-      const bool hasLo = live && ijk[d] > 0, hasHi = live && ijk[d] < n - 1;
-      Real uK[N1], uLo[N1], uHi[N1];
-#pragma unroll
-      for (int a = 0; a < N1; ++a) {
-        const int loc = face_local<N1>(d, a, e0, e1);
-        uK[a] = live ? src[base + loc] : (Real)0;
-        uLo[a] = hasLo ? src[base - stride * NQ + loc] : (Real)0;
-        uHi[a] = hasHi ? src[base + stride * NQ + loc] : (Real)0;
-      }
-      Real dK0 = 0, dK1 = 0, dLo = 0, dHi = 0;
-#pragma unroll
-      for (int a = 0; a < N1; ++a) {
-        dK0 = fmad(tb.d0[a], uK[a], dK0);
-        dK1 = fmad(tb.d1[a], uK[a], dK1);
-        dLo = fmad(tb.d1[a], uLo[a], dLo);
-        dHi = fmad(tb.d0[a], uHi[a], dHi);
-      }
-      // lower face (this cell on its upper side) and upper face (this cell on its lower side): jump
-      // and mean normal derivative at the face nodes
-      Fa[e] = uLo[N1 - 1] - uK[0];
-      Fa[T + e] = hasLo ? (Real)0.5 * ih * (dLo + dK0) : ih * dK0;
-      Fa[2 * T + e] = uK[N1 - 1] - uHi[0];
-      Fa[3 * T + e] = hasHi ? (Real)0.5 * ih * (dK1 + dHi) : ih * dK1;
-      __syncthreads();
-      // The face terms are the face mass matrix h^2 (M x M) applied to sigma [u] - {d_n u} (value
-      // part) and to [u] (derivative part); M = S^T diag(w) S is the Gauss rule's 1D mass matrix,
-      // so the interpolation to the face points and back collapses into one 1D pass per direction.
-      // First tangential direction: lane (a1 = e0, a2 = e1)
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        Real acc = 0;
-#pragma unroll
-        for (int b1 = 0; b1 < N1; ++b1) acc = fmad(tb.M[e0 * N1 + b1], Fa[k * T + b1 + N1 * e1], acc);
-        Ga[k * T + e] = acc;
-      }
-      __syncthreads();
-      Real g[4];
-#pragma unroll
-      for (int k = 0; k < 4; ++k) {
-        Real acc = 0;
-#pragma unroll
-        for (int b2 = 0; b2 < N1; ++b2) acc = fmad(tb.M[e1 * N1 + b2], Ga[k * T + e0 + N1 * b2], acc);
-        g[k] = acc;
-      }
-      const Real fLo = hasLo ? (Real)0.5 : (Real)1, fHi = hasHi ? (Real)0.5 : (Real)1;
-      const Real h2 = h * h;
-      const Real VLo = h2 * (sigma * g[0] - g[1]), DLo = -fLo * h * g[0];
-      const Real VHi = h2 * (sigma * g[2] - g[3]), DHi = -fHi * h * g[2];
-      // value part on the face layer, derivative part along the normal line (this lane's own line:
-      // no other lane touches it in this direction)
-#pragma unroll
-      for (int a = 0; a < N1; ++a) {
-        const int loc = face_local<N1>(d, a, e0, e1);
-        R[loc] += (a == 0 ? -VLo : (Real)0) + (a == N1 - 1 ? VHi : (Real)0) + DLo * tb.d0[a] + DHi * tb.d1[a];
-      }
-    }
-    __syncthreads();
-    // coalesced pass over the workgroup's cells
-    const int64_t limit = (n_cells - cell0) * NQ;
-    const int64_t g0 = cell0 * NQ;
-    if (ep.mode == kStore) {
-      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
-        if (i < limit) ep.dst[g0 + i] = lds[i];
-    } else if (ep.mode == kChebStep) {
-      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
-        if (i < limit) {
-          const int64_t gi = g0 + i;
-          const Real rv = ep.r[gi] - lds[i];
-          const Real dv = ep.c1 * src[gi] + ep.c2 * ep.dinv[gi] * rv;
-          ep.r[gi] = rv;
-          ep.dnew[gi] = dv;
-          ep.x[gi] += dv;
-        }
-    } else {
-      for (int i = tid; i < CPW * NQ; i += DgCell<P>::THREADS)
-        if (i < limit) ep.r[g0 + i] = ep.b[g0 + i] - lds[i];
-    }
+    for (int i = tid; i < CPW * NQ; i += C::THREADS)
+      if (i < limit) ep.r[gb + i] = ep.b[gb + i] - lds[i];
   }
 }
 
@@ -522,14 +321,13 @@ struct DgApplyArgs {
 template <int P, typename Real>
 hipError_t dg_apply_pr(int n, const Real* src, const DgEpilogue<Real>& ep, hipStream_t st) {
   using C = DgCell<P>;
-  static const DgTables<P, Real> tb = make_dg_tables<P, Real>();
-  static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
+  static const DgKron<P, Real> kt = make_dg_kron<P, Real>();
   const Real h = (Real)(1.0 / n);
   const Real sigma = (Real)(2.0 * (P + 1) * (P + 1) * n);
-  const int64_t cells = (int64_t)n * n * n;
-  const int64_t g = (cells + C::CPW - 1) / C::CPW;
+  const int64_t g = (int64_t)((n + C::CPW - 1) / C::CPW) * n * n;  // row segments of CPW cells
   if (g > 0x7fffffff) return hipErrorInvalidValue;
-  dg_fused_kernel<P, Real><<<(unsigned)g, C::THREADS, 0, st>>>(src, n, cells, h, sigma, sh, tb, ep);
+  const int slab_planes = (n + 7) / 8;
+  dg_kron_kernel<P, Real><<<(unsigned)g, C::THREADS, 0, st>>>(src, n, slab_planes, h, sigma, kt, ep);
   return hipGetLastError();
 }
 

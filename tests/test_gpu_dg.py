@@ -100,9 +100,10 @@ def _torch_vec(x, dtype):
 @pytest.mark.parametrize("p", [1, 2, 4, 6, 8])
 def test_dg_vmult_fp32_within_rounding_bound(p):
     """FP32 product: |y32 - A x32| <= 2 k u32 (M |x32|) componentwise, M the oracle's magnitude
-    matrix (every table, weight and term by its absolute value) and k = 8(p+1) + 16 the longest
-    rounding chain (six 1D passes per cell term, the face interpolation passes, the sums of the
-    cell and six face contributions)."""
+    matrix (every table, weight and term by its absolute value) and k = 8(p+1) + 16, which bounds
+    the longest rounding chain of the kernel's tensor-product evaluation (per line a stiffness
+    contraction and the face terms, then at most three mass-matrix passes and the sums: about
+    4(p+1) + 10)."""
     mfq = _mfq()
     torch = _torch()
     n = SIZES[p]
