@@ -430,11 +430,44 @@ __device__ __forceinline__ void scatter_epilogue(const Real* res, int cstride, R
 // idle lanes); ACC adds A src into dst instead of overwriting it.
 // Gauss weights and cell size for the operator of undeformed (axis-parallel cube) cells with
 // coefficient 1, whose quadrature tensors are G_q = h w_r w_s w_t I and need not be read.
+// Undeformed cells with coefficient 1 (axis-parallel cubes of side h): the quadrature tensors are
+// h w_r w_s w_t I, and the cell matrix is h (K x M x M + M x K x M + M x M x K) with the Gauss
+// rule's 1D stiffness and mass matrices K = D^T diag(w) D and M = S^T diag(w) S on the reference
+// interval (the rule is exact for both products), so the cell term is applied in that form.
 template <int P, typename Real>
 struct CartQuad {
   Real w[P + 1];
   Real h;
+  EvenOdd<P + 1, Real> K;  // sum_q w_q l_a'(zeta_q) l_b'(zeta_q)
+  EvenOdd<P + 1, Real> M;  // sum_q w_q l_a(zeta_q) l_b(zeta_q)
 };
+
+template <int P, typename Real>
+CartQuad<P, Real> make_cart_quad(double h) {
+  static const CartQuad<P, Real> base = [] {
+    constexpr int N1 = P + 1;
+    const Tables1D& tb = tables(P);
+    double K[N1 * N1], M[N1 * N1];
+    for (int a = 0; a < N1; ++a)
+      for (int b = 0; b < N1; ++b) {
+        double k = 0, m = 0;
+        for (int q = 0; q < N1; ++q) {
+          k += tb.omega[q] * tb.D[q * N1 + a] * tb.D[q * N1 + b];
+          m += tb.omega[q] * tb.S[q * N1 + a] * tb.S[q * N1 + b];
+        }
+        K[a * N1 + b] = k;
+        M[a * N1 + b] = m;
+      }
+    CartQuad<P, Real> c{};
+    for (int a = 0; a < N1; ++a) c.w[a] = (Real)tb.omega[a];
+    c.K = make_even_odd<N1, Real>(K);
+    c.M = make_even_odd<N1, Real>(M);
+    return c;
+  }();
+  CartQuad<P, Real> c = base;
+  c.h = (Real)h;
+  return c;
+}
 
 // One brick (number b of colour `colour`) of the operator application by the workgroup.  HANG: a
 // space with hanging nodes (X1-low face nodes go through the face arrays `sd`).
@@ -515,7 +548,7 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
   unsigned first;
   Real dv[KPT];
   lattice_index<P, BLOCK, KPT>(idx + ord * (int64_t)NL, bk, bi, bj, bz, gk, first);
-  if (MFQ_G_STAGE == 0) load_g();
+  if (!CART && MFQ_G_STAGE == 0) load_g();
   // the masked dst gather was timed per degree on MI355X: slower only for p = 6 FP64 and p = 5 FP32
   constexpr bool MASK = !((P == 6 && sizeof(Real) == 8) || (P == 5 && sizeof(Real) == 4));
   lattice_values<Real, ACC, BLOCK, KPT, NL, HANG, MASK>(src, dst, gk, first, lat, dv, sd);
@@ -523,6 +556,55 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
   if constexpr (EPI) epilogue_prefetch<P, Real, BLOCK, KPT>(ep, src, gk, bk, bi, bj, bz, er);
   lds_barrier();
 
+  if constexpr (CART) {
+    // h (M_z (K_x M_y + M_x K_y) + K_z M_x M_y) u in three passes, each lane in place on its own line
+    {  // x: lane (b, c) = (e0, e1): L0 = K_x u, L1 = M_x u
+      const Real* up = lat + cx * P + LX * ((cy * P + e0) + LY * (cz * P + e1));
+      Real u[N1], A[N1], B[N1];
+#pragma unroll
+      for (int a = 0; a < N1; ++a) u[a] = up[a];
+      eo_apply<N1, 1, false>(cq.K, u, A);
+      eo_apply<N1, 1, false>(cq.M, u, B);
+#pragma unroll
+      for (int a = 0; a < N1; ++a) {
+        L0[a + N1 * e] = A[a];
+        L1[a + N1 * e] = B[a];
+      }
+    }
+    lds_barrier();
+    {  // y: lane (a, c) = (e0, e1): L0 = M_y L0 + K_y L1, L1 = M_y L1
+      Real a1[N1], b1[N1], r1[N1], r2[N1], r3[N1];
+#pragma unroll
+      for (int b = 0; b < N1; ++b) {
+        a1[b] = L0[e0 + N1 * b + T * e1];
+        b1[b] = L1[e0 + N1 * b + T * e1];
+      }
+      eo_apply<N1, 1, false>(cq.M, a1, r1);
+      eo_apply<N1, 1, false>(cq.K, b1, r2);
+      eo_apply<N1, 1, false>(cq.M, b1, r3);
+#pragma unroll
+      for (int b = 0; b < N1; ++b) {
+        L0[e0 + N1 * b + T * e1] = r1[b] + r2[b];
+        L1[e0 + N1 * b + T * e1] = r3[b];
+      }
+    }
+    lds_barrier();
+    {  // z: lane (a, b) = (e0, e1): the cell result h (M_z L0 + K_z L1) into L0 (zero for cells
+       // outside the mesh, whose lattice can hold nodes of the mesh's boundary face)
+      Real a2[N1], b2[N1], r1[N1], r2[N1];
+#pragma unroll
+      for (int c = 0; c < N1; ++c) {
+        a2[c] = L0[e + T * c];
+        b2[c] = L1[e + T * c];
+      }
+      eo_apply<N1, 1, false>(cq.M, a2, r1);
+      eo_apply<N1, 1, false>(cq.K, b2, r2);
+      const Real hs = cell_in ? cq.h : (Real)0;
+#pragma unroll
+      for (int c = 0; c < N1; ++c) L0[e + T * c] = hs * (r1[c] + r2[c]);
+    }
+    lds_barrier();
+  } else {
   // x: values and x-derivatives at (q, e0, e1) from the lane's x-pencil
   {
     const Real* up = lat + cx * P + LX * ((cy * P + e0) + LY * (cz * P + e1));
@@ -637,6 +719,7 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
     for (int a = 0; a < N1; ++a) L0[a + N1 * e] = y[a];
   }
   lds_barrier();
+  }
   // sum the cells' results per lattice node (fixed order) and write the brick's nodes
   if constexpr (EPI)
     scatter_epilogue<P, Real, BLOCK, KPT>(lds, NQ, dst, gk, first, dv, ep, er);
@@ -1384,12 +1467,7 @@ hipError_t vmult_pr(const OpView& v, const void* src, void* dst, bool acc, hipSt
   // undeformed cells and coefficient 1: the quadrature tensors are h w_r w_s w_t I (the
   // specialised mapping of axis-parallel box cells), formed in registers instead of read
   const bool cart = v.amplitude == 0.0 && v.alpha == 0.0;
-  CartQuad<P, Real> cq{};
-  if (cart) {
-    const Tables1D& tb = tables(P);
-    for (int a = 0; a <= P; ++a) cq.w[a] = (Real)tb.omega[a];
-    cq.h = (Real)(1.0 / v.n);
-  }
+  const CartQuad<P, Real> cq = cart ? make_cart_quad<P, Real>(1.0 / v.n) : CartQuad<P, Real>{};
   if (v.side_base >= 0) {
     // space with hanging nodes: overwrite only, quadrature tensors read
     if (acc || !v.side_in || !v.side_out) return hipErrorInvalidValue;
@@ -1438,12 +1516,7 @@ template <int P, typename Real>
 hipError_t vmult_epi_pr(const OpView& v, const void* src, void* dst, const CellEpilogue& ep, hipStream_t st) {
   static const ShapeEO<P, Real> sh = make_shape_eo<P, Real>();
   const bool cart = v.amplitude == 0.0 && v.alpha == 0.0;
-  CartQuad<P, Real> cq{};
-  if (cart) {
-    const Tables1D& tb = tables(P);
-    for (int a = 0; a <= P; ++a) cq.w[a] = (Real)tb.omega[a];
-    cq.h = (Real)(1.0 / v.n);
-  }
+  const CartQuad<P, Real> cq = cart ? make_cart_quad<P, Real>(1.0 / v.n) : CartQuad<P, Real>{};
   for (int c = 0; c < kColours; ++c) {
     const int64_t nb = v.bricks.count[c];
     if (nb == 0) continue;
@@ -1501,8 +1574,7 @@ hipError_t batch_cells_pr(bool cart, bool coef, bool fused, const CellItem* item
     } else {
       CartQuad<P, Real> cq{};
       if (cart) {
-        const Tables1D& tb = tables(P);
-        for (int a = 0; a <= P; ++a) cq.w[a] = (Real)tb.omega[a];
+        cq = make_cart_quad<P, Real>(1.0);
         batch_vmult_epi_kernel<P, Real, true><<<(unsigned)blocks, Cell<P>::NT, 0, st>>>(items, count, colour, sh, cq);
       } else {
         batch_vmult_epi_kernel<P, Real, false><<<(unsigned)blocks, Cell<P>::NT, 0, st>>>(items, count, colour, sh, cq);
@@ -1511,9 +1583,7 @@ hipError_t batch_cells_pr(bool cart, bool coef, bool fused, const CellItem* item
     }
   }
   if (cart) {
-    CartQuad<P, Real> cq{};
-    const Tables1D& tb = tables(P);
-    for (int a = 0; a <= P; ++a) cq.w[a] = (Real)tb.omega[a];
+    const CartQuad<P, Real> cq = make_cart_quad<P, Real>(1.0);
     batch_vmult_kernel<P, Real, true><<<(unsigned)blocks, Cell<P>::NT, 0, st>>>(items, count, colour, sh, cq);
   } else {
     batch_vmult_kernel<P, Real, false><<<(unsigned)blocks, Cell<P>::NT, 0, st>>>(items, count, colour, sh,
