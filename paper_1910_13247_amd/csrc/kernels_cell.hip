@@ -464,7 +464,6 @@ __device__ __forceinline__ void scatter_epilogue(const Real* res, int cstride, R
 // interval (the rule is exact for both products), so the cell term is applied in that form.
 template <int P, typename Real>
 struct CartQuad {
-  Real w[P + 1];
   Real h;
   EvenOdd<P + 1, Real> K;  // sum_q w_q l_a'(zeta_q) l_b'(zeta_q)
   EvenOdd<P + 1, Real> M;  // sum_q w_q l_a(zeta_q) l_b(zeta_q)
@@ -488,7 +487,6 @@ CartQuad<P, Real> make_cart_quad(double h, int faces = 0) {
         M[a * N1 + b] = m;
       }
     CartQuad<P, Real> c{};
-    for (int a = 0; a < N1; ++a) c.w[a] = (Real)tb.omega[a];
     c.K = make_even_odd<N1, Real>(K);
     c.M = make_even_odd<N1, Real>(M);
     return c;
@@ -550,17 +548,6 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
         const Real v = __builtin_nontemporal_load(cp + t * NT);
         g[t][0] = Real2<Real>{cell_in ? v : (Real)0, 0};
       }
-    } else if constexpr (CART) {
-      // G = h w_r w_s w_t I: kept in g[t][0].x (the diagonal), weights selected with compile-time indices
-      Real w0 = 0, w1 = 0;
-#pragma unroll
-      for (int k = 0; k < N1; ++k) {
-        w0 = e0 == k ? cq.w[k] : w0;
-        w1 = e1 == k ? cq.w[k] : w1;
-      }
-      const Real c = cell_in ? cq.h * w0 * w1 : (Real)0;
-#pragma unroll
-      for (int t = 0; t < N1; ++t) g[t][0] = Real2<Real>{c * cq.w[t], 0};
     } else {
       const Real2<Real>* gp = reinterpret_cast<const Real2<Real>*>(geo) + ord * (int64_t)(N1 * 3 * NT) + (cell_in ? tid : 0);
 #pragma unroll
@@ -693,7 +680,7 @@ __device__ __forceinline__ void vmult_brick(const int* __restrict__ idx, const R
     Real vx[N1], vy[N1], vz[N1];
 #pragma unroll
     for (int t = 0; t < N1; ++t) {
-      if constexpr (CART || COEF) {
+      if constexpr (COEF) {
         const Real c = g[t][0].x;
         vx[t] = c * gx[t];
         vy[t] = c * gy[t];
