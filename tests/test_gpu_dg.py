@@ -382,3 +382,59 @@ def test_dg_full_size_q4_64_fp32_sampled():
     mag = dg.dg_rows(p, n, np.abs(x32), rows, magnitude=True)
     k = 8 * (p + 1) + 16
     assert np.all(np.abs(y[rows] - yo) <= 2 * k * U32 * mag + 1e-30)
+
+
+# Meshes with several row segments per x-row of cells (a workgroup takes 128 / (p+1)^2 cells of a
+# row up to p = 4, 256 / (p+1)^2 above) and several slabs of ceil(n/8) z-planes, the last thinner
+# where 8 does not divide n: the neighbours across segment and slab boundaries come from other
+# workgroups.
+SEGMENTED = {1: 33, 2: 15, 3: 9, 4: 11, 5: 8, 6: 6, 7: 5, 8: 4}
+
+
+def _segment_rows(p, n, rng):
+    """Rows of the cells at both sides of the first segment boundary and of the first slab
+    boundary, at the mesh's upper faces, plus random rows: per cell its corner nodes, the
+    centres of its faces and a few random nodes."""
+    N1 = p + 1
+    nloc = N1 ** 3
+    cpw = max(1, (128 if p <= 4 else 256) // (N1 * N1))
+    sp = (n + 7) // 8
+    xs = sorted({min(cpw - 1, n - 1), min(cpw, n - 1), n - 1})
+    ks = sorted({0, sp - 1, min(sp, n - 1), n - 1})
+    h = N1 // 2
+    local = {a + N1 * b + N1 * N1 * c for a in (0, p) for b in (0, p) for c in (0, p)}
+    local |= {face for face in (h + N1 * h, h + N1 * h + N1 * N1 * p, h + N1 * N1 * h,
+                                h + N1 * p + N1 * N1 * h, N1 * h + N1 * N1 * h, p + N1 * h + N1 * N1 * h)}
+    rows = []
+    for i in xs:
+        for j in (0, n - 1):
+            for k in ks:
+                K = i + n * (j + n * k)
+                loc = sorted(local | set(rng.integers(0, nloc, 4).tolist()))
+                rows += [K * nloc + l for l in loc]
+    rows += rng.integers(0, n ** 3 * nloc, 100).tolist()
+    return np.unique(np.array(rows, dtype=np.int64))
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_dg_segments_and_slabs(p):
+    """FP64 product within 1e-12 of the oracle's rows, FP32 within the componentwise bound, on a
+    mesh with several row segments per x-row and several slabs."""
+    torch = _torch()
+    mfq = _mfq()
+    n = SEGMENTED[p]
+    print(f"dg segments p={p} n={n}", flush=True)
+    op = mfq.DGOperator(mfq.Mesh(n, 0.0), p)
+    x = uniform_vector(op.n_dofs, seed=110 + p)
+    rows = _segment_rows(p, n, np.random.default_rng(p))
+    y = op.vmult(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    yo = dg.dg_rows(p, n, x, rows)
+    assert np.abs(y.cpu().numpy()[rows] - yo).max() <= 1e-12 * np.abs(yo).max()
+    x32 = x.astype(np.float32).astype(np.float64)
+    y32 = op.vmult(_torch_vec(x, torch.float32))
+    torch.cuda.synchronize()
+    yo32 = dg.dg_rows(p, n, x32, rows)
+    mag = dg.dg_rows(p, n, np.abs(x32), rows, magnitude=True)
+    k = 8 * (p + 1) + 16
+    assert np.all(np.abs(y32.double().cpu().numpy()[rows] - yo32) <= 2 * k * U32 * mag + 1e-30)

@@ -225,3 +225,63 @@ def test_undeformed_variable_coefficient_fp32(p):
     mag = ebe.magnitude_bound(p, n, 0.0, 0.5, x32, 1)
     k = 8 * (p + 1) + 16
     assert np.all(np.abs(y.double().cpu().numpy() - yo) <= 2 * k * U32 * mag + 1e-30)
+
+
+@functools.lru_cache(maxsize=2)
+def _oracle_cartesian(p, n, bc):
+    return assemble.operator_csr(p, n, 0.0, 0.0, bc)
+
+
+@pytest.mark.parametrize("p", range(1, 9))
+def test_cartesian_fp64(p):
+    """Undeformed mesh, coefficient 1: the cell loop applies the cell matrix in its tensor-product
+    form and computes its index lattice; vmult and vmult_add against the oracle's assembled matrix
+    to 1e-12 on meshes several bricks wide (Dirichlet faces)."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    n = WIDE[p]
+    print(f"cartesian fp64 p={p} n={n}", flush=True)
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.0), p, mfq.MFQ_BC_DIRICHLET0), 0.0, mfq.MFQ_FP64)
+    assert op.layout()["brick"][0] == BRICK_X[p] and n > BRICK_X[p]
+    x = uniform_vector(op.n_dofs, seed=160 + p)
+    y0 = uniform_vector(op.n_dofs, seed=170 + p)
+    xt = torch.from_numpy(x).cuda()
+    y = op.vmult(xt)
+    ya = op.vmult_add(xt, torch.from_numpy(y0).cuda())
+    torch.cuda.synchronize()
+    yo = _oracle_cartesian(p, n, 1) @ x
+    err = np.abs(y.cpu().numpy() - yo).max() / np.abs(yo).max()
+    erra = np.abs(ya.cpu().numpy() - (yo + y0)).max() / np.abs(yo + y0).max()
+    print(f"  normwise rel err {err:.2e}, accumulate {erra:.2e}")
+    assert err <= 1e-12 and erra <= 1e-12
+
+
+@pytest.mark.parametrize("p", [1, 2, 4, 5, 8])
+def test_cartesian_fp32(p):
+    import torch
+    import paper_1910_13247_amd as mfq
+    n = WIDE[p]
+    print(f"cartesian fp32 p={p} n={n}", flush=True)
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.0), p, mfq.MFQ_BC_DIRICHLET0), 0.0, mfq.MFQ_FP32)
+    x32 = uniform_vector(op.n_dofs, seed=180 + p).astype(np.float32).astype(np.float64)
+    y = op.vmult(torch.from_numpy(x32).float().cuda())
+    torch.cuda.synchronize()
+    yo = _oracle_cartesian(p, n, 1) @ x32
+    mag = ebe.magnitude_bound(p, n, 0.0, 0.0, x32, 1)
+    k = 8 * (p + 1) + 16
+    assert np.all(np.abs(y.double().cpu().numpy() - yo) <= 2 * k * U32 * mag + 1e-30)
+
+
+@pytest.mark.parametrize("p", [2, 4, 7])
+def test_cartesian_natural_boundary(p):
+    """The same without Dirichlet faces (every node free, the computed index lattice marks none)."""
+    import torch
+    import paper_1910_13247_amd as mfq
+    n = WIDE[p]
+    print(f"cartesian natural bc p={p} n={n}", flush=True)
+    op = mfq.Operator(mfq.Space(mfq.Mesh(n, 0.0), p, 0), 0.0, mfq.MFQ_FP64)
+    x = uniform_vector(op.n_dofs, seed=190 + p)
+    y = op.vmult(torch.from_numpy(x).cuda())
+    torch.cuda.synchronize()
+    yo = _oracle_cartesian(p, n, 0) @ x
+    assert np.abs(y.cpu().numpy() - yo).max() <= 1e-12 * np.abs(yo).max()
