@@ -679,7 +679,19 @@ struct mfq_batch {
   double* host_states = nullptr; // pinned copy of the gathered states and residual norms
   double* host_traces = nullptr; // pinned copy of the gathered traces
   hipEvent_t uploaded = nullptr; // the last table upload has left the staging buffer
+  // Side streams for the independent launch groups of one phase (operators of different degrees
+  // or forms, transfers of different degree pairs): the groups run side by side, forked from and
+  // joined back into the step's stream by events.  Default priority, like every stream here.
+  static constexpr int kSide = 3;
+  hipStream_t side[kSide] = {};
+  hipEvent_t fork = nullptr;
+  hipEvent_t join[kSide] = {};
   ~mfq_batch() {
+    for (int k = 0; k < kSide; ++k) {
+      if (join[k]) (void)hipEventDestroy(join[k]);
+      if (side[k]) (void)hipStreamDestroy(side[k]);
+    }
+    if (fork) (void)hipEventDestroy(fork);
     if (uploaded) (void)hipEventDestroy(uploaded);
     if (host_tables) (void)hipHostFree(host_tables);
     if (host_states) (void)hipHostFree(host_states);
@@ -696,6 +708,8 @@ constexpr int kTraceDoubles = 1024;  // Lanczos traces of one solve's levels in 
 struct PlanLaunch {
   enum Kind { kVec, kCells, kTransfer } kind = kVec;
   int op = 0, p = 0, pf = 0, precision = 0, colour = 0;
+  int phase = 0;  // launches of one phase touch disjoint vectors group by group
+  int group = 0;  // within a phase, the launches of one group run in order
   bool h = false, cart = false, prolongate = false, fused = false, coef = false;
   size_t off = 0;
   int count = 0;
@@ -705,6 +719,7 @@ struct PlanLaunch {
 struct Plan {
   std::vector<char> tab;
   std::vector<PlanLaunch> launches;
+  int phases = 0;
 
   template <class T>
   size_t put(const std::vector<T>& v) {
@@ -723,6 +738,7 @@ struct Plan {
     }
     PlanLaunch L;
     L.kind = PlanLaunch::kVec;
+    L.phase = ++phases;
     L.op = op;
     L.off = put(items);
     L.count = (int)items.size();
@@ -740,6 +756,8 @@ struct Plan {
   };
   void cells(const std::vector<Apply>& list) {
     std::vector<int> done(list.size(), 0);
+    const int phase = ++phases;
+    int group = 0;
     for (size_t i = 0; i < list.size(); ++i) {
       if (done[i]) continue;
       const mfq_op* o = list[i].op;
@@ -777,6 +795,8 @@ struct Plan {
         if (tot[c] == 0) continue;
         PlanLaunch L;
         L.kind = PlanLaunch::kCells;
+        L.phase = phase;
+        L.group = group;
         L.p = p;
         L.precision = prec;
         L.cart = cart;
@@ -788,6 +808,7 @@ struct Plan {
         L.blocks = tot[c];
         launches.push_back(L);
       }
+      ++group;
     }
   }
   struct Move {
@@ -810,6 +831,8 @@ struct Plan {
       vec(kBatchFill, clear);
     }
     std::vector<int> done(list.size(), 0);
+    const int phase = ++phases;
+    int group = 0;
     for (size_t i = 0; i < list.size(); ++i) {
       if (done[i]) continue;
       const int pc = list[i].t->coarse->p, pf = list[i].t->fine->p;
@@ -844,6 +867,8 @@ struct Plan {
         if (tot[c] == 0) continue;
         PlanLaunch L;
         L.kind = PlanLaunch::kTransfer;
+        L.phase = phase;
+        L.group = group;
         L.p = pc;
         L.pf = pf;
         L.h = h;
@@ -854,6 +879,7 @@ struct Plan {
         L.blocks = tot[c];
         launches.push_back(L);
       }
+      ++group;
     }
   }
   // `deg` Chebyshev updates on each level (mfq_chebyshev with the work vectors r, d, t of the
@@ -1204,19 +1230,46 @@ void plan_check(Plan& P, const std::vector<mfq_solver*>& g) {
   P.vec(kBatchResidualNorm, res);
 }
 
+int issue(const mfq_batch* b, const PlanLaunch& L, hipStream_t st) {
+  const void* items = b->buf + L.off;
+  hipError_t e = hipSuccess;
+  if (L.kind == PlanLaunch::kVec)
+    e = launch_batch_vec((BatchVecOp)L.op, (const VecItem*)items, L.count, L.blocks, st);
+  else if (L.kind == PlanLaunch::kCells)
+    e = launch_batch_cells(L.p, L.precision, L.cart, L.coef, L.fused, (const CellItem*)items, L.count, L.colour,
+                           L.blocks, st);
+  else
+    e = launch_batch_transfer(L.p, L.pf, L.h, L.prolongate, L.colour, (const TransferItem*)items, L.count,
+                              L.blocks, st);
+  if (e != hipSuccess) return fail(MFQ_EHIP, "batched launch failed: %s", hipGetErrorString(e));
+  return MFQ_OK;
+}
+
+// The launches in plan order; a phase of several groups is forked over the step's stream and
+// the side streams (group g on stream g mod S) and joined back before the next phase.
 int run_plan(const mfq_batch* b, const Plan& P, hipStream_t st) {
-  for (const PlanLaunch& L : P.launches) {
-    const void* items = b->buf + L.off;
-    hipError_t e = hipSuccess;
-    if (L.kind == PlanLaunch::kVec)
-      e = launch_batch_vec((BatchVecOp)L.op, (const VecItem*)items, L.count, L.blocks, st);
-    else if (L.kind == PlanLaunch::kCells)
-      e = launch_batch_cells(L.p, L.precision, L.cart, L.coef, L.fused, (const CellItem*)items, L.count, L.colour,
-                             L.blocks, st);
-    else
-      e = launch_batch_transfer(L.p, L.pf, L.h, L.prolongate, L.colour, (const TransferItem*)items, L.count,
-                                L.blocks, st);
-    if (e != hipSuccess) return fail(MFQ_EHIP, "batched launch failed: %s", hipGetErrorString(e));
+  const size_t n = P.launches.size();
+  for (size_t i = 0; i < n;) {
+    size_t j = i;
+    int groups = 0;
+    while (j < n && P.launches[j].phase == P.launches[i].phase) groups = std::max(groups, P.launches[j++].group + 1);
+    const int S = std::min(groups, mfq_batch::kSide + 1);
+    if (S <= 1) {
+      for (size_t l = i; l < j; ++l)
+        if (int rc = issue(b, P.launches[l], st)) return rc;
+    } else {
+      MFQ_HIP(hipEventRecord(b->fork, st));
+      for (int k = 1; k < S; ++k) MFQ_HIP(hipStreamWaitEvent(b->side[k - 1], b->fork, 0));
+      for (size_t l = i; l < j; ++l) {
+        const int g = P.launches[l].group % S;
+        if (int rc = issue(b, P.launches[l], g == 0 ? st : b->side[g - 1])) return rc;
+      }
+      for (int k = 1; k < S; ++k) {
+        MFQ_HIP(hipEventRecord(b->join[k - 1], b->side[k - 1]));
+        MFQ_HIP(hipStreamWaitEvent(st, b->join[k - 1], 0));
+      }
+    }
+    i = j;
   }
   return MFQ_OK;
 }
@@ -1633,6 +1686,14 @@ int mfq_batch_create(int max_solvers, mfq_batch** out) {
       hipEventCreateWithFlags(&b->uploaded, hipEventDisableTiming) != hipSuccess) {
     delete b;
     return fail(MFQ_ENOMEM, "pinned host staging of the batch tables could not be allocated");
+  }
+  bool ok = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming) == hipSuccess;
+  for (int k = 0; k < mfq_batch::kSide && ok; ++k)
+    ok = hipStreamCreateWithFlags(&b->side[k], hipStreamNonBlocking) == hipSuccess &&
+         hipEventCreateWithFlags(&b->join[k], hipEventDisableTiming) == hipSuccess;
+  if (!ok) {
+    delete b;
+    return fail(MFQ_EHIP, "side streams of the batch could not be created");
   }
   *out = b;
   return MFQ_OK;
