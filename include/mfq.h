@@ -201,9 +201,11 @@ int mfq_dg_create(const mfq_mesh* mesh, int degree, mfq_dg** out);
 void mfq_dg_destroy(mfq_dg* op);
 int64_t mfq_dg_n_dofs(const mfq_dg* op);  /* n^3 (p+1)^3; -1 for NULL */
 /* dst = A src for double device vectors of n_dofs elements that must not overlap: one launch in
- * which each cell computes its volume term and its six faces (an interior face is evaluated by
- * both of its cells, each keeping its own half) and stores its result once.  Asynchronous,
- * deterministic. */
+ * which each cell forms, along every 1D line of each direction, the line's stiffness term and the
+ * terms of its two faces (from its own line and the neighbours' lines through those faces), then
+ * applies the Gauss rule's mass matrix in the two tangential directions, and stores its result
+ * once (an interior face is evaluated by both of its cells, each keeping its own half).
+ * Asynchronous, deterministic. */
 int mfq_dg_vmult(const mfq_dg* op, const double* src, double* dst, void* hip_stream);
 /* The same product in MFQ_FP64 or MFQ_FP32 (vectors and arithmetic of that precision; the FP32
  * form is the smoother operator of the multigrid below). */
