@@ -25,7 +25,9 @@ struct Transfer1D {
   double P[NF1 * (PC + 1)];  // P[i*(PC+1)+a]
 };
 
-constexpr int kTBlock = 128;
+// Threads per coarse cell: 128, or 256 for the high degrees (p >= 6 fine blocks of 13^3 nodes or
+// more, where one cell's passes are long enough to fill more lanes)
+constexpr int tblock(int nf1) { return nf1 >= 13 ? 256 : 128; }
 
 // prolongation of coarse cell `cell` by the workgroup
 template <int PC, int NF1, typename Real>
@@ -39,14 +41,14 @@ __device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse,
   const int64_t N1c = (int64_t)PC * nc + 1;
   const int stride = NF1 - 1;
   const int64_t N1f = (int64_t)stride * nc + 1;
-  for (int k = threadIdx.x; k < M * M * M; k += kTBlock) {
+  for (int k = threadIdx.x; k < M * M * M; k += tblock(NF1)) {
     const int a = k % M, b = (k / M) % M, c = k / (M * M);
     const int64_t I = (int64_t)PC * ic + a, J = (int64_t)PC * jc + b, K = (int64_t)PC * kc + c;
     const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1c - 1 || J == N1c - 1 || K == N1c - 1);
     u[k] = bnd ? (Real)0 : coarse[I + N1c * (J + N1c * K)];
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < NF1 * M * M; k += kTBlock) {  // t1[i][b][c]
+  for (int k = threadIdx.x; k < NF1 * M * M; k += tblock(NF1)) {  // t1[i][b][c]
     const int i = k % NF1, bc2 = k / NF1;
     Real s = 0;
 #pragma unroll
@@ -54,7 +56,7 @@ __device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse,
     t1[k] = s;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < NF1 * NF1 * M; k += kTBlock) {  // t2[i][j][c]
+  for (int k = threadIdx.x; k < NF1 * NF1 * M; k += tblock(NF1)) {  // t2[i][j][c]
     const int i = k % NF1, j = (k / NF1) % NF1, c = k / (NF1 * NF1);
     Real s = 0;
 #pragma unroll
@@ -66,7 +68,7 @@ __device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse,
   // the mesh's last cell in a direction also its upper face (the other cells' values there are
   // bitwise equal, so the choice of writer does not change the result)
   const int ni = ic == nc - 1 ? NF1 : NF1 - 1, nj = jc == nc - 1 ? NF1 : NF1 - 1, nl = kc == nc - 1 ? NF1 : NF1 - 1;
-  for (int k = threadIdx.x; k < ni * nj * nl; k += kTBlock) {
+  for (int k = threadIdx.x; k < ni * nj * nl; k += tblock(NF1)) {
     const int i = k % ni, j = (k / ni) % nj, l = k / (ni * nj);
     Real s = 0;
 #pragma unroll
@@ -78,7 +80,7 @@ __device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse,
 }
 
 template <int PC, int NF1, typename Real>
-__global__ __launch_bounds__(kTBlock) void prolongate_kernel(const Real* __restrict__ coarse, Real* __restrict__ fine,
+__global__ __launch_bounds__(tblock(NF1)) void prolongate_kernel(const Real* __restrict__ coarse, Real* __restrict__ fine,
                                                              int nc, int bc, Transfer1D<PC, NF1> tr) {
   prolongate_cell<PC, NF1, Real>(coarse, fine, nc, bc, tr, blockIdx.x);
 }
@@ -102,14 +104,14 @@ __device__ __forceinline__ void restrict_cell(const Real* __restrict__ fine, Rea
     return ((i == 0 && icell > 0) || (i == NF1 - 1 && icell < nc - 1)) ? (Real)0.5 : (Real)1;
   };
   // the fine block once into LDS (rows along x coalesced), then the three 1D passes from LDS
-  for (int k = threadIdx.x; k < NF1 * NF1 * NF1; k += kTBlock) {
+  for (int k = threadIdx.x; k < NF1 * NF1 * NF1; k += tblock(NF1)) {
     const int i = k % NF1, j = (k / NF1) % NF1, l = k / (NF1 * NF1);
     const int64_t I = (int64_t)stride * ic + i, J = (int64_t)stride * jc + j, K = (int64_t)stride * kc + l;
     const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1f - 1 || J == N1f - 1 || K == N1f - 1);
     f[k] = bnd ? (Real)0 : fine[I + N1f * (J + N1f * K)];
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < M * NF1 * NF1; k += kTBlock) {
+  for (int k = threadIdx.x; k < M * NF1 * NF1; k += tblock(NF1)) {
     const int a = k % M, j = (k / M) % NF1, l = k / (M * NF1);
     const Real wjl = shared_factor(j, jc) * shared_factor(l, kc);
     Real s = 0;
@@ -117,14 +119,14 @@ __device__ __forceinline__ void restrict_cell(const Real* __restrict__ fine, Rea
     t1[k] = s * wjl;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < M * M * NF1; k += kTBlock) {
+  for (int k = threadIdx.x; k < M * M * NF1; k += tblock(NF1)) {
     const int a = k % M, b = (k / M) % M, l = k / (M * M);
     Real s = 0;
     for (int j = 0; j < NF1; ++j) s += (Real)tr.P[j * M + b] * t1[a + M * (j + NF1 * l)];
     t2[k] = s;
   }
   __syncthreads();
-  for (int k = threadIdx.x; k < M * M * M; k += kTBlock) {
+  for (int k = threadIdx.x; k < M * M * M; k += tblock(NF1)) {
     const int a = k % M, b = (k / M) % M, c = k / (M * M);
     Real s = 0;
     for (int l = 0; l < NF1; ++l) s += (Real)tr.P[l * M + c] * t2[a + M * (b + M * l)];
@@ -136,7 +138,7 @@ __device__ __forceinline__ void restrict_cell(const Real* __restrict__ fine, Rea
 }
 
 template <int PC, int NF1, typename Real>
-__global__ __launch_bounds__(kTBlock) void restrict_kernel(const Real* __restrict__ fine, Real* __restrict__ coarse,
+__global__ __launch_bounds__(tblock(NF1)) void restrict_kernel(const Real* __restrict__ fine, Real* __restrict__ coarse,
                                                            int nc, int bc, int colour, Transfer1D<PC, NF1> tr) {
   restrict_cell<PC, NF1, Real>(fine, coarse, nc, bc, colour, tr, blockIdx.x);
 }
@@ -154,14 +156,14 @@ __device__ __forceinline__ int transfer_item(const TransferItem* __restrict__ it
 }
 
 template <int PC, int NF1>
-__global__ __launch_bounds__(kTBlock) void batch_prolongate_kernel(const TransferItem* __restrict__ items, int count,
+__global__ __launch_bounds__(tblock(NF1)) void batch_prolongate_kernel(const TransferItem* __restrict__ items, int count,
                                                                    Transfer1D<PC, NF1> tr) {
   const TransferItem& it = items[transfer_item(items, count, 0, blockIdx.x)];
   prolongate_cell<PC, NF1, float>((const float*)it.in, (float*)it.out, it.nc, it.bc, tr, blockIdx.x - it.first[0]);
 }
 
 template <int PC, int NF1>
-__global__ __launch_bounds__(kTBlock) void batch_restrict_kernel(const TransferItem* __restrict__ items, int count,
+__global__ __launch_bounds__(tblock(NF1)) void batch_restrict_kernel(const TransferItem* __restrict__ items, int count,
                                                                  int colour, Transfer1D<PC, NF1> tr) {
   const TransferItem& it = items[transfer_item(items, count, colour, blockIdx.x)];
   restrict_cell<PC, NF1, float>((const float*)it.in, (float*)it.out, it.nc, it.bc, colour, tr,
@@ -177,9 +179,9 @@ hipError_t batch_transfer_pn(bool h_transfer, bool prolongate, int colour, const
   Transfer1D<PC, NF1> tr;
   for (int k = 0; k < NF1 * (PC + 1); ++k) tr.P[k] = P1[k];
   if (prolongate)
-    batch_prolongate_kernel<PC, NF1><<<(unsigned)blocks, kTBlock, 0, st>>>(items, count, tr);
+    batch_prolongate_kernel<PC, NF1><<<(unsigned)blocks, tblock(NF1), 0, st>>>(items, count, tr);
   else
-    batch_restrict_kernel<PC, NF1><<<(unsigned)blocks, kTBlock, 0, st>>>(items, count, colour, tr);
+    batch_restrict_kernel<PC, NF1><<<(unsigned)blocks, tblock(NF1), 0, st>>>(items, count, colour, tr);
   return hipGetLastError();
 }
 
@@ -193,9 +195,9 @@ hipError_t transfer_pn(const mfq_transfer* t, int precision, bool prolongate, co
   const unsigned grid = (unsigned)t->coarse->n_cells;
   if (prolongate) {
     if (precision == MFQ_FP64)
-      prolongate_kernel<PC, NF1, double><<<grid, kTBlock, 0, st>>>((const double*)in, (double*)out, nc, bc, tr);
+      prolongate_kernel<PC, NF1, double><<<grid, tblock(NF1), 0, st>>>((const double*)in, (double*)out, nc, bc, tr);
     else
-      prolongate_kernel<PC, NF1, float><<<grid, kTBlock, 0, st>>>((const float*)in, (float*)out, nc, bc, tr);
+      prolongate_kernel<PC, NF1, float><<<grid, tblock(NF1), 0, st>>>((const float*)in, (float*)out, nc, bc, tr);
   } else {
     hipError_t e = launch_fill(precision, out, t->coarse->n_dofs, 0.0, st);
     if (e != hipSuccess) return e;
@@ -203,9 +205,9 @@ hipError_t transfer_pn(const mfq_transfer* t, int precision, bool prolongate, co
       const int64_t cells = (int64_t)((nc + 1 - (c & 1)) / 2) * ((nc + 1 - ((c >> 1) & 1)) / 2) * ((nc + 1 - (c >> 2)) / 2);
       if (cells == 0) continue;
       if (precision == MFQ_FP64)
-        restrict_kernel<PC, NF1, double><<<(unsigned)cells, kTBlock, 0, st>>>((const double*)in, (double*)out, nc, bc, c, tr);
+        restrict_kernel<PC, NF1, double><<<(unsigned)cells, tblock(NF1), 0, st>>>((const double*)in, (double*)out, nc, bc, c, tr);
       else
-        restrict_kernel<PC, NF1, float><<<(unsigned)cells, kTBlock, 0, st>>>((const float*)in, (float*)out, nc, bc, c, tr);
+        restrict_kernel<PC, NF1, float><<<(unsigned)cells, tblock(NF1), 0, st>>>((const float*)in, (float*)out, nc, bc, c, tr);
     }
   }
   return hipGetLastError();
