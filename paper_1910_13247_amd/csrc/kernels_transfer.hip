@@ -25,9 +25,10 @@ struct Transfer1D {
   double P[NF1 * (PC + 1)];  // P[i*(PC+1)+a]
 };
 
-// Threads per coarse cell: 128, or 256 for the high degrees (p >= 6 fine blocks of 13^3 nodes or
-// more, where one cell's passes are long enough to fill more lanes)
-constexpr int tblock(int nf1) { return nf1 >= 13 ? 256 : 128; }
+// Threads per coarse cell: 128, or more for the high degrees, whose fine blocks (13^3 nodes and
+// up) give one cell's passes enough work for more lanes (Q8 24^3 GMG_MIXED_IR solve 0.115 s with
+// 128, 0.109 with 256, 0.105 with 512 threads; 256 for the degree 4 blocks: within noise)
+constexpr int tblock(int nf1) { return nf1 >= 15 ? 512 : nf1 >= 13 ? 256 : 128; }
 
 // prolongation of coarse cell `cell` by the workgroup
 template <int PC, int NF1, typename Real>
