@@ -38,10 +38,12 @@ __device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse,
   __shared__ Real u[M * M * M];
   __shared__ Real t1[NF1 * M * M];
   __shared__ Real t2[NF1 * NF1 * M];
+  __shared__ Real Ps[NF1 * M];  // the 1D matrix, read by every pass
   const int ic = (int)(cell % nc), jc = (int)((cell / nc) % nc), kc = (int)(cell / ((int64_t)nc * nc));
   const int64_t N1c = (int64_t)PC * nc + 1;
   const int stride = NF1 - 1;
   const int64_t N1f = (int64_t)stride * nc + 1;
+  for (int k = threadIdx.x; k < NF1 * M; k += tblock(NF1)) Ps[k] = (Real)tr.P[k];
   for (int k = threadIdx.x; k < M * M * M; k += tblock(NF1)) {
     const int a = k % M, b = (k / M) % M, c = k / (M * M);
     const int64_t I = (int64_t)PC * ic + a, J = (int64_t)PC * jc + b, K = (int64_t)PC * kc + c;
@@ -53,7 +55,7 @@ __device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse,
     const int i = k % NF1, bc2 = k / NF1;
     Real s = 0;
 #pragma unroll
-    for (int a = 0; a < M; ++a) s += (Real)tr.P[i * M + a] * u[a + M * bc2];
+    for (int a = 0; a < M; ++a) s += Ps[i * M + a] * u[a + M * bc2];
     t1[k] = s;
   }
   __syncthreads();
@@ -61,7 +63,7 @@ __device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse,
     const int i = k % NF1, j = (k / NF1) % NF1, c = k / (NF1 * NF1);
     Real s = 0;
 #pragma unroll
-    for (int b = 0; b < M; ++b) s += (Real)tr.P[j * M + b] * t1[i + NF1 * (b + M * c)];
+    for (int b = 0; b < M; ++b) s += Ps[j * M + b] * t1[i + NF1 * (b + M * c)];
     t2[k] = s;
   }
   __syncthreads();
@@ -73,7 +75,7 @@ __device__ __forceinline__ void prolongate_cell(const Real* __restrict__ coarse,
     const int i = k % ni, j = (k / ni) % nj, l = k / (ni * nj);
     Real s = 0;
 #pragma unroll
-    for (int c = 0; c < M; ++c) s += (Real)tr.P[l * M + c] * t2[i + NF1 * (j + NF1 * c)];
+    for (int c = 0; c < M; ++c) s += Ps[l * M + c] * t2[i + NF1 * (j + NF1 * c)];
     const int64_t I = (int64_t)stride * ic + i, J = (int64_t)stride * jc + j, K = (int64_t)stride * kc + l;
     const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1f - 1 || J == N1f - 1 || K == N1f - 1);
     fine[I + N1f * (J + N1f * K)] = bnd ? (Real)0 : s;
@@ -94,6 +96,7 @@ __device__ __forceinline__ void restrict_cell(const Real* __restrict__ fine, Rea
   __shared__ Real f[NF1 * NF1 * NF1]; // the cell's fine nodes, zero on Dirichlet nodes
   __shared__ Real t1[M * NF1 * NF1];  // t1[a][j][l]
   __shared__ Real t2[M * M * NF1];    // t2[a][b][l]
+  __shared__ Real Ps[NF1 * M];        // the 1D matrix, read by every pass
   // cell (ic, jc, kc) of colour (ic & 1) + 2 (jc & 1) + 4 (kc & 1), x fastest within the colour
   const int px = colour & 1, py = (colour >> 1) & 1, pz = colour >> 2;
   const int cxn = (nc + 1 - px) / 2, cyn = (nc + 1 - py) / 2;
@@ -105,6 +108,7 @@ __device__ __forceinline__ void restrict_cell(const Real* __restrict__ fine, Rea
     return ((i == 0 && icell > 0) || (i == NF1 - 1 && icell < nc - 1)) ? (Real)0.5 : (Real)1;
   };
   // the fine block once into LDS (rows along x coalesced), then the three 1D passes from LDS
+  for (int k = threadIdx.x; k < NF1 * M; k += tblock(NF1)) Ps[k] = (Real)tr.P[k];
   for (int k = threadIdx.x; k < NF1 * NF1 * NF1; k += tblock(NF1)) {
     const int i = k % NF1, j = (k / NF1) % NF1, l = k / (NF1 * NF1);
     const int64_t I = (int64_t)stride * ic + i, J = (int64_t)stride * jc + j, K = (int64_t)stride * kc + l;
@@ -116,21 +120,24 @@ __device__ __forceinline__ void restrict_cell(const Real* __restrict__ fine, Rea
     const int a = k % M, j = (k / M) % NF1, l = k / (M * NF1);
     const Real wjl = shared_factor(j, jc) * shared_factor(l, kc);
     Real s = 0;
-    for (int i = 0; i < NF1; ++i) s += (Real)tr.P[i * M + a] * shared_factor(i, ic) * f[i + NF1 * (j + NF1 * l)];
+#pragma unroll
+    for (int i = 0; i < NF1; ++i) s += Ps[i * M + a] * shared_factor(i, ic) * f[i + NF1 * (j + NF1 * l)];
     t1[k] = s * wjl;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < M * M * NF1; k += tblock(NF1)) {
     const int a = k % M, b = (k / M) % M, l = k / (M * M);
     Real s = 0;
-    for (int j = 0; j < NF1; ++j) s += (Real)tr.P[j * M + b] * t1[a + M * (j + NF1 * l)];
+#pragma unroll
+    for (int j = 0; j < NF1; ++j) s += Ps[j * M + b] * t1[a + M * (j + NF1 * l)];
     t2[k] = s;
   }
   __syncthreads();
   for (int k = threadIdx.x; k < M * M * M; k += tblock(NF1)) {
     const int a = k % M, b = (k / M) % M, c = k / (M * M);
     Real s = 0;
-    for (int l = 0; l < NF1; ++l) s += (Real)tr.P[l * M + c] * t2[a + M * (b + M * l)];
+#pragma unroll
+    for (int l = 0; l < NF1; ++l) s += Ps[l * M + c] * t2[a + M * (b + M * l)];
     const int64_t I = (int64_t)PC * ic + a, J = (int64_t)PC * jc + b, K = (int64_t)PC * kc + c;
     const bool bnd = bc && (I == 0 || J == 0 || K == 0 || I == N1c - 1 || J == N1c - 1 || K == N1c - 1);
     // this launch's cells share no coarse node; earlier colours' sums are already in place
