@@ -151,13 +151,15 @@ def test_poisson_q2_8_vmult():
 
 
 @pytest.mark.parametrize("p,n", [(1, 1), (2, 1), (8, 1)])
-def test_single_cell_degenerate(p, n):
-    # one cell: with Dirichlet rows every node but the interior ones is the identity
+@pytest.mark.parametrize("amp,alpha", [(0.1, 0.5), (0.0, 0.0)])
+def test_single_cell_degenerate(p, n, amp, alpha):
+    # one cell: with Dirichlet rows every node but the interior ones is the identity (curved, and
+    # the Cartesian instance with its tensor-product cell term and computed index lattice)
     mfq = _mfq()
-    op = _op(p, n, 0.1, 0.5, 1, mfq.MFQ_FP64)
+    op = _op(p, n, amp, alpha, 1, mfq.MFQ_FP64)
     x = uniform_vector(op.n_dofs, seed=3)
     y = _run(op, x)
-    yo = assemble.operator_csr(p, n, 0.1, 0.5, 1) @ x
+    yo = assemble.operator_csr(p, n, amp, alpha, 1) @ x
     assert np.abs(y - yo).max() <= 1e-12 * np.abs(yo).max()
     if p == 1:
         np.testing.assert_array_equal(y, x)
